@@ -1,0 +1,160 @@
+"""Pins of the W1 values the oracle converges to: the 1-D closed form,
+translated densities, brute-force exact transport on tiny grids (two
+independent LP formulations), p = 2 sandwich bounds and invariants."""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import linear_sum_assignment, linprog
+
+import oracle.w1_oracle as o
+import w1data
+
+TIGHT = dict(stop="kkt", tol=1e-9, check_every=10, max_iters=400000)
+
+
+def _solve(p0, p1, n, p, algo=1, L=1, **kw):
+    args = dict(TIGHT)
+    args.update(kw)
+    return o.solve(p0, p1, n, L=L, p=p, algo=algo, **args)
+
+
+def _transport_lp_l1(a, b, n):
+    """Exact W1 between node masses with Manhattan ground cost (HiGHS LP)."""
+    N = (n + 1) ** 2
+    ii, jj = np.divmod(np.arange(N), n + 1)
+    C = (np.abs(ii[:, None] - ii[None, :]) + np.abs(jj[:, None] - jj[None, :])) / n
+    A_eq = np.zeros((2 * N, N * N))
+    for k in range(N):
+        A_eq[k, k * N:(k + 1) * N] = 1.0
+        A_eq[N + k, k::N] = 1.0
+    res = linprog(C.ravel(), A_eq=A_eq, b_eq=np.concatenate([a.ravel(), b.ravel()]), bounds=(0, None),
+                  method="highs")
+    assert res.status == 0
+    return res.fun
+
+
+def _flux_lp_l1(a, b, n):
+    """The paper's discrete problem (opt_flux_dis) for p = 1 as an LP over
+    edge fluxes split into positive and negative parts."""
+    h = 1.0 / n
+    rho = (a - b) / h ** 2
+    N = (n + 1) ** 2
+    edges = []
+    for i in range(n + 1):
+        for j in range(n + 1):
+            if i < n:
+                edges.append(((i, j), (i + 1, j)))
+            if j < n:
+                edges.append(((i, j), (i, j + 1)))
+    E = len(edges)
+    A = np.zeros((N, 2 * E))
+    for e, (s, t) in enumerate(edges):
+        si, ti = s[0] * (n + 1) + s[1], t[0] * (n + 1) + t[1]
+        # flux along the edge leaves s (+1/h at s) and enters t (-1/h at t)
+        A[si, e] += 1 / h; A[ti, e] -= 1 / h
+        A[si, E + e] -= 1 / h; A[ti, E + e] += 1 / h
+    res = linprog(np.full(2 * E, h * h), A_eq=A, b_eq=rho.ravel(), bounds=(0, None), method="highs")
+    assert res.status == 0
+    return res.fun
+
+
+def _assignment_l1(ia, ib, n):
+    """Exact W1 for integer masses by the Hungarian method on unit atoms."""
+    ai = np.repeat(np.arange(ia.size), ia.ravel())
+    bi = np.repeat(np.arange(ib.size), ib.ravel())
+    pa = np.stack(np.divmod(ai, n + 1), 1)
+    pb = np.stack(np.divmod(bi, n + 1), 1)
+    C = np.abs(pa[:, None, :] - pb[None, :, :]).sum(-1) / n
+    r, c = linear_sum_assignment(C)
+    return C[r, c].sum() / ia.sum()
+
+
+@pytest.mark.parametrize("n,seed", [(4, 0), (6, 1), (8, 2)])
+def test_brute_force_min_cost_flow_p1(n, seed):
+    ia, ib = w1data.integer_mass_pair(n, 24, seed)
+    a, b = ia / ia.sum(), ib / ib.sum()
+    exact_tp = _transport_lp_l1(a, b, n)
+    exact_flux = _flux_lp_l1(a, b, n)
+    exact_hu = _assignment_l1(ia, ib, n)
+    assert exact_tp == pytest.approx(exact_flux, rel=1e-9, abs=1e-12)
+    assert exact_tp == pytest.approx(exact_hu, rel=1e-9, abs=1e-12)
+    r = _solve(a, b, n, 1)
+    assert r["lo"] <= exact_tp * (1 + 1e-9) + 1e-12
+    assert r["hi"] >= exact_tp * (1 - 1e-9) - 1e-12
+    assert r["w1"] == pytest.approx(exact_tp, rel=2e-6)
+
+
+@pytest.mark.parametrize("n,p", [(8, 1), (16, 2), (9, 2)])
+def test_stripes_closed_form(n, p):
+    a, b = w1data.stripes_pair(n, seed=n)
+    F0 = np.cumsum(a.sum(axis=1))
+    F1 = np.cumsum(b.sum(axis=1))
+    closed = float(np.sum(np.abs(F0 - F1)) / n)
+    r = _solve(a, b, n, p, algo=2 if p == 2 else 1)
+    assert r["w1"] == pytest.approx(closed, rel=1e-6)
+    assert r["lo"] <= closed * (1 + 1e-9) <= r["hi"] * (1 + 2e-9)
+
+
+@pytest.mark.parametrize("n,shift,p", [(12, (2, 3), 1), (12, (-3, 1), 1), (8, (2, 0), 2), (8, (0, -3), 2)])
+def test_translation_closed_form(n, shift, p):
+    a, b, mass = w1data.translated_bump_pair(n, shift, floor_mass=0.2, seed=sum(shift) + 7)
+    s = np.array(shift, dtype=float) / n
+    closed = (np.abs(s).sum() if p == 1 else np.linalg.norm(s)) * mass
+    r = _solve(a, b, n, p, algo=1 if p == 1 else 2)
+    assert r["w1"] == pytest.approx(closed, rel=2e-6)
+    assert r["lo"] <= closed * (1 + 1e-9)
+    assert r["hi"] >= closed * (1 - 1e-9)
+
+
+def test_p2_sandwich_and_moment_bound():
+    n = 10
+    a, b = w1data.random_pair(n, 11)
+    r1 = _solve(a, b, n, 1, algo=1)["w1"]
+    r2 = _solve(a, b, n, 2, algo=2)
+    assert r1 / math.sqrt(2) - 1e-8 <= r2["w1"] <= r1 + 1e-8
+    x1, x2 = w1data.nodes(n)
+    mom = np.array([np.sum((a - b) * x1), np.sum((a - b) * x2)])
+    assert r2["w1"] >= np.linalg.norm(mom) - 1e-9
+    assert r2["lo"] <= r2["hi"]
+
+
+def test_invariants():
+    n = 8
+    a, b = w1data.random_pair(n, 21)
+    c, _ = w1data.random_pair(n, 22)
+    w_ab = _solve(a, b, n, 2, algo=2)["w1"]
+    assert _solve(a, a, n, 2, algo=2)["w1"] == pytest.approx(0.0, abs=1e-14)
+    assert _solve(b, a, n, 2, algo=2)["w1"] == pytest.approx(w_ab, rel=1e-7)
+    assert _solve(a.T.copy(), b.T.copy(), n, 2, algo=2)["w1"] == pytest.approx(w_ab, rel=1e-7)
+    # a flip of an axis maps the grid graph to itself, so the p = 1 problem is
+    # invariant; for p = 2 it is not (the isotropic norm pairs each node's two
+    # forward edges, and a flip turns them into backward edges)
+    w1_ab = _solve(a, b, n, 1, algo=1)["w1"]
+    assert _solve(a[::-1].copy(), b[::-1].copy(), n, 1, algo=1)["w1"] == pytest.approx(w1_ab, rel=1e-7)
+    assert _solve(a[:, ::-1].copy(), b[:, ::-1].copy(), n, 1, algo=1)["w1"] == pytest.approx(w1_ab, rel=1e-7)
+    w_ac = _solve(a, c, n, 2, algo=2)["w1"]
+    w_bc = _solve(b, c, n, 2, algo=2)["w1"]
+    assert w_ac <= w_ab + w_bc + 1e-9
+
+
+def test_plain_and_prox_agree_and_cascade_preserves_limit():
+    # Algorithms 1-4 are four different iterations with the same limit W1_h
+    n = 8
+    a, b = w1data.random_pair(n, 3)
+    ref = _solve(a, b, n, 1, algo=1)
+    for kw in (dict(algo=2), dict(algo=1, L=3), dict(algo=2, L=3)):
+        r = _solve(a, b, n, 1, **kw)
+        assert r["w1"] == pytest.approx(ref["w1"], rel=1e-7), kw
+    assert len(r["iters"]) == 3
+
+
+def test_certificate_brackets_the_limit():
+    n = 8
+    a, b = w1data.random_pair(n, 31)
+    exact = _solve(a, b, n, 2, algo=2, tol=1e-11)["w1"]
+    for k in (5, 50, 500):
+        r = o.solve(a, b, n, L=1, p=2, algo=1, stop="kkt", tol=0.0, max_iters=k, check_every=k)
+        assert r["status"] == "maxiter"
+        assert r["lo"] <= exact * (1 + 1e-12) + 1e-15
+        assert r["hi"] >= exact * (1 - 1e-12) - 1e-15
