@@ -1,0 +1,942 @@
+// Host engine: per-precision batches of W1 solves advanced one iteration
+// block at a time (Algorithms 3 and 4 of arXiv 1810.00118).
+//
+// A step launches, for every in-flight solve, the work of its current level:
+//   - plain levels whose grid fits one workgroup's LDS: the resident kernel
+//     runs the whole level (to its stop test or cap) in one launch;
+//   - other plain levels: `check_every` iterations in temporally blocked
+//     tiled launches, then the stop test;
+//   - prox levels: `check_every` iterations of (divergence, four DCT passes,
+//     update), then the stop test.
+// One host synchronisation per step reads the per-slot status; finished
+// levels are prolonged to the next level (Sec. 3.3) or evaluated.  Every
+// launch covers all slots of its kind through a device work list, so pairs
+// of different sizes and metrics share launches.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace w1 {
+
+static thread_local std::string g_err;
+const char* last_error_text() { return g_err.c_str(); }
+
+double now_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return W1_OK;
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? W1_ENOMEM : W1_EDEVICE;
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t _e = (x);                            \
+    if (_e != hipSuccess) return hip_status(_e, #x); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+static inline int pitch_of(int n) { return cdiv(n + 1, 32) * 32; }
+static inline size_t plane_elems(int n) { return (size_t)(n + 1) * pitch_of(n); }
+static inline int simple_ti(int n) { return cdiv(n + 1, ST_H); }
+static inline int simple_tj(int n) { return cdiv(n + 1, ST_W); }
+static inline int simple_tiles(int n) { return simple_ti(n) * simple_tj(n); }
+static inline int gemm_t(int n) { return cdiv(n + 1, GEMM_T); }
+static inline int tiled_ti(int n, int rh, int S) { return cdiv(n + 1, rh - 2 * S); }
+static inline int tiled_tj(int n, int S) { return cdiv(n + 1, TILED_RW - 2 * S); }
+static inline int max_tiles(int n) {
+  return std::max(simple_tiles(n), std::max(gemm_t(n) * gemm_t(n), tiled_ti(n, 32, 1) * tiled_tj(n, 1)));
+}
+static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static double paper_eps(int algo, int n, bool multilevel) {
+  const double s = (1.0 / n) / (1.0 / 512.0);
+  if (algo == W1_ALGO_PLAIN) return multilevel ? 1e-6 / 128.0 * s * s : 1e-6 / 512.0 * s * s * s;
+  return multilevel ? std::min(2e-4, 1e-4 / 32.0 * s * s) : std::min(2e-4, 1e-4 / 16.0 * s * s);
+}
+
+size_t request_bytes(const w1_params& p) {
+  const size_t es = p.precision == W1_FP64 ? 8 : 4;
+  size_t b = 0;
+  for (int l = 0; l < p.levels; ++l) {
+    const int nl = p.n >> (p.levels - 1 - l);
+    const size_t pe = plane_elems(nl);
+    b += (NPLANES + 1) * align256(pe * es) + 2 * align256(pe * 8);
+  }
+  b += align256((size_t)max_tiles(p.n) * NQ * 8);
+  b += 3 * align256((size_t)(p.n + 1) * (p.n + 1) * 8);
+  return b;
+}
+
+// Temporal-block depth and region height of the plain tiled kernel.  Deep
+// blocks cut HBM traffic per iteration; the halo recomputation grows as
+// (RH+2T)/RH * (128+2T)/128, so the depth is bounded by the region.
+TileChoice choose_tiles(int precision, int side, int nslots, int check_every, int requested) {
+  TileChoice c;
+  c.rh = precision == W1_FP64 ? 32 : 64;
+  int T = requested > 0 ? requested : (precision == W1_FP64 ? 2 : 6);
+  const int maxT = c.rh / 2 - 4;
+  if (T > maxT) T = maxT;
+  if (T < 1) T = 1;
+  (void)side;
+  (void)nslots;
+  (void)check_every;
+  c.steps = T;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// caching device allocator for solve state (exact-size reuse)
+// ---------------------------------------------------------------------------
+class BlockCache {
+ public:
+  int get(size_t bytes, char** out) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = free_.find(bytes);
+    if (it != free_.end()) {
+      *out = it->second;
+      free_.erase(it);
+      return W1_OK;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      // release cached blocks and retry once
+      for (auto& kv : free_) (void)hipFree(kv.second);
+      free_.clear();
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) return hip_status(e, "hipMalloc(solve state)");
+    }
+    *out = (char*)p;
+    return W1_OK;
+  }
+  void put(size_t bytes, char* p) {
+    std::lock_guard<std::mutex> g(mu_);
+    free_.emplace(bytes, p);
+  }
+  ~BlockCache() {
+    for (auto& kv : free_) (void)hipFree(kv.second);
+  }
+
+ private:
+  std::mutex mu_;
+  std::multimap<size_t, char*> free_;
+};
+
+// ---------------------------------------------------------------------------
+// DCT-II tables per length and precision (process lifetime)
+// ---------------------------------------------------------------------------
+struct DctTab {
+  void* C = nullptr;
+  void* Ct = nullptr;
+  double* s = nullptr;
+};
+static std::mutex g_dct_mu;
+static std::map<std::pair<int, int>, DctTab> g_dct;
+
+template <typename T>
+static int dct_tables(int N, DctTab* out) {
+  std::lock_guard<std::mutex> g(g_dct_mu);
+  auto key = std::make_pair(N, (int)sizeof(T));
+  auto it = g_dct.find(key);
+  if (it != g_dct.end()) {
+    *out = it->second;
+    return W1_OK;
+  }
+  std::vector<T> C((size_t)N * N), Ct((size_t)N * N);
+  std::vector<double> s(N);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < N; ++k) {
+    const double sk = k == 0 ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N);
+    for (int j = 0; j < N; ++j) {
+      const double v = sk * std::cos(pi * k * (2.0 * j + 1.0) / (2.0 * N));
+      C[(size_t)k * N + j] = (T)v;
+      Ct[(size_t)j * N + k] = (T)v;
+    }
+    const double sn = std::sin(pi * k / (2.0 * N));
+    s[k] = 4.0 * sn * sn;
+  }
+  DctTab t;
+  HIPCHK(hipMalloc(&t.C, C.size() * sizeof(T)));
+  HIPCHK(hipMalloc(&t.Ct, Ct.size() * sizeof(T)));
+  HIPCHK(hipMalloc((void**)&t.s, N * sizeof(double)));
+  HIPCHK(hipMemcpy(t.C, C.data(), C.size() * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t.Ct, Ct.data(), Ct.size() * sizeof(T), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(t.s, s.data(), N * sizeof(double), hipMemcpyHostToDevice));
+  g_dct[key] = t;
+  *out = t;
+  return W1_OK;
+}
+
+// ---------------------------------------------------------------------------
+// upload arena: pinned staging + device copy, reset once per step (after the
+// step's synchronisation), so staged bytes are never rewritten while a copy
+// may still read them
+// ---------------------------------------------------------------------------
+class Arena {
+ public:
+  explicit Arena(hipStream_t s) : st_(s) {}
+  ~Arena() {
+    for (auto& c : chunks_) {
+      (void)hipHostFree(c.h);
+      (void)hipFree(c.d);
+    }
+  }
+  void reset() {
+    for (auto& c : chunks_) c.used = 0;
+    cur_ = 0;
+  }
+  template <typename X>
+  X* put(const std::vector<X>& v, int* status) {
+    return (X*)put_bytes(v.data(), v.size() * sizeof(X), status);
+  }
+  void* put_bytes(const void* src, size_t nbytes, int* status) {
+    const size_t bytes = std::max<size_t>(align256(nbytes), 256);
+    while (cur_ < chunks_.size() && chunks_[cur_].used + bytes > chunks_[cur_].cap) ++cur_;
+    if (cur_ == chunks_.size()) {
+      Chunk c;
+      c.cap = std::max<size_t>(bytes, (size_t)4 << 20);
+      if (hipHostMalloc((void**)&c.h, c.cap, hipHostMallocDefault) != hipSuccess ||
+          hipMalloc((void**)&c.d, c.cap) != hipSuccess) {
+        *status = W1_ENOMEM;
+        g_err = "upload arena allocation failed";
+        return nullptr;
+      }
+      chunks_.push_back(c);
+    }
+    Chunk& c = chunks_[cur_];
+    char* h = c.h + c.used;
+    char* d = c.d + c.used;
+    if (nbytes) std::memcpy(h, src, nbytes);
+    c.used += bytes;
+    hipError_t e = hipMemcpyAsync(d, h, nbytes ? nbytes : 1, hipMemcpyHostToDevice, st_);
+    if (e != hipSuccess) {
+      *status = hip_status(e, "hipMemcpyAsync(upload)");
+      return nullptr;
+    }
+    return d;
+  }
+
+ private:
+  struct Chunk {
+    char* h = nullptr;
+    char* d = nullptr;
+    size_t cap = 0, used = 0;
+  };
+  hipStream_t st_;
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0;
+};
+
+// never destroyed: freeing device memory from a static destructor would race
+// the HIP runtime's own teardown at process exit
+static BlockCache& g_blocks_ref() {
+  static BlockCache* b = new BlockCache();
+  return *b;
+}
+#define g_blocks g_blocks_ref()
+
+// ---------------------------------------------------------------------------
+// Batch<T>
+// ---------------------------------------------------------------------------
+template <typename T>
+class Batch : public BatchBase {
+ public:
+  Batch(int capacity, hipStream_t s) : cap_(capacity), st_(s), arena_(s) {
+    slots_.assign(cap_, nullptr);
+    hdesc_.assign((size_t)cap_ * MAXL, SlotDesc<T>{});
+    ok_ = hipMalloc((void**)&ddesc_, sizeof(SlotDesc<T>) * cap_ * MAXL) == hipSuccess &&
+          hipMalloc((void**)&dsc_, sizeof(SlotScalars) * cap_) == hipSuccess &&
+          hipHostMalloc((void**)&hsc_, sizeof(SlotScalars) * cap_, hipHostMallocDefault) == hipSuccess;
+    if (ok_) ok_ = hipMemsetAsync(dsc_, 0, sizeof(SlotScalars) * cap_, st_) == hipSuccess;
+    if (ok_) ok_ = hipStreamSynchronize(st_) == hipSuccess;
+  }
+  ~Batch() override {
+    (void)hipStreamSynchronize(st_);
+    for (auto* r : slots_)
+      if (r && r->mem) g_blocks.put(r->bytes, r->mem);
+    (void)hipFree(ddesc_);
+    (void)hipFree(dsc_);
+    (void)hipHostFree(hsc_);
+  }
+
+  int active() const override {
+    int a = 0;
+    for (auto* r : slots_)
+      if (r && r->state != Request::DONE) ++a;
+    return a;
+  }
+
+  int admit(Request* r, const double* p0, const double* p1, int on_device) override {
+    if (!ok_) return W1_EDEVICE;
+    int slot = -1;
+    for (int i = 0; i < cap_; ++i)
+      if (!slots_[i]) {
+        slot = i;
+        break;
+      }
+    if (slot < 0) return W1_EBUSY;
+    r->bytes = request_bytes(r->prm);
+    int st = g_blocks.get(r->bytes, &r->mem);
+    if (st) return st;
+    r->slot = slot;
+    slots_[slot] = r;
+    // carve the block
+    const int L = r->prm.levels;
+    char* p = r->mem;
+    for (int l = 0; l < L; ++l) {
+      const int nl = r->sides[l];
+      const size_t pe = plane_elems(nl);
+      SlotDesc<T>& d = hdesc_[(size_t)slot * MAXL + l];
+      d = SlotDesc<T>{};
+      for (int k = 0; k < NPLANES; ++k) {
+        d.p[k] = (T*)p;
+        p += align256(pe * sizeof(T));
+      }
+      d.rho = (T*)p;
+      p += align256(pe * sizeof(T));
+      d.r0 = (double*)p;
+      p += align256(pe * 8);
+      d.r1 = (double*)p;
+      p += align256(pe * 8);
+      d.n = nl;
+      d.pitch = pitch_of(nl);
+      d.h = 1.0 / nl;
+      d.ih = (T)((double)nl);
+      double mu, tau;
+      const double sc = r->prm.step_scale > 0 ? r->prm.step_scale : 0.5;
+      if (r->kind == K_PLAIN) {
+        mu = tau = sc / (2.0 * std::sqrt(2.0) / d.h);
+      } else {
+        mu = tau = sc;
+      }
+      d.mud = mu;
+      d.taud = tau;
+      d.mu = (T)mu;
+      d.tau = (T)tau;
+      d.metric = r->prm.metric;
+      d.rule = r->prm.stop_rule == W1_STOP_FPR ? RULE_FPR : RULE_KKT;
+      double tolL = r->prm.tol;
+      if (d.rule == RULE_FPR && tolL <= 0) tolL = paper_eps(r->prm.algo, r->prm.n, L > 1);
+      d.tol = tolL * std::pow(2.0, (double)(L - 1 - l) * r->prm.alpha);
+      d.cap = r->prm.max_iters;
+      d.par0 = 0;
+      if (r->kind == K_PROX || l == L - 1) {
+        DctTab t;
+        st = dct_tables<T>(nl + 1, &t);
+        if (st) return st;
+        d.dctC = (const T*)t.C;
+        d.dctCt = (const T*)t.Ct;
+        d.dcts = t.s;
+      }
+    }
+    double* part = (double*)p;
+    p += align256((size_t)max_tiles(r->prm.n) * NQ * 8);
+    const size_t ne = (size_t)(r->prm.n + 1) * (r->prm.n + 1);
+    double* in0 = (double*)p;
+    p += align256(ne * 8);
+    double* in1 = (double*)p;
+    p += align256(ne * 8);
+    for (int l = 0; l < L; ++l) hdesc_[(size_t)slot * MAXL + l].part = part;
+    SlotDesc<T>& fin = hdesc_[(size_t)slot * MAXL + L - 1];
+    fin.in0 = in0;
+    fin.in1 = in1;
+    // the caller's buffers are consumed before returning
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpyAsync(in0, p0, ne * 8, kind, st_));
+    HIPCHK(hipMemcpyAsync(in1, p1, ne * 8, kind, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    r->state = Request::PREP;
+    r->level = 0;
+    r->res = w1_result{};
+    r->t_admit = now_seconds();
+    dirty_.push_back(slot);
+    return W1_OK;
+  }
+
+  int step() override {
+    if (!ok_) return W1_EDEVICE;
+    arena_.reset();
+    int st = W1_OK;
+    // ---- preparation of newly admitted solves ----
+    std::vector<Request*> prep;
+    for (auto* r : slots_)
+      if (r && r->state == Request::PREP) prep.push_back(r);
+    if (!prep.empty()) {
+      st = run_prep(prep);
+      if (st) return fail(st);
+    }
+    // ---- one block of the current level for every running solve ----
+    std::vector<Request*> R, P, X;
+    for (auto* r : slots_) {
+      if (!r || r->state != Request::RUN) continue;
+      if (r->kind == K_PROX) X.push_back(r);
+      else if (r->resident_level) R.push_back(r);
+      else P.push_back(r);
+    }
+    st = flush_desc();
+    if (st) return fail(st);
+    if (!R.empty()) {
+      st = launch_resident(R);
+      if (st) return fail(st);
+    }
+    if (!P.empty()) {
+      st = launch_tiled_block(P);
+      if (st) return fail(st);
+    }
+    if (!X.empty()) {
+      st = launch_prox_block(X);
+      if (st) return fail(st);
+    }
+    if (R.empty() && P.empty() && X.empty()) return W1_OK;
+    st = read_scalars();
+    if (st) return fail(st);
+    // ---- level transitions ----
+    std::vector<Request*> up, fin;
+    auto consider = [&](Request* r) {
+      const SlotScalars& s = hsc_[r->slot];
+      if (s.status == ST_RUN) return;
+      const int l = r->level;
+      r->res.iters[l] = s.iters;
+      r->res.measure[l] = s.measure;
+      r->res.levels_run = l + 1;
+      if (r->resident_level) {  // the resident kernel leaves the level in set A
+        hdesc_[(size_t)r->slot * MAXL + l].par0 = gpar_;
+        dirty_.push_back(r->slot);
+      }
+      if (s.status == ST_DIVERGED) {
+        r->res.status = W1_SOLVE_DIVERGED;
+        fin.push_back(r);
+        return;
+      }
+      if (s.status == ST_CAP) r->res.status = W1_SOLVE_MAXITER;
+      if (l + 1 < r->prm.levels) up.push_back(r);
+      else fin.push_back(r);
+    };
+    for (auto* r : R) consider(r);
+    for (auto* r : P) consider(r);
+    for (auto* r : X) consider(r);
+    st = flush_desc();
+    if (st) return fail(st);
+    if (!up.empty()) {
+      st = advance_levels(up);
+      if (st) return fail(st);
+    }
+    if (!fin.empty()) {
+      st = finalize(fin);
+      if (st) return fail(st);
+    }
+    return W1_OK;
+  }
+
+  void collect(std::vector<Request*>& done) override {
+    for (auto* r : slots_)
+      if (r && r->state == Request::DONE) done.push_back(r);
+  }
+
+  int fetch_fields(Request* r) override {
+    if (r->fields_ready) return W1_OK;
+    const size_t ne = (size_t)(r->prm.n + 1) * (r->prm.n + 1);
+    r->f_m1.resize(ne);
+    r->f_m2.resize(ne);
+    r->f_psi.resize(ne);
+    const SlotDesc<T>& fin = hdesc_[(size_t)r->slot * MAXL + r->prm.levels - 1];
+    HIPCHK(hipMemcpyAsync(r->f_m1.data(), fin.in0, ne * 8, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipMemcpyAsync(r->f_m2.data(), fin.in1, ne * 8, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipMemcpyAsync(r->f_psi.data(), psi_stage(r), ne * 8, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    r->fields_ready = true;
+    return W1_OK;
+  }
+
+  int release(Request* r) override {
+    if (r->slot >= 0 && r->slot < cap_ && slots_[r->slot] == r) {
+      HIPCHK(hipStreamSynchronize(st_));
+      g_blocks.put(r->bytes, r->mem);
+      r->mem = nullptr;
+      slots_[r->slot] = nullptr;
+      r->slot = -1;
+    }
+    return W1_OK;
+  }
+
+  int prep_export(Request* r, void* const* rho_out) override {
+    arena_.reset();
+    std::vector<Request*> one{r};
+    int st = run_prep(one);
+    if (st) return fail(st);
+    if (r->state == Request::DONE) return W1_EINVAL;
+    for (int l = 0; l < r->prm.levels; ++l) {
+      std::vector<std::pair<Request*, int>> lv{{r, l}};
+      auto w = simple_work(lv);
+      Work* dw = arena_.put(w, &st);
+      if (st) return st;
+      K<T>::export_dense(st_, dw, (int)w.size(), ddesc_, NPLANES, (T*)rho_out[l]);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st_));
+    r->state = Request::DONE;
+    return W1_OK;
+  }
+
+ private:
+  int fail(int st) {
+    ok_ = false;
+    return st;
+  }
+  size_t didx(const Request* r, int l) const { return (size_t)r->slot * MAXL + l; }
+  int dx(const Request* r, int l) const { return r->slot * MAXL + l; }
+  double* psi_stage(const Request* r) const {
+    const SlotDesc<T>& fin = hdesc_[didx(r, r->prm.levels - 1)];
+    const size_t ne = (size_t)(r->prm.n + 1) * (r->prm.n + 1);
+    return (double*)((char*)fin.in1 + align256(ne * 8));
+  }
+
+  int flush_desc() {
+    int st = W1_OK;
+    std::sort(dirty_.begin(), dirty_.end());
+    dirty_.erase(std::unique(dirty_.begin(), dirty_.end()), dirty_.end());
+    for (int s : dirty_) {
+      std::vector<SlotDesc<T>> v(hdesc_.begin() + (size_t)s * MAXL, hdesc_.begin() + (size_t)(s + 1) * MAXL);
+      SlotDesc<T>* src = arena_.put(v, &st);
+      if (st) return st;
+      HIPCHK(hipMemcpyAsync(ddesc_ + (size_t)s * MAXL, src, sizeof(SlotDesc<T>) * MAXL, hipMemcpyDeviceToDevice,
+                            st_));
+    }
+    dirty_.clear();
+    return W1_OK;
+  }
+
+  int read_scalars() {
+    HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    return W1_OK;
+  }
+
+  int reset_scalars(const std::vector<Request*>& rs) {
+    int st = W1_OK;
+    for (auto* r : rs) {
+      SlotScalars z{};
+      z.status = ST_RUN;
+      std::vector<SlotScalars> v(1, z);
+      SlotScalars* src = arena_.put(v, &st);
+      if (st) return st;
+      HIPCHK(hipMemcpyAsync(dsc_ + r->slot, src, sizeof(SlotScalars), hipMemcpyDeviceToDevice, st_));
+    }
+    return W1_OK;
+  }
+
+  // -- work lists --------------------------------------------------------
+  // XCD-aware order: the launch's workgroup i runs on XCD i mod 8, so each
+  // XCD receives spatially contiguous tiles (a slot's row band, or whole
+  // slots when there are many) and halo re-reads hit its own L2.
+  std::vector<Work> order_xcd(std::vector<std::vector<Work>>& q) {
+    size_t mx = 0;
+    for (auto& v : q) mx = std::max(mx, v.size());
+    std::vector<Work> out;
+    out.reserve(mx * 8);
+    for (size_t k = 0; k < mx; ++k)
+      for (int x = 0; x < 8; ++x) out.push_back(k < q[x].size() ? q[x][k] : make_int4(-1, 0, 0, 0));
+    return out;
+  }
+
+  std::vector<Work> simple_work(const std::vector<std::pair<Request*, int>>& lv) {
+    std::vector<std::vector<Work>> q(8);
+    int rank = 0;
+    for (auto& e : lv) {
+      const int n = e.first->sides[e.second];
+      const int ti = simple_ti(n), tj = simple_tj(n);
+      for (int a = 0; a < ti; ++a)
+        for (int b = 0; b < tj; ++b) {
+          const int x = lv.size() >= 8 ? rank % 8 : (a * 8) / ti;
+          q[x].push_back(make_int4(dx(e.first, e.second), a, b, a * tj + b));
+        }
+      ++rank;
+    }
+    return order_xcd(q);
+  }
+  std::vector<Work> gemm_work(const std::vector<std::pair<Request*, int>>& lv) {
+    std::vector<std::vector<Work>> q(8);
+    int rank = 0;
+    for (auto& e : lv) {
+      const int t = gemm_t(e.first->sides[e.second]);
+      for (int a = 0; a < t; ++a)
+        for (int b = 0; b < t; ++b) {
+          const int x = lv.size() >= 8 ? rank % 8 : (a * 8) / t;
+          q[x].push_back(make_int4(dx(e.first, e.second), a, b, a * t + b));
+        }
+      ++rank;
+    }
+    return order_xcd(q);
+  }
+  std::vector<Work> tiled_work(const std::vector<Request*>& rs, int rh, int S) {
+    std::vector<std::vector<Work>> q(8);
+    int rank = 0;
+    for (auto* r : rs) {
+      const int n = r->sides[r->level];
+      const int ti = tiled_ti(n, rh, S), tj = tiled_tj(n, S);
+      for (int a = 0; a < ti; ++a)
+        for (int b = 0; b < tj; ++b) {
+          const int x = rs.size() >= 8 ? rank % 8 : (a * 8) / ti;
+          q[x].push_back(make_int4(dx(r, r->level), a, b, a * tj + b));
+        }
+      ++rank;
+    }
+    return order_xcd(q);
+  }
+  static std::vector<std::pair<Request*, int>> at_level(const std::vector<Request*>& rs) {
+    std::vector<std::pair<Request*, int>> v;
+    for (auto* r : rs) v.emplace_back(r, r->level);
+    return v;
+  }
+  static std::vector<std::pair<Request*, int>> at_finest(const std::vector<Request*>& rs) {
+    std::vector<std::pair<Request*, int>> v;
+    for (auto* r : rs) v.emplace_back(r, r->prm.levels - 1);
+    return v;
+  }
+
+  int reduce_lists(const std::vector<std::pair<Request*, int>>& lv, int (*tiles)(int), int** didx_out,
+                   int** dnt_out) {
+    int st = W1_OK;
+    std::vector<int> idx, nt;
+    for (auto& e : lv) {
+      idx.push_back(dx(e.first, e.second));
+      nt.push_back(tiles(e.first->sides[e.second]));
+    }
+    *didx_out = arena_.put(idx, &st);
+    if (st) return st;
+    *dnt_out = arena_.put(nt, &st);
+    return st;
+  }
+  static int simple_tiles_f(int n) { return simple_tiles(n); }
+
+  // -- preparation: masses -> rho pyramid (Sec. 2.2, restriction) --------
+  int run_prep(std::vector<Request*>& prep) {
+    int st = W1_OK;
+    // descriptors of the new slots must be on the device first
+    st = flush_desc();
+    if (st) return st;
+    auto fin = at_finest(prep);
+    {
+      auto w = simple_work(fin);
+      Work* dw = arena_.put(w, &st);
+      if (st) return st;
+      K<T>::prep_stats(st_, dw, (int)w.size(), ddesc_);
+      int *di, *dn;
+      st = reduce_lists(fin, simple_tiles_f, &di, &dn);
+      if (st) return st;
+      K<T>::reduce(st_, di, dn, (int)fin.size(), ddesc_, dsc_, 3, 0, 0u);
+      HIPCHK(hipGetLastError());
+    }
+    st = read_scalars();
+    if (st) return st;
+    std::vector<Request*> good;
+    for (auto* r : prep) {
+      const SlotScalars& s = hsc_[r->slot];
+      const double a = s.sums[0], b = s.sums[1];
+      const bool bad = s.sums[2] > 0 || !(a > 0) || !(std::fabs(a - b) <= 1e-9 * a);
+      if (bad) {
+        r->res.status = W1_SOLVE_REJECTED;
+        r->res.w1 = r->res.dual = r->res.lo = r->res.hi = r->res.kkt = NAN;
+        r->state = Request::DONE;
+        r->res.seconds = now_seconds() - r->t_submit;
+      } else {
+        good.push_back(r);
+      }
+    }
+    if (good.empty()) return W1_OK;
+    auto gfin = at_finest(good);
+    {
+      auto w = simple_work(gfin);
+      Work* dw = arena_.put(w, &st);
+      if (st) return st;
+      K<T>::prep_scale(st_, dw, (int)w.size(), ddesc_, dsc_);
+    }
+    int maxL = 0;
+    for (auto* r : good) maxL = std::max(maxL, r->prm.levels);
+    // depth 0 is the finest level of every request, depth k its k-th coarser
+    for (int depth = 0; depth < maxL; ++depth) {
+      std::vector<std::pair<Request*, int>> lv;
+      for (auto* r : good)
+        if (r->prm.levels - 1 - depth >= 0) lv.emplace_back(r, r->prm.levels - 1 - depth);
+      if (lv.empty()) continue;
+      auto w = simple_work(lv);
+      Work* dw = arena_.put(w, &st);
+      if (st) return st;
+      int *di, *dn;
+      st = reduce_lists(lv, simple_tiles_f, &di, &dn);
+      if (st) return st;
+      if (depth > 0) {
+        K<T>::restrict_level(st_, dw, (int)w.size(), ddesc_);
+        K<T>::reduce(st_, di, dn, (int)lv.size(), ddesc_, dsc_, 2, 0, 0u);
+        K<T>::scale_level(st_, dw, (int)w.size(), ddesc_, dsc_);
+      }
+      K<T>::rho_diff(st_, dw, (int)w.size(), ddesc_);
+      K<T>::reduce(st_, di, dn, (int)lv.size(), ddesc_, dsc_, 1, 0, 0u);
+      K<T>::rho_write(st_, dw, (int)w.size(), ddesc_, dsc_);
+    }
+    HIPCHK(hipGetLastError());
+    // level 1 starts from zero (Algorithms 3 and 4)
+    for (auto* r : good) start_level(r, 0);
+    st = flush_desc();
+    if (st) return st;
+    {
+      auto lv = at_level(good);
+      auto w = simple_work(lv);
+      Work* dw = arena_.put(w, &st);
+      if (st) return st;
+      // plain: set A; prox: m, vphi, vphibar
+      unsigned mask = 0;
+      for (auto* r : good) mask |= r->kind == K_PLAIN ? 0x7u : 0x3Fu;
+      K<T>::zero(st_, dw, (int)w.size(), ddesc_, mask);
+    }
+    st = reset_scalars(good);
+    if (st) return st;
+    HIPCHK(hipGetLastError());
+    return W1_OK;
+  }
+
+  void start_level(Request* r, int l) {
+    r->level = l;
+    r->state = Request::RUN;
+    r->t_level = now_seconds();
+    SlotDesc<T>& d = hdesc_[didx(r, l)];
+    d.par0 = gpar_;
+    const bool allow = !(r->prm.flags & W1_FLAG_NO_RESIDENT);
+    r->resident_level = r->kind == K_PLAIN && allow && (r->sides[l] + 1) <= K<T>::plain_resident_max_side();
+    dirty_.push_back(r->slot);
+  }
+
+  // -- plain: resident levels ---------------------------------------------
+  int launch_resident(std::vector<Request*>& R) {
+    int st = W1_OK;
+    std::vector<int> idx;
+    int maxside = 0;
+    std::map<int, std::vector<int>> by_ce;
+    for (auto* r : R) {
+      by_ce[r->prm.check_every].push_back(dx(r, r->level));
+      maxside = std::max(maxside, r->sides[r->level] + 1);
+    }
+    for (auto& kv : by_ce) {
+      int* di = arena_.put(kv.second, &st);
+      if (st) return st;
+      K<T>::plain_resident(st_, di, (int)kv.second.size(), ddesc_, dsc_, maxside, kv.first);
+    }
+    HIPCHK(hipGetLastError());
+    return W1_OK;
+  }
+
+  // -- plain: one block of check_every iterations, tiled -------------------
+  int launch_tiled_block(std::vector<Request*>& P) {
+    int st = W1_OK;
+    int maxside = 0, ce = P[0]->prm.check_every, req_T = P[0]->prm.block_steps;
+    bool any_kkt = false, any_fpr = false;
+    for (auto* r : P) {
+      maxside = std::max(maxside, r->sides[r->level]);
+      (r->prm.stop_rule == W1_STOP_FPR ? any_fpr : any_kkt) = true;
+    }
+    const int prec = sizeof(T) == 8 ? W1_FP64 : W1_FP32;
+    TileChoice tc = choose_tiles(prec, maxside, (int)P.size(), ce, req_T);
+    // FPR needs the last step in a single-step checking launch
+    const int body = any_fpr ? ce - 1 : ce;
+    std::map<int, Work*> wl;
+    std::map<int, int> wn;
+    auto list_for = [&](int S) -> Work* {
+      auto it = wl.find(S);
+      if (it != wl.end()) return it->second;
+      auto w = tiled_work(P, tc.rh, S);
+      Work* d = arena_.put(w, &st);
+      wl[S] = d;
+      wn[S] = (int)w.size();
+      return d;
+    };
+    int done = 0;
+    while (done < body) {
+      const int S = std::min(tc.steps, body - done);
+      Work* w = list_for(S);
+      if (st) return st;
+      K<T>::plain_tiled(st_, w, wn[S], ddesc_, gpar_, S, tc.rh, false);
+      gpar_ ^= 1;
+      done += S;
+    }
+    if (any_fpr) {
+      Work* w = list_for(1);
+      if (st) return st;
+      K<T>::plain_tiled(st_, w, wn[1], ddesc_, gpar_, 1, tc.rh, true);
+      gpar_ ^= 1;
+    }
+    if (any_kkt) {
+      auto lv = at_level(P);
+      auto w = simple_work(lv);
+      Work* dw = arena_.put(w, &st);
+      if (st) return st;
+      K<T>::kkt(st_, dw, (int)w.size(), ddesc_, K_PLAIN, gpar_);
+    }
+    // stop test: FPR partials come from the checking launch's tiles, KKT
+    // partials from the simple tiles
+    std::vector<int> idx, nt;
+    for (auto* r : P) {
+      const int n = r->sides[r->level];
+      idx.push_back(dx(r, r->level));
+      nt.push_back(r->prm.stop_rule == W1_STOP_FPR ? tiled_ti(n, tc.rh, 1) * tiled_tj(n, 1) : simple_tiles(n));
+    }
+    int* di = arena_.put(idx, &st);
+    if (st) return st;
+    int* dn = arena_.put(nt, &st);
+    if (st) return st;
+    K<T>::check(st_, di, dn, (int)P.size(), ddesc_, dsc_, K_PLAIN, ce);
+    HIPCHK(hipGetLastError());
+    return W1_OK;
+  }
+
+  // -- Poisson solve through four DCT passes ------------------------------
+  void poisson(Work* gw, int ng, int dst) {
+    K<T>::gemm(st_, gw, ng, ddesc_, 0, 6, 7, 1, false);   // rows:    X C^T
+    K<T>::gemm(st_, gw, ng, ddesc_, 1, 7, 6, 0, true);    // columns: C X, / lambda
+    K<T>::gemm(st_, gw, ng, ddesc_, 1, 6, 7, 1, false);   // columns: C^T X
+    K<T>::gemm(st_, gw, ng, ddesc_, 0, 7, dst, 0, false); // rows:    X C
+  }
+
+  // -- prox: one block of check_every iterations ---------------------------
+  int launch_prox_block(std::vector<Request*>& X) {
+    int st = W1_OK;
+    const int ce = X[0]->prm.check_every;
+    auto lv = at_level(X);
+    auto sw = simple_work(lv);
+    auto gw = gemm_work(lv);
+    Work* dsw = arena_.put(sw, &st);
+    if (st) return st;
+    Work* dgw = arena_.put(gw, &st);
+    if (st) return st;
+    bool any_kkt = false, any_fpr = false;
+    for (auto* r : X) (r->prm.stop_rule == W1_STOP_FPR ? any_fpr : any_kkt) = true;
+    for (int it = 0; it < ce; ++it) {
+      K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 0, K_PROX, gpar_);
+      poisson(dgw, (int)gw.size(), 6);
+      K<T>::prox_post(st_, dsw, (int)sw.size(), ddesc_, any_fpr && it == ce - 1);
+    }
+    if (any_kkt) {
+      K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 1, K_PROX, gpar_);
+      poisson(dgw, (int)gw.size(), 8);
+      K<T>::kkt(st_, dsw, (int)sw.size(), ddesc_, K_PROX, gpar_);
+    }
+    int *di, *dn;
+    st = reduce_lists(lv, simple_tiles_f, &di, &dn);
+    if (st) return st;
+    K<T>::check(st_, di, dn, (int)X.size(), ddesc_, dsc_, K_PROX, ce);
+    HIPCHK(hipGetLastError());
+    return W1_OK;
+  }
+
+  // -- next level: prolongation (Sec. 3.3) ---------------------------------
+  int advance_levels(std::vector<Request*>& up) {
+    int st = W1_OK;
+    std::vector<std::pair<Request*, int>> lv;
+    std::vector<Request*> plain, prox;
+    for (auto* r : up) {
+      lv.emplace_back(r, r->level + 1);
+      (r->kind == K_PLAIN ? plain : prox).push_back(r);
+    }
+    for (auto* r : up) start_level(r, r->level + 1);
+    st = flush_desc();
+    if (st) return st;
+    for (int pass = 0; pass < 2; ++pass) {
+      auto& grp = pass == 0 ? plain : prox;
+      if (grp.empty()) continue;
+      auto w = simple_work(at_level(grp));
+      Work* dw = arena_.put(w, &st);
+      if (st) return st;
+      K<T>::prolong(st_, dw, (int)w.size(), ddesc_, pass == 0 ? K_PLAIN : K_PROX, gpar_);
+    }
+    st = reset_scalars(up);
+    if (st) return st;
+    HIPCHK(hipGetLastError());
+    return W1_OK;
+  }
+
+  // -- FP64 certificate and field export on the finest level ---------------
+  int finalize(std::vector<Request*>& fin) {
+    int st = W1_OK;
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<Request*> grp;
+      for (auto* r : fin)
+        if ((r->kind == K_PLAIN) == (pass == 0)) grp.push_back(r);
+      if (grp.empty()) continue;
+      const int kind = pass == 0 ? K_PLAIN : K_PROX;
+      auto lv = at_finest(grp);
+      auto sw = simple_work(lv);
+      auto gw = gemm_work(lv);
+      Work* dsw = arena_.put(sw, &st);
+      if (st) return st;
+      Work* dgw = arena_.put(gw, &st);
+      if (st) return st;
+      if (kind == K_PROX) {
+        K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 1, kind, gpar_);
+        poisson(dgw, (int)gw.size(), 8);
+      }
+      K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 2, kind, gpar_);
+      poisson(dgw, (int)gw.size(), 6);
+      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, kind, gpar_);
+      int *di, *dn;
+      st = reduce_lists(lv, simple_tiles_f, &di, &dn);
+      if (st) return st;
+      K<T>::eval_final(st_, di, dn, (int)grp.size(), ddesc_, dsc_, kind);
+      // fields to the FP64 staging planes (reused input area)
+      for (auto* r : grp) {
+        std::vector<std::pair<Request*, int>> one{{r, r->prm.levels - 1}};
+        auto w1l = simple_work(one);
+        Work* dw = arena_.put(w1l, &st);
+        if (st) return st;
+        const SlotDesc<T>& f = hdesc_[didx(r, r->prm.levels - 1)];
+        K<T>::export_fields(st_, dw, (int)w1l.size(), ddesc_, dsc_, kind, gpar_, (double*)f.in0, (double*)f.in1,
+                            psi_stage(r));
+      }
+      HIPCHK(hipGetLastError());
+    }
+    st = read_scalars();
+    if (st) return st;
+    const double t = now_seconds();
+    for (auto* r : fin) {
+      const SlotScalars& s = hsc_[r->slot];
+      r->res.w1 = s.eval[0];
+      r->res.dual = s.eval[1];
+      r->res.lo = s.eval[2];
+      r->res.hi = s.eval[3];
+      r->res.kkt = s.eval[4];
+      r->res.seconds = t - r->t_submit;
+      r->res.queue_seconds = r->t_admit - r->t_submit;
+      r->state = Request::DONE;
+      r->fields_ready = false;
+    }
+    return W1_OK;
+  }
+
+  int cap_;
+  hipStream_t st_;
+  Arena arena_;
+  bool ok_ = false;
+  std::vector<Request*> slots_;
+  std::vector<SlotDesc<T>> hdesc_;
+  SlotDesc<T>* ddesc_ = nullptr;
+  SlotScalars* dsc_ = nullptr;
+  SlotScalars* hsc_ = nullptr;
+  std::vector<int> dirty_;
+  int gpar_ = 0;
+};
+
+std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t stream) {
+  if (fp64) return std::unique_ptr<BatchBase>(new Batch<double>(capacity, stream));
+  return std::unique_ptr<BatchBase>(new Batch<float>(capacity, stream));
+}
+
+}  // namespace w1

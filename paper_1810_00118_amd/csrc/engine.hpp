@@ -1,0 +1,75 @@
+// Host engine of the multilevel W1 solver: per-precision batches of solves
+// ("slots") advanced together, one iteration block per step.
+#pragma once
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/w1.h"
+#include "w1_internal.hpp"
+
+namespace w1 {
+
+double now_seconds();
+
+// hipError_t -> status, with a message kept for w1_strerror-style reporting
+int hip_status(hipError_t e, const char* what);
+const char* last_error_text();
+
+// A solve request (one pair) and its lifecycle.
+struct Request {
+  uint64_t ticket = 0;
+  w1_params prm{};
+  std::vector<int> sides;           // level sides, coarsest first
+  int kind = K_PLAIN;               // K_PLAIN or K_PROX
+  // device memory of the solve (all levels, staging, partials)
+  char* mem = nullptr;
+  size_t bytes = 0;
+  // state
+  enum { QUEUED, PREP, RUN, FINAL, DONE } state = QUEUED;
+  int slot = -1;
+  int level = 0;
+  bool resident_level = false;
+  w1_result res{};
+  double t_submit = 0, t_admit = 0, t_level = 0;
+  bool want_fields = true;
+  // finest-level fields after completion (host, FP64), filled on demand
+  std::vector<double> f_m1, f_m2, f_psi;
+  bool fields_ready = false;
+};
+
+// Device bytes of one request.
+size_t request_bytes(const w1_params& p);
+
+// Per-precision batch of in-flight requests.
+class BatchBase {
+ public:
+  virtual ~BatchBase() {}
+  virtual int admit(Request* r, const double* p0, const double* p1, int on_device) = 0;
+  virtual int step() = 0;                 // advance every slot by one block
+  virtual int active() const = 0;
+  virtual void collect(std::vector<Request*>& done) = 0;
+  virtual int fetch_fields(Request* r) = 0;   // copy finest fields to host
+  virtual int release(Request* r) = 0;        // free a finished slot
+  // input preparation only: rho of every level to dense caller buffers
+  virtual int prep_export(Request* r, void* const* rho_out) = 0;
+};
+
+std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t stream);
+
+// Tuning choice for the plain tiled kernel.
+struct TileChoice {
+  int rh;      // region rows (32 or 64)
+  int steps;   // temporal block depth
+};
+TileChoice choose_tiles(int precision, int side, int nslots, int check_every, int requested);
+
+}  // namespace w1

@@ -1,0 +1,1321 @@
+// HIP kernels of the multilevel W1 solver for gfx950 (CDNA4).
+//
+// Every kernel is batched over a device work list: one workgroup per work
+// item (descriptor index, tile row, tile column, tile index), so one launch
+// covers any mix of pairs, grid sides and ground metrics.  Padding items
+// (descriptor index -1) return at once.
+//
+// All per-node arithmetic lives in the __device__ helpers below and is
+// compiled without floating-point contraction (-ffp-contract=off); the few
+// fused multiply-adds are explicit.  The tiled, resident and single-step
+// kernels therefore produce bitwise identical iterates for a node whatever
+// tiling, temporal-block depth or batch it runs in.
+//
+// Plain-PDHG iterate at node x (eq. (primaldual), A* = minus forward
+// difference, so m - mu A* phi = m + mu grad phi):
+//   m+    = shrink_p(m + mu grad+ phi, mu)
+//   mbar  = 2 m+ - m
+//   phi+  = phi + tau (div mbar - rho)
+// Prox-PDHG iterate (eq. (pdhg)):
+//   v = m - mu vphibar;  u = (A A*)^{-1}(A v - rho);  m+ = v + grad+ u;
+//   vphi+ = Proj_{||.||_q <= 1}(vphi + tau m+);  vphibar+ = 2 vphi+ - vphi.
+#include "w1_internal.hpp"
+#include <cmath>
+#include <cstdio>
+
+namespace w1 {
+
+// ---------------------------------------------------------------------------
+// per-node helpers
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T fma_(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+template <> __device__ __forceinline__ double fma_(double a, double b, double c) { return __fma_rn(a, b, c); }
+
+template <typename T> __device__ __forceinline__ T sqrt_(T a);
+template <> __device__ __forceinline__ float sqrt_(float a) { return sqrtf(a); }
+template <> __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); }
+
+template <typename T> __device__ __forceinline__ T abs_(T a) { return a < T(0) ? -a : a; }
+
+// prox of mu ||.||_p at one node: p = 1 soft-threshold per component,
+// p = 2 isotropic shrink (0 when ||v|| <= mu).
+template <typename T>
+__device__ __forceinline__ void shrink_(T v1, T v2, T mu, int metric, T& o1, T& o2) {
+  if (metric == 1) {
+    T a1 = abs_(v1) - mu, a2 = abs_(v2) - mu;
+    a1 = a1 > T(0) ? a1 : T(0);
+    a2 = a2 > T(0) ? a2 : T(0);
+    o1 = v1 < T(0) ? -a1 : a1;
+    o2 = v2 < T(0) ? -a2 : a2;
+  } else {
+    T s2 = v1 * v1 + v2 * v2;
+    T nv = sqrt_(s2);
+    T s = nv > mu ? T(1) - mu / nv : T(0);
+    o1 = v1 * s;
+    o2 = v2 * s;
+  }
+}
+
+// projection onto the unit ball of the dual norm q (q = inf for p = 1,
+// q = 2 for p = 2)
+template <typename T>
+__device__ __forceinline__ void proj_ball_(T w1, T w2, int metric, T& o1, T& o2) {
+  if (metric == 1) {
+    o1 = w1 > T(1) ? T(1) : (w1 < T(-1) ? T(-1) : w1);
+    o2 = w2 > T(1) ? T(1) : (w2 < T(-1) ? T(-1) : w2);
+  } else {
+    T s2 = w1 * w1 + w2 * w2;
+    T nw = sqrt_(s2);
+    if (nw > T(1)) {
+      o1 = w1 / nw;
+      o2 = w2 / nw;
+    } else {
+      o1 = w1;
+      o2 = w2;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T norm_p_(T a, T b, int metric) {
+  return metric == 1 ? abs_(a) + abs_(b) : sqrt_(a * a + b * b);
+}
+// dual norm q of a gradient
+template <typename T>
+__device__ __forceinline__ T norm_q_(T a, T b, int metric) {
+  T x = abs_(a), y = abs_(b);
+  return metric == 1 ? (x > y ? x : y) : sqrt_(a * a + b * b);
+}
+
+// flux half of the plain iterate; hd / hr say whether the node has a
+// neighbour along x1 / x2 (false on the last row / column)
+template <typename T>
+__device__ __forceinline__ void plain_flux_(T m1, T m2, T pc, T pd, T pr, bool hd, bool hr, T ih, T mu,
+                                            int metric, T& n1, T& n2) {
+  T g1 = hd ? (pd - pc) * ih : T(0);
+  T g2 = hr ? (pr - pc) * ih : T(0);
+  T v1 = fma_(mu, g1, m1);
+  T v2 = fma_(mu, g2, m2);
+  shrink_(v1, v2, mu, metric, n1, n2);
+}
+
+// potential half: b1c, b2c extrapolated flux at the node, b1u at (i-1, j),
+// b2l at (i, j-1) (zero outside the grid)
+template <typename T>
+__device__ __forceinline__ T plain_potential_(T pc, T b1c, T b1u, T b2c, T b2l, T rho, T ih, T tau) {
+  T dv = ((b1c - b1u) + (b2c - b2l)) * ih;
+  return fma_(tau, dv - rho, pc);
+}
+
+template <typename T> __device__ __forceinline__ bool finite_(T v) { return isfinite(v); }
+
+// Neumaier-compensated FP64 accumulation
+struct Acc {
+  double s, c;
+  __device__ void add(double v) {
+    double t = s + v;
+    if (fabs(s) >= fabs(v)) c += (s - t) + v;
+    else c += (v - t) + s;
+    s = t;
+  }
+  __device__ double get() const { return s + c; }
+};
+
+// Block reduction of NQ doubles per thread into out[0..NQ): wave shuffles,
+// then waves in order through LDS.  `maxmask` marks quantities reduced with
+// max instead of sum.  Deterministic for a fixed block size.
+template <int NT>
+__device__ void block_reduce_(double (&v)[NQ], double* out, double* lds, unsigned maxmask) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_xor(v[q], off, 64);
+      v[q] = ((maxmask >> q) & 1) ? (o > v[q] ? o : v[q]) : v[q] + o;
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[wv * NQ + q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    const int q = threadIdx.x;
+    double s = lds[q];
+    for (int k = 1; k < NT / 64; ++k) {
+      double o = lds[k * NQ + q];
+      s = ((maxmask >> q) & 1) ? (o > s ? o : s) : s + o;
+    }
+    out[q] = s;
+  }
+}
+
+// simple tile: 16 rows x 64 columns, 256 threads, 4 rows per thread
+#define SIMPLE_TILE_LOOP(d, w, ...)                                         \
+  {                                                                         \
+    const int _c = threadIdx.x & 63, _r0 = threadIdx.x >> 6;                \
+    _Pragma("unroll") for (int _k = 0; _k < 4; ++_k) {                      \
+      const int i = (w).y * ST_H + _r0 + 4 * _k;                            \
+      const int j = (w).z * ST_W + _c;                                      \
+      if (i <= (d).n && j <= (d).n) {                                       \
+        const size_t off = (size_t)i * (d).pitch + j;                       \
+        (void)off;                                                          \
+        __VA_ARGS__                                                         \
+      }                                                                     \
+    }                                                                       \
+  }
+
+// ---------------------------------------------------------------------------
+// utility kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                              unsigned mask) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  SIMPLE_TILE_LOOP(d, w, {
+    for (int k = 0; k < NPLANES; ++k)
+      if ((mask >> k) & 1) d.p[k][off] = T(0);
+  })
+}
+
+// copy a dense (pitch n+1) array into / out of a plane
+template <typename T>
+__global__ __launch_bounds__(256) void k_import(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                                int plane, const T* __restrict__ src) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  T* dst = plane < NPLANES ? d.p[plane] : d.rho;
+  SIMPLE_TILE_LOOP(d, w, { dst[off] = src[(size_t)i * (d.n + 1) + j]; })
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_export(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                                int plane, T* __restrict__ dst) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const T* src = plane < NPLANES ? d.p[plane] : d.rho;
+  SIMPLE_TILE_LOOP(d, w, { dst[(size_t)i * (d.n + 1) + j] = src[off]; })
+}
+
+// per-slot reduction of tile partials: one workgroup per listed descriptor
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce(const int* __restrict__ idx, const int* __restrict__ ntiles,
+                                                const SlotDesc<T>* __restrict__ desc, SlotScalars* __restrict__ sc,
+                                                int nq, int out_base, unsigned maxmask) {
+  __shared__ double lds[4 * NQ];
+  __shared__ double res[NQ];
+  const int x = idx[blockIdx.x];
+  const int nt = ntiles[blockIdx.x];
+  const SlotDesc<T>& d = desc[x];
+  double v[NQ];
+  for (int q = 0; q < NQ; ++q) {
+    Acc a{0.0, 0.0};
+    double mx = -INFINITY;
+    if (q < nq) {
+      for (int t = threadIdx.x; t < nt; t += 256) {
+        double p = d.part[(size_t)t * NQ + q];
+        a.add(p);
+        mx = p > mx ? p : mx;
+      }
+    }
+    v[q] = ((maxmask >> q) & 1) ? mx : a.get();
+  }
+  block_reduce_<256>(v, res, lds, maxmask);
+  __syncthreads();
+  if (threadIdx.x < nq && out_base + (int)threadIdx.x < 8) sc[x / MAXL].sums[out_base + threadIdx.x] = res[threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// input preparation and the density pyramid (Sec. 2.2; restriction by
+// normalised full weighting, the transpose of eq. (inter_phi))
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep_stats(const Work* __restrict__ work,
+                                                    const SlotDesc<T>* __restrict__ desc) {
+  __shared__ double lds[4 * NQ];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+  SIMPLE_TILE_LOOP(d, w, {
+    const size_t o = (size_t)i * (d.n + 1) + j;
+    double a = d.in0[o], b = d.in1[o];
+    if (!(isfinite(a) && isfinite(b)) || a < 0.0 || b < 0.0) v[2] += 1.0;
+    else { v[0] += a; v[1] += b; }
+  })
+  block_reduce_<256>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+}
+
+// rho^k = p^k / (S^k h^2) on the finest level (FP64 staging planes)
+template <typename T>
+__global__ __launch_bounds__(256) void k_prep_scale(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                                    const SlotScalars* __restrict__ sc) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const SlotScalars& s = sc[w.x / MAXL];
+  const double h2 = d.h * d.h;
+  const double a0 = s.sums[0] * h2, a1 = s.sums[1] * h2;
+  SIMPLE_TILE_LOOP(d, w, {
+    const size_t o = (size_t)i * (d.n + 1) + j;
+    d.r0[off] = d.in0[o] / a0;
+    d.r1[off] = d.in1[o] / a1;
+  })
+}
+
+// 1-D factor of the restriction: weights of fine index I for coarse a
+__device__ __forceinline__ double rw1d_(int I, int a, int nf) {
+  int dI = I - 2 * a;
+  if (I < 0 || I > nf) return 0.0;
+  return dI == 0 ? 1.0 : ((dI == 1 || dI == -1) ? 0.5 : 0.0);
+}
+
+// coarse level x from fine level x+1: c = D^{-1} P^T f, both staging planes;
+// partial sums of the result (for the unit-mass renormalisation)
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc) {
+  __shared__ double lds[4 * NQ];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const SlotDesc<T>& f = desc[w.x + 1];
+  const int nf = f.n;
+  double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+  SIMPLE_TILE_LOOP(d, w, {
+    double s0 = 0.0, s1 = 0.0, wi_sum = 0.0, wj_sum = 0.0;
+    for (int di = -1; di <= 1; ++di) wi_sum += rw1d_(2 * i + di, i, nf);
+    for (int dj = -1; dj <= 1; ++dj) wj_sum += rw1d_(2 * j + dj, j, nf);
+    for (int di = -1; di <= 1; ++di) {
+      const int I = 2 * i + di;
+      const double wi = rw1d_(I, i, nf);
+      if (wi == 0.0) continue;
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int J = 2 * j + dj;
+        const double wj = rw1d_(J, j, nf);
+        if (wj == 0.0) continue;
+        const size_t fo = (size_t)I * f.pitch + J;
+        s0 += wi * wj * f.r0[fo];
+        s1 += wi * wj * f.r1[fo];
+      }
+    }
+    const double dw = wi_sum * wj_sum;
+    const double c0 = s0 / dw, c1 = s1 / dw;
+    d.r0[off] = c0;
+    d.r1[off] = c1;
+    v[0] += c0;
+    v[1] += c1;
+  })
+  block_reduce_<256>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_level(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                                     const SlotScalars* __restrict__ sc) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const SlotScalars& s = sc[w.x / MAXL];
+  const double h2 = d.h * d.h;
+  const double a0 = s.sums[0] * h2, a1 = s.sums[1] * h2;
+  SIMPLE_TILE_LOOP(d, w, {
+    d.r0[off] = d.r0[off] / a0;
+    d.r1[off] = d.r1[off] / a1;
+  })
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rho_diff(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc) {
+  __shared__ double lds[4 * NQ];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+  SIMPLE_TILE_LOOP(d, w, { v[0] += d.r0[off] - d.r1[off]; })
+  block_reduce_<256>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+}
+
+// rho_l = rho0_l - rho1_l - mean, cast to the iterate precision
+template <typename T>
+__global__ __launch_bounds__(256) void k_rho_write(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                                   const SlotScalars* __restrict__ sc) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const double N = (double)(d.n + 1);
+  const double mean = sc[w.x / MAXL].sums[0] / (N * N);
+  SIMPLE_TILE_LOOP(d, w, { d.rho[off] = (T)((d.r0[off] - d.r1[off]) - mean); })
+}
+
+// ---------------------------------------------------------------------------
+// prolongation, Sec. 3.3: eq. (inter_phi) (bilinear) for the potential and
+// eq. (inter_m) for the flux and the edge dual (nearest along the edge's own
+// axis with the tie to x_i - h_l, average across).  Work items tile the fine
+// level x; the coarse level is x - 1, read from its current plane set.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T pro_node_(const T* c, int pc, int I, int J) {
+  const int a0 = I >> 1, a1 = (I + 1) >> 1, b0 = J >> 1, b1 = (J + 1) >> 1;
+  if (!(I & 1) && !(J & 1)) return c[(size_t)a0 * pc + b0];
+  if ((I & 1) && !(J & 1)) return (c[(size_t)a0 * pc + b0] + c[(size_t)a1 * pc + b0]) / T(2);
+  if (!(I & 1) && (J & 1)) return (c[(size_t)a0 * pc + b0] + c[(size_t)a0 * pc + b1]) / T(2);
+  return (((c[(size_t)a0 * pc + b0] + c[(size_t)a0 * pc + b1]) + c[(size_t)a1 * pc + b0]) + c[(size_t)a1 * pc + b1]) /
+         T(4);
+}
+// flux along x1: coarse row floor(I/2), average across J
+template <typename T>
+__device__ __forceinline__ T pro_e1_(const T* c, int pc, int I, int J) {
+  const int a = I >> 1, b0 = J >> 1, b1 = (J + 1) >> 1;
+  if (!(J & 1)) return c[(size_t)a * pc + b0];
+  return (c[(size_t)a * pc + b0] + c[(size_t)a * pc + b1]) / T(2);
+}
+template <typename T>
+__device__ __forceinline__ T pro_e2_(const T* c, int pc, int I, int J) {
+  const int b = J >> 1, a0 = I >> 1, a1 = (I + 1) >> 1;
+  if (!(I & 1)) return c[(size_t)a0 * pc + b];
+  return (c[(size_t)a0 * pc + b] + c[(size_t)a1 * pc + b]) / T(2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                                 int kind, int gpar) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const SlotDesc<T>& c = desc[w.x - 1];
+  const int pc = c.pitch, nf = d.n;
+  if (kind == K_PLAIN) {
+    const int cs = (gpar ^ c.par0) & 1;
+    const T* c1 = c.p[3 * cs];
+    const T* c2 = c.p[3 * cs + 1];
+    const T* cp = c.p[3 * cs + 2];
+    SIMPLE_TILE_LOOP(d, w, {
+      d.p[0][off] = i < nf ? pro_e1_(c1, pc, i, j) : T(0);
+      d.p[1][off] = j < nf ? pro_e2_(c2, pc, i, j) : T(0);
+      d.p[2][off] = pro_node_(cp, pc, i, j);
+    })
+  } else {
+    SIMPLE_TILE_LOOP(d, w, {
+      d.p[0][off] = i < nf ? pro_e1_(c.p[0], pc, i, j) : T(0);
+      d.p[1][off] = j < nf ? pro_e2_(c.p[1], pc, i, j) : T(0);
+      const T q1 = i < nf ? pro_e1_(c.p[2], pc, i, j) : T(0);
+      const T q2 = j < nf ? pro_e2_(c.p[3], pc, i, j) : T(0);
+      d.p[2][off] = q1;
+      d.p[3][off] = q2;
+      d.p[4][off] = q1;   // vphibar starts equal to vphi at a level start
+      d.p[5][off] = q2;
+    })
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1, LDS-tiled with temporal blocking.
+// A workgroup loads a RH x 128 region (its output tile plus a halo of
+// `steps` nodes on every side) into LDS, runs `steps` iterations there and
+// writes the (RH - 2 steps) x (128 - 2 steps) interior.  After s steps the
+// flux is valid on rows [s-1, RH-1-s] and the potential on [s, RH-1-s]
+// (same for columns), so the interior is exact.  Reads plane set
+// cur = gpar ^ par0 and writes the other one.  Every thread owns 8 rows x 2
+// columns of the region (256 threads for RH = 32, 512 for RH = 64).
+// With CHECK (launched with steps = 1 only) the epilogue also produces the
+// FPR partials of eq. (pd_stop) for the interior: sum |dm|^2, sum dphi^2,
+// sum dphi * A dm, count of non-finite values; the previous iterate is
+// re-read from the source planes.
+// ---------------------------------------------------------------------------
+template <typename T, int RH, bool CHECK>
+__global__ __launch_bounds__(RH * 8) void k_plain_tiled(const Work* __restrict__ work,
+                                                        const SlotDesc<T>* __restrict__ desc, int gpar, int steps) {
+  constexpr int RW = TILED_RW, NTH = RH * 8, NWV = NTH / 64, NR = RH / NWV, NC = RW / 64;
+  static_assert(NR == 8, "8 rows per thread");
+  __shared__ T Lp[RH * RW];
+  __shared__ T L1[RH * RW];
+  __shared__ T L2[RH * RW];
+  __shared__ double lds[NWV * NQ];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const int n = d.n, pitch = d.pitch, S = steps;
+  const int OH = RH - 2 * S, OW = RW - 2 * S;
+  const int gi0 = w.y * OH - S, gj0 = w.z * OW - S;
+  const int rs = (gpar ^ d.par0) & 1, ws = rs ^ 1;
+  const T* __restrict__ sm1 = d.p[3 * rs];
+  const T* __restrict__ sm2 = d.p[3 * rs + 1];
+  const T* __restrict__ sph = d.p[3 * rs + 2];
+  const T* __restrict__ srho = d.rho;
+  const T ih = d.ih, mu = d.mu, tau = d.tau;
+  const int metric = d.metric;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  T m1[NR][NC], m2[NR][NC], rh[NR][NC];
+#pragma unroll
+  for (int a = 0; a < NR; ++a)
+#pragma unroll
+    for (int b = 0; b < NC; ++b) {
+      const int r = wv + NWV * a, c = lane + 64 * b;
+      const int gi = gi0 + r, gj = gj0 + c;
+      const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
+      const size_t off = in ? (size_t)gi * pitch + gj : 0;
+      m1[a][b] = in ? sm1[off] : T(0);
+      m2[a][b] = in ? sm2[off] : T(0);
+      rh[a][b] = in ? srho[off] : T(0);
+      Lp[r * RW + c] = in ? sph[off] : T(0);
+    }
+  __syncthreads();
+
+  for (int s = 0; s < S; ++s) {
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        const int r = wv + NWV * a, c = lane + 64 * b;
+        const int gi = gi0 + r, gj = gj0 + c;
+        const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
+        const T pc = Lp[r * RW + c];
+        const T pd = (r + 1 < RH) ? Lp[(r + 1) * RW + c] : pc;
+        const T pr = (c + 1 < RW) ? Lp[r * RW + c + 1] : pc;
+        T n1, n2;
+        plain_flux_(m1[a][b], m2[a][b], pc, pd, pr, gi < n && r + 1 < RH, gj < n && c + 1 < RW, ih, mu,
+                    metric, n1, n2);
+        if (!in) { n1 = T(0); n2 = T(0); }
+        L1[r * RW + c] = (n1 + n1) - m1[a][b];
+        L2[r * RW + c] = (n2 + n2) - m2[a][b];
+        m1[a][b] = n1;
+        m2[a][b] = n2;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        const int r = wv + NWV * a, c = lane + 64 * b;
+        const int gi = gi0 + r, gj = gj0 + c;
+        const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
+        const T b1c = L1[r * RW + c];
+        const T b1u = r > 0 ? L1[(r - 1) * RW + c] : T(0);
+        const T b2c = L2[r * RW + c];
+        const T b2l = c > 0 ? L2[r * RW + c - 1] : T(0);
+        const T pc = Lp[r * RW + c];
+        T pn = plain_potential_(pc, b1c, b1u, b2c, b2l, rh[a][b], ih, tau);
+        if (!in) pn = T(0);
+        Lp[r * RW + c] = pn;
+      }
+    __syncthreads();
+  }
+
+  if (CHECK) {
+    // dm of every region node with a valid previous iterate (steps == 1)
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        const int r = wv + NWV * a, c = lane + 64 * b;
+        const int gi = gi0 + r, gj = gj0 + c;
+        const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
+        const size_t off = in ? (size_t)gi * pitch + gj : 0;
+        L1[r * RW + c] = in ? m1[a][b] - sm1[off] : T(0);
+        L2[r * RW + c] = in ? m2[a][b] - sm2[off] : T(0);
+      }
+    __syncthreads();
+    double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < NR; ++a)
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        const int r = wv + NWV * a, c = lane + 64 * b;
+        const int gi = gi0 + r, gj = gj0 + c;
+        const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
+        if (in && r >= S && r < RH - S && c >= S && c < RW - S) {
+          const size_t off = (size_t)gi * pitch + gj;
+          const T e1 = L1[r * RW + c], e2 = L2[r * RW + c];
+          const T u1 = L1[(r - 1) * RW + c];
+          const T l2 = L2[r * RW + c - 1];
+          const T pn = Lp[r * RW + c];
+          const double adm = (double)(((e1 - u1) + (e2 - l2)) * ih);
+          const double ep = (double)(pn - sph[off]);
+          v[0] += (double)e1 * (double)e1 + (double)e2 * (double)e2;
+          v[1] += ep * ep;
+          v[2] += ep * adm;
+          if (!(finite_(m1[a][b]) && finite_(m2[a][b]) && finite_(pn))) v[3] += 1.0;
+        }
+      }
+    block_reduce_<NTH>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+  }
+
+  T* __restrict__ dm1p = d.p[3 * ws];
+  T* __restrict__ dm2p = d.p[3 * ws + 1];
+  T* __restrict__ dphp = d.p[3 * ws + 2];
+#pragma unroll
+  for (int a = 0; a < NR; ++a)
+#pragma unroll
+    for (int b = 0; b < NC; ++b) {
+      const int r = wv + NWV * a, c = lane + 64 * b;
+      const int gi = gi0 + r, gj = gj0 + c;
+      const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
+      if (in && r >= S && r < RH - S && c >= S && c < RW - S) {
+        const size_t off = (size_t)gi * pitch + gj;
+        dm1p[off] = m1[a][b];
+        dm2p[off] = m2[a][b];
+        dphp[off] = Lp[r * RW + c];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1, whole level resident in one workgroup's LDS.
+// For grids whose potential and one extrapolated-flux plane fit in LDS
+// ((n+1)^2 * 2 * sizeof(T) bytes), one 512-thread workgroup per pair runs
+// the level to its stop test or cap without touching HBM in between.  The
+// flux stays in registers; the divergence is split into its two axis terms
+// so that one LDS plane carries both extrapolated components in turn.
+// Stop tests (both rules) run every `check_every` iterations and at the cap;
+// on those iterations the previous iterate is parked in the slot's spare
+// planes 3..5 and dm in planes 6, 7 (global memory, same workgroup).
+// Reads and writes plane set A.
+// ---------------------------------------------------------------------------
+template <typename T, int NPT>
+__global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __restrict__ idx,
+                                                                const SlotDesc<T>* __restrict__ desc,
+                                                                SlotScalars* __restrict__ scal, int check_every) {
+  extern __shared__ double smem_d[];
+  constexpr int NT = RES_THREADS;
+  static_assert(NPT <= 32, "column masks hold 32 nodes");
+  const int x = idx[blockIdx.x];
+  const SlotDesc<T>& d = desc[x];
+  SlotScalars& sc = scal[x / MAXL];
+  const int n = d.n, N = n + 1, NN = N * N, pitch = d.pitch;
+  const int last_row = NN - N;          // e >= last_row  <=>  row n
+  double* red = smem_d;                 // [NT/64 * NQ]
+  double* res = smem_d + 16 * NQ;       // [NQ]
+  int* flag = (int*)(smem_d + 17 * NQ);
+  T* Lp = (T*)(smem_d + 18 * NQ);
+  T* Lb = Lp + NN;
+  // spare planes of the level, indexed densely (e = r*N + c < NN <= N*pitch)
+  T* __restrict__ o1 = d.p[3];
+  T* __restrict__ o2 = d.p[4];
+  T* __restrict__ op = d.p[5];
+  T* __restrict__ e1p = d.p[6];
+  T* __restrict__ e2p = d.p[7];
+  const T ih = d.ih, mu = d.mu, tau = d.tau;
+  const int metric = d.metric;
+  const int cap = d.cap;
+  const double h2 = d.h * d.h;
+
+  T m1[NPT], m2[NPT], rh[NPT], b2[NPT], ac[NPT];
+  unsigned first_col = 0u, last_col = 0u;   // bit s: node s is on column 0 / column n
+  for (int s = 0; s < NPT; ++s) {
+    const int e = threadIdx.x + NT * s;
+    if (e < NN) {
+      const int r = e / N, c = e - r * N;
+      if (c == 0) first_col |= 1u << s;
+      if (c == n) last_col |= 1u << s;
+      const size_t off = (size_t)r * pitch + c;
+      m1[s] = d.p[0][off];
+      m2[s] = d.p[1][off];
+      rh[s] = d.rho[off];
+      Lp[e] = d.p[2][off];
+    } else {
+      m1[s] = m2[s] = rh[s] = T(0);
+    }
+    b2[s] = ac[s] = T(0);
+  }
+  __syncthreads();
+
+  int k = 0;
+  int status = ST_RUN;
+  double measure = 0.0;
+  const bool fpr = d.rule == RULE_FPR;
+  while (true) {
+    ++k;
+    const bool chk = (k % check_every == 0) || (k >= cap);
+    if (chk && fpr) {
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          o1[e] = m1[s];
+          o2[e] = m2[s];
+          op[e] = Lp[e];
+        }
+      }
+    }
+    // flux half; Lb <- mbar1
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      if (e < NN) {
+        const bool hd = e < last_row, hr = !((last_col >> s) & 1u);
+        const T pc = Lp[e];
+        const T pd = hd ? Lp[e + N] : pc;
+        const T pr = hr ? Lp[e + 1] : pc;
+        T n1, n2;
+        plain_flux_(m1[s], m2[s], pc, pd, pr, hd, hr, ih, mu, metric, n1, n2);
+        Lb[e] = (n1 + n1) - m1[s];
+        b2[s] = (n2 + n2) - m2[s];
+        m1[s] = n1;
+        m2[s] = n2;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      if (e < NN) ac[s] = Lb[e] - (e >= N ? Lb[e - N] : T(0));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      if (e < NN) Lb[e] = b2[s];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      if (e < NN) {
+        const T pc = Lp[e];
+        const T bl = ((first_col >> s) & 1u) ? T(0) : Lb[e - 1];
+        const T dv = (ac[s] + (b2[s] - bl)) * ih;
+        Lp[e] = fma_(tau, dv - rh[s], pc);
+      }
+    }
+    __syncthreads();
+    if (!chk) continue;
+
+    // ---- stop test ----
+    double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (fpr) {
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          e1p[e] = m1[s] - o1[e];
+          e2p[e] = m2[s] - o2[e];
+        }
+      }
+      __syncthreads();
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          const T f1 = e1p[e], f2 = e2p[e];
+          const T u1 = e >= N ? e1p[e - N] : T(0);
+          const T l2 = ((first_col >> s) & 1u) ? T(0) : e2p[e - 1];
+          const double adm = (double)(((f1 - u1) + (f2 - l2)) * ih);
+          const T pn = Lp[e];
+          const double ep = (double)(pn - op[e]);
+          v[0] += (double)f1 * (double)f1 + (double)f2 * (double)f2;
+          v[1] += ep * ep;
+          v[2] += ep * adm;
+          if (!(finite_(m1[s]) && finite_(m2[s]) && finite_(pn))) v[3] += 1.0;
+        }
+      }
+    } else {
+      // KKT: residual A m - rho, Lipschitz excess of grad phi, cost, <phi, rho>
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          e1p[e] = m1[s];
+          e2p[e] = m2[s];
+        }
+      }
+      __syncthreads();
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          const bool hd = e < last_row, hr = !((last_col >> s) & 1u);
+          const T u1 = e >= N ? e1p[e - N] : T(0);
+          const T l2 = ((first_col >> s) & 1u) ? T(0) : e2p[e - 1];
+          const double am = (double)(((m1[s] - u1) + (m2[s] - l2)) * ih);
+          const double rr = (double)rh[s];
+          const double res1 = am - rr;
+          const T pc = Lp[e];
+          const T g1 = hd ? (Lp[e + N] - pc) * ih : T(0);
+          const T g2 = hr ? (Lp[e + 1] - pc) * ih : T(0);
+          const double gq = (double)norm_q_(g1, g2, metric);
+          const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
+          v[0] += res1 * res1;
+          v[1] += rr * rr;
+          v[2] += ex * ex;
+          v[3] += (double)norm_p_(m1[s], m2[s], metric);
+          v[4] += (double)pc * rr;
+          v[6] += (double)pc;
+          v[7] += rr;
+        }
+      }
+    }
+    __syncthreads();
+    block_reduce_<NT>(v, res, red, 0u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m;
+      if (fpr) {
+        m = h2 * (res[0] / d.mud + res[1] / d.taud - 2.0 * res[2]);
+        if (res[3] > 0.0) m = NAN;
+      } else {
+        const double rp = sqrt(res[0] / (res[1] > 1e-300 ? res[1] : 1e-300));
+        const double rdl = sqrt(res[2] * h2);
+        const double P = res[3] * h2;
+        const double D = -(res[4] - res[6] / (double)NN * res[7]) * h2;
+        const double den = fmax(fmax(fabs(P), fabs(D)), 1e-300);
+        const double gap = fabs(P - D) / den;
+        m = fmax(rp, fmax(rdl, gap));
+      }
+      int st = ST_RUN;
+      if (!isfinite(m)) st = ST_DIVERGED;
+      else if (m <= d.tol) st = ST_CONV;
+      else if (k >= cap) st = ST_CAP;
+      flag[0] = st;
+      res[0] = m;
+    }
+    __syncthreads();
+    status = flag[0];
+    measure = res[0];
+    __syncthreads();
+    if (status != ST_RUN) break;
+  }
+
+  for (int s = 0; s < NPT; ++s) {
+    const int e = threadIdx.x + NT * s;
+    if (e < NN) {
+      const int r = e / N, c = e - r * N;
+      const size_t off = (size_t)r * pitch + c;
+      d.p[0][off] = m1[s];
+      d.p[1][off] = m2[s];
+      d.p[2][off] = Lp[e];
+    }
+  }
+  if (threadIdx.x == 0) {
+    sc.iters = k;
+    sc.status = status;
+    sc.measure = measure;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// KKT partials of an Algorithm 1 iterate (current set) or of an Algorithm 2
+// iterate with its potential psi in plane 8:
+// q0 sum (A m - rho)^2, q1 sum rho^2, q2 sum excess^2, q3 sum ||m||_p,
+// q4 sum pot*rho, q6 sum pot, q7 sum rho.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_kkt(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                             int kind, int gpar) {
+  __shared__ double lds[4 * NQ];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const int n = d.n, pitch = d.pitch;
+  const T* m1;
+  const T* m2;
+  const T* pot;
+  if (kind == K_PLAIN) {
+    const int cs = (gpar ^ d.par0) & 1;
+    m1 = d.p[3 * cs];
+    m2 = d.p[3 * cs + 1];
+    pot = d.p[3 * cs + 2];
+  } else {
+    m1 = d.p[0];
+    m2 = d.p[1];
+    pot = d.p[8];
+  }
+  const T ih = d.ih;
+  double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+  SIMPLE_TILE_LOOP(d, w, {
+    const T a1 = m1[off] - (i > 0 ? m1[off - pitch] : T(0));
+    const T a2 = m2[off] - (j > 0 ? m2[off - 1] : T(0));
+    const double am = (double)((a1 + a2) * ih);
+    const double rr = (double)d.rho[off];
+    const double r1 = am - rr;
+    const T pc = pot[off];
+    const T g1 = i < n ? (pot[off + pitch] - pc) * ih : T(0);
+    const T g2 = j < n ? (pot[off + 1] - pc) * ih : T(0);
+    const double gq = (double)norm_q_(g1, g2, d.metric);
+    const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
+    v[0] += r1 * r1;
+    v[1] += rr * rr;
+    v[2] += ex * ex;
+    v[3] += (double)norm_p_(m1[off], m2[off], d.metric);
+    v[4] += (double)pc * rr;
+    v[6] += (double)pc;
+    v[7] += rr;
+  })
+  block_reduce_<256>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// node-field inputs of a Poisson solve, written to plane 6:
+//   mode 0: A(m - mu vphibar) - rho   (projection step of eq. (pdhg))
+//   mode 1: A vphi                    (Appendix B potential)
+//   mode 2: A m - rho                 (certificate correction), m from the
+//           current plain set (kind plain) or planes 0, 1 (prox)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_div_pre(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                                 int mode, int kind, int gpar) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const int n = d.n, pitch = d.pitch;
+  const T ih = d.ih, mu = d.mu;
+  const T *a1p, *a2p;
+  if (mode == 1) {
+    a1p = d.p[2];
+    a2p = d.p[3];
+  } else if (kind == K_PLAIN) {
+    const int cs = (gpar ^ d.par0) & 1;
+    a1p = d.p[3 * cs];
+    a2p = d.p[3 * cs + 1];
+  } else {
+    a1p = d.p[0];
+    a2p = d.p[1];
+  }
+  T* out = d.p[6];
+  SIMPLE_TILE_LOOP(d, w, {
+    T v1c, v1u, v2c, v2l;
+    if (mode == 0) {
+      v1c = i < n ? fma_(-mu, d.p[4][off], a1p[off]) : T(0);
+      v1u = i > 0 ? fma_(-mu, d.p[4][off - pitch], a1p[off - pitch]) : T(0);
+      v2c = j < n ? fma_(-mu, d.p[5][off], a2p[off]) : T(0);
+      v2l = j > 0 ? fma_(-mu, d.p[5][off - 1], a2p[off - 1]) : T(0);
+    } else {
+      v1c = i < n ? a1p[off] : T(0);
+      v1u = i > 0 ? a1p[off - pitch] : T(0);
+      v2c = j < n ? a2p[off] : T(0);
+      v2l = j > 0 ? a2p[off - 1] : T(0);
+    }
+    const T dv = ((v1c - v1u) + (v2c - v2l)) * ih;
+    out[off] = mode == 1 ? dv : dv - d.rho[off];
+  })
+}
+
+// ---------------------------------------------------------------------------
+// One pass of the DCT Neumann-Poisson solve: a batched product with the
+// orthonormal DCT-II matrix C of length N = n+1 (or its transpose).
+//   MODE 0 (along rows):    Y = X * M   (M = C^T: forward, M = C: inverse)
+//   MODE 1 (along columns): Y = M * X   (M = C: forward, M = C^T: inverse)
+// With SCALE the result is divided by the eigenvalue
+// lambda_kl = (4/h^2)(sin^2(pi k/2N) + sin^2(pi l/2N)) and mode (0,0) set to
+// zero.  64 x 64 output tile per workgroup, 4 x 4 per thread, K in chunks of 16.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE, bool SCALE>
+__global__ __launch_bounds__(256) void k_gemm(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                              int src, int dst, int mat) {
+  __shared__ T As[16][GEMM_T + 4];
+  __shared__ T Bs[16][GEMM_T + 4];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const int N = d.n + 1, ld = d.pitch;
+  const T* M = mat ? d.dctCt : d.dctC;
+  const T* X = d.p[src];
+  T* Y = d.p[dst];
+  const T* A = MODE == 0 ? X : M;
+  const T* B = MODE == 0 ? M : X;
+  const int lda = MODE == 0 ? ld : N;
+  const int ldb = MODE == 0 ? N : ld;
+  const int i0 = w.y * GEMM_T, j0 = w.z * GEMM_T;
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  T acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = T(0);
+  for (int p0 = 0; p0 < N; p0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      const int ii = e >> 4, pp = e & 15;
+      const int gi = i0 + ii, gp = p0 + pp;
+      As[pp][ii] = (gi < N && gp < N) ? A[(size_t)gi * lda + gp] : T(0);
+      const int pb = e >> 6, jj = e & 63;
+      const int gq = p0 + pb, gj = j0 + jj;
+      Bs[pb][jj] = (gq < N && gj < N) ? B[(size_t)gq * ldb + gj] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pp = 0; pp < 16; ++pp) {
+      T a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[pp][ty * 4 + r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = Bs[pp][tx * 4 + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma_(a[r], b[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+  const double h2 = d.h * d.h;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int gi = i0 + ty * 4 + r, gj = j0 + tx * 4 + c;
+      if (gi < N && gj < N) {
+        T v = acc[r][c];
+        if (SCALE) {
+          const double lam = d.dcts[gi] + d.dcts[gj];
+          v = (gi == 0 && gj == 0) ? T(0) : (T)((double)v * (h2 / lam));
+        }
+        Y[(size_t)gi * ld + gj] = v;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2 update after the Poisson solve (u in plane 6), in place:
+// m+ = v + grad+ u, vphi+ = Proj(vphi + tau m+), vphibar+ = 2 vphi+ - vphi.
+// With CHECK: partials of G^k (eq. (pdhg_stop)): sum |dm|^2, sum |dvphi|^2,
+// sum dvphi . dm, count of non-finite values.
+// ---------------------------------------------------------------------------
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(256) void k_prox_post(const Work* __restrict__ work,
+                                                   const SlotDesc<T>* __restrict__ desc) {
+  __shared__ double lds[4 * NQ];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const int n = d.n, pitch = d.pitch;
+  const T ih = d.ih, mu = d.mu, tau = d.tau;
+  const T* u = d.p[6];
+  double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+  SIMPLE_TILE_LOOP(d, w, {
+    const T uc = u[off];
+    const T g1 = i < n ? (u[off + pitch] - uc) * ih : T(0);
+    const T g2 = j < n ? (u[off + 1] - uc) * ih : T(0);
+    const T m1 = d.p[0][off], m2 = d.p[1][off];
+    const T w1 = d.p[2][off], w2 = d.p[3][off];
+    const T v1 = i < n ? fma_(-mu, d.p[4][off], m1) : T(0);
+    const T v2 = j < n ? fma_(-mu, d.p[5][off], m2) : T(0);
+    const T n1 = v1 + g1, n2 = v2 + g2;
+    T q1, q2;
+    proj_ball_(fma_(tau, n1, w1), fma_(tau, n2, w2), d.metric, q1, q2);
+    if (i >= n) q1 = T(0);
+    if (j >= n) q2 = T(0);
+    d.p[0][off] = n1;
+    d.p[1][off] = n2;
+    d.p[2][off] = q1;
+    d.p[3][off] = q2;
+    d.p[4][off] = (q1 + q1) - w1;
+    d.p[5][off] = (q2 + q2) - w2;
+    if (CHECK) {
+      const double e1 = (double)(n1 - m1), e2 = (double)(n2 - m2);
+      const double f1 = (double)(q1 - w1), f2 = (double)(q2 - w2);
+      v[0] += e1 * e1 + e2 * e2;
+      v[1] += f1 * f1 + f2 * f2;
+      v[2] += f1 * e1 + f2 * e2;
+      if (!(finite_(n1) && finite_(n2) && finite_(q1) && finite_(q2))) v[3] += 1.0;
+    }
+  })
+  if (CHECK) block_reduce_<256>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// stop test after a block: reduce the slot's partials, form R^k / G^k or the
+// normalised KKT residual, compare with tol_l and the cap.
+// ---------------------------------------------------------------------------
+__device__ double measure_from_(const double* r, int kind, int rule, double h2, double mud, double taud, int NN) {
+  if (rule == RULE_FPR) {
+    if (r[3] > 0.0) return NAN;
+    if (kind == K_PLAIN) return h2 * (r[0] / mud + r[1] / taud - 2.0 * r[2]);
+    return h2 * (r[0] / mud + r[1] / taud + 2.0 * r[2]);
+  }
+  const double rp = sqrt(r[0] / (r[1] > 1e-300 ? r[1] : 1e-300));
+  const double rdl = sqrt(r[2] * h2);
+  const double P = r[3] * h2;
+  const double sgn = kind == K_PLAIN ? -1.0 : 1.0;
+  const double D = sgn * (r[4] - r[6] / (double)NN * r[7]) * h2;
+  const double den = fmax(fmax(fabs(P), fabs(D)), 1e-300);
+  return fmax(rp, fmax(rdl, fabs(P - D) / den));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, const int* __restrict__ ntiles,
+                                               const SlotDesc<T>* __restrict__ desc, SlotScalars* __restrict__ scal,
+                                               int kind, int block_len) {
+  __shared__ double lds[4 * NQ];
+  __shared__ double res[NQ];
+  const int x = idx[blockIdx.x];
+  const int nt = ntiles[blockIdx.x];
+  const SlotDesc<T>& d = desc[x];
+  double v[NQ];
+  for (int q = 0; q < NQ; ++q) {
+    Acc a{0.0, 0.0};
+    for (int t = threadIdx.x; t < nt; t += 256) a.add(d.part[(size_t)t * NQ + q]);
+    v[q] = a.get();
+  }
+  block_reduce_<256>(v, res, lds, 0u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SlotScalars& sc = scal[x / MAXL];
+    const int N = d.n + 1;
+    const double m = measure_from_(res, kind, d.rule, d.h * d.h, d.mud, d.taud, N * N);
+    const int k = sc.iters + block_len;
+    int st = ST_RUN;
+    if (!isfinite(m)) st = ST_DIVERGED;
+    else if (m <= d.tol) st = ST_CONV;
+    else if (k >= d.cap) st = ST_CAP;
+    sc.iters = k;
+    sc.measure = m;
+    sc.status = st;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 certificate (finest level): needs the Poisson correction
+// corr = (A A*)^{-1}(A m - rho) in plane 6 and, for prox, psi in plane 8.
+// q0 sum ||m||_p, q1 sum pot*rho, q2 sum ||m + grad+ corr||_p,
+// q3 sum |grad+ corr|^2, q4 sum excess^2, q5 max ||grad pot||_q (max),
+// q6 sum pot, q7 sum rho.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
+                                                   int kind, int gpar) {
+  __shared__ double lds[4 * NQ];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const int n = d.n, pitch = d.pitch;
+  const T *m1, *m2, *pot;
+  if (kind == K_PLAIN) {
+    const int cs = (gpar ^ d.par0) & 1;
+    m1 = d.p[3 * cs];
+    m2 = d.p[3 * cs + 1];
+    pot = d.p[3 * cs + 2];
+  } else {
+    m1 = d.p[0];
+    m2 = d.p[1];
+    pot = d.p[8];
+  }
+  const T* corr = d.p[6];
+  const double ih = 1.0 / d.h;
+  double v[NQ] = {0, 0, 0, 0, 0, -INFINITY, 0, 0};
+  SIMPLE_TILE_LOOP(d, w, {
+    const double a = (double)m1[off], b = (double)m2[off];
+    const double cc = (double)corr[off];
+    const double c1 = i < n ? ((double)corr[off + pitch] - cc) * ih : 0.0;
+    const double c2 = j < n ? ((double)corr[off + 1] - cc) * ih : 0.0;
+    const double pc = (double)pot[off];
+    const double g1 = i < n ? ((double)pot[off + pitch] - pc) * ih : 0.0;
+    const double g2 = j < n ? ((double)pot[off + 1] - pc) * ih : 0.0;
+    const double rr = (double)d.rho[off];
+    const double gq = d.metric == 1 ? fmax(fabs(g1), fabs(g2)) : sqrt(g1 * g1 + g2 * g2);
+    const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
+    v[0] += d.metric == 1 ? fabs(a) + fabs(b) : sqrt(a * a + b * b);
+    v[1] += pc * rr;
+    const double f1 = a + c1, f2 = b + c2;
+    v[2] += d.metric == 1 ? fabs(f1) + fabs(f2) : sqrt(f1 * f1 + f2 * f2);
+    v[3] += c1 * c1 + c2 * c2;
+    v[4] += ex * ex;
+    v[5] = gq > v[5] ? gq : v[5];
+    v[6] += pc;
+    v[7] += rr;
+  })
+  block_reduce_<256>(v, d.part + (size_t)w.w * NQ, lds, 1u << 5);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_eval_final(const int* __restrict__ idx, const int* __restrict__ ntiles,
+                                                    const SlotDesc<T>* __restrict__ desc,
+                                                    SlotScalars* __restrict__ scal, int kind) {
+  __shared__ double lds[4 * NQ];
+  __shared__ double res[NQ];
+  const int x = idx[blockIdx.x];
+  const int nt = ntiles[blockIdx.x];
+  const SlotDesc<T>& d = desc[x];
+  double v[NQ];
+  for (int q = 0; q < NQ; ++q) {
+    Acc a{0.0, 0.0};
+    double mx = -INFINITY;
+    for (int t = threadIdx.x; t < nt; t += 256) {
+      const double p = d.part[(size_t)t * NQ + q];
+      a.add(p);
+      mx = p > mx ? p : mx;
+    }
+    v[q] = q == 5 ? mx : a.get();
+  }
+  block_reduce_<256>(v, res, lds, 1u << 5);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SlotScalars& sc = scal[x / MAXL];
+    const double h2 = d.h * d.h;
+    const int N = d.n + 1;
+    const double mean = res[6] / ((double)N * (double)N);
+    const double P = res[0] * h2;
+    const double sgn = kind == K_PLAIN ? -1.0 : 1.0;
+    const double D = sgn * (res[1] - mean * res[7]) * h2;
+    const double hi = res[2] * h2;
+    const double gmax = res[5];
+    const double lo = D / (gmax > 1.0 ? gmax : 1.0);
+    const double rp = sqrt(res[3] * h2) / fmax(P, 1e-300);
+    const double rd = sqrt(res[4] * h2);
+    const double gap = fabs(P - D) / fmax(fmax(fabs(P), fabs(D)), 1e-300);
+    sc.eval[0] = P;
+    sc.eval[1] = D;
+    sc.eval[2] = lo;
+    sc.eval[3] = hi;
+    sc.eval[4] = fmax(rp, fmax(rd, gap));
+    sc.eval[5] = gmax;
+    sc.eval[6] = rp;
+    sc.eval[7] = rd;
+    sc.mean = mean;
+  }
+}
+
+// finest-level fields to dense FP64 buffers (pitch n+1); the plain
+// potential is reported as psi = -(phi - mean), the prox one is plane 8
+template <typename T>
+__global__ __launch_bounds__(256) void k_export_fields(const Work* __restrict__ work,
+                                                       const SlotDesc<T>* __restrict__ desc,
+                                                       const SlotScalars* __restrict__ scal, int kind, int gpar,
+                                                       double* __restrict__ om1, double* __restrict__ om2,
+                                                       double* __restrict__ opsi) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  const SlotDesc<T>& d = desc[w.x];
+  const double mean = scal[w.x / MAXL].mean;
+  const T *m1, *m2, *pot;
+  if (kind == K_PLAIN) {
+    const int cs = (gpar ^ d.par0) & 1;
+    m1 = d.p[3 * cs];
+    m2 = d.p[3 * cs + 1];
+    pot = d.p[3 * cs + 2];
+  } else {
+    m1 = d.p[0];
+    m2 = d.p[1];
+    pot = d.p[8];
+  }
+  SIMPLE_TILE_LOOP(d, w, {
+    const size_t o = (size_t)i * (d.n + 1) + j;
+    if (om1) om1[o] = (double)m1[off];
+    if (om2) om2[o] = (double)m2[off];
+    if (opsi) opsi[o] = kind == K_PLAIN ? -((double)pot[off] - mean) : (double)pot[off];
+  })
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+#define LAUNCH(kern, grid, block, lds, s, ...) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__)
+
+template <typename T> void K<T>::zero(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, unsigned mask) {
+  if (nw) LAUNCH(k_zero<T>, nw, 256, 0, s, w, d, mask);
+}
+template <typename T> void K<T>::import_dense(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int plane, const T* src) {
+  if (nw) LAUNCH(k_import<T>, nw, 256, 0, s, w, d, plane, src);
+}
+template <typename T> void K<T>::export_dense(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int plane, T* dst) {
+  if (nw) LAUNCH(k_export<T>, nw, 256, 0, s, w, d, plane, dst);
+}
+template <typename T> void K<T>::reduce(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
+                                        SlotScalars* sc, int nq, int out_base, unsigned maxmask) {
+  if (ns) LAUNCH(k_reduce<T>, ns, 256, 0, s, idx, nt, d, sc, nq, out_base, maxmask);
+}
+template <typename T> void K<T>::prep_stats(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d) {
+  if (nw) LAUNCH(k_prep_stats<T>, nw, 256, 0, s, w, d);
+}
+template <typename T> void K<T>::prep_scale(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc) {
+  if (nw) LAUNCH(k_prep_scale<T>, nw, 256, 0, s, w, d, sc);
+}
+template <typename T> void K<T>::restrict_level(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d) {
+  if (nw) LAUNCH(k_restrict<T>, nw, 256, 0, s, w, d);
+}
+template <typename T> void K<T>::scale_level(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc) {
+  if (nw) LAUNCH(k_scale_level<T>, nw, 256, 0, s, w, d, sc);
+}
+template <typename T> void K<T>::rho_diff(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d) {
+  if (nw) LAUNCH(k_rho_diff<T>, nw, 256, 0, s, w, d);
+}
+template <typename T> void K<T>::rho_write(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc) {
+  if (nw) LAUNCH(k_rho_write<T>, nw, 256, 0, s, w, d, sc);
+}
+template <typename T> void K<T>::prolong(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar) {
+  if (nw) LAUNCH(k_prolong<T>, nw, 256, 0, s, w, d, kind, gpar);
+}
+template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int gpar,
+                                             int steps, int rh, bool check) {
+  if (!nw) return;
+  if (check && steps != 1) {
+    fprintf(stderr, "w1: internal error: checking launch with %d steps\n", steps);
+    return;
+  }
+  // a 64-row region of doubles would not fit in LDS: double always uses 32
+  if constexpr (sizeof(T) == 4) {
+    if (rh == 64) {
+      if (check) LAUNCH((k_plain_tiled<T, 64, true>), nw, 512, 0, s, w, d, gpar, steps);
+      else LAUNCH((k_plain_tiled<T, 64, false>), nw, 512, 0, s, w, d, gpar, steps);
+      return;
+    }
+  }
+  if (check) LAUNCH((k_plain_tiled<T, 32, true>), nw, 256, 0, s, w, d, gpar, steps);
+  else LAUNCH((k_plain_tiled<T, 32, false>), nw, 256, 0, s, w, d, gpar, steps);
+}
+
+// resident kernel: sides up to 65, 9 nodes per thread of 512
+template <typename T> struct ResCfg;
+template <> struct ResCfg<float> { static constexpr int NPT = 9; static constexpr int MAXN = 65; };
+template <> struct ResCfg<double> { static constexpr int NPT = 9; static constexpr int MAXN = 65; };
+
+int resident_lds_bytes(int side, int elem) { return 18 * NQ * 8 + 2 * side * side * elem; }
+
+template <typename T> int K<T>::plain_resident_max_side() { return ResCfg<T>::MAXN; }
+
+template <typename T> void K<T>::plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d,
+                                                SlotScalars* sc, int max_side, int check_every) {
+  if (!ns) return;
+  static bool attr_set = false;
+  const int bytes = resident_lds_bytes(max_side, sizeof(T));
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_plain_resident<T, ResCfg<T>::NPT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, resident_lds_bytes(ResCfg<T>::MAXN, sizeof(T)));
+    attr_set = true;
+  }
+  LAUNCH((k_plain_resident<T, ResCfg<T>::NPT>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every);
+}
+template <typename T> void K<T>::kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar) {
+  if (nw) LAUNCH(k_kkt<T>, nw, 256, 0, s, w, d, kind, gpar);
+}
+template <typename T> void K<T>::div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int mode,
+                                         int kind, int gpar) {
+  if (nw) LAUNCH(k_div_pre<T>, nw, 256, 0, s, w, d, mode, kind, gpar);
+}
+template <typename T> void K<T>::gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int mode, int src,
+                                      int dst, int mat, bool scale) {
+  if (!nw) return;
+  if (mode == 0) {
+    if (scale) LAUNCH((k_gemm<T, 0, true>), nw, 256, 0, s, w, d, src, dst, mat);
+    else LAUNCH((k_gemm<T, 0, false>), nw, 256, 0, s, w, d, src, dst, mat);
+  } else {
+    if (scale) LAUNCH((k_gemm<T, 1, true>), nw, 256, 0, s, w, d, src, dst, mat);
+    else LAUNCH((k_gemm<T, 1, false>), nw, 256, 0, s, w, d, src, dst, mat);
+  }
+}
+template <typename T> void K<T>::prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, bool check) {
+  if (!nw) return;
+  if (check) LAUNCH((k_prox_post<T, true>), nw, 256, 0, s, w, d);
+  else LAUNCH((k_prox_post<T, false>), nw, 256, 0, s, w, d);
+}
+template <typename T> void K<T>::check(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
+                                       SlotScalars* sc, int kind, int block_len) {
+  if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len);
+}
+template <typename T> void K<T>::eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar) {
+  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, kind, gpar);
+}
+template <typename T> void K<T>::eval_final(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
+                                            SlotScalars* sc, int kind) {
+  if (ns) LAUNCH(k_eval_final<T>, ns, 256, 0, s, idx, nt, d, sc, kind);
+}
+template <typename T> void K<T>::export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                               const SlotScalars* sc, int kind, int gpar, double* m1, double* m2,
+                                               double* psi) {
+  if (nw) LAUNCH(k_export_fields<T>, nw, 256, 0, s, w, d, sc, kind, gpar, m1, m2, psi);
+}
+
+template struct K<float>;
+template struct K<double>;
+
+}  // namespace w1

@@ -1,0 +1,112 @@
+// Internal declarations shared by the HIP kernels and the host engine.
+//
+// Layout of one solve ("slot") in HBM: every level l owns NPLANES planes of
+// (n_l+1) rows x pitch_l elements (pitch a multiple of 32 elements), one
+// rho plane and two FP64 staging planes, plus a per-slot partial-sum area
+// for per-tile FP64 reductions.  Plane roles:
+//
+//   plain (Algorithm 1/3): 0 m1[A] 1 m2[A] 2 phi[A] 3 m1[B] 4 m2[B] 5 phi[B]
+//                          6, 7 Poisson ping-pong, 8 spare
+//   prox  (Algorithm 2/4): 0 m1 1 m2 2 vphi1 3 vphi2 4 vphibar1 5 vphibar2
+//                          6, 7 Poisson ping-pong, 8 potential psi
+//
+// Descriptors are indexed slot * MAXL + level (level 0 = coarsest), so a
+// kernel that reads level l-1 and writes level l finds both.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace w1 {
+
+constexpr int MAXL = 12;
+constexpr int NPLANES = 9;
+constexpr int NQ = 8;                // FP64 partial sums per tile
+constexpr int ST_H = 16;             // simple per-node tile: 16 rows x 64 cols
+constexpr int ST_W = 64;
+constexpr int GEMM_T = 64;           // DCT GEMM output tile
+constexpr int TILED_RW = 128;        // plain tiled kernel region width
+constexpr int RES_THREADS = 512;     // resident kernel workgroup size
+
+enum Status : int { ST_RUN = 0, ST_CONV = 1, ST_CAP = 2, ST_DIVERGED = 3, ST_REJECT = 4 };
+enum Rule : int { RULE_KKT = 1, RULE_FPR = 2 };
+enum Kind : int { K_PLAIN = 1, K_PROX = 2 };
+
+// Per-slot, per-level descriptor read by every batched kernel.
+template <typename T>
+struct SlotDesc {
+  T* p[NPLANES];
+  T* rho;
+  double* r0;          // FP64 staging: rho0_l, rho1_l
+  double* r1;
+  double* part;        // per-tile partial sums of the slot, NQ doubles per tile
+  const T* dctC;       // orthonormal DCT-II matrix C[k][j], N x N row-major
+  const T* dctCt;      // its transpose
+  const double* dcts;  // 4 sin^2(pi k / 2N), k < N
+  const double* in0;   // finest level only: input masses, dense pitch n+1
+  const double* in1;
+  int n, pitch;
+  T ih, mu, tau;
+  double h, mud, taud;  // FP64 copies of h, mu, tau for the measures
+  double tol;          // stop tolerance of this level
+  int metric;          // 1 or 2
+  int par0;            // ping-pong parity offset (plain tiled kernel)
+  int rule;            // RULE_KKT or RULE_FPR
+  int cap;             // iteration cap of this level
+};
+
+// Per-slot scalars written by the reduction epilogues (device memory).
+struct SlotScalars {
+  double sums[8];      // reduction outputs (prep: masses, level sums)
+  double measure;      // last stop measure
+  double eval[8];      // P, D, lo, hi, kkt, grad max, r_pri, r_dual
+  double mean;         // mean of the plain potential (export)
+  int status;          // Status
+  int iters;           // iterations run at the current level
+  int bad;             // count of invalid input masses
+  int pad;
+};
+
+// Work item: x = descriptor index (or -1 for padding), y = tile row,
+// z = tile col, w = tile index inside the slot's partial area.
+using Work = int4;
+
+// ---------------- launchers (kernels.hip) ----------------
+// `gpar` is the global ping-pong parity: a plain slot's current plane set
+// is (gpar ^ par0) & 1.
+template <typename T>
+struct K {
+  static void zero(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, unsigned mask);
+  static void import_dense(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int plane, const T* src);
+  static void export_dense(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int plane, T* dst);
+  static void reduce(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
+                     SlotScalars* sc, int nq, int out_base, unsigned maxmask);
+  static void prep_stats(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d);
+  static void prep_scale(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc);
+  static void restrict_level(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d);
+  static void scale_level(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc);
+  static void rho_diff(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d);
+  static void rho_write(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc);
+  static void prolong(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar);
+  static void plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int gpar, int steps,
+                          int rh, bool check);
+  static int plain_resident_max_side();
+  static void plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
+                             int max_side, int check_every);
+  static void kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar);
+  static void div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int mode, int kind, int gpar);
+  static void gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int mode, int src, int dst,
+                   int mat, bool scale);
+  static void prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, bool check);
+  static void check(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
+                    SlotScalars* sc, int kind, int block_len);
+  static void eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar);
+  static void eval_final(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
+                         SlotScalars* sc, int kind);
+  static void export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
+                            int kind, int gpar, double* m1, double* m2, double* psi);
+};
+
+int resident_lds_bytes(int side, int elem);
+
+}  // namespace w1

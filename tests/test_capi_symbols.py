@@ -1,0 +1,49 @@
+"""The C-ABI library loads and exports every function include/w1.h declares
+(no device calls)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "w1.h")
+LIB = os.path.join(ROOT, "paper_1810_00118_amd", "libw1.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(w1_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("w1_plan", "w1_solve", "w1_submit", "w1_poll", "w1_destroy", "w1_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("libw1.so not built")
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (w1_[a-z_0-9]+)\b", out))
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+
+
+def test_library_loads_and_checks_params_without_a_device():
+    if not os.path.exists(LIB):
+        pytest.skip("libw1.so not built")
+    import paper_1810_00118_amd as w1
+    assert "gfx950" in w1.version()
+    p = w1.params(n=512, levels=4)
+    assert w1.check_params(p) == 0
+    assert w1.bytes_per_solve(p) > 0
+    for bad in (dict(n=100, levels=4), dict(levels=0), dict(metric=3), dict(max_iters=15, check_every=10),
+                dict(step_scale=1.0), dict(algo=7)):
+        q = w1.params(n=512, levels=4)
+        for k, v in bad.items():
+            setattr(q, k, v)
+        assert w1.check_params(q) == w1.W1_EINVAL, bad
+    assert w1.strerror(w1.W1_EINVAL) == "invalid argument"

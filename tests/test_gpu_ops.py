@@ -1,0 +1,201 @@
+"""GPU parity of each row of the method through the single-step entry
+points of the C ABI, against the FP64 oracle on identical seeded inputs.
+Sizes span several tiles and ragged tails."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle.w1_oracle as o
+import w1data
+from tests.gpu_util import dev, host, rel_err, require_gpu, tdtype
+
+pytestmark = pytest.mark.gpu
+
+FP32, FP64 = 1, 2
+
+
+def _rho(n, seed):
+    p0, p1 = w1data.random_pair(n, seed)
+    return o.prepare_levels(p0, p1, n, 1)[0]
+
+
+def _rand_state(n, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    m1 = rng.standard_normal((n + 1, n + 1)) * scale; m1[n, :] = 0
+    m2 = rng.standard_normal((n + 1, n + 1)) * scale; m2[:, n] = 0
+    phi = rng.standard_normal((n + 1, n + 1)) * 0.1
+    return m1, m2, phi
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [33, 100, 200])
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("block", [1, 4, -1])
+def test_plain_steps_trajectory(precision, n, metric, block):
+    w1 = require_gpu()
+    if block < 0 and n + 1 > 65:
+        pytest.skip("resident kernel holds sides up to 65")
+    h = 1.0 / n
+    rho = _rho(n, n)
+    m1, m2, phi = _rand_state(n, n + 1)
+    mu, tau = o.plain_step_sizes(h)
+    dt = tdtype(precision)
+    g = [dev(x, dt) for x in (m1, m2, phi, rho)]
+    for k in (1, 10, 40):
+        R = w1.op_plain_steps(n, metric, precision, k, g[0], g[1], g[2], g[3], block_steps=block, fpr=True)
+        a1, a2, ap = m1.copy(), m2.copy(), phi.copy()
+        for _ in range(k):
+            a1, a2, ap, Rw = o.pd_step(a1, a2, ap, rho, h, mu, tau, metric)
+        tol = 1e-12 if precision == FP64 else 2e-5 * math.sqrt(k)
+        assert rel_err(host(g[0]), a1) <= tol
+        assert rel_err(host(g[1]), a2) <= tol
+        assert rel_err(host(g[2]), ap) <= tol
+        assert R == pytest.approx(Rw, rel=1e-9 if precision == FP64 else 1e-3)
+        # restart both sides from the same state for the next k
+        m1, m2, phi = a1, a2, ap
+        g = [dev(x, dt) for x in (m1, m2, phi, rho)]
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [32, 64, 100])
+def test_resident_and_tiled_agree_bitwise(precision, n):
+    w1 = require_gpu()
+    if n + 1 > 65:
+        pytest.skip("resident kernel holds sides up to 65")
+    rho = _rho(n, 3)
+    m1, m2, phi = _rand_state(n, 4)
+    dt = tdtype(precision)
+    outs = []
+    for block in (-1, 1, 3, 6):
+        g = [dev(x, dt) for x in (m1, m2, phi, rho)]
+        w1.op_plain_steps(n, 2, precision, 25, g[0], g[1], g[2], g[3], block_steps=block)
+        outs.append([host(x) for x in g[:3]])
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [32, 64, 100])
+@pytest.mark.parametrize("metric", [1, 2])
+def test_prox_steps_trajectory(precision, n, metric):
+    w1 = require_gpu()
+    h = 1.0 / n
+    rho = _rho(n, 7 + n)
+    m1, m2, _ = _rand_state(n, 8)
+    rng = np.random.default_rng(9)
+    v1 = rng.uniform(-1, 1, (n + 1, n + 1)); v1[n, :] = 0
+    v2 = rng.uniform(-1, 1, (n + 1, n + 1)); v2[:, n] = 0
+    dt = tdtype(precision)
+    g = [dev(x, dt) for x in (m1, m2, v1, v2, v1, v2, rho)]
+    k = 10
+    G = w1.op_prox_steps(n, metric, precision, k, *g, fpr=True)
+    st = (m1, m2, v1, v2, v1.copy(), v2.copy())
+    for _ in range(k):
+        out = o.prox_step(*st, rho, h, 0.5, 0.5, metric)
+        st, Gw = out[:6], out[6]
+    tol = 1e-10 if precision == FP64 else 1e-4
+    for got, want in zip(g[:6], st):
+        assert rel_err(host(got), want) <= tol
+    assert G == pytest.approx(Gw, rel=1e-8 if precision == FP64 else 1e-2, abs=1e-12)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [16, 64, 128, 200])
+def test_poisson(precision, n):
+    w1 = require_gpu()
+    rng = np.random.default_rng(n)
+    r = rng.standard_normal((n + 1, n + 1)); r -= r.mean()
+    want = o.poisson_neumann(r, 1.0 / n)
+    dt = tdtype(precision)
+    gr = dev(r, dt)
+    gu = dev(np.zeros_like(r), dt)
+    w1.op_poisson(n, precision, gr, gu)
+    tol = 1e-11 if precision == FP64 else 2e-5
+    assert rel_err(host(gu), want) <= tol
+    # aliasing input and output is allowed
+    w1.op_poisson(n, precision, gr, gr)
+    assert rel_err(host(gr), want) <= tol
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [16, 100])
+def test_potential(precision, n):
+    w1 = require_gpu()
+    rng = np.random.default_rng(n + 5)
+    v1 = rng.uniform(-1, 1, (n + 1, n + 1)); v1[n, :] = 0
+    v2 = rng.uniform(-1, 1, (n + 1, n + 1)); v2[:, n] = 0
+    want = o.potential_from_dual(v1, v2, 1.0 / n)
+    dt = tdtype(precision)
+    g = [dev(x, dt) for x in (v1, v2, np.zeros_like(v1))]
+    w1.op_potential(n, precision, *g)
+    assert rel_err(host(g[2]), want) <= (1e-11 if precision == FP64 else 3e-5)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("nc", [1, 7, 50])
+def test_prolong(precision, nc):
+    w1 = require_gpu()
+    rng = np.random.default_rng(nc)
+    c1 = rng.standard_normal((nc + 1, nc + 1)); c1[nc, :] = 0
+    c2 = rng.standard_normal((nc + 1, nc + 1)); c2[:, nc] = 0
+    cp = rng.standard_normal((nc + 1, nc + 1))
+    f1, f2 = o.prolong_flux(c1, c2)
+    fp = o.prolong_potential(cp)
+    dt = tdtype(precision)
+    g = [dev(x, dt) for x in (c1, c2, cp)]
+    out = [dev(np.zeros_like(f1), dt) for _ in range(3)]
+    w1.op_prolong(nc, precision, *g, *out)
+    tol = 0 if precision == FP64 else 1e-7
+    for got, want in zip(out, (f1, f2, fp)):
+        assert rel_err(host(got), want) <= tol
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n,L", [(64, 3), (100, 1), (256, 4)])
+def test_prepare(precision, n, L):
+    w1 = require_gpu()
+    import torch
+    p0, p1 = w1data.pair_shapes(0, n=n) if n % 4 == 0 else w1data.random_pair(n, 1)
+    want = o.prepare_levels(p0, p1, n, L)
+    dt = tdtype(precision)
+    outs = [dev(np.zeros_like(r), dt) for r in want]
+    w1.op_prepare(n, L, precision, dev(p0, torch.float64), dev(p1, torch.float64), outs)
+    for got, ref in zip(outs, want):
+        assert rel_err(host(got), ref) <= (1e-13 if precision == FP64 else 1e-6)
+
+
+def test_prepare_rejects_bad_masses():
+    w1 = require_gpu()
+    import torch
+    n = 16
+    p0, p1 = w1data.random_pair(n, 2)
+    bad = p0.copy(); bad[3, 3] = -1e-3
+    rho = [dev(np.zeros((n + 1, n + 1)), torch.float64)]
+    with pytest.raises(w1.W1Error):
+        w1.op_prepare(n, 1, FP64, dev(bad, torch.float64), dev(p1, torch.float64), rho)
+    with pytest.raises(w1.W1Error):
+        w1.op_prepare(n, 1, FP64, dev(p0, torch.float64), dev(p1 * 1.001, torch.float64), rho)
+    nanm = p0.copy(); nanm[0, 0] = np.nan
+    with pytest.raises(w1.W1Error):
+        w1.op_prepare(n, 1, FP64, dev(nanm, torch.float64), dev(p1, torch.float64), rho)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("n", [24, 100])
+def test_evaluate(precision, metric, n):
+    w1 = require_gpu()
+    rho = _rho(n, 11)
+    r = o.solve(*w1data.random_pair(n, 11), n, L=1, p=metric, algo=1, stop="kkt", tol=0.0, max_iters=200,
+                check_every=200)
+    m1, m2, psi = r["m1"], r["m2"], r["psi"]
+    want = o.evaluate(m1, m2, psi, rho, 1.0 / n, metric)
+    dt = tdtype(precision)
+    got = w1.op_evaluate(n, metric, precision, *[dev(x, dt) for x in (m1, m2, psi, rho)])
+    rt = 1e-10 if precision == FP64 else 2e-5
+    for k in ("P", "D", "lo", "hi"):
+        assert got[k] == pytest.approx(want[k], rel=rt, abs=1e-12), k
+    assert got["kkt"] == pytest.approx(want["kkt"], rel=1e-6 if precision == FP64 else 2e-3)
+    assert got["grad_max"] == pytest.approx(want["grad_max"], rel=rt)

@@ -1,0 +1,141 @@
+"""End-to-end GPU parity of the multilevel solver (Algorithms 3 and 4)
+through w1_solve / w1_submit against the FP64 oracle: W1 within 1e-4
+relative, the normalised KKT of both sides' fields within 1e-5, the oracle's
+W1 inside the GPU certificate; batch composition and served mode."""
+import numpy as np
+import pytest
+
+import oracle.w1_oracle as o
+import w1data
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+FP32, FP64 = 1, 2
+
+
+def _oracle(p0, p1, n, L, metric, algo, rule, tol, cap, ce):
+    return o.solve(p0, p1, n, L=L, p=metric, algo=algo, stop="fpr" if rule == 2 else "kkt",
+                   tol=tol, eps_L=tol if rule == 2 and tol > 0 else None, max_iters=cap, check_every=ce,
+                   alpha=-1.0)
+
+
+def _check_parity(w1, res, fields, ref, n, metric, rho):
+    assert res["status"] in (0, 1)
+    assert res["w1"] == pytest.approx(ref["w1"], rel=1e-4)
+    m1, m2, psi = fields
+    ev_gpu = o.evaluate(m1, m2, psi, rho, 1.0 / n, metric)
+    ev_ref = o.evaluate(ref["m1"], ref["m2"], ref["psi"], rho, 1.0 / n, metric)
+    assert abs(ev_gpu["kkt"] - ev_ref["kkt"]) <= 1e-5
+    assert res["lo"] - 1e-4 * abs(ref["w1"]) <= ref["w1"] <= res["hi"] + 1e-4 * abs(ref["w1"])
+    # the library's own FP64 evaluator agrees with the oracle's on its fields
+    assert res["w1"] == pytest.approx(ev_gpu["P"], rel=1e-9)
+    assert res["hi"] == pytest.approx(ev_gpu["hi"], rel=1e-7)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_config1_plain_fp64_kkt(precision):
+    """64x64, three isotropic Gaussians + floor, L1, plain PDHG, 2 levels,
+    KKT 1e-6 or 20k iterations per level."""
+    w1 = require_gpu()
+    n, L, metric = 64, 2, 1
+    p0, p1 = w1data.pair_gauss3(0)
+    prm = w1.params(n=n, levels=L, metric=metric, algo=w1.ALGO_PLAIN, precision=precision,
+                    stop_rule=w1.STOP_KKT, tol=1e-6, max_iters=20000, check_every=10)
+    with w1.Solver(prm) as s:
+        res = s.solve([(p0, p1)])[0]
+        fields = s.fields(0)
+    ref = _oracle(p0, p1, n, L, metric, 1, 1, 1e-6, 20000, 10)
+    if precision == FP64:
+        assert res["iters"] == ref["iters"]
+    rho = o.prepare_levels(p0, p1, n, L)[-1]
+    _check_parity(w1, res, fields, ref, n, metric, rho)
+
+
+@pytest.mark.parametrize("algo", [1, 2])
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("metric", [1, 2])
+def test_multilevel_paper_rule(algo, precision, metric):
+    """Algorithm 3 / 4 with the paper's tolerance rule eq. (stop_tol),
+    alpha = -1, on a 128-grid, 3 levels (tiled plain levels beyond 65)."""
+    w1 = require_gpu()
+    n, L = 128, 3
+    p0, p1 = w1data.pair_gauss3(3, n=n)
+    eps = o.paper_stop_tolerance(algo, n, True)
+    prm = w1.params(n=n, levels=L, metric=metric, algo=algo, precision=precision, stop_rule=w1.STOP_FPR,
+                    tol=eps, max_iters=20000, check_every=10)
+    with w1.Solver(prm) as s:
+        res = s.solve([(p0, p1)])[0]
+        fields = s.fields(0)
+    ref = _oracle(p0, p1, n, L, metric, algo, 2, eps, 20000, 10)
+    rho = o.prepare_levels(p0, p1, n, L)[-1]
+    if precision == FP64:
+        assert res["iters"] == ref["iters"]
+    _check_parity(w1, res, fields, ref, n, metric, rho)
+
+
+def test_batch_equals_alone_bitwise():
+    w1 = require_gpu()
+    n, L = 64, 2
+    pairs = [w1data.pair_gauss3(i) for i in range(5)]
+    prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_FPR,
+                    tol=0.0, max_iters=4000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+    with w1.Solver(prm, capacity=5) as s:
+        batch = s.solve(pairs)
+        fb = [s.fields(i) for i in range(5)]
+    for i, pr in enumerate(pairs):
+        with w1.Solver(prm) as s:
+            alone = s.solve([pr])[0]
+            fa = s.fields(0)
+        assert alone["iters"] == batch[i]["iters"]
+        assert alone["w1"] == batch[i]["w1"]
+        for a, b in zip(fa, fb[i]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_rejected_pair_does_not_disturb_batch():
+    w1 = require_gpu()
+    n = 32
+    good = w1data.pair_gauss3(0, n=n)
+    bad = (good[0], good[1] * 1.5)
+    prm = w1.params(n=n, levels=2, metric=1, algo=w1.ALGO_PROX, precision=FP32)
+    with w1.Solver(prm, capacity=3) as s:
+        out = s.solve([good, bad, good])
+    assert out[1]["status"] == w1.SOLVE_REJECTED
+    assert out[0]["w1"] == out[2]["w1"]
+    assert out[0]["status"] in (0, 1)
+
+
+def test_served_mix_equals_alone():
+    """Continuous batching: requests of different sizes, metrics and
+    algorithms arrive while others run; each served result equals the same
+    request solved alone."""
+    w1 = require_gpu()
+    reqs = []
+    for i in range(10):
+        n = (32, 64, 128)[i % 3]
+        p0, p1 = w1data.pair_gauss3(100 + i, n=n)
+        algo = 2 if i % 2 == 0 else 1
+        L = {32: 1, 64: 2, 128: 3}[n]
+        prm = w1.params(n=n, levels=L, metric=1 + (i % 2), algo=algo, precision=FP32, stop_rule=w1.STOP_FPR,
+                        tol=0.0, max_iters=3000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+        reqs.append((prm, p0, p1))
+    base = reqs[0][0]
+    with w1.Solver(base, capacity=4) as srv:
+        tickets = []
+        for prm, p0, p1 in reqs:
+            tickets.append(srv.submit(p0, p1, prm))
+        srv.drain()
+        served = []
+        for t, (prm, _, _) in zip(tickets, reqs):
+            r = None
+            while r is None:
+                r = srv.poll(t, n=prm.n, fields=True)
+            served.append(r)
+        st = srv.stats()
+        assert st["finished"] == len(reqs) and st["running"] == 0
+    for (prm, p0, p1), (res, fields) in zip(reqs, served):
+        with w1.Solver(prm) as s:
+            alone = s.solve([(p0, p1)])[0]
+        assert res["iters"] == alone["iters"]
+        assert res["w1"] == pytest.approx(alone["w1"], rel=1e-6)
