@@ -242,6 +242,22 @@ int w1_op_evaluate(int32_t n, int32_t metric, int32_t precision,
                    const void* m1, const void* m2, const void* psi,
                    const void* rho, double* out, void* hip_stream);
 
+/* ---- kernel timing ------------------------------------------------------
+ * w1_profile(h, 1) resets and enables per-launch HIP-event timing on the
+ * handle's stream (0 disables it).  w1_kernel_stats(h, family, out) then
+ * returns for one kernel family, summed over both precisions:
+ *   out[0] launches, out[1] total milliseconds,
+ *   out[2] node updates (one node of one PDHG iteration), out[3] algorithmic
+ *   HBM bytes (per family: plain tiled 7 words per node update; prox
+ *   elementwise 13 words per node per iteration; DCT pass 2 words per node
+ *   per pass; resident 0), out[4] floating-point operations (DCT passes).
+ * Families: W1_FAM_PLAIN_TILED, W1_FAM_PLAIN_RESIDENT, W1_FAM_DCT,
+ * W1_FAM_PROX_ELEM, W1_FAM_OTHER.                                           */
+enum { W1_FAM_PLAIN_TILED = 0, W1_FAM_PLAIN_RESIDENT = 1, W1_FAM_DCT = 2,
+       W1_FAM_PROX_ELEM = 3, W1_FAM_OTHER = 4, W1_NFAM = 5 };
+int w1_profile(w1_handle h, int32_t enable);
+int w1_kernel_stats(w1_handle h, int32_t family, double* out5);
+
 /* Library version string.                                                  */
 const char* w1_version(void);
 

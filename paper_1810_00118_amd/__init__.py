@@ -24,6 +24,8 @@ FP32, FP64 = 1, 2
 STOP_KKT, STOP_FPR = 1, 2
 FLAG_NO_RESIDENT, FLAG_NO_CERT = 1, 2
 MAX_LEVELS = 12
+FAM_PLAIN_TILED, FAM_PLAIN_RESIDENT, FAM_DCT, FAM_PROX_ELEM, FAM_OTHER = 0, 1, 2, 3, 4
+FAMILIES = {0: "plain_tiled", 1: "plain_resident", 2: "dct", 3: "prox_elem", 4: "other"}
 
 
 class W1Error(RuntimeError):
@@ -83,6 +85,8 @@ def lib():
         "w1_destroy": (C.c_int, [vp]),
         "w1_strerror": (C.c_char_p, [C.c_int]),
         "w1_version": (C.c_char_p, []),
+        "w1_profile": (C.c_int, [vp, i32]),
+        "w1_kernel_stats": (C.c_int, [vp, i32, dp]),
         "w1_op_prepare": (C.c_int, [i32, i32, i32, vp, vp, C.POINTER(vp), vp]),
         "w1_op_prolong": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp, vp]),
         "w1_op_plain_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, dp, vp]),
@@ -248,6 +252,18 @@ class Solver:
             return None
         _check(st, "w1_poll")
         return r.as_dict(), (tuple(bufs) if fields else None)
+
+    def profile(self, enable=True):
+        _check(lib().w1_profile(self.h, 1 if enable else 0), "w1_profile")
+
+    def kernel_stats(self):
+        out = {}
+        for f, name in FAMILIES.items():
+            o = (C.c_double * 5)()
+            _check(lib().w1_kernel_stats(self.h, f, o), "w1_kernel_stats")
+            out[name] = {"launches": int(o[0]), "ms": o[1], "node_updates": o[2], "alg_bytes": o[3],
+                         "flops": o[4]}
+        return out
 
     def drain(self):
         _check(lib().w1_drain(self.h), "w1_drain")

@@ -366,6 +366,30 @@ extern "C" int w1_destroy(w1_handle h) {
   return W1_OK;
 }
 
+extern "C" int w1_profile(w1_handle h, int32_t enable) {
+  if (!h) return W1_EINVAL;
+  std::lock_guard<std::mutex> g(h->run_mu);
+  for (int prec = W1_FP32; prec <= W1_FP64; ++prec) {
+    BatchBase* b = h->batch(prec);
+    if (!b) return W1_EDEVICE;
+    b->profile(enable != 0);
+  }
+  return W1_OK;
+}
+
+extern "C" int w1_kernel_stats(w1_handle h, int32_t family, double* out5) {
+  if (!h || !out5 || family < 0 || family >= W1_NFAM) return W1_EINVAL;
+  std::lock_guard<std::mutex> g(h->run_mu);
+  for (int k = 0; k < 5; ++k) out5[k] = 0;
+  for (auto* b : {h->b32.get(), h->b64.get()}) {
+    if (!b) continue;
+    double o[5];
+    b->kernel_stats(family, o);
+    for (int k = 0; k < 5; ++k) out5[k] += o[k];
+  }
+  return W1_OK;
+}
+
 // ---------------------------------------------------------------------------
 // single-step entry points: one level, caller buffers in dense layout
 // ---------------------------------------------------------------------------

@@ -247,12 +247,95 @@ static BlockCache& g_blocks_ref() {
 #define g_blocks g_blocks_ref()
 
 // ---------------------------------------------------------------------------
+// per-family launch timing with HIP events on the batch's stream
+// ---------------------------------------------------------------------------
+class Prof {
+ public:
+  explicit Prof(hipStream_t s) : st_(s) {}
+  ~Prof() {
+    for (auto& p : pend_) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    for (auto e : pool_) (void)hipEventDestroy(e);
+  }
+  bool on = false;
+  void reset() {
+    for (int f = 0; f < W1_NFAM; ++f) tot_[f][0] = tot_[f][1] = tot_[f][2] = tot_[f][3] = tot_[f][4] = 0;
+  }
+  // returns the pending index (or -1 when off)
+  int begin() {
+    if (!on) return -1;
+    Pend p;
+    p.a = ev();
+    p.b = ev();
+    (void)hipEventRecord(p.a, st_);
+    pend_.push_back(p);
+    return (int)pend_.size() - 1;
+  }
+  void end(int i, int fam, double units, double bytes, double flops) {
+    if (i < 0) return;
+    Pend& p = pend_[i];
+    (void)hipEventRecord(p.b, st_);
+    p.fam = fam;
+    p.units = units;
+    p.bytes = bytes;
+    p.flops = flops;
+  }
+  void set_units(int i, double units, double bytes) {
+    if (i < 0) return;
+    pend_[i].units = units;
+    pend_[i].bytes = bytes;
+  }
+  // after the stream has been synchronised
+  void harvest() {
+    for (auto& p : pend_) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        tot_[p.fam][0] += 1;
+        tot_[p.fam][1] += ms;
+        tot_[p.fam][2] += p.units;
+        tot_[p.fam][3] += p.bytes;
+        tot_[p.fam][4] += p.flops;
+      }
+      pool_.push_back(p.a);
+      pool_.push_back(p.b);
+    }
+    pend_.clear();
+  }
+  void stats(int f, double* o) const {
+    for (int k = 0; k < 5; ++k) o[k] = tot_[f][k];
+  }
+
+ private:
+  struct Pend {
+    hipEvent_t a, b;
+    int fam = W1_FAM_OTHER;
+    double units = 0, bytes = 0, flops = 0;
+  };
+  hipEvent_t ev() {
+    if (!pool_.empty()) {
+      hipEvent_t e = pool_.back();
+      pool_.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  hipStream_t st_;
+  std::vector<Pend> pend_;
+  std::vector<hipEvent_t> pool_;
+  double tot_[W1_NFAM][5] = {};
+};
+
+// ---------------------------------------------------------------------------
 // Batch<T>
 // ---------------------------------------------------------------------------
 template <typename T>
 class Batch : public BatchBase {
  public:
-  Batch(int capacity, hipStream_t s) : cap_(capacity), st_(s), arena_(s) {
+  Batch(int capacity, hipStream_t s) : cap_(capacity), st_(s), arena_(s), prof_(s) {
     slots_.assign(cap_, nullptr);
     hdesc_.assign((size_t)cap_ * MAXL, SlotDesc<T>{});
     ok_ = hipMalloc((void**)&ddesc_, sizeof(SlotDesc<T>) * cap_ * MAXL) == hipSuccess &&
@@ -489,6 +572,12 @@ class Batch : public BatchBase {
     return W1_OK;
   }
 
+  void profile(bool on) override {
+    prof_.on = on;
+    prof_.reset();
+  }
+  void kernel_stats(int f, double* o) const override { prof_.stats(f, o); }
+
  private:
   int fail(int st) {
     ok_ = false;
@@ -520,8 +609,18 @@ class Batch : public BatchBase {
   int read_scalars() {
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
+    if (prof_.on) {
+      for (auto& ru : resident_pending_) {
+        double u = 0;
+        for (auto* r : ru.second) u += (double)hsc_[r->slot].iters * node_count(r->sides[r->level]);
+        prof_.set_units(ru.first, u, 0.0);
+      }
+      prof_.harvest();
+    }
+    resident_pending_.clear();
     return W1_OK;
   }
+  static double node_count(int n) { return (double)(n + 1) * (double)(n + 1); }
 
   int reset_scalars(const std::vector<Request*>& rs) {
     int st = W1_OK;
@@ -730,7 +829,15 @@ class Batch : public BatchBase {
     for (auto& kv : by_ce) {
       int* di = arena_.put(kv.second, &st);
       if (st) return st;
+      const int pi = prof_.begin();
       K<T>::plain_resident(st_, di, (int)kv.second.size(), ddesc_, dsc_, maxside, kv.first);
+      prof_.end(pi, W1_FAM_PLAIN_RESIDENT, 0, 0, 0);
+      if (pi >= 0) {
+        std::vector<Request*> rs;
+        for (auto* r : R)
+          if (r->prm.check_every == kv.first) rs.push_back(r);
+        resident_pending_.emplace_back(pi, rs);
+      }
     }
     HIPCHK(hipGetLastError());
     return W1_OK;
@@ -760,19 +867,26 @@ class Batch : public BatchBase {
       wn[S] = (int)w.size();
       return d;
     };
+    double nodes = 0;
+    for (auto* r : P) nodes += node_count(r->sides[r->level]);
+    const double wb = 7.0 * sizeof(T);  // read m1 m2 phi rho, write m1 m2 phi
     int done = 0;
     while (done < body) {
       const int S = std::min(tc.steps, body - done);
       Work* w = list_for(S);
       if (st) return st;
+      const int pi = prof_.begin();
       K<T>::plain_tiled(st_, w, wn[S], ddesc_, gpar_, S, tc.rh, false);
+      prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * S, nodes * S * wb, 0);
       gpar_ ^= 1;
       done += S;
     }
     if (any_fpr) {
       Work* w = list_for(1);
       if (st) return st;
+      const int pi = prof_.begin();
       K<T>::plain_tiled(st_, w, wn[1], ddesc_, gpar_, 1, tc.rh, true);
+      prof_.end(pi, W1_FAM_PLAIN_TILED, nodes, nodes * wb, 0);
       gpar_ ^= 1;
     }
     if (any_kkt) {
@@ -820,10 +934,22 @@ class Batch : public BatchBase {
     if (st) return st;
     bool any_kkt = false, any_fpr = false;
     for (auto* r : X) (r->prm.stop_rule == W1_STOP_FPR ? any_fpr : any_kkt) = true;
+    double nodes = 0, flops = 0;
+    for (auto* r : X) {
+      const double N = r->sides[r->level] + 1;
+      nodes += N * N;
+      flops += 4.0 * 2.0 * N * N * N;
+    }
     for (int it = 0; it < ce; ++it) {
+      int pi = prof_.begin();
       K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 0, K_PROX, gpar_);
+      prof_.end(pi, W1_FAM_PROX_ELEM, nodes, nodes * 6.0 * sizeof(T), 0);
+      pi = prof_.begin();
       poisson(dgw, (int)gw.size(), 6);
+      prof_.end(pi, W1_FAM_DCT, nodes, nodes * 8.0 * sizeof(T), flops);
+      pi = prof_.begin();
       K<T>::prox_post(st_, dsw, (int)sw.size(), ddesc_, any_fpr && it == ce - 1);
+      prof_.end(pi, W1_FAM_PROX_ELEM, 0, nodes * 13.0 * sizeof(T), 0);
     }
     if (any_kkt) {
       K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 1, K_PROX, gpar_);
@@ -932,6 +1058,8 @@ class Batch : public BatchBase {
   SlotScalars* hsc_ = nullptr;
   std::vector<int> dirty_;
   int gpar_ = 0;
+  Prof prof_;
+  std::vector<std::pair<int, std::vector<Request*>>> resident_pending_;
 };
 
 std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t stream) {

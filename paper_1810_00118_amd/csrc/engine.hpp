@@ -61,6 +61,9 @@ class BatchBase {
   virtual int release(Request* r) = 0;        // free a finished slot
   // input preparation only: rho of every level to dense caller buffers
   virtual int prep_export(Request* r, void* const* rho_out) = 0;
+  // per-family kernel timing (HIP events on the batch's stream)
+  virtual void profile(bool on) = 0;
+  virtual void kernel_stats(int family, double* out5) const = 0;
 };
 
 std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t stream);
