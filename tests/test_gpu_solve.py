@@ -27,7 +27,11 @@ def _check_parity(w1, res, fields, ref, n, metric, rho):
     ev_gpu = o.evaluate(m1, m2, psi, rho, 1.0 / n, metric)
     ev_ref = o.evaluate(ref["m1"], ref["m2"], ref["psi"], rho, 1.0 / n, metric)
     assert abs(ev_gpu["kkt"] - ev_ref["kkt"]) <= 1e-5
-    assert res["lo"] - 1e-4 * abs(ref["w1"]) <= ref["w1"] <= res["hi"] + 1e-4 * abs(ref["w1"])
+    # W1_h lies in both certified brackets, so they overlap; the oracle's own
+    # f(m^K) need not lie in the GPU bracket when m^K is not yet feasible
+    assert max(res["lo"], ref["lo"]) <= min(res["hi"], ref["hi"]) * (1 + 1e-6)
+    assert res["lo"] == pytest.approx(ref["lo"], rel=1e-4)
+    assert res["hi"] == pytest.approx(ref["hi"], rel=1e-4)
     # the library's own FP64 evaluator agrees with the oracle's on its fields
     assert res["w1"] == pytest.approx(ev_gpu["P"], rel=1e-9)
     assert res["hi"] == pytest.approx(ev_gpu["hi"], rel=1e-7)
