@@ -438,7 +438,6 @@ struct Op {
     d.rule = RULE_FPR;
     d.tol = -1.0;
     d.cap = 1 << 30;
-    d.par0 = 0;
     return W1_OK;
   }
   int dct(SlotDesc<T>& d) {
@@ -509,10 +508,10 @@ struct Op {
     return w;
   }
   void poisson(Work* gw, int ng, int dst) {
-    K<T>::gemm(st, gw, ng, dd, 0, 6, 7, 1, false);
-    K<T>::gemm(st, gw, ng, dd, 1, 7, 6, 0, true);
-    K<T>::gemm(st, gw, ng, dd, 1, 6, 7, 1, false);
-    K<T>::gemm(st, gw, ng, dd, 0, 7, dst, 0, false);
+    K<T>::gemm(st, gw, ng, dd, dsc, 0, 6, 7, 1, false, 0);
+    K<T>::gemm(st, gw, ng, dd, dsc, 1, 7, 6, 0, true, 0);
+    K<T>::gemm(st, gw, ng, dd, dsc, 1, 6, 7, 1, false, 0);
+    K<T>::gemm(st, gw, ng, dd, dsc, 0, 7, dst, 0, false, 0);
   }
   int read_scalars(SlotScalars* h) {
     HIPCHK(hipMemcpyAsync(h, dsc, sizeof(SlotScalars), hipMemcpyDeviceToHost, st));
@@ -560,34 +559,28 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, void* 
   int st = op.commit(1);
   if (st) return st;
   const int rh = sizeof(T) == 8 ? 32 : 64;
-  int T_ = block > 0 ? block : 1;
-  T_ = std::min(T_, rh / 2 - 4);
-  int gpar = 0;
-  const int body = fpr ? steps - 1 : steps;
-  int done = 0;
-  while (done < body) {
-    const int S = std::min(T_, body - done);
+  const int T_ = std::max(1, std::min(block > 0 ? block : 1, rh / 2 - 6));
+  int done = 0, li = 0, lastS = 1;
+  while (done < steps) {
+    const int S = std::min(T_, steps - done);
+    const bool chk = fpr && done + S == steps;
     auto w = op.tiled(0, n, rh, S);
     Work* dw = op.upload(w);
     if (!dw) return W1_EDEVICE;
-    K<T>::plain_tiled(s, dw, (int)w.size(), op.dd, gpar, S, rh, false);
-    gpar ^= 1;
+    K<T>::plain_tiled(s, dw, (int)w.size(), op.dd, op.dsc, li, S, rh, chk);
+    ++li;
     done += S;
+    lastS = S;
   }
   if (fpr) {
-    auto w = op.tiled(0, n, rh, 1);
-    Work* dw = op.upload(w);
-    if (!dw) return W1_EDEVICE;
-    K<T>::plain_tiled(s, dw, (int)w.size(), op.dd, gpar, 1, rh, true);
-    gpar ^= 1;
-    std::vector<int> idx{0}, nt{(int)w.size()};
+    std::vector<int> idx{0}, nt{(int)op.tiled(0, n, rh, lastS).size()};
     int* di = op.upload(idx);
     int* dn = op.upload(nt);
     if (!di || !dn) return W1_EDEVICE;
-    K<T>::check(s, di, dn, 1, op.dd, op.dsc, K_PLAIN, 1);
+    K<T>::check(s, di, dn, 1, op.dd, op.dsc, K_PLAIN, steps, li);
   }
   HIPCHK(hipGetLastError());
-  if (gpar) {  // the result is in set B: copy back to the caller's planes
+  if (li & 1) {  // the result is in set B: copy back to the caller's planes
     const size_t b = (size_t)(n + 1) * (n + 1) * sizeof(T);
     HIPCHK(hipMemcpyAsync(m1, d.p[3], b, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(m2, d.p[4], b, hipMemcpyDeviceToDevice, s));
@@ -629,16 +622,16 @@ int op_prox_steps(int n, int metric, double scale, int steps, void* m1, void* m2
   Work* dgw = op.upload(gw);
   if (!dsw || !dgw) return W1_EDEVICE;
   for (int it = 0; it < steps; ++it) {
-    K<T>::div_pre(s, dsw, (int)sw.size(), op.dd, 0, K_PROX, 0);
+    K<T>::div_pre(s, dsw, (int)sw.size(), op.dd, op.dsc, 0, K_PROX, 1);
     op.poisson(dgw, (int)gw.size(), 6);
-    K<T>::prox_post(s, dsw, (int)sw.size(), op.dd, fpr && it == steps - 1);
+    K<T>::prox_post(s, dsw, (int)sw.size(), op.dd, op.dsc, fpr && it == steps - 1);
   }
   if (fpr) {
     std::vector<int> idx{0}, nt{(int)sw.size()};
     int* di = op.upload(idx);
     int* dn = op.upload(nt);
     if (!di || !dn) return W1_EDEVICE;
-    K<T>::check(s, di, dn, 1, op.dd, op.dsc, K_PROX, 1);
+    K<T>::check(s, di, dn, 1, op.dd, op.dsc, K_PROX, steps, 0);
   }
   HIPCHK(hipGetLastError());
   SlotScalars h;
@@ -670,7 +663,7 @@ int op_poisson(int n, const void* r, void* u, const void* w1, const void* w2, hi
   Work* dgw = op.upload(gw);
   if (!dsw || !dgw) return W1_EDEVICE;
   if (w1) {
-    K<T>::div_pre(s, dsw, (int)sw.size(), op.dd, 1, K_PROX, 0);
+    K<T>::div_pre(s, dsw, (int)sw.size(), op.dd, op.dsc, 1, K_PROX, 0);
   } else {
     HIPCHK(hipMemcpyAsync(d.p[6], r, (size_t)(n + 1) * (n + 1) * sizeof(T), hipMemcpyDeviceToDevice, s));
   }
@@ -707,9 +700,9 @@ int op_evaluate(int n, int metric, const void* m1, const void* m2, const void* p
   int* di = op.upload(idx);
   int* dn = op.upload(nt);
   if (!dsw || !dgw || !di || !dn) return W1_EDEVICE;
-  K<T>::div_pre(s, dsw, (int)sw.size(), op.dd, 2, K_PROX, 0);
+  K<T>::div_pre(s, dsw, (int)sw.size(), op.dd, op.dsc, 2, K_PROX, 0);
   op.poisson(dgw, (int)gw.size(), 6);
-  K<T>::eval_sums(s, dsw, (int)sw.size(), op.dd, K_PROX, 0);
+  K<T>::eval_sums(s, dsw, (int)sw.size(), op.dd, op.dsc, K_PROX);
   K<T>::eval_final(s, di, dn, 1, op.dd, op.dsc, K_PROX);
   HIPCHK(hipGetLastError());
   SlotScalars h;
@@ -751,7 +744,7 @@ int op_prolong(int nc, const void* c1, const void* c2, const void* cp, void* f1,
   auto w = op.simple(1, 2 * nc);
   Work* dw = op.upload(w);
   if (!dw) return W1_EDEVICE;
-  K<T>::prolong(s, dw, (int)w.size(), op.dd, K_PLAIN, 0);
+  K<T>::prolong(s, dw, (int)w.size(), op.dd, op.dsc, K_PLAIN);
   HIPCHK(hipGetLastError());
   const size_t fb = (size_t)(2 * nc + 1) * (2 * nc + 1) * sizeof(T);
   if (f1) HIPCHK(hipMemcpyAsync(f1, f.p[0], fb, hipMemcpyDeviceToDevice, s));

@@ -79,18 +79,23 @@ size_t request_bytes(const w1_params& p) {
 }
 
 // Temporal-block depth and region height of the plain tiled kernel.  Deep
-// blocks cut HBM traffic per iteration; the halo recomputation grows as
-// (RH+2T)/RH * (128+2T)/128, so the depth is bounded by the region.
-TileChoice choose_tiles(int precision, int side, int nslots, int check_every, int requested) {
+// blocks cut HBM traffic and launches per iteration; the halo recomputation
+// grows as RH/(RH-2T) * 128/(128-2T).  Large active sets (HBM-bound) take a
+// moderate depth, small ones (latency-bound) the deepest depth that divides
+// the stop-test cadence, so a block of check_every iterations is whole
+// launches and its last launch carries the stop test.
+TileChoice choose_tiles(int precision, double active_nodes, int check_every, int requested) {
   TileChoice c;
   c.rh = precision == W1_FP64 ? 32 : 64;
-  int T = requested > 0 ? requested : (precision == W1_FP64 ? 2 : 6);
-  const int maxT = c.rh / 2 - 4;
-  if (T > maxT) T = maxT;
-  if (T < 1) T = 1;
-  (void)side;
-  (void)nslots;
-  (void)check_every;
+  const int maxT = c.rh / 2 - 6;                // keep half the region as output
+  int want = requested > 0 ? requested : (precision == W1_FP64 ? 2 : (active_nodes > 4.0e6 ? 5 : 10));
+  want = std::min(want, maxT);
+  int T = 1;
+  for (int t = std::min(want, check_every); t >= 1; --t)
+    if (check_every % t == 0) {
+      T = t;
+      break;
+    }
   c.steps = T;
   return c;
 }
@@ -348,6 +353,7 @@ class Batch : public BatchBase {
     (void)hipStreamSynchronize(st_);
     for (auto* r : slots_)
       if (r && r->mem) g_blocks.put(r->bytes, r->mem);
+    for (auto& kv : lists_) (void)hipFree(kv.second.d);
     (void)hipFree(ddesc_);
     (void)hipFree(dsc_);
     (void)hipHostFree(hsc_);
@@ -374,7 +380,6 @@ class Batch : public BatchBase {
     if (st) return st;
     r->slot = slot;
     slots_[slot] = r;
-    // carve the block
     const int L = r->prm.levels;
     char* p = r->mem;
     for (int l = 0; l < L; ++l) {
@@ -399,7 +404,7 @@ class Batch : public BatchBase {
       double mu, tau;
       const double sc = r->prm.step_scale > 0 ? r->prm.step_scale : 0.5;
       if (r->kind == K_PLAIN) {
-        mu = tau = sc / (2.0 * std::sqrt(2.0) / d.h);
+        mu = tau = sc / (2.0 * std::sqrt(2.0) / d.h);   // scale / (Gershgorin bound of ||A||)
       } else {
         mu = tau = sc;
       }
@@ -413,7 +418,6 @@ class Batch : public BatchBase {
       if (d.rule == RULE_FPR && tolL <= 0) tolL = paper_eps(r->prm.algo, r->prm.n, L > 1);
       d.tol = tolL * std::pow(2.0, (double)(L - 1 - l) * r->prm.alpha);
       d.cap = r->prm.max_iters;
-      d.par0 = 0;
       if (r->kind == K_PROX || l == L - 1) {
         DctTab t;
         st = dct_tables<T>(nl + 1, &t);
@@ -430,11 +434,15 @@ class Batch : public BatchBase {
     p += align256(ne * 8);
     double* in1 = (double*)p;
     p += align256(ne * 8);
+    double* psi = (double*)p;
     for (int l = 0; l < L; ++l) hdesc_[(size_t)slot * MAXL + l].part = part;
     SlotDesc<T>& fin = hdesc_[(size_t)slot * MAXL + L - 1];
     fin.in0 = in0;
     fin.in1 = in1;
-    // the caller's buffers are consumed before returning
+    // the inputs are consumed by the preparation, so the fields reuse them
+    fin.out_m1 = in0;
+    fin.out_m2 = in1;
+    fin.out_psi = psi;
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpyAsync(in0, p0, ne * 8, kind, st_));
     HIPCHK(hipMemcpyAsync(in1, p1, ne * 8, kind, st_));
@@ -444,6 +452,7 @@ class Batch : public BatchBase {
     r->res = w1_result{};
     r->t_admit = now_seconds();
     dirty_.push_back(slot);
+    ++gen_;
     return W1_OK;
   }
 
@@ -451,7 +460,6 @@ class Batch : public BatchBase {
     if (!ok_) return W1_EDEVICE;
     arena_.reset();
     int st = W1_OK;
-    // ---- preparation of newly admitted solves ----
     std::vector<Request*> prep;
     for (auto* r : slots_)
       if (r && r->state == Request::PREP) prep.push_back(r);
@@ -459,32 +467,39 @@ class Batch : public BatchBase {
       st = run_prep(prep);
       if (st) return fail(st);
     }
-    // ---- one block of the current level for every running solve ----
-    std::vector<Request*> R, P, X;
+    std::vector<Request*> R;
+    std::map<std::pair<int, int>, std::vector<Request*>> P, X;   // by (check_every, rule)
     for (auto* r : slots_) {
       if (!r || r->state != Request::RUN) continue;
-      if (r->kind == K_PROX) X.push_back(r);
+      const auto key = std::make_pair(r->prm.check_every, r->prm.stop_rule);
+      if (r->kind == K_PROX) X[key].push_back(r);
       else if (r->resident_level) R.push_back(r);
-      else P.push_back(r);
+      else P[key].push_back(r);
     }
+    if (R.empty() && P.empty() && X.empty()) return W1_OK;
     st = flush_desc();
     if (st) return fail(st);
     if (!R.empty()) {
       st = launch_resident(R);
       if (st) return fail(st);
     }
-    if (!P.empty()) {
-      st = launch_tiled_block(P);
-      if (st) return fail(st);
+    // several iteration blocks per host synchronisation: slots that stop
+    // inside the pipeline are skipped by the gated kernels
+    const int nblocks = (P.empty() && X.empty()) ? 0 : blocks_per_sync_;
+    for (int b = 0; b < nblocks; ++b) {
+      int gi = 0;
+      for (auto& kv : P) {
+        st = launch_tiled_block(kv.second, gi++);
+        if (st) return fail(st);
+      }
+      gi = 0;
+      for (auto& kv : X) {
+        st = launch_prox_block(kv.second, gi++);
+        if (st) return fail(st);
+      }
     }
-    if (!X.empty()) {
-      st = launch_prox_block(X);
-      if (st) return fail(st);
-    }
-    if (R.empty() && P.empty() && X.empty()) return W1_OK;
     st = read_scalars();
     if (st) return fail(st);
-    // ---- level transitions ----
     std::vector<Request*> up, fin;
     auto consider = [&](Request* r) {
       const SlotScalars& s = hsc_[r->slot];
@@ -493,10 +508,6 @@ class Batch : public BatchBase {
       r->res.iters[l] = s.iters;
       r->res.measure[l] = s.measure;
       r->res.levels_run = l + 1;
-      if (r->resident_level) {  // the resident kernel leaves the level in set A
-        hdesc_[(size_t)r->slot * MAXL + l].par0 = gpar_;
-        dirty_.push_back(r->slot);
-      }
       if (s.status == ST_DIVERGED) {
         r->res.status = W1_SOLVE_DIVERGED;
         fin.push_back(r);
@@ -507,10 +518,10 @@ class Batch : public BatchBase {
       else fin.push_back(r);
     };
     for (auto* r : R) consider(r);
-    for (auto* r : P) consider(r);
-    for (auto* r : X) consider(r);
-    st = flush_desc();
-    if (st) return fail(st);
+    for (auto& kv : P)
+      for (auto* r : kv.second) consider(r);
+    for (auto& kv : X)
+      for (auto* r : kv.second) consider(r);
     if (!up.empty()) {
       st = advance_levels(up);
       if (st) return fail(st);
@@ -533,10 +544,10 @@ class Batch : public BatchBase {
     r->f_m1.resize(ne);
     r->f_m2.resize(ne);
     r->f_psi.resize(ne);
-    const SlotDesc<T>& fin = hdesc_[(size_t)r->slot * MAXL + r->prm.levels - 1];
-    HIPCHK(hipMemcpyAsync(r->f_m1.data(), fin.in0, ne * 8, hipMemcpyDeviceToHost, st_));
-    HIPCHK(hipMemcpyAsync(r->f_m2.data(), fin.in1, ne * 8, hipMemcpyDeviceToHost, st_));
-    HIPCHK(hipMemcpyAsync(r->f_psi.data(), psi_stage(r), ne * 8, hipMemcpyDeviceToHost, st_));
+    const SlotDesc<T>& fin = hdesc_[didx(r, r->prm.levels - 1)];
+    HIPCHK(hipMemcpyAsync(r->f_m1.data(), fin.out_m1, ne * 8, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipMemcpyAsync(r->f_m2.data(), fin.out_m2, ne * 8, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipMemcpyAsync(r->f_psi.data(), fin.out_psi, ne * 8, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
     r->fields_ready = true;
     return W1_OK;
@@ -549,6 +560,7 @@ class Batch : public BatchBase {
       r->mem = nullptr;
       slots_[r->slot] = nullptr;
       r->slot = -1;
+      ++gen_;
     }
     return W1_OK;
   }
@@ -585,11 +597,7 @@ class Batch : public BatchBase {
   }
   size_t didx(const Request* r, int l) const { return (size_t)r->slot * MAXL + l; }
   int dx(const Request* r, int l) const { return r->slot * MAXL + l; }
-  double* psi_stage(const Request* r) const {
-    const SlotDesc<T>& fin = hdesc_[didx(r, r->prm.levels - 1)];
-    const size_t ne = (size_t)(r->prm.n + 1) * (r->prm.n + 1);
-    return (double*)((char*)fin.in1 + align256(ne * 8));
-  }
+  static double node_count(int n) { return (double)(n + 1) * (double)(n + 1); }
 
   int flush_desc() {
     int st = W1_OK;
@@ -620,8 +628,8 @@ class Batch : public BatchBase {
     resident_pending_.clear();
     return W1_OK;
   }
-  static double node_count(int n) { return (double)(n + 1) * (double)(n + 1); }
 
+  // status RUN, iteration 0, iterate in plane set A
   int reset_scalars(const std::vector<Request*>& rs) {
     int st = W1_OK;
     for (auto* r : rs) {
@@ -639,22 +647,24 @@ class Batch : public BatchBase {
   // XCD-aware order: the launch's workgroup i runs on XCD i mod 8, so each
   // XCD receives spatially contiguous tiles (a slot's row band, or whole
   // slots when there are many) and halo re-reads hit its own L2.
-  std::vector<Work> order_xcd(std::vector<std::vector<Work>>& q) {
+  static std::vector<Work> order_xcd(std::vector<std::vector<Work>>& q) {
     size_t mx = 0;
     for (auto& v : q) mx = std::max(mx, v.size());
     std::vector<Work> out;
     out.reserve(mx * 8);
     for (size_t k = 0; k < mx; ++k)
       for (int x = 0; x < 8; ++x) out.push_back(k < q[x].size() ? q[x][k] : make_int4(-1, 0, 0, 0));
+    // trailing padding carries no work: drop it
+    while (!out.empty() && out.back().x < 0) out.pop_back();
     return out;
   }
-
-  std::vector<Work> simple_work(const std::vector<std::pair<Request*, int>>& lv) {
+  template <typename F>
+  std::vector<Work> make_work(const std::vector<std::pair<Request*, int>>& lv, F tiles) {
     std::vector<std::vector<Work>> q(8);
     int rank = 0;
     for (auto& e : lv) {
-      const int n = e.first->sides[e.second];
-      const int ti = simple_ti(n), tj = simple_tj(n);
+      int ti, tj;
+      tiles(e.first->sides[e.second], &ti, &tj);
       for (int a = 0; a < ti; ++a)
         for (int b = 0; b < tj; ++b) {
           const int x = lv.size() >= 8 ? rank % 8 : (a * 8) / ti;
@@ -664,34 +674,20 @@ class Batch : public BatchBase {
     }
     return order_xcd(q);
   }
-  std::vector<Work> gemm_work(const std::vector<std::pair<Request*, int>>& lv) {
-    std::vector<std::vector<Work>> q(8);
-    int rank = 0;
-    for (auto& e : lv) {
-      const int t = gemm_t(e.first->sides[e.second]);
-      for (int a = 0; a < t; ++a)
-        for (int b = 0; b < t; ++b) {
-          const int x = lv.size() >= 8 ? rank % 8 : (a * 8) / t;
-          q[x].push_back(make_int4(dx(e.first, e.second), a, b, a * t + b));
-        }
-      ++rank;
-    }
-    return order_xcd(q);
+  std::vector<Work> simple_work(const std::vector<std::pair<Request*, int>>& lv) {
+    return make_work(lv, [](int n, int* ti, int* tj) {
+      *ti = simple_ti(n);
+      *tj = simple_tj(n);
+    });
   }
-  std::vector<Work> tiled_work(const std::vector<Request*>& rs, int rh, int S) {
-    std::vector<std::vector<Work>> q(8);
-    int rank = 0;
-    for (auto* r : rs) {
-      const int n = r->sides[r->level];
-      const int ti = tiled_ti(n, rh, S), tj = tiled_tj(n, S);
-      for (int a = 0; a < ti; ++a)
-        for (int b = 0; b < tj; ++b) {
-          const int x = rs.size() >= 8 ? rank % 8 : (a * 8) / ti;
-          q[x].push_back(make_int4(dx(r, r->level), a, b, a * tj + b));
-        }
-      ++rank;
-    }
-    return order_xcd(q);
+  std::vector<Work> gemm_work(const std::vector<std::pair<Request*, int>>& lv) {
+    return make_work(lv, [](int n, int* ti, int* tj) { *ti = *tj = gemm_t(n); });
+  }
+  std::vector<Work> tiled_work(const std::vector<std::pair<Request*, int>>& lv, int rh, int S) {
+    return make_work(lv, [rh, S](int n, int* ti, int* tj) {
+      *ti = tiled_ti(n, rh, S);
+      *tj = tiled_tj(n, S);
+    });
   }
   static std::vector<std::pair<Request*, int>> at_level(const std::vector<Request*>& rs) {
     std::vector<std::pair<Request*, int>> v;
@@ -702,6 +698,43 @@ class Batch : public BatchBase {
     std::vector<std::pair<Request*, int>> v;
     for (auto* r : rs) v.emplace_back(r, r->prm.levels - 1);
     return v;
+  }
+
+  // device lists cached until the set of running slots or their levels
+  // change (generation counter); staged through the per-step arena
+  struct DevList {
+    void* d = nullptr;
+    size_t cap = 0;
+    int n = 0;
+    uint64_t gen = ~0ull;
+  };
+  template <typename X, typename F>
+  X* cached(const std::string& key, F build, int* count, int* status) {
+    DevList& L = lists_[key];
+    if (L.gen != gen_) {
+      std::vector<X> v = build();
+      const size_t bytes = std::max<size_t>(v.size() * sizeof(X), 16);
+      if (bytes > L.cap) {
+        (void)hipFree(L.d);  // no kernel of this step has used it yet
+        L.cap = bytes * 2;
+        if (hipMalloc(&L.d, L.cap) != hipSuccess) {
+          L.d = nullptr;
+          L.cap = 0;
+          *status = W1_ENOMEM;
+          return nullptr;
+        }
+      }
+      X* src = arena_.put(v, status);
+      if (*status) return nullptr;
+      if (hipMemcpyAsync(L.d, src, v.size() * sizeof(X), hipMemcpyDeviceToDevice, st_) != hipSuccess) {
+        *status = W1_EDEVICE;
+        return nullptr;
+      }
+      L.n = (int)v.size();
+      L.gen = gen_;
+    }
+    *count = L.n;
+    return (X*)L.d;
   }
 
   int reduce_lists(const std::vector<std::pair<Request*, int>>& lv, int (*tiles)(int), int** didx_out,
@@ -722,7 +755,6 @@ class Batch : public BatchBase {
   // -- preparation: masses -> rho pyramid (Sec. 2.2, restriction) --------
   int run_prep(std::vector<Request*>& prep) {
     int st = W1_OK;
-    // descriptors of the new slots must be on the device first
     st = flush_desc();
     if (st) return st;
     auto fin = at_finest(prep);
@@ -737,8 +769,8 @@ class Batch : public BatchBase {
       K<T>::reduce(st_, di, dn, (int)fin.size(), ddesc_, dsc_, 3, 0, 0u);
       HIPCHK(hipGetLastError());
     }
-    st = read_scalars();
-    if (st) return st;
+    HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
     std::vector<Request*> good;
     for (auto* r : prep) {
       const SlotScalars& s = hsc_[r->slot];
@@ -749,6 +781,7 @@ class Batch : public BatchBase {
         r->res.w1 = r->res.dual = r->res.lo = r->res.hi = r->res.kkt = NAN;
         r->state = Request::DONE;
         r->res.seconds = now_seconds() - r->t_submit;
+        ++gen_;
       } else {
         good.push_back(r);
       }
@@ -794,7 +827,6 @@ class Batch : public BatchBase {
       auto w = simple_work(lv);
       Work* dw = arena_.put(w, &st);
       if (st) return st;
-      // plain: set A; prox: m, vphi, vphibar
       unsigned mask = 0;
       for (auto* r : good) mask |= r->kind == K_PLAIN ? 0x7u : 0x3Fu;
       K<T>::zero(st_, dw, (int)w.size(), ddesc_, mask);
@@ -809,17 +841,15 @@ class Batch : public BatchBase {
     r->level = l;
     r->state = Request::RUN;
     r->t_level = now_seconds();
-    SlotDesc<T>& d = hdesc_[didx(r, l)];
-    d.par0 = gpar_;
     const bool allow = !(r->prm.flags & W1_FLAG_NO_RESIDENT);
     r->resident_level = r->kind == K_PLAIN && allow && (r->sides[l] + 1) <= K<T>::plain_resident_max_side();
     dirty_.push_back(r->slot);
+    ++gen_;
   }
 
   // -- plain: resident levels ---------------------------------------------
   int launch_resident(std::vector<Request*>& R) {
     int st = W1_OK;
-    std::vector<int> idx;
     int maxside = 0;
     std::map<int, std::vector<int>> by_ce;
     for (auto* r : R) {
@@ -844,96 +874,86 @@ class Batch : public BatchBase {
   }
 
   // -- plain: one block of check_every iterations, tiled -------------------
-  int launch_tiled_block(std::vector<Request*>& P) {
+  int launch_tiled_block(std::vector<Request*>& P, int group) {
     int st = W1_OK;
-    int maxside = 0, ce = P[0]->prm.check_every, req_T = P[0]->prm.block_steps;
-    bool any_kkt = false, any_fpr = false;
-    for (auto* r : P) {
-      maxside = std::max(maxside, r->sides[r->level]);
-      (r->prm.stop_rule == W1_STOP_FPR ? any_fpr : any_kkt) = true;
-    }
-    const int prec = sizeof(T) == 8 ? W1_FP64 : W1_FP32;
-    TileChoice tc = choose_tiles(prec, maxside, (int)P.size(), ce, req_T);
-    // FPR needs the last step in a single-step checking launch
-    const int body = any_fpr ? ce - 1 : ce;
-    std::map<int, Work*> wl;
-    std::map<int, int> wn;
-    auto list_for = [&](int S) -> Work* {
-      auto it = wl.find(S);
-      if (it != wl.end()) return it->second;
-      auto w = tiled_work(P, tc.rh, S);
-      Work* d = arena_.put(w, &st);
-      wl[S] = d;
-      wn[S] = (int)w.size();
-      return d;
-    };
+    const int ce = P[0]->prm.check_every;
+    const bool fpr = P[0]->prm.stop_rule == W1_STOP_FPR;
     double nodes = 0;
     for (auto* r : P) nodes += node_count(r->sides[r->level]);
+    const int prec = sizeof(T) == 8 ? W1_FP64 : W1_FP32;
+    const TileChoice tc = choose_tiles(prec, nodes, ce, P[0]->prm.block_steps);
+    const int nl = ce / tc.steps;   // choose_tiles returns a divisor of ce
+    auto lv = at_level(P);
+    const std::string key = "P" + std::to_string(group) + "_" + std::to_string(tc.rh) + "_" + std::to_string(tc.steps);
+    int nw = 0;
+    Work* w = cached<Work>(key, [&] { return tiled_work(lv, tc.rh, tc.steps); }, &nw, &st);
+    if (st) return st;
     const double wb = 7.0 * sizeof(T);  // read m1 m2 phi rho, write m1 m2 phi
-    int done = 0;
-    while (done < body) {
-      const int S = std::min(tc.steps, body - done);
-      Work* w = list_for(S);
-      if (st) return st;
+    for (int li = 0; li < nl; ++li) {
+      const bool chk = fpr && li == nl - 1;
       const int pi = prof_.begin();
-      K<T>::plain_tiled(st_, w, wn[S], ddesc_, gpar_, S, tc.rh, false);
-      prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * S, nodes * S * wb, 0);
-      gpar_ ^= 1;
-      done += S;
+      K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, li, tc.steps, tc.rh, chk);
+      prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * tc.steps, nodes * tc.steps * wb, 0);
     }
-    if (any_fpr) {
-      Work* w = list_for(1);
+    int ns = 0;
+    int* di;
+    int* dn;
+    if (!fpr) {
+      int nsw = 0;
+      Work* sw = cached<Work>(key + "_s", [&] { return simple_work(lv); }, &nsw, &st);
       if (st) return st;
-      const int pi = prof_.begin();
-      K<T>::plain_tiled(st_, w, wn[1], ddesc_, gpar_, 1, tc.rh, true);
-      prof_.end(pi, W1_FAM_PLAIN_TILED, nodes, nodes * wb, 0);
-      gpar_ ^= 1;
+      K<T>::kkt(st_, sw, nsw, ddesc_, dsc_, K_PLAIN, nl & 1, 1);
+      di = cached<int>(key + "_i", [&] {
+        std::vector<int> v;
+        for (auto* r : P) v.push_back(dx(r, r->level));
+        return v;
+      }, &ns, &st);
+      dn = cached<int>(key + "_ns", [&] {
+        std::vector<int> v;
+        for (auto* r : P) v.push_back(simple_tiles(r->sides[r->level]));
+        return v;
+      }, &ns, &st);
+    } else {
+      di = cached<int>(key + "_i", [&] {
+        std::vector<int> v;
+        for (auto* r : P) v.push_back(dx(r, r->level));
+        return v;
+      }, &ns, &st);
+      dn = cached<int>(key + "_nt", [&] {
+        std::vector<int> v;
+        for (auto* r : P) {
+          const int n = r->sides[r->level];
+          v.push_back(tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.steps));
+        }
+        return v;
+      }, &ns, &st);
     }
-    if (any_kkt) {
-      auto lv = at_level(P);
-      auto w = simple_work(lv);
-      Work* dw = arena_.put(w, &st);
-      if (st) return st;
-      K<T>::kkt(st_, dw, (int)w.size(), ddesc_, K_PLAIN, gpar_);
-    }
-    // stop test: FPR partials come from the checking launch's tiles, KKT
-    // partials from the simple tiles
-    std::vector<int> idx, nt;
-    for (auto* r : P) {
-      const int n = r->sides[r->level];
-      idx.push_back(dx(r, r->level));
-      nt.push_back(r->prm.stop_rule == W1_STOP_FPR ? tiled_ti(n, tc.rh, 1) * tiled_tj(n, 1) : simple_tiles(n));
-    }
-    int* di = arena_.put(idx, &st);
     if (st) return st;
-    int* dn = arena_.put(nt, &st);
-    if (st) return st;
-    K<T>::check(st_, di, dn, (int)P.size(), ddesc_, dsc_, K_PLAIN, ce);
+    K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PLAIN, ce, nl);
     HIPCHK(hipGetLastError());
     return W1_OK;
   }
 
   // -- Poisson solve through four DCT passes ------------------------------
-  void poisson(Work* gw, int ng, int dst) {
-    K<T>::gemm(st_, gw, ng, ddesc_, 0, 6, 7, 1, false);   // rows:    X C^T
-    K<T>::gemm(st_, gw, ng, ddesc_, 1, 7, 6, 0, true);    // columns: C X, / lambda
-    K<T>::gemm(st_, gw, ng, ddesc_, 1, 6, 7, 1, false);   // columns: C^T X
-    K<T>::gemm(st_, gw, ng, ddesc_, 0, 7, dst, 0, false); // rows:    X C
+  void poisson(Work* gw, int ng, int dst, int gate) {
+    K<T>::gemm(st_, gw, ng, ddesc_, dsc_, 0, 6, 7, 1, false, gate);   // rows:    X C^T
+    K<T>::gemm(st_, gw, ng, ddesc_, dsc_, 1, 7, 6, 0, true, gate);    // columns: C X, / lambda
+    K<T>::gemm(st_, gw, ng, ddesc_, dsc_, 1, 6, 7, 1, false, gate);   // columns: C^T X
+    K<T>::gemm(st_, gw, ng, ddesc_, dsc_, 0, 7, dst, 0, false, gate); // rows:    X C
   }
 
   // -- prox: one block of check_every iterations ---------------------------
-  int launch_prox_block(std::vector<Request*>& X) {
+  int launch_prox_block(std::vector<Request*>& X, int group) {
     int st = W1_OK;
     const int ce = X[0]->prm.check_every;
+    const bool fpr = X[0]->prm.stop_rule == W1_STOP_FPR;
     auto lv = at_level(X);
-    auto sw = simple_work(lv);
-    auto gw = gemm_work(lv);
-    Work* dsw = arena_.put(sw, &st);
+    const std::string key = "X" + std::to_string(group);
+    int nsw = 0, ngw = 0, ns = 0;
+    Work* dsw = cached<Work>(key + "_s", [&] { return simple_work(lv); }, &nsw, &st);
     if (st) return st;
-    Work* dgw = arena_.put(gw, &st);
+    Work* dgw = cached<Work>(key + "_g", [&] { return gemm_work(lv); }, &ngw, &st);
     if (st) return st;
-    bool any_kkt = false, any_fpr = false;
-    for (auto* r : X) (r->prm.stop_rule == W1_STOP_FPR ? any_fpr : any_kkt) = true;
     double nodes = 0, flops = 0;
     for (auto* r : X) {
       const double N = r->sides[r->level] + 1;
@@ -942,24 +962,33 @@ class Batch : public BatchBase {
     }
     for (int it = 0; it < ce; ++it) {
       int pi = prof_.begin();
-      K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 0, K_PROX, gpar_);
+      K<T>::div_pre(st_, dsw, nsw, ddesc_, dsc_, 0, K_PROX, 1);
       prof_.end(pi, W1_FAM_PROX_ELEM, nodes, nodes * 6.0 * sizeof(T), 0);
       pi = prof_.begin();
-      poisson(dgw, (int)gw.size(), 6);
+      poisson(dgw, ngw, 6, 1);
       prof_.end(pi, W1_FAM_DCT, nodes, nodes * 8.0 * sizeof(T), flops);
       pi = prof_.begin();
-      K<T>::prox_post(st_, dsw, (int)sw.size(), ddesc_, any_fpr && it == ce - 1);
+      K<T>::prox_post(st_, dsw, nsw, ddesc_, dsc_, fpr && it == ce - 1);
       prof_.end(pi, W1_FAM_PROX_ELEM, 0, nodes * 13.0 * sizeof(T), 0);
     }
-    if (any_kkt) {
-      K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 1, K_PROX, gpar_);
-      poisson(dgw, (int)gw.size(), 8);
-      K<T>::kkt(st_, dsw, (int)sw.size(), ddesc_, K_PROX, gpar_);
+    if (!fpr) {
+      K<T>::div_pre(st_, dsw, nsw, ddesc_, dsc_, 1, K_PROX, 1);
+      poisson(dgw, ngw, 8, 1);
+      K<T>::kkt(st_, dsw, nsw, ddesc_, dsc_, K_PROX, 0, 1);
     }
-    int *di, *dn;
-    st = reduce_lists(lv, simple_tiles_f, &di, &dn);
+    int* di = cached<int>(key + "_i", [&] {
+      std::vector<int> v;
+      for (auto* r : X) v.push_back(dx(r, r->level));
+      return v;
+    }, &ns, &st);
     if (st) return st;
-    K<T>::check(st_, di, dn, (int)X.size(), ddesc_, dsc_, K_PROX, ce);
+    int* dn = cached<int>(key + "_n", [&] {
+      std::vector<int> v;
+      for (auto* r : X) v.push_back(simple_tiles(r->sides[r->level]));
+      return v;
+    }, &ns, &st);
+    if (st) return st;
+    K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PROX, ce, 0);
     HIPCHK(hipGetLastError());
     return W1_OK;
   }
@@ -967,12 +996,8 @@ class Batch : public BatchBase {
   // -- next level: prolongation (Sec. 3.3) ---------------------------------
   int advance_levels(std::vector<Request*>& up) {
     int st = W1_OK;
-    std::vector<std::pair<Request*, int>> lv;
     std::vector<Request*> plain, prox;
-    for (auto* r : up) {
-      lv.emplace_back(r, r->level + 1);
-      (r->kind == K_PLAIN ? plain : prox).push_back(r);
-    }
+    for (auto* r : up) (r->kind == K_PLAIN ? plain : prox).push_back(r);
     for (auto* r : up) start_level(r, r->level + 1);
     st = flush_desc();
     if (st) return st;
@@ -982,7 +1007,7 @@ class Batch : public BatchBase {
       auto w = simple_work(at_level(grp));
       Work* dw = arena_.put(w, &st);
       if (st) return st;
-      K<T>::prolong(st_, dw, (int)w.size(), ddesc_, pass == 0 ? K_PLAIN : K_PROX, gpar_);
+      K<T>::prolong(st_, dw, (int)w.size(), ddesc_, dsc_, pass == 0 ? K_PLAIN : K_PROX);
     }
     st = reset_scalars(up);
     if (st) return st;
@@ -1007,30 +1032,21 @@ class Batch : public BatchBase {
       Work* dgw = arena_.put(gw, &st);
       if (st) return st;
       if (kind == K_PROX) {
-        K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 1, kind, gpar_);
-        poisson(dgw, (int)gw.size(), 8);
+        K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 1, kind, 0);
+        poisson(dgw, (int)gw.size(), 8, 0);
       }
-      K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, 2, kind, gpar_);
-      poisson(dgw, (int)gw.size(), 6);
-      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, kind, gpar_);
+      K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 2, kind, 0);
+      poisson(dgw, (int)gw.size(), 6, 0);
+      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind);
       int *di, *dn;
       st = reduce_lists(lv, simple_tiles_f, &di, &dn);
       if (st) return st;
       K<T>::eval_final(st_, di, dn, (int)grp.size(), ddesc_, dsc_, kind);
-      // fields to the FP64 staging planes (reused input area)
-      for (auto* r : grp) {
-        std::vector<std::pair<Request*, int>> one{{r, r->prm.levels - 1}};
-        auto w1l = simple_work(one);
-        Work* dw = arena_.put(w1l, &st);
-        if (st) return st;
-        const SlotDesc<T>& f = hdesc_[didx(r, r->prm.levels - 1)];
-        K<T>::export_fields(st_, dw, (int)w1l.size(), ddesc_, dsc_, kind, gpar_, (double*)f.in0, (double*)f.in1,
-                            psi_stage(r));
-      }
+      K<T>::export_fields(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind);
       HIPCHK(hipGetLastError());
     }
-    st = read_scalars();
-    if (st) return st;
+    HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
     const double t = now_seconds();
     for (auto* r : fin) {
       const SlotScalars& s = hsc_[r->slot];
@@ -1044,6 +1060,7 @@ class Batch : public BatchBase {
       r->state = Request::DONE;
       r->fields_ready = false;
     }
+    ++gen_;
     return W1_OK;
   }
 
@@ -1057,7 +1074,9 @@ class Batch : public BatchBase {
   SlotScalars* dsc_ = nullptr;
   SlotScalars* hsc_ = nullptr;
   std::vector<int> dirty_;
-  int gpar_ = 0;
+  uint64_t gen_ = 0;
+  std::map<std::string, DevList> lists_;
+  int blocks_per_sync_ = 8;
   Prof prof_;
   std::vector<std::pair<int, std::vector<Request*>>> resident_pending_;
 };

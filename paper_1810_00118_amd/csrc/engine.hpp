@@ -73,6 +73,6 @@ struct TileChoice {
   int rh;      // region rows (32 or 64)
   int steps;   // temporal block depth
 };
-TileChoice choose_tiles(int precision, int side, int nslots, int check_every, int requested);
+TileChoice choose_tiles(int precision, double active_nodes, int check_every, int requested);
 
 }  // namespace w1

@@ -383,14 +383,14 @@ __device__ __forceinline__ T pro_e2_(const T* c, int pc, int I, int J) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
-                                                 int kind, int gpar) {
+                                                 const SlotScalars* __restrict__ scal, int kind) {
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
   const SlotDesc<T>& d = desc[w.x];
   const SlotDesc<T>& c = desc[w.x - 1];
   const int pc = c.pitch, nf = d.n;
   if (kind == K_PLAIN) {
-    const int cs = (gpar ^ c.par0) & 1;
+    const int cs = scal[w.x / MAXL].cur & 1;
     const T* c1 = c.p[3 * cs];
     const T* c2 = c.p[3 * cs + 1];
     const T* cp = c.p[3 * cs + 2];
@@ -419,17 +419,17 @@ __global__ __launch_bounds__(256) void k_prolong(const Work* __restrict__ work, 
 // `steps` nodes on every side) into LDS, runs `steps` iterations there and
 // writes the (RH - 2 steps) x (128 - 2 steps) interior.  After s steps the
 // flux is valid on rows [s-1, RH-1-s] and the potential on [s, RH-1-s]
-// (same for columns), so the interior is exact.  Reads plane set
-// cur = gpar ^ par0 and writes the other one.  Every thread owns 8 rows x 2
-// columns of the region (256 threads for RH = 32, 512 for RH = 64).
-// With CHECK (launched with steps = 1 only) the epilogue also produces the
-// FPR partials of eq. (pd_stop) for the interior: sum |dm|^2, sum dphi^2,
-// sum dphi * A dm, count of non-finite values; the previous iterate is
-// re-read from the source planes.
+// (same for columns), so the interior is exact.  The launch with index li
+// inside a block reads plane set cur ^ (li & 1) and writes the other one.
+// Every thread owns 8 rows x 2 columns of the region (256 threads for
+// RH = 32, 512 for RH = 64).  The last step is peeled off the loop; with
+// CHECK it also produces the FPR partials of eq. (pd_stop) over the
+// interior: sum |dm|^2, sum dphi^2, sum dphi * A dm, non-finite count.
 // ---------------------------------------------------------------------------
 template <typename T, int RH, bool CHECK>
 __global__ __launch_bounds__(RH * 8) void k_plain_tiled(const Work* __restrict__ work,
-                                                        const SlotDesc<T>* __restrict__ desc, int gpar, int steps) {
+                                                        const SlotDesc<T>* __restrict__ desc,
+                                                        const SlotScalars* __restrict__ scal, int li, int steps) {
   constexpr int RW = TILED_RW, NTH = RH * 8, NWV = NTH / 64, NR = RH / NWV, NC = RW / 64;
   static_assert(NR == 8, "8 rows per thread");
   __shared__ T Lp[RH * RW];
@@ -438,11 +438,13 @@ __global__ __launch_bounds__(RH * 8) void k_plain_tiled(const Work* __restrict__
   __shared__ double lds[NWV * NQ];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
+  const SlotScalars& sc = scal[w.x / MAXL];
+  if (sc.status != ST_RUN) return;
   const SlotDesc<T>& d = desc[w.x];
   const int n = d.n, pitch = d.pitch, S = steps;
   const int OH = RH - 2 * S, OW = RW - 2 * S;
   const int gi0 = w.y * OH - S, gj0 = w.z * OW - S;
-  const int rs = (gpar ^ d.par0) & 1, ws = rs ^ 1;
+  const int rs = (sc.cur ^ li) & 1, ws = rs ^ 1;
   const T* __restrict__ sm1 = d.p[3 * rs];
   const T* __restrict__ sm2 = d.p[3 * rs + 1];
   const T* __restrict__ sph = d.p[3 * rs + 2];
@@ -467,58 +469,65 @@ __global__ __launch_bounds__(RH * 8) void k_plain_tiled(const Work* __restrict__
     }
   __syncthreads();
 
-  for (int s = 0; s < S; ++s) {
-#pragma unroll
-    for (int a = 0; a < NR; ++a)
-#pragma unroll
-      for (int b = 0; b < NC; ++b) {
-        const int r = wv + NWV * a, c = lane + 64 * b;
-        const int gi = gi0 + r, gj = gj0 + c;
-        const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
-        const T pc = Lp[r * RW + c];
-        const T pd = (r + 1 < RH) ? Lp[(r + 1) * RW + c] : pc;
-        const T pr = (c + 1 < RW) ? Lp[r * RW + c + 1] : pc;
-        T n1, n2;
-        plain_flux_(m1[a][b], m2[a][b], pc, pd, pr, gi < n && r + 1 < RH, gj < n && c + 1 < RW, ih, mu,
-                    metric, n1, n2);
-        if (!in) { n1 = T(0); n2 = T(0); }
-        L1[r * RW + c] = (n1 + n1) - m1[a][b];
-        L2[r * RW + c] = (n2 + n2) - m2[a][b];
-        m1[a][b] = n1;
-        m2[a][b] = n2;
-      }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < NR; ++a)
-#pragma unroll
-      for (int b = 0; b < NC; ++b) {
-        const int r = wv + NWV * a, c = lane + 64 * b;
-        const int gi = gi0 + r, gj = gj0 + c;
-        const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
-        const T b1c = L1[r * RW + c];
-        const T b1u = r > 0 ? L1[(r - 1) * RW + c] : T(0);
-        const T b2c = L2[r * RW + c];
-        const T b2l = c > 0 ? L2[r * RW + c - 1] : T(0);
-        const T pc = Lp[r * RW + c];
-        T pn = plain_potential_(pc, b1c, b1u, b2c, b2l, rh[a][b], ih, tau);
-        if (!in) pn = T(0);
-        Lp[r * RW + c] = pn;
-      }
-    __syncthreads();
+  // flux half of one step; with KEEP the flux change of the step is returned
+#define W1_TILED_FLUX(KEEP)                                                                          \
+  _Pragma("unroll") for (int a = 0; a < NR; ++a) _Pragma("unroll") for (int b = 0; b < NC; ++b) {    \
+    const int r = wv + NWV * a, c = lane + 64 * b;                                                   \
+    const int gi = gi0 + r, gj = gj0 + c;                                                            \
+    const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;                      \
+    const T pc = Lp[r * RW + c];                                                                     \
+    const T pd = (r + 1 < RH) ? Lp[(r + 1) * RW + c] : pc;                                           \
+    const T pr = (c + 1 < RW) ? Lp[r * RW + c + 1] : pc;                                             \
+    T n1, n2;                                                                                        \
+    plain_flux_(m1[a][b], m2[a][b], pc, pd, pr, gi < n && r + 1 < RH, gj < n && c + 1 < RW, ih, mu,  \
+                metric, n1, n2);                                                                     \
+    if (!in) { n1 = T(0); n2 = T(0); }                                                               \
+    L1[r * RW + c] = (n1 + n1) - m1[a][b];                                                           \
+    L2[r * RW + c] = (n2 + n2) - m2[a][b];                                                           \
+    if (KEEP) { dm1[a][b] = n1 - m1[a][b]; dm2[a][b] = n2 - m2[a][b]; }                              \
+    m1[a][b] = n1;                                                                                   \
+    m2[a][b] = n2;                                                                                   \
+  }
+  // potential half of one step; with KEEP the potential change is returned
+#define W1_TILED_POT(KEEP)                                                                           \
+  _Pragma("unroll") for (int a = 0; a < NR; ++a) _Pragma("unroll") for (int b = 0; b < NC; ++b) {    \
+    const int r = wv + NWV * a, c = lane + 64 * b;                                                   \
+    const int gi = gi0 + r, gj = gj0 + c;                                                            \
+    const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;                      \
+    const T b1c = L1[r * RW + c];                                                                    \
+    const T b1u = r > 0 ? L1[(r - 1) * RW + c] : T(0);                                               \
+    const T b2c = L2[r * RW + c];                                                                    \
+    const T b2l = c > 0 ? L2[r * RW + c - 1] : T(0);                                                 \
+    const T pc = Lp[r * RW + c];                                                                     \
+    T pn = plain_potential_(pc, b1c, b1u, b2c, b2l, rh[a][b], ih, tau);                              \
+    if (!in) pn = T(0);                                                                              \
+    if (KEEP) dph[a][b] = pn - pc;                                                                   \
+    Lp[r * RW + c] = pn;                                                                             \
   }
 
+  {
+    T dm1[1][1], dm2[1][1], dph[1][1];  // unused in the loop body
+    (void)dm1; (void)dm2; (void)dph;
+    for (int s = 0; s < S - 1; ++s) {
+      W1_TILED_FLUX(false)
+      __syncthreads();
+      W1_TILED_POT(false)
+      __syncthreads();
+    }
+  }
   if (CHECK) {
-    // dm of every region node with a valid previous iterate (steps == 1)
+    T dm1[NR][NC], dm2[NR][NC], dph[NR][NC];
+    W1_TILED_FLUX(true)
+    __syncthreads();
+    W1_TILED_POT(true)
+    __syncthreads();
 #pragma unroll
     for (int a = 0; a < NR; ++a)
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
         const int r = wv + NWV * a, c = lane + 64 * b;
-        const int gi = gi0 + r, gj = gj0 + c;
-        const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
-        const size_t off = in ? (size_t)gi * pitch + gj : 0;
-        L1[r * RW + c] = in ? m1[a][b] - sm1[off] : T(0);
-        L2[r * RW + c] = in ? m2[a][b] - sm2[off] : T(0);
+        L1[r * RW + c] = dm1[a][b];
+        L2[r * RW + c] = dm2[a][b];
       }
     __syncthreads();
     double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -530,21 +539,28 @@ __global__ __launch_bounds__(RH * 8) void k_plain_tiled(const Work* __restrict__
         const int gi = gi0 + r, gj = gj0 + c;
         const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
         if (in && r >= S && r < RH - S && c >= S && c < RW - S) {
-          const size_t off = (size_t)gi * pitch + gj;
-          const T e1 = L1[r * RW + c], e2 = L2[r * RW + c];
+          const T e1 = dm1[a][b], e2 = dm2[a][b];
           const T u1 = L1[(r - 1) * RW + c];
           const T l2 = L2[r * RW + c - 1];
-          const T pn = Lp[r * RW + c];
           const double adm = (double)(((e1 - u1) + (e2 - l2)) * ih);
-          const double ep = (double)(pn - sph[off]);
+          const double ep = (double)dph[a][b];
           v[0] += (double)e1 * (double)e1 + (double)e2 * (double)e2;
           v[1] += ep * ep;
           v[2] += ep * adm;
-          if (!(finite_(m1[a][b]) && finite_(m2[a][b]) && finite_(pn))) v[3] += 1.0;
+          if (!(finite_(m1[a][b]) && finite_(m2[a][b]) && finite_(Lp[r * RW + c]))) v[3] += 1.0;
         }
       }
     block_reduce_<NTH>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+  } else {
+    T dm1[1][1], dm2[1][1], dph[1][1];
+    (void)dm1; (void)dm2; (void)dph;
+    W1_TILED_FLUX(false)
+    __syncthreads();
+    W1_TILED_POT(false)
+    __syncthreads();
   }
+#undef W1_TILED_FLUX
+#undef W1_TILED_POT
 
   T* __restrict__ dm1p = d.p[3 * ws];
   T* __restrict__ dm2p = d.p[3 * ws + 1];
@@ -790,6 +806,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
     sc.iters = k;
     sc.status = status;
     sc.measure = measure;
+    sc.cur = 0;
   }
 }
 
@@ -801,17 +818,19 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_kkt(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
-                                             int kind, int gpar) {
+                                             const SlotScalars* __restrict__ scal, int kind, int set_xor, int gate) {
   __shared__ double lds[4 * NQ];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
+  const SlotScalars& sc = scal[w.x / MAXL];
+  if (gate && sc.status != ST_RUN) return;
   const SlotDesc<T>& d = desc[w.x];
   const int n = d.n, pitch = d.pitch;
   const T* m1;
   const T* m2;
   const T* pot;
   if (kind == K_PLAIN) {
-    const int cs = (gpar ^ d.par0) & 1;
+    const int cs = (sc.cur ^ set_xor) & 1;
     m1 = d.p[3 * cs];
     m2 = d.p[3 * cs + 1];
     pot = d.p[3 * cs + 2];
@@ -853,9 +872,12 @@ __global__ __launch_bounds__(256) void k_kkt(const Work* __restrict__ work, cons
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_div_pre(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
-                                                 int mode, int kind, int gpar) {
+                                                 const SlotScalars* __restrict__ scal, int mode, int kind,
+                                                 int gate) {
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
+  const SlotScalars& sc = scal[w.x / MAXL];
+  if (gate && sc.status != ST_RUN) return;
   const SlotDesc<T>& d = desc[w.x];
   const int n = d.n, pitch = d.pitch;
   const T ih = d.ih, mu = d.mu;
@@ -864,7 +886,7 @@ __global__ __launch_bounds__(256) void k_div_pre(const Work* __restrict__ work, 
     a1p = d.p[2];
     a2p = d.p[3];
   } else if (kind == K_PLAIN) {
-    const int cs = (gpar ^ d.par0) & 1;
+    const int cs = sc.cur & 1;
     a1p = d.p[3 * cs];
     a2p = d.p[3 * cs + 1];
   } else {
@@ -901,11 +923,13 @@ __global__ __launch_bounds__(256) void k_div_pre(const Work* __restrict__ work, 
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, bool SCALE>
 __global__ __launch_bounds__(256) void k_gemm(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
-                                              int src, int dst, int mat) {
+                                              const SlotScalars* __restrict__ scal, int src, int dst, int mat,
+                                              int gate) {
   __shared__ T As[16][GEMM_T + 4];
   __shared__ T Bs[16][GEMM_T + 4];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
+  if (gate && scal[w.x / MAXL].status != ST_RUN) return;
   const SlotDesc<T>& d = desc[w.x];
   const int N = d.n + 1, ld = d.pitch;
   const T* M = mat ? d.dctCt : d.dctC;
@@ -973,10 +997,12 @@ __global__ __launch_bounds__(256) void k_gemm(const Work* __restrict__ work, con
 // ---------------------------------------------------------------------------
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(256) void k_prox_post(const Work* __restrict__ work,
-                                                   const SlotDesc<T>* __restrict__ desc) {
+                                                   const SlotDesc<T>* __restrict__ desc,
+                                                   const SlotScalars* __restrict__ scal) {
   __shared__ double lds[4 * NQ];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
+  if (scal[w.x / MAXL].status != ST_RUN) return;
   const SlotDesc<T>& d = desc[w.x];
   const int n = d.n, pitch = d.pitch;
   const T ih = d.ih, mu = d.mu, tau = d.tau;
@@ -1035,11 +1061,12 @@ __device__ double measure_from_(const double* r, int kind, int rule, double h2, 
 template <typename T>
 __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, const int* __restrict__ ntiles,
                                                const SlotDesc<T>* __restrict__ desc, SlotScalars* __restrict__ scal,
-                                               int kind, int block_len) {
+                                               int kind, int block_len, int launches) {
   __shared__ double lds[4 * NQ];
   __shared__ double res[NQ];
   const int x = idx[blockIdx.x];
   const int nt = ntiles[blockIdx.x];
+  if (scal[x / MAXL].status != ST_RUN) return;
   const SlotDesc<T>& d = desc[x];
   double v[NQ];
   for (int q = 0; q < NQ; ++q) {
@@ -1061,6 +1088,7 @@ __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, cons
     sc.iters = k;
     sc.measure = m;
     sc.status = st;
+    sc.cur ^= launches & 1;
   }
 }
 
@@ -1073,7 +1101,7 @@ __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, cons
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
-                                                   int kind, int gpar) {
+                                                   const SlotScalars* __restrict__ scal, int kind) {
   __shared__ double lds[4 * NQ];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
@@ -1081,7 +1109,7 @@ __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work
   const int n = d.n, pitch = d.pitch;
   const T *m1, *m2, *pot;
   if (kind == K_PLAIN) {
-    const int cs = (gpar ^ d.par0) & 1;
+    const int cs = scal[w.x / MAXL].cur & 1;
     m1 = d.p[3 * cs];
     m2 = d.p[3 * cs + 1];
     pot = d.p[3 * cs + 2];
@@ -1170,16 +1198,17 @@ __global__ __launch_bounds__(256) void k_eval_final(const int* __restrict__ idx,
 template <typename T>
 __global__ __launch_bounds__(256) void k_export_fields(const Work* __restrict__ work,
                                                        const SlotDesc<T>* __restrict__ desc,
-                                                       const SlotScalars* __restrict__ scal, int kind, int gpar,
-                                                       double* __restrict__ om1, double* __restrict__ om2,
-                                                       double* __restrict__ opsi) {
+                                                       const SlotScalars* __restrict__ scal, int kind) {
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
   const SlotDesc<T>& d = desc[w.x];
   const double mean = scal[w.x / MAXL].mean;
+  double* __restrict__ om1 = d.out_m1;
+  double* __restrict__ om2 = d.out_m2;
+  double* __restrict__ opsi = d.out_psi;
   const T *m1, *m2, *pot;
   if (kind == K_PLAIN) {
-    const int cs = (gpar ^ d.par0) & 1;
+    const int cs = scal[w.x / MAXL].cur & 1;
     m1 = d.p[3 * cs];
     m2 = d.p[3 * cs + 1];
     pot = d.p[3 * cs + 2];
@@ -1232,26 +1261,27 @@ template <typename T> void K<T>::rho_diff(hipStream_t s, const Work* w, int nw, 
 template <typename T> void K<T>::rho_write(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc) {
   if (nw) LAUNCH(k_rho_write<T>, nw, 256, 0, s, w, d, sc);
 }
-template <typename T> void K<T>::prolong(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar) {
-  if (nw) LAUNCH(k_prolong<T>, nw, 256, 0, s, w, d, kind, gpar);
+template <typename T> void K<T>::prolong(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                         const SlotScalars* sc, int kind) {
+  if (nw) LAUNCH(k_prolong<T>, nw, 256, 0, s, w, d, sc, kind);
 }
-template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int gpar,
-                                             int steps, int rh, bool check) {
+template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                             const SlotScalars* sc, int li, int steps, int rh, bool check) {
   if (!nw) return;
-  if (check && steps != 1) {
-    fprintf(stderr, "w1: internal error: checking launch with %d steps\n", steps);
+  if (steps < 1 || 2 * steps >= rh) {
+    fprintf(stderr, "w1: internal error: %d steps in a %d-row region\n", steps, rh);
     return;
   }
   // a 64-row region of doubles would not fit in LDS: double always uses 32
   if constexpr (sizeof(T) == 4) {
     if (rh == 64) {
-      if (check) LAUNCH((k_plain_tiled<T, 64, true>), nw, 512, 0, s, w, d, gpar, steps);
-      else LAUNCH((k_plain_tiled<T, 64, false>), nw, 512, 0, s, w, d, gpar, steps);
+      if (check) LAUNCH((k_plain_tiled<T, 64, true>), nw, 512, 0, s, w, d, sc, li, steps);
+      else LAUNCH((k_plain_tiled<T, 64, false>), nw, 512, 0, s, w, d, sc, li, steps);
       return;
     }
   }
-  if (check) LAUNCH((k_plain_tiled<T, 32, true>), nw, 256, 0, s, w, d, gpar, steps);
-  else LAUNCH((k_plain_tiled<T, 32, false>), nw, 256, 0, s, w, d, gpar, steps);
+  if (check) LAUNCH((k_plain_tiled<T, 32, true>), nw, 256, 0, s, w, d, sc, li, steps);
+  else LAUNCH((k_plain_tiled<T, 32, false>), nw, 256, 0, s, w, d, sc, li, steps);
 }
 
 // resident kernel: sides up to 65, 9 nodes per thread of 512
@@ -1275,44 +1305,47 @@ template <typename T> void K<T>::plain_resident(hipStream_t s, const int* idx, i
   }
   LAUNCH((k_plain_resident<T, ResCfg<T>::NPT>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every);
 }
-template <typename T> void K<T>::kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar) {
-  if (nw) LAUNCH(k_kkt<T>, nw, 256, 0, s, w, d, kind, gpar);
+template <typename T> void K<T>::kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                     const SlotScalars* sc, int kind, int set_xor, int gate) {
+  if (nw) LAUNCH(k_kkt<T>, nw, 256, 0, s, w, d, sc, kind, set_xor, gate);
 }
-template <typename T> void K<T>::div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int mode,
-                                         int kind, int gpar) {
-  if (nw) LAUNCH(k_div_pre<T>, nw, 256, 0, s, w, d, mode, kind, gpar);
+template <typename T> void K<T>::div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                         const SlotScalars* sc, int mode, int kind, int gate) {
+  if (nw) LAUNCH(k_div_pre<T>, nw, 256, 0, s, w, d, sc, mode, kind, gate);
 }
-template <typename T> void K<T>::gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int mode, int src,
-                                      int dst, int mat, bool scale) {
+template <typename T> void K<T>::gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                      const SlotScalars* sc, int mode, int src, int dst, int mat, bool scale,
+                                      int gate) {
   if (!nw) return;
   if (mode == 0) {
-    if (scale) LAUNCH((k_gemm<T, 0, true>), nw, 256, 0, s, w, d, src, dst, mat);
-    else LAUNCH((k_gemm<T, 0, false>), nw, 256, 0, s, w, d, src, dst, mat);
+    if (scale) LAUNCH((k_gemm<T, 0, true>), nw, 256, 0, s, w, d, sc, src, dst, mat, gate);
+    else LAUNCH((k_gemm<T, 0, false>), nw, 256, 0, s, w, d, sc, src, dst, mat, gate);
   } else {
-    if (scale) LAUNCH((k_gemm<T, 1, true>), nw, 256, 0, s, w, d, src, dst, mat);
-    else LAUNCH((k_gemm<T, 1, false>), nw, 256, 0, s, w, d, src, dst, mat);
+    if (scale) LAUNCH((k_gemm<T, 1, true>), nw, 256, 0, s, w, d, sc, src, dst, mat, gate);
+    else LAUNCH((k_gemm<T, 1, false>), nw, 256, 0, s, w, d, sc, src, dst, mat, gate);
   }
 }
-template <typename T> void K<T>::prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, bool check) {
+template <typename T> void K<T>::prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                           const SlotScalars* sc, bool check) {
   if (!nw) return;
-  if (check) LAUNCH((k_prox_post<T, true>), nw, 256, 0, s, w, d);
-  else LAUNCH((k_prox_post<T, false>), nw, 256, 0, s, w, d);
+  if (check) LAUNCH((k_prox_post<T, true>), nw, 256, 0, s, w, d, sc);
+  else LAUNCH((k_prox_post<T, false>), nw, 256, 0, s, w, d, sc);
 }
 template <typename T> void K<T>::check(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
-                                       SlotScalars* sc, int kind, int block_len) {
-  if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len);
+                                       SlotScalars* sc, int kind, int block_len, int launches) {
+  if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len, launches);
 }
-template <typename T> void K<T>::eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar) {
-  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, kind, gpar);
+template <typename T> void K<T>::eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                           const SlotScalars* sc, int kind) {
+  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, sc, kind);
 }
 template <typename T> void K<T>::eval_final(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
                                             SlotScalars* sc, int kind) {
   if (ns) LAUNCH(k_eval_final<T>, ns, 256, 0, s, idx, nt, d, sc, kind);
 }
 template <typename T> void K<T>::export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                               const SlotScalars* sc, int kind, int gpar, double* m1, double* m2,
-                                               double* psi) {
-  if (nw) LAUNCH(k_export_fields<T>, nw, 256, 0, s, w, d, sc, kind, gpar, m1, m2, psi);
+                                               const SlotScalars* sc, int kind) {
+  if (nw) LAUNCH(k_export_fields<T>, nw, 256, 0, s, w, d, sc, kind);
 }
 
 template struct K<float>;

@@ -45,12 +45,15 @@ struct SlotDesc {
   const double* dcts;  // 4 sin^2(pi k / 2N), k < N
   const double* in0;   // finest level only: input masses, dense pitch n+1
   const double* in1;
+  double* out_m1;      // finest level only: exported fields, dense FP64
+  double* out_m2;
+  double* out_psi;
   int n, pitch;
   T ih, mu, tau;
   double h, mud, taud;  // FP64 copies of h, mu, tau for the measures
   double tol;          // stop tolerance of this level
   int metric;          // 1 or 2
-  int par0;            // ping-pong parity offset (plain tiled kernel)
+  int pad1;
   int rule;            // RULE_KKT or RULE_FPR
   int cap;             // iteration cap of this level
 };
@@ -61,9 +64,10 @@ struct SlotScalars {
   double measure;      // last stop measure
   double eval[8];      // P, D, lo, hi, kkt, grad max, r_pri, r_dual
   double mean;         // mean of the plain potential (export)
-  int status;          // Status
+  int status;          // Status; kernels of an iteration block skip a slot
+                       // whose status is not ST_RUN
   int iters;           // iterations run at the current level
-  int bad;             // count of invalid input masses
+  int cur;             // plain: plane set (0 = A, 1 = B) holding the iterate
   int pad;
 };
 
@@ -72,8 +76,10 @@ struct SlotScalars {
 using Work = int4;
 
 // ---------------- launchers (kernels.hip) ----------------
-// `gpar` is the global ping-pong parity: a plain slot's current plane set
-// is (gpar ^ par0) & 1.
+// Kernels that belong to an iteration block take `gate`: a slot whose
+// status is not ST_RUN is skipped.  A plain slot's iterate is in plane set
+// SlotScalars::cur; inside a block the i-th tiled launch reads set
+// cur ^ (i & 1), and the stop test flips cur by the block's launch count.
 template <typename T>
 struct K {
   static void zero(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, unsigned mask);
@@ -87,24 +93,29 @@ struct K {
   static void scale_level(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc);
   static void rho_diff(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d);
   static void rho_write(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc);
-  static void prolong(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar);
-  static void plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int gpar, int steps,
-                          int rh, bool check);
+  static void prolong(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
+                      int kind);
+  static void plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
+                          int launch_index, int steps, int rh, bool check);
   static int plain_resident_max_side();
   static void plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
                              int max_side, int check_every);
-  static void kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar);
-  static void div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int mode, int kind, int gpar);
-  static void gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int mode, int src, int dst,
-                   int mat, bool scale);
-  static void prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, bool check);
+  static void kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int kind,
+                  int set_xor, int gate);
+  static void div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int mode,
+                      int kind, int gate);
+  static void gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int mode,
+                   int src, int dst, int mat, bool scale, int gate);
+  static void prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
+                        bool check);
   static void check(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
-                    SlotScalars* sc, int kind, int block_len);
-  static void eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int kind, int gpar);
+                    SlotScalars* sc, int kind, int block_len, int launches);
+  static void eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
+                        int kind);
   static void eval_final(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
                          SlotScalars* sc, int kind);
   static void export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                            int kind, int gpar, double* m1, double* m2, double* psi);
+                            int kind);
 };
 
 int resident_lds_bytes(int side, int elem);

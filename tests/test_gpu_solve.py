@@ -20,7 +20,7 @@ def _oracle(p0, p1, n, L, metric, algo, rule, tol, cap, ce):
                    alpha=-1.0)
 
 
-def _check_parity(w1, res, fields, ref, n, metric, rho):
+def _check_parity(w1, res, fields, ref, n, metric, rho, precision=FP64):
     assert res["status"] in (0, 1)
     assert res["w1"] == pytest.approx(ref["w1"], rel=1e-4)
     m1, m2, psi = fields
@@ -30,8 +30,11 @@ def _check_parity(w1, res, fields, ref, n, metric, rho):
     # W1_h lies in both certified brackets, so they overlap; the oracle's own
     # f(m^K) need not lie in the GPU bracket when m^K is not yet feasible
     assert max(res["lo"], ref["lo"]) <= min(res["hi"], ref["hi"]) * (1 + 1e-6)
-    assert res["lo"] == pytest.approx(ref["lo"], rel=1e-4)
-    assert res["hi"] == pytest.approx(ref["hi"], rel=1e-4)
+    # the bounds themselves: FP64 agrees to 1e-4; in FP32 the lower bound's
+    # max Lipschitz ratio is a max over differences of rounded potentials
+    ct = 1e-4 if precision == FP64 else 1e-3
+    assert res["lo"] == pytest.approx(ref["lo"], rel=ct)
+    assert res["hi"] == pytest.approx(ref["hi"], rel=ct)
     # the library's own FP64 evaluator agrees with the oracle's on its fields
     assert res["w1"] == pytest.approx(ev_gpu["P"], rel=1e-9)
     assert res["hi"] == pytest.approx(ev_gpu["hi"], rel=1e-7)
@@ -53,7 +56,7 @@ def test_config1_plain_fp64_kkt(precision):
     if precision == FP64:
         assert res["iters"] == ref["iters"]
     rho = o.prepare_levels(p0, p1, n, L)[-1]
-    _check_parity(w1, res, fields, ref, n, metric, rho)
+    _check_parity(w1, res, fields, ref, n, metric, rho, precision)
 
 
 @pytest.mark.parametrize("algo", [1, 2])
@@ -75,7 +78,7 @@ def test_multilevel_paper_rule(algo, precision, metric):
     rho = o.prepare_levels(p0, p1, n, L)[-1]
     if precision == FP64:
         assert res["iters"] == ref["iters"]
-    _check_parity(w1, res, fields, ref, n, metric, rho)
+    _check_parity(w1, res, fields, ref, n, metric, rho, precision)
 
 
 def test_batch_equals_alone_bitwise():
