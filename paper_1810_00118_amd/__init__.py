@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libw1.so")
+LIB_PATH = os.environ.get("W1_LIB_PATH") or os.path.join(HERE, "libw1.so")
 
 W1_OK, W1_EAGAIN = 0, 1
 W1_EINVAL, W1_ENOMEM, W1_EBUSY, W1_EDEVICE, W1_ESTATE, W1_ENOTFOUND = -1, -2, -3, -4, -5, -6

@@ -548,7 +548,7 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, void* 
     std::vector<int> idx{0};
     int* di = op.upload(idx);
     if (!di) return W1_EDEVICE;
-    K<T>::plain_resident(s, di, 1, op.dd, op.dsc, n + 1, steps);
+    K<T>::plain_resident(s, di, 1, op.dd, op.dsc, n + 1, steps, 0);
     HIPCHK(hipGetLastError());
     SlotScalars h;
     st = op.read_scalars(&h);
@@ -558,7 +558,7 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, void* 
   }
   int st = op.commit(1);
   if (st) return st;
-  const int rh = sizeof(T) == 8 ? 32 : 64;
+  const int rh = 64;
   const int T_ = std::max(1, std::min(block > 0 ? block : 1, rh / 2 - 6));
   int done = 0, li = 0, lastS = 1;
   while (done < steps) {

@@ -86,9 +86,12 @@ size_t request_bytes(const w1_params& p) {
 // launches and its last launch carries the stop test.
 TileChoice choose_tiles(int precision, double active_nodes, int check_every, int requested) {
   TileChoice c;
-  c.rh = precision == W1_FP64 ? 32 : 64;
-  const int maxT = c.rh / 2 - 6;                // keep half the region as output
-  int want = requested > 0 ? requested : (precision == W1_FP64 ? 2 : (active_nodes > 4.0e6 ? 5 : 10));
+  c.rh = 64;
+  const int maxT = c.rh / 2 - 6;                // keep most of the region as output
+  // T = 5 keeps 78% of a region as output; below ~2 workgroups per CU the
+  // launch is latency-bound and T = 10 halves the launches per block
+  const double wg5 = active_nodes / ((c.rh - 10) * (TILED_RW - 10.0));
+  int want = requested > 0 ? requested : (precision == W1_FP64 ? 2 : (wg5 >= 512 ? 5 : 10));
   want = std::min(want, maxT);
   int T = 1;
   for (int t = std::min(want, check_every); t >= 1; --t)
@@ -288,7 +291,7 @@ class Prof {
     p.flops = flops;
   }
   void set_units(int i, double units, double bytes) {
-    if (i < 0) return;
+    if (i < 0 || i >= (int)pend_.size()) return;
     pend_[i].units = units;
     pend_[i].bytes = bytes;
   }
@@ -340,8 +343,13 @@ class Prof {
 template <typename T>
 class Batch : public BatchBase {
  public:
-  Batch(int capacity, hipStream_t s) : cap_(capacity), st_(s), arena_(s), prof_(s) {
+  Batch(int capacity, hipStream_t s) : cap_(capacity), st_(s), arena_(s), prof_(s), prof2_(nullptr) {
     slots_.assign(cap_, nullptr);
+    // resident levels run on a second stream beside the tiled / prox blocks
+    ok2_ = hipStreamCreateWithFlags(&st2_, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming) == hipSuccess;
+    prof2_ = Prof(ok2_ ? st2_ : s);
     hdesc_.assign((size_t)cap_ * MAXL, SlotDesc<T>{});
     ok_ = hipMalloc((void**)&ddesc_, sizeof(SlotDesc<T>) * cap_ * MAXL) == hipSuccess &&
           hipMalloc((void**)&dsc_, sizeof(SlotScalars) * cap_) == hipSuccess &&
@@ -351,6 +359,12 @@ class Batch : public BatchBase {
   }
   ~Batch() override {
     (void)hipStreamSynchronize(st_);
+    if (ok2_) {
+      (void)hipStreamSynchronize(st2_);
+      (void)hipEventDestroy(ev_main_);
+      (void)hipEventDestroy(ev_side_);
+      (void)hipStreamDestroy(st2_);
+    }
     for (auto* r : slots_)
       if (r && r->mem) g_blocks.put(r->bytes, r->mem);
     for (auto& kv : lists_) (void)hipFree(kv.second.d);
@@ -479,13 +493,27 @@ class Batch : public BatchBase {
     if (R.empty() && P.empty() && X.empty()) return W1_OK;
     st = flush_desc();
     if (st) return fail(st);
+    // Several iteration blocks per host synchronisation (slots that stop
+    // inside the pipeline are skipped by the gated kernels), sized so one
+    // step is a few milliseconds of device work.  LDS-resident levels run
+    // in bounded chunks of about the same duration on the second stream.
+    double active = 0;
+    for (auto& kv : P)
+      for (auto* r : kv.second) active += node_count(r->sides[r->level]) * r->prm.check_every;
+    for (auto& kv : X)
+      for (auto* r : kv.second) active += 6.0 * node_count(r->sides[r->level]) * r->prm.check_every;
+    const double block_us = std::max(30.0, active / 3.0e5);   // ~3e11 node updates / s
+    const int nblocks = (P.empty() && X.empty()) ? 0 : std::max(8, std::min(64, (int)(2000.0 / block_us)));
     if (!R.empty()) {
-      st = launch_resident(R);
+      // ~3.6 us per resident iteration: beside other work a chunk lasts about
+      // as long as the blocks queued with it
+      // alone (no other level running) the launch runs to its stop tests:
+      // chunking a uniform batch spreads the next level over many small
+      // launches, which costs more than the wait for the slowest pair
+      const bool alone = P.empty() && X.empty();
+      st = launch_resident(R, alone ? 0 : std::max(1, (int)(nblocks * block_us / 3.6)));
       if (st) return fail(st);
     }
-    // several iteration blocks per host synchronisation: slots that stop
-    // inside the pipeline are skipped by the gated kernels
-    const int nblocks = (P.empty() && X.empty()) ? 0 : blocks_per_sync_;
     for (int b = 0; b < nblocks; ++b) {
       int gi = 0;
       for (auto& kv : P) {
@@ -585,10 +613,16 @@ class Batch : public BatchBase {
   }
 
   void profile(bool on) override {
-    prof_.on = on;
+    prof_.on = prof2_.on = on;
     prof_.reset();
+    prof2_.reset();
   }
-  void kernel_stats(int f, double* o) const override { prof_.stats(f, o); }
+  void kernel_stats(int f, double* o) const override {
+    double a[5], b[5];
+    prof_.stats(f, a);
+    prof2_.stats(f, b);
+    for (int k = 0; k < 5; ++k) o[k] = a[k] + b[k];
+  }
 
  private:
   int fail(int st) {
@@ -615,14 +649,24 @@ class Batch : public BatchBase {
   }
 
   int read_scalars() {
+    if (side_pending_) {  // the main stream waits for the resident chunk
+      HIPCHK(hipEventRecord(ev_side_, st2_));
+      HIPCHK(hipStreamWaitEvent(st_, ev_side_, 0));
+      side_pending_ = false;
+    }
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
     if (prof_.on) {
       for (auto& ru : resident_pending_) {
         double u = 0;
-        for (auto* r : ru.second) u += (double)hsc_[r->slot].iters * node_count(r->sides[r->level]);
-        prof_.set_units(ru.first, u, 0.0);
+        for (auto* r : ru.second) {
+          const int it = hsc_[r->slot].iters;
+          u += (double)(it - r->res_iters_seen) * node_count(r->sides[r->level]);
+          r->res_iters_seen = it;
+        }
+        prof2_.set_units(ru.first, u, 0.0);
       }
+      prof2_.harvest();
       prof_.harvest();
     }
     resident_pending_.clear();
@@ -839,6 +883,7 @@ class Batch : public BatchBase {
 
   void start_level(Request* r, int l) {
     r->level = l;
+    r->res_iters_seen = 0;
     r->state = Request::RUN;
     r->t_level = now_seconds();
     const bool allow = !(r->prm.flags & W1_FLAG_NO_RESIDENT);
@@ -848,7 +893,10 @@ class Batch : public BatchBase {
   }
 
   // -- plain: resident levels ---------------------------------------------
-  int launch_resident(std::vector<Request*>& R) {
+  // `chunk` bounds the iterations of this launch (0: run to the stop test);
+  // the launch goes to the second stream after the main stream's pending
+  // uploads and transitions
+  int launch_resident(std::vector<Request*>& R, int chunk) {
     int st = W1_OK;
     int maxside = 0;
     std::map<int, std::vector<int>> by_ce;
@@ -856,17 +904,24 @@ class Batch : public BatchBase {
       by_ce[r->prm.check_every].push_back(dx(r, r->level));
       maxside = std::max(maxside, r->sides[r->level] + 1);
     }
+    hipStream_t rs = ok2_ ? st2_ : st_;
     for (auto& kv : by_ce) {
       int* di = arena_.put(kv.second, &st);
       if (st) return st;
-      const int pi = prof_.begin();
-      K<T>::plain_resident(st_, di, (int)kv.second.size(), ddesc_, dsc_, maxside, kv.first);
-      prof_.end(pi, W1_FAM_PLAIN_RESIDENT, 0, 0, 0);
+      const int c = chunk > 0 ? ((chunk + kv.first - 1) / kv.first) * kv.first : 0;
+      if (ok2_) {
+        HIPCHK(hipEventRecord(ev_main_, st_));
+        HIPCHK(hipStreamWaitEvent(st2_, ev_main_, 0));
+        side_pending_ = true;
+      }
+      const int pi = prof2_.begin();
+      K<T>::plain_resident(rs, di, (int)kv.second.size(), ddesc_, dsc_, maxside, kv.first, c);
+      prof2_.end(pi, W1_FAM_PLAIN_RESIDENT, 0, 0, 0);
       if (pi >= 0) {
-        std::vector<Request*> rs;
+        std::vector<Request*> grp;
         for (auto* r : R)
-          if (r->prm.check_every == kv.first) rs.push_back(r);
-        resident_pending_.emplace_back(pi, rs);
+          if (r->prm.check_every == kv.first) grp.push_back(r);
+        resident_pending_.emplace_back(pi, grp);
       }
     }
     HIPCHK(hipGetLastError());
@@ -1076,8 +1131,10 @@ class Batch : public BatchBase {
   std::vector<int> dirty_;
   uint64_t gen_ = 0;
   std::map<std::string, DevList> lists_;
-  int blocks_per_sync_ = 8;
-  Prof prof_;
+  hipStream_t st2_ = nullptr;
+  hipEvent_t ev_main_ = nullptr, ev_side_ = nullptr;
+  bool ok2_ = false, side_pending_ = false;
+  Prof prof_, prof2_;
   std::vector<std::pair<int, std::vector<Request*>>> resident_pending_;
 };
 

@@ -44,6 +44,7 @@ struct Request {
   // finest-level fields after completion (host, FP64), filled on demand
   std::vector<double> f_m1, f_m2, f_psi;
   bool fields_ready = false;
+  int res_iters_seen = 0;           // profiling: iterations already counted
 };
 
 // Device bytes of one request.

@@ -22,6 +22,7 @@
 #include "w1_internal.hpp"
 #include <cmath>
 #include <cstdio>
+#include <type_traits>
 
 namespace w1 {
 
@@ -39,19 +40,38 @@ template <> __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); 
 template <typename T> __device__ __forceinline__ T abs_(T a) { return a < T(0) ? -a : a; }
 
 // prox of mu ||.||_p at one node: p = 1 soft-threshold per component,
-// p = 2 isotropic shrink (0 when ||v|| <= mu).
+// p = 2 isotropic shrink (0 when ||v|| <= mu).  The FP32 isotropic factor
+// 1 - mu/||v|| uses the hardware reciprocal square root (about 1 ulp);
+// FP64 keeps the correctly rounded square root and division.
 template <typename T>
-__device__ __forceinline__ void shrink_(T v1, T v2, T mu, int metric, T& o1, T& o2) {
+__device__ __forceinline__ void shrink_(T v1, T v2, T mu, int metric, T& o1, T& o2);
+template <>
+__device__ __forceinline__ void shrink_(float v1, float v2, float mu, int metric, float& o1, float& o2) {
   if (metric == 1) {
-    T a1 = abs_(v1) - mu, a2 = abs_(v2) - mu;
-    a1 = a1 > T(0) ? a1 : T(0);
-    a2 = a2 > T(0) ? a2 : T(0);
-    o1 = v1 < T(0) ? -a1 : a1;
-    o2 = v2 < T(0) ? -a2 : a2;
+    float a1 = fabsf(v1) - mu, a2 = fabsf(v2) - mu;
+    a1 = a1 > 0.f ? a1 : 0.f;
+    a2 = a2 > 0.f ? a2 : 0.f;
+    o1 = v1 < 0.f ? -a1 : a1;
+    o2 = v2 < 0.f ? -a2 : a2;
   } else {
-    T s2 = v1 * v1 + v2 * v2;
-    T nv = sqrt_(s2);
-    T s = nv > mu ? T(1) - mu / nv : T(0);
+    const float s2 = v1 * v1 + v2 * v2;
+    const float s = s2 > mu * mu ? 1.f - mu * __builtin_amdgcn_rsqf(s2) : 0.f;
+    o1 = v1 * s;
+    o2 = v2 * s;
+  }
+}
+template <>
+__device__ __forceinline__ void shrink_(double v1, double v2, double mu, int metric, double& o1, double& o2) {
+  if (metric == 1) {
+    double a1 = fabs(v1) - mu, a2 = fabs(v2) - mu;
+    a1 = a1 > 0.0 ? a1 : 0.0;
+    a2 = a2 > 0.0 ? a2 : 0.0;
+    o1 = v1 < 0.0 ? -a1 : a1;
+    o2 = v2 < 0.0 ? -a2 : a2;
+  } else {
+    const double s2 = v1 * v1 + v2 * v2;
+    const double nv = sqrt(s2);
+    const double s = nv > mu ? 1.0 - mu / nv : 0.0;
     o1 = v1 * s;
     o2 = v2 * s;
   }
@@ -125,11 +145,13 @@ struct Acc {
 // Block reduction of NQ doubles per thread into out[0..NQ): wave shuffles,
 // then waves in order through LDS.  `maxmask` marks quantities reduced with
 // max instead of sum.  Deterministic for a fixed block size.
-template <int NT>
+template <int NT, int NUSED = NQ>
 __device__ void block_reduce_(double (&v)[NQ], double* out, double* lds, unsigned maxmask) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
+  for (int q = NUSED; q < NQ; ++q) v[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < NUSED; ++q) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       double o = __shfl_xor(v[q], off, 64);
@@ -414,27 +436,64 @@ __global__ __launch_bounds__(256) void k_prolong(const Work* __restrict__ work, 
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 1, LDS-tiled with temporal blocking.
-// A workgroup loads a RH x 128 region (its output tile plus a halo of
-// `steps` nodes on every side) into LDS, runs `steps` iterations there and
-// writes the (RH - 2 steps) x (128 - 2 steps) interior.  After s steps the
-// flux is valid on rows [s-1, RH-1-s] and the potential on [s, RH-1-s]
-// (same for columns), so the interior is exact.  The launch with index li
-// inside a block reads plane set cur ^ (li & 1) and writes the other one.
-// Every thread owns 8 rows x 2 columns of the region (256 threads for
-// RH = 32, 512 for RH = 64).  The last step is peeled off the loop; with
+// cross-lane moves inside a 64-wide wavefront (DPP wave shifts, readlane)
+// ---------------------------------------------------------------------------
+// lane i receives lane i-1 (lane 0 receives 0)
+__device__ __forceinline__ int lane_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+// lane i receives lane i+1 (lane 63 receives 0)
+__device__ __forceinline__ int lane_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
+
+__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(lane_prev_i(__float_as_int(v))); }
+__device__ __forceinline__ float lane_next(float v) { return __int_as_float(lane_next_i(__float_as_int(v))); }
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_prev(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_prev_i((int)(b & 0xffffffffll)), hi = lane_prev_i((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_next_i((int)(b & 0xffffffffll)), hi = lane_next_i((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1, tiled with temporal blocking, iterate held in registers.
+// A workgroup of 8 wavefronts covers a 64 x 128 region: wavefront w owns
+// rows [8w, 8w+8), lane l owns columns l and l+64.  The region is the
+// output tile plus a halo of `steps` nodes on every side; after s steps the
+// flux is valid on rows [s-1, 63-s] and the potential on [s, 63-s] (same for
+// columns), so `steps` iterations run without leaving the workgroup and the
+// (64 - 2 steps) x (128 - 2 steps) interior is exact.
+// Every node's neighbours come from registers: the next / previous row of
+// the thread's own column strip, the next / previous column through DPP
+// wave shifts (readlane across the two column halves).  Only the first
+// potential row and the last extrapolated-flux row of each strip cross
+// wavefronts, through 8 KB of LDS, so a step costs two barriers.
+// The launch with index li inside a block reads plane set cur ^ (li & 1)
+// and writes the other one.  The last step is peeled off the loop; with
 // CHECK it also produces the FPR partials of eq. (pd_stop) over the
 // interior: sum |dm|^2, sum dphi^2, sum dphi * A dm, non-finite count.
 // ---------------------------------------------------------------------------
-template <typename T, int RH, bool CHECK>
-__global__ __launch_bounds__(RH * 8) void k_plain_tiled(const Work* __restrict__ work,
-                                                        const SlotDesc<T>* __restrict__ desc,
-                                                        const SlotScalars* __restrict__ scal, int li, int steps) {
-  constexpr int RW = TILED_RW, NTH = RH * 8, NWV = NTH / 64, NR = RH / NWV, NC = RW / 64;
-  static_assert(NR == 8, "8 rows per thread");
-  __shared__ T Lp[RH * RW];
-  __shared__ T L1[RH * RW];
-  __shared__ T L2[RH * RW];
+#ifndef W1_TILED_WPE
+#define W1_TILED_WPE 2
+#endif
+template <typename T, bool CHECK, int WAVES_PER_EU = (sizeof(T) == 4 ? W1_TILED_WPE : 2)>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU, 8))) void k_plain_tiled(
+    const Work* __restrict__ work,
+                                                     const SlotDesc<T>* __restrict__ desc,
+                                                     const SlotScalars* __restrict__ scal, int li, int steps) {
+  constexpr int RH = 64, RW = TILED_RW, NWV = 8, NR = 8, NC = 2;
+  __shared__ T Bp[NWV][RW];   // first potential row of each strip
+  __shared__ T Bb[NWV][RW];   // last extrapolated-flux row (axis 1) of each strip
   __shared__ double lds[NWV * NQ];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
@@ -452,131 +511,136 @@ __global__ __launch_bounds__(RH * 8) void k_plain_tiled(const Work* __restrict__
   const T ih = d.ih, mu = d.mu, tau = d.tau;
   const int metric = d.metric;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r0 = wv * NR;
 
-  T m1[NR][NC], m2[NR][NC], rh[NR][NC];
+  // per-node geometry: row / column inside the grid, has-next flags
+  bool rin[NR], rhd[NR];
+  bool cin[NC], chr[NC];
+#pragma unroll
+  for (int a = 0; a < NR; ++a) {
+    const int gi = gi0 + r0 + a;
+    rin[a] = (unsigned)gi <= (unsigned)n;
+    rhd[a] = gi < n && r0 + a + 1 < RH;
+  }
+#pragma unroll
+  for (int b = 0; b < NC; ++b) {
+    const int c = lane + 64 * b, gj = gj0 + c;
+    cin[b] = (unsigned)gj <= (unsigned)n;
+    chr[b] = gj < n && c + 1 < RW;
+  }
+
+  T m1[NR][NC], m2[NR][NC], ph[NR][NC], rh[NR][NC], b1[NR][NC], b2[NR][NC];
 #pragma unroll
   for (int a = 0; a < NR; ++a)
 #pragma unroll
     for (int b = 0; b < NC; ++b) {
-      const int r = wv + NWV * a, c = lane + 64 * b;
-      const int gi = gi0 + r, gj = gj0 + c;
-      const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
-      const size_t off = in ? (size_t)gi * pitch + gj : 0;
+      const bool in = rin[a] && cin[b];
+      const size_t off = in ? (size_t)(gi0 + r0 + a) * pitch + (gj0 + lane + 64 * b) : 0;
       m1[a][b] = in ? sm1[off] : T(0);
       m2[a][b] = in ? sm2[off] : T(0);
+      ph[a][b] = in ? sph[off] : T(0);
       rh[a][b] = in ? srho[off] : T(0);
-      Lp[r * RW + c] = in ? sph[off] : T(0);
     }
-  __syncthreads();
 
-  // flux half of one step; with KEEP the flux change of the step is returned
-#define W1_TILED_FLUX(KEEP)                                                                          \
-  _Pragma("unroll") for (int a = 0; a < NR; ++a) _Pragma("unroll") for (int b = 0; b < NC; ++b) {    \
-    const int r = wv + NWV * a, c = lane + 64 * b;                                                   \
-    const int gi = gi0 + r, gj = gj0 + c;                                                            \
-    const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;                      \
-    const T pc = Lp[r * RW + c];                                                                     \
-    const T pd = (r + 1 < RH) ? Lp[(r + 1) * RW + c] : pc;                                           \
-    const T pr = (c + 1 < RW) ? Lp[r * RW + c + 1] : pc;                                             \
-    T n1, n2;                                                                                        \
-    plain_flux_(m1[a][b], m2[a][b], pc, pd, pr, gi < n && r + 1 < RH, gj < n && c + 1 < RW, ih, mu,  \
-                metric, n1, n2);                                                                     \
-    if (!in) { n1 = T(0); n2 = T(0); }                                                               \
-    L1[r * RW + c] = (n1 + n1) - m1[a][b];                                                           \
-    L2[r * RW + c] = (n2 + n2) - m2[a][b];                                                           \
-    if (KEEP) { dm1[a][b] = n1 - m1[a][b]; dm2[a][b] = n2 - m2[a][b]; }                              \
-    m1[a][b] = n1;                                                                                   \
-    m2[a][b] = n2;                                                                                   \
-  }
-  // potential half of one step; with KEEP the potential change is returned
-#define W1_TILED_POT(KEEP)                                                                           \
-  _Pragma("unroll") for (int a = 0; a < NR; ++a) _Pragma("unroll") for (int b = 0; b < NC; ++b) {    \
-    const int r = wv + NWV * a, c = lane + 64 * b;                                                   \
-    const int gi = gi0 + r, gj = gj0 + c;                                                            \
-    const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;                      \
-    const T b1c = L1[r * RW + c];                                                                    \
-    const T b1u = r > 0 ? L1[(r - 1) * RW + c] : T(0);                                               \
-    const T b2c = L2[r * RW + c];                                                                    \
-    const T b2l = c > 0 ? L2[r * RW + c - 1] : T(0);                                                 \
-    const T pc = Lp[r * RW + c];                                                                     \
-    T pn = plain_potential_(pc, b1c, b1u, b2c, b2l, rh[a][b], ih, tau);                              \
-    if (!in) pn = T(0);                                                                              \
-    if (KEEP) dph[a][b] = pn - pc;                                                                   \
-    Lp[r * RW + c] = pn;                                                                             \
-  }
+  // Stop-test partials of the last step (CHECK): the flux change of every
+  // region node is parked in LDS so A dm can read its row / column
+  // neighbours; sums run over the interior.
+  __shared__ T E1[CHECK ? RH * RW : 1];
+  __shared__ T E2[CHECK ? RH * RW : 1];
+  // per-thread partials in the iterate precision (16 nodes per thread),
+  // summed in FP64 across the workgroup
+  T q0 = T(0), q1 = T(0), q2 = T(0), q3 = T(0);
 
-  {
-    T dm1[1][1], dm2[1][1], dph[1][1];  // unused in the loop body
-    (void)dm1; (void)dm2; (void)dph;
-    for (int s = 0; s < S - 1; ++s) {
-      W1_TILED_FLUX(false)
-      __syncthreads();
-      W1_TILED_POT(false)
-      __syncthreads();
-    }
-  }
-  if (CHECK) {
-    T dm1[NR][NC], dm2[NR][NC], dph[NR][NC];
-    W1_TILED_FLUX(true)
-    __syncthreads();
-    W1_TILED_POT(true)
+  // one step; KEEP marks the checked last step
+  auto step = [&](auto keep) {
+    constexpr bool KEEP = decltype(keep)::value;
+#pragma unroll
+    for (int b = 0; b < NC; ++b) Bp[wv][lane + 64 * b] = ph[0][b];
     __syncthreads();
 #pragma unroll
-    for (int a = 0; a < NR; ++a)
+    for (int a = 0; a < NR; ++a) {
+      // potential at the next column: lane + 1, crossing into the second
+      // column half at lane 63; the region's last column has no neighbour
+      const T x0 = lane_next(ph[a][0]);
+      const T x1 = lane_next(ph[a][1]);
+      const T h0 = lane_read(ph[a][1], 0);
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
-        const int r = wv + NWV * a, c = lane + 64 * b;
-        L1[r * RW + c] = dm1[a][b];
-        L2[r * RW + c] = dm2[a][b];
-      }
-    __syncthreads();
-    double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < NR; ++a)
-#pragma unroll
-      for (int b = 0; b < NC; ++b) {
-        const int r = wv + NWV * a, c = lane + 64 * b;
-        const int gi = gi0 + r, gj = gj0 + c;
-        const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
-        if (in && r >= S && r < RH - S && c >= S && c < RW - S) {
-          const T e1 = dm1[a][b], e2 = dm2[a][b];
-          const T u1 = L1[(r - 1) * RW + c];
-          const T l2 = L2[r * RW + c - 1];
-          const double adm = (double)(((e1 - u1) + (e2 - l2)) * ih);
-          const double ep = (double)dph[a][b];
-          v[0] += (double)e1 * (double)e1 + (double)e2 * (double)e2;
-          v[1] += ep * ep;
-          v[2] += ep * adm;
-          if (!(finite_(m1[a][b]) && finite_(m2[a][b]) && finite_(Lp[r * RW + c]))) v[3] += 1.0;
+        const T pc = ph[a][b];
+        const T pd = a + 1 < NR ? ph[a + 1 < NR ? a + 1 : a][b] : (wv + 1 < NWV ? Bp[wv + 1 < NWV ? wv + 1 : wv][lane + 64 * b] : pc);
+        const T pr = b == 0 ? (lane == 63 ? h0 : x0) : x1;
+        T n1, n2;
+        plain_flux_(m1[a][b], m2[a][b], pc, pd, pr, rhd[a], chr[b], ih, mu, metric, n1, n2);
+        if (!(rin[a] && cin[b])) { n1 = T(0); n2 = T(0); }
+        b1[a][b] = (n1 + n1) - m1[a][b];
+        b2[a][b] = (n2 + n2) - m2[a][b];
+        if constexpr (KEEP) {
+          const int r = r0 + a, c = lane + 64 * b;
+          const T e1 = n1 - m1[a][b], e2 = n2 - m2[a][b];
+          E1[r * RW + c] = e1;
+          E2[r * RW + c] = e2;
+          if (rin[a] && cin[b] && r >= S && r < RH - S && c >= S && c < RW - S)
+            q0 = fma_(e1, e1, fma_(e2, e2, q0));
         }
+        m1[a][b] = n1;
+        m2[a][b] = n2;
       }
-    block_reduce_<NTH>(v, d.part + (size_t)w.w * NQ, lds, 0u);
-  } else {
-    T dm1[1][1], dm2[1][1], dph[1][1];
-    (void)dm1; (void)dm2; (void)dph;
-    W1_TILED_FLUX(false)
+    }
+#pragma unroll
+    for (int b = 0; b < NC; ++b) Bb[wv][lane + 64 * b] = b1[NR - 1][b];
     __syncthreads();
-    W1_TILED_POT(false)
-    __syncthreads();
-  }
-#undef W1_TILED_FLUX
-#undef W1_TILED_POT
+#pragma unroll
+    for (int a = 0; a < NR; ++a) {
+      // extrapolated flux (axis 2) at the previous column: lane - 1,
+      // crossing back from the second column half at lane 0
+      const T y0 = lane_prev(b2[a][0]);
+      const T y1 = lane_prev(b2[a][1]);
+      const T g63 = lane_read(b2[a][0], 63);
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        const T b1u = a > 0 ? b1[a > 0 ? a - 1 : 0][b] : (wv > 0 ? Bb[wv > 0 ? wv - 1 : 0][lane + 64 * b] : T(0));
+        const T b2l = b == 0 ? y0 : (lane == 0 ? g63 : y1);
+        T pn = plain_potential_(ph[a][b], b1[a][b], b1u, b2[a][b], b2l, rh[a][b], ih, tau);
+        if (!(rin[a] && cin[b])) pn = T(0);
+        if constexpr (KEEP) {
+          const int r = r0 + a, c = lane + 64 * b;
+          if (rin[a] && cin[b] && r >= S && r < RH - S && c >= S && c < RW - S) {
+            // interior nodes have r, c >= S >= 1, so both neighbours exist
+            const T e1 = E1[r * RW + c], e2 = E2[r * RW + c];
+            const T adm = ((e1 - E1[(r - 1) * RW + c]) + (e2 - E2[r * RW + c - 1])) * ih;
+            const T pe = pn - ph[a][b];
+            q1 = fma_(pe, pe, q1);
+            q2 = fma_(pe, adm, q2);
+            if (!(finite_(m1[a][b]) && finite_(m2[a][b]) && finite_(pn))) q3 += T(1);
+          }
+        }
+        ph[a][b] = pn;
+      }
+    }
+  };
 
-  T* __restrict__ dm1p = d.p[3 * ws];
-  T* __restrict__ dm2p = d.p[3 * ws + 1];
-  T* __restrict__ dphp = d.p[3 * ws + 2];
+  for (int s = 0; s < S - 1; ++s) step(std::false_type{});
+  if constexpr (CHECK) {
+    step(std::true_type{});
+    double v[NQ] = {(double)q0, (double)q1, (double)q2, (double)q3, 0, 0, 0, 0};
+    block_reduce_<512, 4>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+  } else {
+    step(std::false_type{});
+  }
+
+  T* __restrict__ om1 = d.p[3 * ws];
+  T* __restrict__ om2 = d.p[3 * ws + 1];
+  T* __restrict__ oph = d.p[3 * ws + 2];
 #pragma unroll
   for (int a = 0; a < NR; ++a)
 #pragma unroll
     for (int b = 0; b < NC; ++b) {
-      const int r = wv + NWV * a, c = lane + 64 * b;
-      const int gi = gi0 + r, gj = gj0 + c;
-      const bool in = (unsigned)gi <= (unsigned)n && (unsigned)gj <= (unsigned)n;
-      if (in && r >= S && r < RH - S && c >= S && c < RW - S) {
-        const size_t off = (size_t)gi * pitch + gj;
-        dm1p[off] = m1[a][b];
-        dm2p[off] = m2[a][b];
-        dphp[off] = Lp[r * RW + c];
+      const int r = r0 + a, c = lane + 64 * b;
+      if (rin[a] && cin[b] && r >= S && r < RH - S && c >= S && c < RW - S) {
+        const size_t off = (size_t)(gi0 + r) * pitch + (gj0 + c);
+        om1[off] = m1[a][b];
+        om2[off] = m2[a][b];
+        oph[off] = ph[a][b];
       }
     }
 }
@@ -591,12 +655,15 @@ __global__ __launch_bounds__(RH * 8) void k_plain_tiled(const Work* __restrict__
 // Stop tests (both rules) run every `check_every` iterations and at the cap;
 // on those iterations the previous iterate is parked in the slot's spare
 // planes 3..5 and dm in planes 6, 7 (global memory, same workgroup).
-// Reads and writes plane set A.
+// Reads and writes plane set A.  A launch runs at most `chunk` iterations
+// (0: no limit) and resumes from the slot's iteration count, so long
+// levels run in bounded pieces beside other work.
 // ---------------------------------------------------------------------------
 template <typename T, int NPT>
 __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __restrict__ idx,
                                                                 const SlotDesc<T>* __restrict__ desc,
-                                                                SlotScalars* __restrict__ scal, int check_every) {
+                                                                SlotScalars* __restrict__ scal, int check_every,
+                                                                int chunk) {
   extern __shared__ double smem_d[];
   constexpr int NT = RES_THREADS;
   static_assert(NPT <= 32, "column masks hold 32 nodes");
@@ -641,11 +708,13 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
   }
   __syncthreads();
 
-  int k = 0;
+  // resume where the previous chunk of this level stopped
+  int k = sc.iters;
+  const int kend = chunk > 0 ? k + chunk : cap;
   int status = ST_RUN;
-  double measure = 0.0;
+  double measure = sc.measure;
   const bool fpr = d.rule == RULE_FPR;
-  while (true) {
+  while (k < kend) {
     ++k;
     const bool chk = (k % check_every == 0) || (k >= cap);
     if (chk && fpr) {
@@ -1268,20 +1337,12 @@ template <typename T> void K<T>::prolong(hipStream_t s, const Work* w, int nw, c
 template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                              const SlotScalars* sc, int li, int steps, int rh, bool check) {
   if (!nw) return;
-  if (steps < 1 || 2 * steps >= rh) {
+  if (rh != 64 || steps < 1 || 2 * steps >= rh) {
     fprintf(stderr, "w1: internal error: %d steps in a %d-row region\n", steps, rh);
     return;
   }
-  // a 64-row region of doubles would not fit in LDS: double always uses 32
-  if constexpr (sizeof(T) == 4) {
-    if (rh == 64) {
-      if (check) LAUNCH((k_plain_tiled<T, 64, true>), nw, 512, 0, s, w, d, sc, li, steps);
-      else LAUNCH((k_plain_tiled<T, 64, false>), nw, 512, 0, s, w, d, sc, li, steps);
-      return;
-    }
-  }
-  if (check) LAUNCH((k_plain_tiled<T, 32, true>), nw, 256, 0, s, w, d, sc, li, steps);
-  else LAUNCH((k_plain_tiled<T, 32, false>), nw, 256, 0, s, w, d, sc, li, steps);
+  if (check) LAUNCH((k_plain_tiled<T, true>), nw, 512, 0, s, w, d, sc, li, steps);
+  else LAUNCH((k_plain_tiled<T, false>), nw, 512, 0, s, w, d, sc, li, steps);
 }
 
 // resident kernel: sides up to 65, 9 nodes per thread of 512
@@ -1294,7 +1355,7 @@ int resident_lds_bytes(int side, int elem) { return 18 * NQ * 8 + 2 * side * sid
 template <typename T> int K<T>::plain_resident_max_side() { return ResCfg<T>::MAXN; }
 
 template <typename T> void K<T>::plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d,
-                                                SlotScalars* sc, int max_side, int check_every) {
+                                                SlotScalars* sc, int max_side, int check_every, int chunk) {
   if (!ns) return;
   static bool attr_set = false;
   const int bytes = resident_lds_bytes(max_side, sizeof(T));
@@ -1303,7 +1364,7 @@ template <typename T> void K<T>::plain_resident(hipStream_t s, const int* idx, i
                         hipFuncAttributeMaxDynamicSharedMemorySize, resident_lds_bytes(ResCfg<T>::MAXN, sizeof(T)));
     attr_set = true;
   }
-  LAUNCH((k_plain_resident<T, ResCfg<T>::NPT>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every);
+  LAUNCH((k_plain_resident<T, ResCfg<T>::NPT>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
 }
 template <typename T> void K<T>::kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                      const SlotScalars* sc, int kind, int set_xor, int gate) {

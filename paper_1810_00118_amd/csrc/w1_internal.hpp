@@ -99,7 +99,7 @@ struct K {
                           int launch_index, int steps, int rh, bool check);
   static int plain_resident_max_side();
   static void plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
-                             int max_side, int check_every);
+                             int max_side, int check_every, int chunk);
   static void kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int kind,
                   int set_xor, int gate);
   static void div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int mode,
