@@ -343,13 +343,8 @@ class Prof {
 template <typename T>
 class Batch : public BatchBase {
  public:
-  Batch(int capacity, hipStream_t s) : cap_(capacity), st_(s), arena_(s), prof_(s), prof2_(nullptr) {
+  Batch(int capacity, hipStream_t s) : cap_(capacity), st_(s), arena_(s), prof_(s) {
     slots_.assign(cap_, nullptr);
-    // resident levels run on a second stream beside the tiled / prox blocks
-    ok2_ = hipStreamCreateWithFlags(&st2_, hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming) == hipSuccess;
-    prof2_ = Prof(ok2_ ? st2_ : s);
     hdesc_.assign((size_t)cap_ * MAXL, SlotDesc<T>{});
     ok_ = hipMalloc((void**)&ddesc_, sizeof(SlotDesc<T>) * cap_ * MAXL) == hipSuccess &&
           hipMalloc((void**)&dsc_, sizeof(SlotScalars) * cap_) == hipSuccess &&
@@ -359,12 +354,6 @@ class Batch : public BatchBase {
   }
   ~Batch() override {
     (void)hipStreamSynchronize(st_);
-    if (ok2_) {
-      (void)hipStreamSynchronize(st2_);
-      (void)hipEventDestroy(ev_main_);
-      (void)hipEventDestroy(ev_side_);
-      (void)hipStreamDestroy(st2_);
-    }
     for (auto* r : slots_)
       if (r && r->mem) g_blocks.put(r->bytes, r->mem);
     for (auto& kv : lists_) (void)hipFree(kv.second.d);
@@ -495,8 +484,8 @@ class Batch : public BatchBase {
     if (st) return fail(st);
     // Several iteration blocks per host synchronisation (slots that stop
     // inside the pipeline are skipped by the gated kernels), sized so one
-    // step is a few milliseconds of device work.  LDS-resident levels run
-    // in bounded chunks of about the same duration on the second stream.
+    // step is a few milliseconds of device work.  Beside running tiled or
+    // prox levels, LDS-resident levels run in chunks of about that length.
     double active = 0;
     for (auto& kv : P)
       for (auto* r : kv.second) active += node_count(r->sides[r->level]) * r->prm.check_every;
@@ -613,16 +602,10 @@ class Batch : public BatchBase {
   }
 
   void profile(bool on) override {
-    prof_.on = prof2_.on = on;
+    prof_.on = on;
     prof_.reset();
-    prof2_.reset();
   }
-  void kernel_stats(int f, double* o) const override {
-    double a[5], b[5];
-    prof_.stats(f, a);
-    prof2_.stats(f, b);
-    for (int k = 0; k < 5; ++k) o[k] = a[k] + b[k];
-  }
+  void kernel_stats(int f, double* o) const override { prof_.stats(f, o); }
 
  private:
   int fail(int st) {
@@ -649,11 +632,6 @@ class Batch : public BatchBase {
   }
 
   int read_scalars() {
-    if (side_pending_) {  // the main stream waits for the resident chunk
-      HIPCHK(hipEventRecord(ev_side_, st2_));
-      HIPCHK(hipStreamWaitEvent(st_, ev_side_, 0));
-      side_pending_ = false;
-    }
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
     if (prof_.on) {
@@ -664,9 +642,8 @@ class Batch : public BatchBase {
           u += (double)(it - r->res_iters_seen) * node_count(r->sides[r->level]);
           r->res_iters_seen = it;
         }
-        prof2_.set_units(ru.first, u, 0.0);
+        prof_.set_units(ru.first, u, 0.0);
       }
-      prof2_.harvest();
       prof_.harvest();
     }
     resident_pending_.clear();
@@ -893,9 +870,7 @@ class Batch : public BatchBase {
   }
 
   // -- plain: resident levels ---------------------------------------------
-  // `chunk` bounds the iterations of this launch (0: run to the stop test);
-  // the launch goes to the second stream after the main stream's pending
-  // uploads and transitions
+  // `chunk` bounds the iterations of this launch (0: run to the stop test)
   int launch_resident(std::vector<Request*>& R, int chunk) {
     int st = W1_OK;
     int maxside = 0;
@@ -904,19 +879,13 @@ class Batch : public BatchBase {
       by_ce[r->prm.check_every].push_back(dx(r, r->level));
       maxside = std::max(maxside, r->sides[r->level] + 1);
     }
-    hipStream_t rs = ok2_ ? st2_ : st_;
     for (auto& kv : by_ce) {
       int* di = arena_.put(kv.second, &st);
       if (st) return st;
       const int c = chunk > 0 ? ((chunk + kv.first - 1) / kv.first) * kv.first : 0;
-      if (ok2_) {
-        HIPCHK(hipEventRecord(ev_main_, st_));
-        HIPCHK(hipStreamWaitEvent(st2_, ev_main_, 0));
-        side_pending_ = true;
-      }
-      const int pi = prof2_.begin();
-      K<T>::plain_resident(rs, di, (int)kv.second.size(), ddesc_, dsc_, maxside, kv.first, c);
-      prof2_.end(pi, W1_FAM_PLAIN_RESIDENT, 0, 0, 0);
+      const int pi = prof_.begin();
+      K<T>::plain_resident(st_, di, (int)kv.second.size(), ddesc_, dsc_, maxside, kv.first, c);
+      prof_.end(pi, W1_FAM_PLAIN_RESIDENT, 0, 0, 0);
       if (pi >= 0) {
         std::vector<Request*> grp;
         for (auto* r : R)
@@ -1131,10 +1100,7 @@ class Batch : public BatchBase {
   std::vector<int> dirty_;
   uint64_t gen_ = 0;
   std::map<std::string, DevList> lists_;
-  hipStream_t st2_ = nullptr;
-  hipEvent_t ev_main_ = nullptr, ev_side_ = nullptr;
-  bool ok2_ = false, side_pending_ = false;
-  Prof prof_, prof2_;
+  Prof prof_;
   std::vector<std::pair<int, std::vector<Request*>>> resident_pending_;
 };
 
