@@ -481,12 +481,17 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 // The launch with index li inside a block reads plane set cur ^ (li & 1)
 // and writes the other one.  The last step is peeled off the loop; with
 // CHECK it also produces the FPR partials of eq. (pd_stop) over the
-// interior: sum |dm|^2, sum dphi^2, sum dphi * A dm, non-finite count.
+// interior: sum |dm|^2, sum dphi^2, sum dphi * A dm, without extra
+// per-node state (the checked step needs no more registers
+// than a plain one, so both variants run at the same occupancy).
 // ---------------------------------------------------------------------------
 #ifndef W1_TILED_WPE
 #define W1_TILED_WPE 2
 #endif
-template <typename T, bool CHECK, int WAVES_PER_EU = (sizeof(T) == 4 ? W1_TILED_WPE : 2)>
+#ifndef W1_TILED_WPE_CHECK
+#define W1_TILED_WPE_CHECK 4
+#endif
+template <typename T, bool CHECK, int WAVES_PER_EU = (sizeof(T) == 4 ? (CHECK ? W1_TILED_WPE_CHECK : W1_TILED_WPE) : 2)>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU, 8))) void k_plain_tiled(
     const Work* __restrict__ work,
                                                      const SlotDesc<T>* __restrict__ desc,
@@ -542,14 +547,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
       rh[a][b] = in ? srho[off] : T(0);
     }
 
-  // Stop-test partials of the last step (CHECK): the flux change of every
-  // region node is parked in LDS so A dm can read its row / column
-  // neighbours; sums run over the interior.
-  __shared__ T E1[CHECK ? RH * RW : 1];
-  __shared__ T E2[CHECK ? RH * RW : 1];
+  // Stop-test partials of the last step (CHECK), summed over the interior.
+  // The flux change is not stored: after the flux half, m holds m+ and b
+  // holds 2 m+ - m, so b - m is the change, and A dm is read from the same
+  // neighbours as the divergence of b (the last new-flux row of each strip
+  // crosses wavefronts through Bm).
+  __shared__ T Bm[CHECK ? NWV : 1][RW];
   // per-thread partials in the iterate precision (16 nodes per thread),
   // summed in FP64 across the workgroup
-  T q0 = T(0), q1 = T(0), q2 = T(0), q3 = T(0);
+  // (a non-finite iterate makes q0 or q1 non-finite, and with them the
+  // measure, which the stop test reports as divergence)
+  T q0 = T(0), q1 = T(0), q2 = T(0);
 
   // one step; KEEP marks the checked last step
   auto step = [&](auto keep) {
@@ -577,8 +585,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
         if constexpr (KEEP) {
           const int r = r0 + a, c = lane + 64 * b;
           const T e1 = n1 - m1[a][b], e2 = n2 - m2[a][b];
-          E1[r * RW + c] = e1;
-          E2[r * RW + c] = e2;
           if (rin[a] && cin[b] && r >= S && r < RH - S && c >= S && c < RW - S)
             q0 = fma_(e1, e1, fma_(e2, e2, q0));
         }
@@ -587,7 +593,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
       }
     }
 #pragma unroll
-    for (int b = 0; b < NC; ++b) Bb[wv][lane + 64 * b] = b1[NR - 1][b];
+    for (int b = 0; b < NC; ++b) {
+      Bb[wv][lane + 64 * b] = b1[NR - 1][b];
+      if constexpr (KEEP) Bm[wv][lane + 64 * b] = m1[NR - 1][b];
+    }
     __syncthreads();
 #pragma unroll
     for (int a = 0; a < NR; ++a) {
@@ -596,6 +605,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
       const T y0 = lane_prev(b2[a][0]);
       const T y1 = lane_prev(b2[a][1]);
       const T g63 = lane_read(b2[a][0], 63);
+      // the same shifts of the new flux (axis 2) for the checked step; the
+      // cross-lane reads run with every lane active, outside any per-lane
+      // condition, so no lane reads a masked-off neighbour
+      T z0 = T(0), z1 = T(0), z63 = T(0);
+      if constexpr (KEEP) {
+        z0 = lane_prev(m2[a][0]);
+        z1 = lane_prev(m2[a][1]);
+        z63 = lane_read(m2[a][0], 63);
+      }
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
         const T b1u = a > 0 ? b1[a > 0 ? a - 1 : 0][b] : (wv > 0 ? Bb[wv > 0 ? wv - 1 : 0][lane + 64 * b] : T(0));
@@ -604,14 +622,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
         if (!(rin[a] && cin[b])) pn = T(0);
         if constexpr (KEEP) {
           const int r = r0 + a, c = lane + 64 * b;
+          // flux change at the node, at (i-1, j) and at (i, j-1); interior
+          // nodes have r, c >= S >= 1, so both neighbours are in the region
+          const T m1u = a > 0 ? m1[a > 0 ? a - 1 : 0][b] : (wv > 0 ? Bm[wv > 0 ? wv - 1 : 0][lane + 64 * b] : T(0));
+          const T m2l = b == 0 ? z0 : (lane == 0 ? z63 : z1);
           if (rin[a] && cin[b] && r >= S && r < RH - S && c >= S && c < RW - S) {
-            // interior nodes have r, c >= S >= 1, so both neighbours exist
-            const T e1 = E1[r * RW + c], e2 = E2[r * RW + c];
-            const T adm = ((e1 - E1[(r - 1) * RW + c]) + (e2 - E2[r * RW + c - 1])) * ih;
+            const T e1c = b1[a][b] - m1[a][b], e1u = b1u - m1u;
+            const T e2c = b2[a][b] - m2[a][b], e2l = b2l - m2l;
+            const T adm = ((e1c - e1u) + (e2c - e2l)) * ih;
             const T pe = pn - ph[a][b];
             q1 = fma_(pe, pe, q1);
             q2 = fma_(pe, adm, q2);
-            if (!(finite_(m1[a][b]) && finite_(m2[a][b]) && finite_(pn))) q3 += T(1);
           }
         }
         ph[a][b] = pn;
@@ -622,7 +643,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
   for (int s = 0; s < S - 1; ++s) step(std::false_type{});
   if constexpr (CHECK) {
     step(std::true_type{});
-    double v[NQ] = {(double)q0, (double)q1, (double)q2, (double)q3, 0, 0, 0, 0};
+    double v[NQ] = {(double)q0, (double)q1, (double)q2, 0, 0, 0, 0, 0};
     block_reduce_<512, 4>(v, d.part + (size_t)w.w * NQ, lds, 0u);
   } else {
     step(std::false_type{});
