@@ -154,6 +154,13 @@ def main():
             roof = {"kernel": dom, "bound": "alu", "achieved": ups, "peak": None, "unit": "node-updates/s",
                     "frac": None, "traffic": None, "avg_launch_ms": avg_ms, "launches": st["launches"]}
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in kstats.items() if v["launches"]}
+    # launch shapes the autotuner settled on (per size class of the active set)
+    tuned = []
+    for e in w1.tuner_table():
+        if e["best"] >= 0:
+            a = e["arms"][e["best"]]
+            tuned.append({"precision": e["precision"], "class": e["class"], "waves": a["waves"], "T": a["T"],
+                          "ns_per_update": a["ns_per_update"]})
 
     # ---- FP64 CPU oracle on this host (bounded sample) ----
     cpu = None
@@ -185,7 +192,7 @@ def main():
                         "speedup_batched_fp32": solves_per_s / fp64_sps if fp64_sps else None},
         "accuracy": {"checked": len(rel), "within_1e-4": sum(x <= 1e-4 for x in rel),
                      "max_rel": max(rel) if rel else None},
-        "iterations": iter_stats, "roofline": roof, "kernels": kernels, "cpu_baseline": cpu,
+        "iterations": iter_stats, "roofline": roof, "kernels": kernels, "autotune": tuned, "cpu_baseline": cpu,
         "context": "paper: 0.2-1.5 s per 512x512 W1 on one i7-2600 (MATLAB, Algorithm 4)",
     }
     solver.close()

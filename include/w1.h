@@ -82,14 +82,15 @@ typedef struct {
     int32_t max_iters;    /* per-level iteration cap (> 0)                    */
     int32_t check_every;  /* stop-test cadence in iterations (> 0)           */
     int32_t block_steps;  /* plain: PDHG steps fused per launch (temporal
-                             block depth); 0 = autotuned; must divide
-                             check_every                                     */
+                             block depth), 0..26; 0 = autotuned; otherwise
+                             the deepest divisor of check_every not above it */
     int32_t flags;        /* W1_FLAG_* bit set                                */
 } w1_params;
 
 /* W1_FLAG_NO_RESIDENT: never keep a whole level in one workgroup's LDS     */
 #define W1_FLAG_NO_RESIDENT 1
-/* W1_FLAG_NO_CERT: skip the FP64 certificate (lo, hi, kkt) at the end      */
+/* W1_FLAG_NO_CERT: skip the FP64 certificate at the end (w1 and dual are   */
+/* still computed; lo, hi and kkt are returned as NaN)                       */
 #define W1_FLAG_NO_CERT 2
 
 typedef struct {
@@ -206,11 +207,14 @@ int w1_op_prolong(int32_t nc, int32_t precision,
 /* `steps` iterations of eq. (primaldual) in place on (m1, m2, phi), with
  * mu = tau = step_scale * h / (2 sqrt 2) (step_scale <= 0: 1/2).
  * fpr_out (host, may be NULL) receives R^k of the last step
- * (eq. (pd_stop)).  block_steps > 0 fuses that many steps per launch.     */
+ * (eq. (pd_stop)).  block_steps > 0 (at most 26) fuses that many steps per
+ * tiled launch, block_steps < 0 runs the whole-level LDS kernel (n <= 64);
+ * waves (0, 8 or 16) splits each tiled 64 x 128 region over that many
+ * wavefronts.  Every choice gives the same iterates bit for bit.           */
 int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision,
                       double step_scale, int32_t steps, int32_t block_steps,
-                      void* m1, void* m2, void* phi, const void* rho,
-                      double* fpr_out, void* hip_stream);
+                      int32_t waves, void* m1, void* m2, void* phi,
+                      const void* rho, double* fpr_out, void* hip_stream);
 
 /* `steps` iterations of eq. (pdhg) in place on (m1, m2, vphi1, vphi2,
  * vphibar1, vphibar2), mu = tau = step_scale (<= 0: 1/2).  fpr_out
@@ -257,6 +261,17 @@ enum { W1_FAM_PLAIN_TILED = 0, W1_FAM_PLAIN_RESIDENT = 1, W1_FAM_DCT = 2,
        W1_FAM_PROX_ELEM = 3, W1_FAM_OTHER = 4, W1_NFAM = 5 };
 int w1_profile(w1_handle h, int32_t enable);
 int w1_kernel_stats(w1_handle h, int32_t family, double* out5);
+
+/* ---- launch-shape autotuner ---------------------------------------------
+ * The plain tiled kernel's temporal depth and wavefronts per workgroup are
+ * picked per (precision, check_every, requested depth, size class of the
+ * active set) by timing each candidate on a few live iteration blocks and
+ * keeping the fastest; all candidates give the same iterates bit for bit.
+ * The table is process-wide.  w1_tuner_table writes it as JSON text into
+ * buf (len bytes, NUL-terminated, truncated if short) and returns the full
+ * length; w1_tuner_reset forgets every measurement.                        */
+int w1_tuner_table(char* buf, size_t len);
+int w1_tuner_reset(void);
 
 /* Library version string.                                                  */
 const char* w1_version(void);

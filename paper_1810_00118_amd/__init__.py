@@ -87,9 +87,11 @@ def lib():
         "w1_version": (C.c_char_p, []),
         "w1_profile": (C.c_int, [vp, i32]),
         "w1_kernel_stats": (C.c_int, [vp, i32, dp]),
+        "w1_tuner_table": (C.c_int, [C.c_char_p, C.c_size_t]),
+        "w1_tuner_reset": (C.c_int, []),
         "w1_op_prepare": (C.c_int, [i32, i32, i32, vp, vp, C.POINTER(vp), vp]),
         "w1_op_prolong": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp, vp]),
-        "w1_op_plain_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, dp, vp]),
+        "w1_op_plain_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, i32, vp, vp, vp, vp, dp, vp]),
         "w1_op_prox_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, vp, vp, vp, vp, vp, vp, vp, dp, vp]),
         "w1_op_poisson": (C.c_int, [i32, i32, vp, vp, vp]),
         "w1_op_potential": (C.c_int, [i32, i32, vp, vp, vp, vp]),
@@ -295,13 +297,26 @@ def op_prolong(nc, precision, c_m1, c_m2, c_phi, f_m1, f_m2, f_phi, stream=None)
 
 
 def op_plain_steps(n, metric, precision, steps, m1, m2, phi, rho, step_scale=0.0, block_steps=0, fpr=False,
-                   stream=None):
+                   stream=None, waves=0):
     d = _dt(precision)
     out = C.c_double(np.nan)
-    _check(lib().w1_op_plain_steps(n, metric, precision, step_scale, steps, block_steps,
+    _check(lib().w1_op_plain_steps(n, metric, precision, step_scale, steps, block_steps, waves,
                                    *[_ptr(x, d)[0] for x in (m1, m2, phi, rho)],
                                    C.byref(out) if fpr else None, _stream(stream)), "w1_op_plain_steps")
     return out.value if fpr else None
+
+
+def tuner_table():
+    """The launch-shape autotuner's measurements (list of dicts)."""
+    import json
+    n = lib().w1_tuner_table(None, 0)
+    buf = C.create_string_buffer(n + 1)
+    lib().w1_tuner_table(buf, n + 1)
+    return json.loads(buf.value.decode())
+
+
+def tuner_reset():
+    _check(lib().w1_tuner_reset(), "w1_tuner_reset")
 
 
 def op_prox_steps(n, metric, precision, steps, m1, m2, w1, w2, wb1, wb2, rho, step_scale=0.0, fpr=False,

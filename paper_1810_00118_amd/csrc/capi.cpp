@@ -50,7 +50,7 @@ extern "C" int w1_params_check(const w1_params* p) {
   if (p->max_iters < 1 || p->check_every < 1) return W1_EINVAL;
   // checks fall on multiples of check_every; the cap must be one of them
   if (p->max_iters % p->check_every != 0) return W1_EINVAL;
-  if (p->block_steps < 0 || p->block_steps > 28) return W1_EINVAL;
+  if (p->block_steps < 0 || p->block_steps > TILED_MAX_STEPS) return W1_EINVAL;
   if (p->step_scale >= 1.0) return W1_EINVAL;  // mu tau ||A||^2 < 1 (plain), mu tau < 1 (prox)
   return W1_OK;
 }
@@ -523,7 +523,7 @@ struct Op {
 int check_side(int n) { return (n >= 1 && n <= 8192) ? W1_OK : W1_EINVAL; }
 
 template <typename T>
-int op_plain_steps(int n, int metric, double scale, int steps, int block, void* m1, void* m2, void* phi,
+int op_plain_steps(int n, int metric, double scale, int steps, int block, int nwv, void* m1, void* m2, void* phi,
                    const void* rho, double* fpr, hipStream_t s) {
   Op<T> op(n, s);
   const double sc = scale > 0 ? scale : 0.5;
@@ -537,7 +537,9 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, void* 
     if (!(d.p[k] = op.plane())) return W1_ENOMEM;
   d.rho = (T*)rho;
   void* pp;
-  if (op.alloc(sizeof(double) * NQ * (size_t)cdiv(n + 1, 16) * cdiv(n + 1, 64) * 4 + 4096, &pp)) return W1_ENOMEM;
+  // one partial per tile at the deepest temporal block (the most tiles)
+  const size_t ntile = (size_t)cdiv(n + 1, TILED_RH - 2 * TILED_MAX_STEPS) * cdiv(n + 1, TILED_RW - 2 * TILED_MAX_STEPS);
+  if (op.alloc(sizeof(double) * NQ * ntile + 4096, &pp)) return W1_ENOMEM;
   d.part = (double*)pp;
   if (block < 0) {
     // resident kernel: the whole grid in one workgroup's LDS
@@ -548,7 +550,7 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, void* 
     std::vector<int> idx{0};
     int* di = op.upload(idx);
     if (!di) return W1_EDEVICE;
-    K<T>::plain_resident(s, di, 1, op.dd, op.dsc, n + 1, steps, 0);
+    K<T>::plain_resident(s, di, 1, op.dd, op.dsc, n + 1, steps, 0, metric);
     HIPCHK(hipGetLastError());
     SlotScalars h;
     st = op.read_scalars(&h);
@@ -558,8 +560,8 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, void* 
   }
   int st = op.commit(1);
   if (st) return st;
-  const int rh = 64;
-  const int T_ = std::max(1, std::min(block > 0 ? block : 1, rh / 2 - 6));
+  const int rh = TILED_RH;
+  const int T_ = std::max(1, std::min(block > 0 ? block : 1, TILED_MAX_STEPS));
   int done = 0, li = 0, lastS = 1;
   while (done < steps) {
     const int S = std::min(T_, steps - done);
@@ -567,7 +569,7 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, void* 
     auto w = op.tiled(0, n, rh, S);
     Work* dw = op.upload(w);
     if (!dw) return W1_EDEVICE;
-    K<T>::plain_tiled(s, dw, (int)w.size(), op.dd, op.dsc, li, S, rh, chk);
+    K<T>::plain_tiled(s, dw, (int)w.size(), op.dd, op.dsc, li, S, rh, chk, metric, nwv);
     ++li;
     done += S;
     lastS = S;
@@ -702,8 +704,8 @@ int op_evaluate(int n, int metric, const void* m1, const void* m2, const void* p
   if (!dsw || !dgw || !di || !dn) return W1_EDEVICE;
   K<T>::div_pre(s, dsw, (int)sw.size(), op.dd, op.dsc, 2, K_PROX, 0);
   op.poisson(dgw, (int)gw.size(), 6);
-  K<T>::eval_sums(s, dsw, (int)sw.size(), op.dd, op.dsc, K_PROX);
-  K<T>::eval_final(s, di, dn, 1, op.dd, op.dsc, K_PROX);
+  K<T>::eval_sums(s, dsw, (int)sw.size(), op.dd, op.dsc, K_PROX, 1);
+  K<T>::eval_final(s, di, dn, 1, op.dd, op.dsc, K_PROX, 1);
   HIPCHK(hipGetLastError());
   SlotScalars h;
   st = op.read_scalars(&h);
@@ -791,14 +793,32 @@ extern "C" int w1_op_prolong(int32_t nc, int32_t precision, const void* c_m1, co
 }
 
 extern "C" int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,
-                                 int32_t block_steps, void* m1, void* m2, void* phi, const void* rho,
+                                 int32_t block_steps, int32_t waves, void* m1, void* m2, void* phi, const void* rho,
                                  double* fpr_out, void* hip_stream) {
   if (check_side(n) || steps < 1 || (metric != 1 && metric != 2) || !m1 || !m2 || !phi || !rho) return W1_EINVAL;
-  if (step_scale >= 1.0 || block_steps > 28) return W1_EINVAL;
+  if (step_scale >= 1.0 || block_steps > TILED_MAX_STEPS || (waves != 0 && waves != 8 && waves != 16))
+    return W1_EINVAL;
+  const int nwv = waves ? waves : 8;
   hipStream_t s = (hipStream_t)hip_stream;
   return DISPATCH(precision,
-                  op_plain_steps<float>(n, metric, step_scale, steps, block_steps, m1, m2, phi, rho, fpr_out, s),
-                  op_plain_steps<double>(n, metric, step_scale, steps, block_steps, m1, m2, phi, rho, fpr_out, s));
+                  op_plain_steps<float>(n, metric, step_scale, steps, block_steps, nwv, m1, m2, phi, rho, fpr_out, s),
+                  op_plain_steps<double>(n, metric, step_scale, steps, block_steps, nwv, m1, m2, phi, rho, fpr_out,
+                                         s));
+}
+
+extern "C" int w1_tuner_table(char* buf, size_t len) {
+  const std::string t = tuner_table();
+  if (buf && len) {
+    const size_t k = std::min(len - 1, t.size());
+    std::memcpy(buf, t.data(), k);
+    buf[k] = 0;
+  }
+  return (int)t.size();
+}
+
+extern "C" int w1_tuner_reset(void) {
+  tuner_reset();
+  return W1_OK;
 }
 
 extern "C" int w1_op_prox_steps(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,

@@ -18,7 +18,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <tuple>
 
 namespace w1 {
 
@@ -55,7 +58,9 @@ static inline int gemm_t(int n) { return cdiv(n + 1, GEMM_T); }
 static inline int tiled_ti(int n, int rh, int S) { return cdiv(n + 1, rh - 2 * S); }
 static inline int tiled_tj(int n, int S) { return cdiv(n + 1, TILED_RW - 2 * S); }
 static inline int max_tiles(int n) {
-  return std::max(simple_tiles(n), std::max(gemm_t(n) * gemm_t(n), tiled_ti(n, 32, 1) * tiled_tj(n, 1)));
+  // the tiled kernel has the most tiles at its deepest temporal block
+  const int tiled = tiled_ti(n, TILED_RH, TILED_MAX_STEPS) * tiled_tj(n, TILED_MAX_STEPS);
+  return std::max(simple_tiles(n), std::max(gemm_t(n) * gemm_t(n), tiled));
 }
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -78,30 +83,156 @@ size_t request_bytes(const w1_params& p) {
   return b;
 }
 
-// Temporal-block depth and region height of the plain tiled kernel.  Deep
-// blocks cut HBM traffic and launches per iteration; the halo recomputation
-// grows as RH/(RH-2T) * 128/(128-2T).  Large active sets (HBM-bound) take a
-// moderate depth, small ones (latency-bound) the deepest depth that divides
-// the stop-test cadence, so a block of check_every iterations is whole
-// launches and its last launch carries the stop test.
-TileChoice choose_tiles(int precision, double active_nodes, int check_every, int requested) {
-  TileChoice c;
-  c.rh = 64;
-  const int maxT = c.rh / 2 - 6;                // keep most of the region as output
-  // T = 5 keeps 78% of a region as output; below ~2 workgroups per CU the
-  // launch is latency-bound and T = 10 halves the launches per block
-  const double wg5 = active_nodes / ((c.rh - 10) * (TILED_RW - 10.0));
-  int want = requested > 0 ? requested : (precision == W1_FP64 ? 2 : (wg5 >= 512 ? 5 : 10));
-  want = std::min(want, maxT);
-  int T = 1;
-  for (int t = std::min(want, check_every); t >= 1; --t)
-    if (check_every % t == 0) {
-      T = t;
-      break;
+// ---------------------------------------------------------------------------
+// Launch-shape autotuner for the plain tiled kernel.
+// Every shape (temporal depth T dividing check_every, 8 or 16 wavefronts per
+// workgroup) computes bit-identical iterates, so shapes can be tried on live
+// work: per (precision, check_every, requested depth, size class of the
+// active set) each candidate runs a few iteration blocks, timed with HIP
+// events (tiled launches of the block only), and the one with the lowest
+// time per node update is kept from then on.  Shared by all handles of the
+// process.
+// ---------------------------------------------------------------------------
+class Tuner {
+ public:
+  static constexpr int kTrials = 3;   // timed blocks per candidate (first one discarded)
+
+  TileChoice pick(int precision, double active_nodes, int check_every, int requested, int* arm_out,
+                  long* entry_out) {
+    std::lock_guard<std::mutex> g(mu_);
+    const int cls = size_class(active_nodes);
+    const auto key = std::make_tuple(precision, check_every, requested, cls);
+    auto it = tab_.find(key);
+    if (it == tab_.end()) {
+      Entry e;
+      e.key = key;
+      for (int nwv : {8, 16}) {
+        if (requested > 0) {
+          e.arms.push_back(Arm{nwv, depth_for(requested, check_every)});
+          continue;
+        }
+        // depth 1 only when nothing deeper divides the cadence
+        for (int t = 2; t <= std::min(check_every, TILED_MAX_STEPS); ++t)
+          if (check_every % t == 0) e.arms.push_back(Arm{nwv, t});
+        if (e.arms.empty() || e.arms.back().nwv != nwv) e.arms.push_back(Arm{nwv, depth_for(1, check_every)});
+      }
+      it = tab_.emplace(key, e).first;
+      order_.push_back(key);
     }
-  c.steps = T;
-  return c;
+    Entry& e = it->second;
+    int a = e.best;
+    if (a < 0) {
+      bool measured = true;
+      for (auto& A : e.arms) measured = measured && A.done >= kTrials;
+      if (measured) {
+        a = 0;
+        for (size_t c = 1; c < e.arms.size(); ++c)
+          if (e.arms[c].cost() < e.arms[a].cost()) a = (int)c;
+        e.best = a;
+      } else {
+        // round robin, preferring candidates with the fewest blocks issued
+        int least = 1 << 30;
+        for (auto& A : e.arms) least = std::min(least, A.seen);
+        for (size_t k = 0; k < e.arms.size(); ++k) {
+          const int c = (int)((e.rr + k) % e.arms.size());
+          if (e.arms[c].seen == least) {
+            a = c;
+            break;
+          }
+        }
+        e.rr = (a + 1) % (int)e.arms.size();
+        e.arms[a].seen++;
+      }
+    }
+    TileChoice c;
+    c.rh = TILED_RH;
+    c.steps = e.arms[a].T;
+    c.nwv = e.arms[a].nwv;
+    *arm_out = e.best < 0 ? a : -1;   // only exploration blocks are timed
+    *entry_out = (long)(std::find(order_.begin(), order_.end(), key) - order_.begin());
+    return c;
+  }
+
+  void report(long entry, int arm, double ms, double node_updates) {
+    if (arm < 0 || node_updates <= 0) return;
+    std::lock_guard<std::mutex> g(mu_);
+    if (entry < 0 || entry >= (long)order_.size()) return;
+    Entry& e = tab_[order_[entry]];
+    if (arm >= (int)e.arms.size()) return;
+    Arm& A = e.arms[arm];
+    A.done++;
+    if (A.done == 1) return;   // first block of a shape: cold caches, not counted
+    A.ms += ms;
+    A.units += node_updates;
+  }
+
+  // "precision/check_every/requested/class: best nwv x T (ns per node update)"
+  std::string table() {
+    std::lock_guard<std::mutex> g(mu_);
+    std::string out = "[";
+    for (size_t i = 0; i < order_.size(); ++i) {
+      const Entry& e = tab_[order_[i]];
+      char buf[256];
+      std::snprintf(buf, sizeof buf, "%s{\"precision\":%d,\"check_every\":%d,\"requested\":%d,\"class\":%d,",
+                    i ? "," : "", std::get<0>(e.key), std::get<1>(e.key), std::get<2>(e.key), std::get<3>(e.key));
+      out += buf;
+      out += "\"arms\":[";
+      for (size_t a = 0; a < e.arms.size(); ++a) {
+        const Arm& A = e.arms[a];
+        std::snprintf(buf, sizeof buf, "%s{\"waves\":%d,\"T\":%d,\"blocks\":%d,\"ns_per_update\":%.6g}",
+                      a ? "," : "", A.nwv, A.T, A.done, A.units > 0 ? A.ms * 1e6 / A.units : -1.0);
+        out += buf;
+      }
+      std::snprintf(buf, sizeof buf, "],\"best\":%d}", e.best);
+      out += buf;
+    }
+    return out + "]";
+  }
+
+  void reset() {
+    std::lock_guard<std::mutex> g(mu_);
+    tab_.clear();
+    order_.clear();
+  }
+
+ private:
+  struct Arm {
+    int nwv, T;
+    int seen = 0, done = 0;
+    double ms = 0, units = 0;
+    double cost() const { return units > 0 ? ms / units : 1e300; }
+  };
+  using Key = std::tuple<int, int, int, int>;
+  struct Entry {
+    Key key;
+    std::vector<Arm> arms;
+    int rr = 0, best = -1;
+  };
+  // size classes of the active set: factors of 4 in node count
+  static int size_class(double nodes) {
+    int c = 0;
+    for (double x = nodes / 16384.0; x >= 4.0 && c < 12; x /= 4.0) ++c;
+    return c;
+  }
+  // the deepest depth dividing check_every that is not above `want`
+  static int depth_for(int want, int check_every) {
+    want = std::min(want, TILED_MAX_STEPS);
+    for (int t = std::min(want, check_every); t >= 1; --t)
+      if (check_every % t == 0) return t;
+    return 1;
+  }
+  std::mutex mu_;
+  std::map<Key, Entry> tab_;
+  std::vector<Key> order_;
+};
+
+static Tuner& g_tuner() {
+  static Tuner* t = new Tuner();
+  return *t;
 }
+
+std::string tuner_table() { return g_tuner().table(); }
+void tuner_reset() { g_tuner().reset(); }
 
 // ---------------------------------------------------------------------------
 // caching device allocator for solve state (exact-size reuse)
@@ -354,9 +485,18 @@ class Batch : public BatchBase {
   }
   ~Batch() override {
     (void)hipStreamSynchronize(st_);
+    for (auto& t : tune_pending_) {
+      tune_pool_.push_back(t.a);
+      tune_pool_.push_back(t.b);
+    }
+    for (auto e : tune_pool_) (void)hipEventDestroy(e);
     for (auto* r : slots_)
       if (r && r->mem) g_blocks.put(r->bytes, r->mem);
-    for (auto& kv : lists_) (void)hipFree(kv.second.d);
+    for (auto& kv : lists_) {
+      (void)hipFree(kv.second.d);
+      (void)hipHostFree(kv.second.h);
+      if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
+    }
     (void)hipFree(ddesc_);
     (void)hipFree(dsc_);
     (void)hipHostFree(hsc_);
@@ -471,10 +611,11 @@ class Batch : public BatchBase {
       if (st) return fail(st);
     }
     std::vector<Request*> R;
-    std::map<std::pair<int, int>, std::vector<Request*>> P, X;   // by (check_every, rule)
+    // grouped by (check_every, rule, metric): one launch sequence per group
+    std::map<std::tuple<int, int, int>, std::vector<Request*>> P, X;
     for (auto* r : slots_) {
       if (!r || r->state != Request::RUN) continue;
-      const auto key = std::make_pair(r->prm.check_every, r->prm.stop_rule);
+      const auto key = std::make_tuple(r->prm.check_every, r->prm.stop_rule, r->prm.metric);
       if (r->kind == K_PROX) X[key].push_back(r);
       else if (r->resident_level) R.push_back(r);
       else P[key].push_back(r);
@@ -634,6 +775,13 @@ class Batch : public BatchBase {
   int read_scalars() {
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
+    for (auto& t : tune_pending_) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) g_tuner().report(t.entry, t.arm, ms, t.units);
+      tune_pool_.push_back(t.a);
+      tune_pool_.push_back(t.b);
+    }
+    tune_pending_.clear();
     if (prof_.on) {
       for (auto& ru : resident_pending_) {
         double u = 0;
@@ -647,20 +795,6 @@ class Batch : public BatchBase {
       prof_.harvest();
     }
     resident_pending_.clear();
-    return W1_OK;
-  }
-
-  // status RUN, iteration 0, iterate in plane set A
-  int reset_scalars(const std::vector<Request*>& rs) {
-    int st = W1_OK;
-    for (auto* r : rs) {
-      SlotScalars z{};
-      z.status = ST_RUN;
-      std::vector<SlotScalars> v(1, z);
-      SlotScalars* src = arena_.put(v, &st);
-      if (st) return st;
-      HIPCHK(hipMemcpyAsync(dsc_ + r->slot, src, sizeof(SlotScalars), hipMemcpyDeviceToDevice, st_));
-    }
     return W1_OK;
   }
 
@@ -722,12 +856,15 @@ class Batch : public BatchBase {
   }
 
   // device lists cached until the set of running slots or their levels
-  // change (generation counter); staged through the per-step arena
+  // change (generation counter); each list has its own pinned staging copy,
+  // rewritten only after the previous upload from it has completed
   struct DevList {
     void* d = nullptr;
+    void* h = nullptr;
     size_t cap = 0;
     int n = 0;
     uint64_t gen = ~0ull;
+    hipEvent_t ev = nullptr;
   };
   template <typename X, typename F>
   X* cached(const std::string& key, F build, int* count, int* status) {
@@ -735,19 +872,36 @@ class Batch : public BatchBase {
     if (L.gen != gen_) {
       std::vector<X> v = build();
       const size_t bytes = std::max<size_t>(v.size() * sizeof(X), 16);
+      if (L.ev && hipEventSynchronize(L.ev) != hipSuccess) {
+        *status = W1_EDEVICE;
+        return nullptr;
+      }
       if (bytes > L.cap) {
-        (void)hipFree(L.d);  // no kernel of this step has used it yet
+        // kernels queued earlier may still read the old list
+        if (L.d && hipStreamSynchronize(st_) != hipSuccess) {
+          *status = W1_EDEVICE;
+          return nullptr;
+        }
+        (void)hipFree(L.d);
+        (void)hipHostFree(L.h);
+        L.d = L.h = nullptr;
         L.cap = bytes * 2;
-        if (hipMalloc(&L.d, L.cap) != hipSuccess) {
-          L.d = nullptr;
+        if (hipMalloc(&L.d, L.cap) != hipSuccess ||
+            hipHostMalloc(&L.h, L.cap, hipHostMallocDefault) != hipSuccess) {
           L.cap = 0;
           *status = W1_ENOMEM;
+          g_err = "work list allocation failed";
           return nullptr;
         }
       }
-      X* src = arena_.put(v, status);
-      if (*status) return nullptr;
-      if (hipMemcpyAsync(L.d, src, v.size() * sizeof(X), hipMemcpyDeviceToDevice, st_) != hipSuccess) {
+      if (!L.ev && hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess) {
+        *status = W1_EDEVICE;
+        return nullptr;
+      }
+      if (!v.empty()) std::memcpy(L.h, v.data(), v.size() * sizeof(X));
+      if (hipMemcpyAsync(L.d, L.h, std::max<size_t>(v.size() * sizeof(X), 1), hipMemcpyHostToDevice, st_) !=
+              hipSuccess ||
+          hipEventRecord(L.ev, st_) != hipSuccess) {
         *status = W1_EDEVICE;
         return nullptr;
       }
@@ -851,9 +1005,8 @@ class Batch : public BatchBase {
       unsigned mask = 0;
       for (auto* r : good) mask |= r->kind == K_PLAIN ? 0x7u : 0x3Fu;
       K<T>::zero(st_, dw, (int)w.size(), ddesc_, mask);
+      K<T>::reset_scalars(st_, dw, (int)w.size(), dsc_);
     }
-    st = reset_scalars(good);
-    if (st) return st;
     HIPCHK(hipGetLastError());
     return W1_OK;
   }
@@ -865,7 +1018,7 @@ class Batch : public BatchBase {
     r->t_level = now_seconds();
     const bool allow = !(r->prm.flags & W1_FLAG_NO_RESIDENT);
     r->resident_level = r->kind == K_PLAIN && allow && (r->sides[l] + 1) <= K<T>::plain_resident_max_side();
-    dirty_.push_back(r->slot);
+    // descriptors are fixed at admission; only the work lists change
     ++gen_;
   }
 
@@ -874,22 +1027,24 @@ class Batch : public BatchBase {
   int launch_resident(std::vector<Request*>& R, int chunk) {
     int st = W1_OK;
     int maxside = 0;
-    std::map<int, std::vector<int>> by_ce;
+    // one launch per (check_every, metric)
+    std::map<std::pair<int, int>, std::vector<int>> by_ce;
     for (auto* r : R) {
-      by_ce[r->prm.check_every].push_back(dx(r, r->level));
+      by_ce[std::make_pair(r->prm.check_every, r->prm.metric)].push_back(dx(r, r->level));
       maxside = std::max(maxside, r->sides[r->level] + 1);
     }
     for (auto& kv : by_ce) {
       int* di = arena_.put(kv.second, &st);
       if (st) return st;
-      const int c = chunk > 0 ? ((chunk + kv.first - 1) / kv.first) * kv.first : 0;
+      const int ce = kv.first.first;
+      const int c = chunk > 0 ? ((chunk + ce - 1) / ce) * ce : 0;
       const int pi = prof_.begin();
-      K<T>::plain_resident(st_, di, (int)kv.second.size(), ddesc_, dsc_, maxside, kv.first, c);
+      K<T>::plain_resident(st_, di, (int)kv.second.size(), ddesc_, dsc_, maxside, ce, c, kv.first.second);
       prof_.end(pi, W1_FAM_PLAIN_RESIDENT, 0, 0, 0);
       if (pi >= 0) {
         std::vector<Request*> grp;
         for (auto* r : R)
-          if (r->prm.check_every == kv.first) grp.push_back(r);
+          if (r->prm.check_every == ce && r->prm.metric == kv.first.second) grp.push_back(r);
         resident_pending_.emplace_back(pi, grp);
       }
     }
@@ -905,19 +1060,31 @@ class Batch : public BatchBase {
     double nodes = 0;
     for (auto* r : P) nodes += node_count(r->sides[r->level]);
     const int prec = sizeof(T) == 8 ? W1_FP64 : W1_FP32;
-    const TileChoice tc = choose_tiles(prec, nodes, ce, P[0]->prm.block_steps);
-    const int nl = ce / tc.steps;   // choose_tiles returns a divisor of ce
+    int arm = -1;
+    long entry = -1;
+    const TileChoice tc = g_tuner().pick(prec, nodes, ce, P[0]->prm.block_steps, &arm, &entry);
+    const int nl = ce / tc.steps;   // the tuner only offers divisors of ce
     auto lv = at_level(P);
     const std::string key = "P" + std::to_string(group) + "_" + std::to_string(tc.rh) + "_" + std::to_string(tc.steps);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (arm >= 0) {
+      t0 = tune_event();
+      t1 = tune_event();
+    }
     int nw = 0;
     Work* w = cached<Work>(key, [&] { return tiled_work(lv, tc.rh, tc.steps); }, &nw, &st);
     if (st) return st;
     const double wb = 7.0 * sizeof(T);  // read m1 m2 phi rho, write m1 m2 phi
+    if (t0 && t1) HIPCHK(hipEventRecord(t0, st_));
     for (int li = 0; li < nl; ++li) {
       const bool chk = fpr && li == nl - 1;
       const int pi = prof_.begin();
-      K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, li, tc.steps, tc.rh, chk);
+      K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, li, tc.steps, tc.rh, chk, P[0]->prm.metric, tc.nwv);
       prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * tc.steps, nodes * tc.steps * wb, 0);
+    }
+    if (t0 && t1) {
+      HIPCHK(hipEventRecord(t1, st_));
+      tune_pending_.push_back(TunePend{t0, t1, entry, arm, nodes * ce});
     }
     int ns = 0;
     int* di;
@@ -1032,9 +1199,9 @@ class Batch : public BatchBase {
       Work* dw = arena_.put(w, &st);
       if (st) return st;
       K<T>::prolong(st_, dw, (int)w.size(), ddesc_, dsc_, pass == 0 ? K_PLAIN : K_PROX);
+      // after the prolongation, which reads the coarse plane set
+      K<T>::reset_scalars(st_, dw, (int)w.size(), dsc_);
     }
-    st = reset_scalars(up);
-    if (st) return st;
     HIPCHK(hipGetLastError());
     return W1_OK;
   }
@@ -1042,12 +1209,14 @@ class Batch : public BatchBase {
   // -- FP64 certificate and field export on the finest level ---------------
   int finalize(std::vector<Request*>& fin) {
     int st = W1_OK;
-    for (int pass = 0; pass < 2; ++pass) {
+    // passes: (plain, prox) x (with, without the certificate)
+    for (int pass = 0; pass < 4; ++pass) {
+      const int kind = (pass & 1) == 0 ? K_PLAIN : K_PROX;
+      const int cert = pass < 2 ? 1 : 0;
       std::vector<Request*> grp;
       for (auto* r : fin)
-        if ((r->kind == K_PLAIN) == (pass == 0)) grp.push_back(r);
+        if (r->kind == kind && (cert == 0) == ((r->prm.flags & W1_FLAG_NO_CERT) != 0)) grp.push_back(r);
       if (grp.empty()) continue;
-      const int kind = pass == 0 ? K_PLAIN : K_PROX;
       auto lv = at_finest(grp);
       auto sw = simple_work(lv);
       auto gw = gemm_work(lv);
@@ -1059,13 +1228,15 @@ class Batch : public BatchBase {
         K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 1, kind, 0);
         poisson(dgw, (int)gw.size(), 8, 0);
       }
-      K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 2, kind, 0);
-      poisson(dgw, (int)gw.size(), 6, 0);
-      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind);
+      if (cert) {
+        K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 2, kind, 0);
+        poisson(dgw, (int)gw.size(), 6, 0);
+      }
+      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, cert);
       int *di, *dn;
       st = reduce_lists(lv, simple_tiles_f, &di, &dn);
       if (st) return st;
-      K<T>::eval_final(st_, di, dn, (int)grp.size(), ddesc_, dsc_, kind);
+      K<T>::eval_final(st_, di, dn, (int)grp.size(), ddesc_, dsc_, kind, cert);
       K<T>::export_fields(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind);
       HIPCHK(hipGetLastError());
     }
@@ -1087,6 +1258,26 @@ class Batch : public BatchBase {
     ++gen_;
     return W1_OK;
   }
+
+  // timing events of the autotuner's exploration blocks
+  struct TunePend {
+    hipEvent_t a, b;
+    long entry;
+    int arm;
+    double units;
+  };
+  hipEvent_t tune_event() {
+    if (!tune_pool_.empty()) {
+      hipEvent_t e = tune_pool_.back();
+      tune_pool_.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  std::vector<TunePend> tune_pending_;
+  std::vector<hipEvent_t> tune_pool_;
 
   int cap_;
   hipStream_t st_;

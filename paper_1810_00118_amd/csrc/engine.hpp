@@ -71,9 +71,12 @@ std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t strea
 
 // Tuning choice for the plain tiled kernel.
 struct TileChoice {
-  int rh;      // region rows (32 or 64)
+  int rh;      // region rows
   int steps;   // temporal block depth
+  int nwv;     // wavefronts per workgroup (8 or 16)
 };
-TileChoice choose_tiles(int precision, double active_nodes, int check_every, int requested);
+// launch-shape autotuner of the plain tiled kernel (process-wide)
+std::string tuner_table();   // JSON array of the tuner's entries
+void tuner_reset();
 
 }  // namespace w1

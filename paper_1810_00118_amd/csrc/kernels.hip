@@ -204,6 +204,16 @@ __global__ __launch_bounds__(256) void k_zero(const Work* __restrict__ work, con
   })
 }
 
+// a slot's scalars at a level start: status RUN, iteration 0, iterate in
+// plane set A (the list's item with tile index 0 writes them)
+__global__ __launch_bounds__(64) void k_reset_scalars(const Work* __restrict__ work, SlotScalars* __restrict__ scal) {
+  const Work w = work[blockIdx.x];
+  if (w.x < 0 || w.w != 0 || threadIdx.x != 0) return;
+  SlotScalars z{};
+  z.status = ST_RUN;
+  scal[w.x / MAXL] = z;
+}
+
 // copy a dense (pitch n+1) array into / out of a plane
 template <typename T>
 __global__ __launch_bounds__(256) void k_import(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
@@ -491,12 +501,14 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 #ifndef W1_TILED_WPE_CHECK
 #define W1_TILED_WPE_CHECK 4
 #endif
-template <typename T, bool CHECK, int WAVES_PER_EU = (sizeof(T) == 4 ? (CHECK ? W1_TILED_WPE_CHECK : W1_TILED_WPE) : 2)>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU, 8))) void k_plain_tiled(
-    const Work* __restrict__ work,
-                                                     const SlotDesc<T>* __restrict__ desc,
-                                                     const SlotScalars* __restrict__ scal, int li, int steps) {
-  constexpr int RH = 64, RW = TILED_RW, NWV = 8, NR = 8, NC = 2;
+template <typename T, bool CHECK, int METRIC, int NWV = 8,
+          int WAVES_PER_EU = (NWV == 16 ? (sizeof(T) == 4 ? 8 : 4)
+                                        : (sizeof(T) == 4 ? (CHECK ? W1_TILED_WPE_CHECK : W1_TILED_WPE) : 2))>
+__global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU, 8))) void k_plain_tiled(
+    const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc, const SlotScalars* __restrict__ scal,
+    int li, int steps) {
+  constexpr int RH = TILED_RH, RW = TILED_RW, NR = RH / NWV, NC = 2;
+  static_assert(NR * NWV == RH, "wavefronts split the region's rows evenly");
   __shared__ T Bp[NWV][RW];   // first potential row of each strip
   __shared__ T Bb[NWV][RW];   // last extrapolated-flux row (axis 1) of each strip
   __shared__ double lds[NWV * NQ];
@@ -505,6 +517,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
   const SlotScalars& sc = scal[w.x / MAXL];
   if (sc.status != ST_RUN) return;
   const SlotDesc<T>& d = desc[w.x];
+  if (d.metric != METRIC) return;
   const int n = d.n, pitch = d.pitch, S = steps;
   const int OH = RH - 2 * S, OW = RW - 2 * S;
   const int gi0 = w.y * OH - S, gj0 = w.z * OW - S;
@@ -514,8 +527,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
   const T* __restrict__ sph = d.p[3 * rs + 2];
   const T* __restrict__ srho = d.rho;
   const T ih = d.ih, mu = d.mu, tau = d.tau;
-  const int metric = d.metric;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int metric = METRIC;   // one launch per ground metric
+  // the wavefront index is uniform across the wavefront: held in a scalar
+  // register, every row test below is a scalar branch
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r0 = wv * NR;
 
   // per-node geometry: row / column inside the grid, has-next flags
@@ -534,6 +549,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
     chr[b] = gj < n && c + 1 < RW;
   }
 
+  // a row of the strip, or a column half, that lies wholly outside the grid
+  // keeps zero iterates: its arithmetic is skipped (wave-uniform test)
+  bool hact[NC];
+#pragma unroll
+  for (int b = 0; b < NC; ++b) hact[b] = gj0 + 64 * b <= n;
+
   T m1[NR][NC], m2[NR][NC], ph[NR][NC], rh[NR][NC], b1[NR][NC], b2[NR][NC];
 #pragma unroll
   for (int a = 0; a < NR; ++a)
@@ -545,6 +566,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
       m2[a][b] = in ? sm2[off] : T(0);
       ph[a][b] = in ? sph[off] : T(0);
       rh[a][b] = in ? srho[off] : T(0);
+      b1[a][b] = T(0);
+      b2[a][b] = T(0);
     }
 
   // Stop-test partials of the last step (CHECK), summed over the interior.
@@ -574,6 +597,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
       const T h0 = lane_read(ph[a][1], 0);
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
+        if (!(rin[a] && hact[b])) continue;
         const T pc = ph[a][b];
         const T pd = a + 1 < NR ? ph[a + 1 < NR ? a + 1 : a][b] : (wv + 1 < NWV ? Bp[wv + 1 < NWV ? wv + 1 : wv][lane + 64 * b] : pc);
         const T pr = b == 0 ? (lane == 63 ? h0 : x0) : x1;
@@ -616,6 +640,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
       }
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
+        if (!(rin[a] && hact[b])) continue;
         const T b1u = a > 0 ? b1[a > 0 ? a - 1 : 0][b] : (wv > 0 ? Bb[wv > 0 ? wv - 1 : 0][lane + 64 * b] : T(0));
         const T b2l = b == 0 ? y0 : (lane == 0 ? g63 : y1);
         T pn = plain_potential_(ph[a][b], b1[a][b], b1u, b2[a][b], b2l, rh[a][b], ih, tau);
@@ -644,7 +669,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
   if constexpr (CHECK) {
     step(std::true_type{});
     double v[NQ] = {(double)q0, (double)q1, (double)q2, 0, 0, 0, 0, 0};
-    block_reduce_<512, 4>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+    block_reduce_<NWV * 64, 4>(v, d.part + (size_t)w.w * NQ, lds, 0u);
   } else {
     step(std::false_type{});
   }
@@ -667,20 +692,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES_PER_E
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 1, whole level resident in one workgroup's LDS.
-// For grids whose potential and one extrapolated-flux plane fit in LDS
-// ((n+1)^2 * 2 * sizeof(T) bytes), one 512-thread workgroup per pair runs
-// the level to its stop test or cap without touching HBM in between.  The
-// flux stays in registers; the divergence is split into its two axis terms
-// so that one LDS plane carries both extrapolated components in turn.
-// Stop tests (both rules) run every `check_every` iterations and at the cap;
-// on those iterations the previous iterate is parked in the slot's spare
-// planes 3..5 and dm in planes 6, 7 (global memory, same workgroup).
-// Reads and writes plane set A.  A launch runs at most `chunk` iterations
-// (0: no limit) and resumes from the slot's iteration count, so long
-// levels run in bounded pieces beside other work.
+// Algorithm 1, whole level resident in one workgroup.
+// For grids whose potential and both extrapolated-flux planes fit in LDS
+// (3 (n+1)^2 sizeof(T) bytes), one 512-thread workgroup per pair runs the
+// level to its stop test or cap without touching HBM in between.  Node e
+// (row-major, dense) belongs to thread e mod 512; the flux, rho and the
+// node's own potential and extrapolated flux stay in registers, the planes
+// in LDS carry the neighbours: an iteration is two phases with one barrier
+// each (flux half writing 2 m+ - m, potential half reading it at (i-1, j)
+// and (i, j-1)).  Stop tests (both rules) run every `check_every`
+// iterations and at the cap, with the flux change (FPR) or the new flux
+// (KKT) exchanged through the same planes.  Reads and writes plane set A.
+// A launch runs at most `chunk` iterations (0: no limit) and resumes from
+// the slot's iteration count, so long levels can run in bounded pieces.
 // ---------------------------------------------------------------------------
-template <typename T, int NPT>
+template <typename T, int NPT, int METRIC>
 __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __restrict__ idx,
                                                                 const SlotDesc<T>* __restrict__ desc,
                                                                 SlotScalars* __restrict__ scal, int check_every,
@@ -690,29 +716,27 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
   static_assert(NPT <= 32, "column masks hold 32 nodes");
   const int x = idx[blockIdx.x];
   const SlotDesc<T>& d = desc[x];
+  if (d.metric != METRIC) return;
   SlotScalars& sc = scal[x / MAXL];
   const int n = d.n, N = n + 1, NN = N * N, pitch = d.pitch;
   const int last_row = NN - N;          // e >= last_row  <=>  row n
-  double* red = smem_d;                 // [NT/64 * NQ]
+  double* red = smem_d;                 // [16 * NQ]
   double* res = smem_d + 16 * NQ;       // [NQ]
   int* flag = (int*)(smem_d + 17 * NQ);
-  T* Lp = (T*)(smem_d + 18 * NQ);
-  T* Lb = Lp + NN;
-  // spare planes of the level, indexed densely (e = r*N + c < NN <= N*pitch)
-  T* __restrict__ o1 = d.p[3];
-  T* __restrict__ o2 = d.p[4];
-  T* __restrict__ op = d.p[5];
-  T* __restrict__ e1p = d.p[6];
-  T* __restrict__ e2p = d.p[7];
+  T* Lp = (T*)(smem_d + 18 * NQ);       // potential
+  T* Lb = Lp + NN;                      // extrapolated flux, axis 1
+  T* Lc = Lb + NN;                      // extrapolated flux, axis 2
   const T ih = d.ih, mu = d.mu, tau = d.tau;
-  const int metric = d.metric;
+  constexpr int metric = METRIC;   // one launch per ground metric
   const int cap = d.cap;
   const double h2 = d.h * d.h;
 
-  T m1[NPT], m2[NPT], rh[NPT], b2[NPT], ac[NPT];
+  T m1[NPT], m2[NPT], rh[NPT], pv[NPT], b1[NPT], b2[NPT];
   unsigned first_col = 0u, last_col = 0u;   // bit s: node s is on column 0 / column n
+#pragma unroll
   for (int s = 0; s < NPT; ++s) {
     const int e = threadIdx.x + NT * s;
+    m1[s] = m2[s] = rh[s] = pv[s] = b1[s] = b2[s] = T(0);
     if (e < NN) {
       const int r = e / N, c = e - r * N;
       if (c == 0) first_col |= 1u << s;
@@ -721,11 +745,9 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
       m1[s] = d.p[0][off];
       m2[s] = d.p[1][off];
       rh[s] = d.rho[off];
-      Lp[e] = d.p[2][off];
-    } else {
-      m1[s] = m2[s] = rh[s] = T(0);
+      pv[s] = d.p[2][off];
+      Lp[e] = pv[s];
     }
-    b2[s] = ac[s] = T(0);
   }
   __syncthreads();
 
@@ -738,105 +760,81 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
   while (k < kend) {
     ++k;
     const bool chk = (k % check_every == 0) || (k >= cap);
-    if (chk && fpr) {
-      for (int s = 0; s < NPT; ++s) {
-        const int e = threadIdx.x + NT * s;
-        if (e < NN) {
-          o1[e] = m1[s];
-          o2[e] = m2[s];
-          op[e] = Lp[e];
-        }
-      }
-    }
-    // flux half; Lb <- mbar1
+    // flux half: potential neighbours from LDS; 2 m+ - m to Lb, Lc
+    T e1[NPT], e2[NPT];
 #pragma unroll
     for (int s = 0; s < NPT; ++s) {
       const int e = threadIdx.x + NT * s;
+      e1[s] = e2[s] = T(0);
       if (e < NN) {
         const bool hd = e < last_row, hr = !((last_col >> s) & 1u);
-        const T pc = Lp[e];
+        const T pc = pv[s];
         const T pd = hd ? Lp[e + N] : pc;
         const T pr = hr ? Lp[e + 1] : pc;
         T n1, n2;
         plain_flux_(m1[s], m2[s], pc, pd, pr, hd, hr, ih, mu, metric, n1, n2);
-        Lb[e] = (n1 + n1) - m1[s];
+        b1[s] = (n1 + n1) - m1[s];
         b2[s] = (n2 + n2) - m2[s];
+        Lb[e] = b1[s];
+        Lc[e] = b2[s];
+        e1[s] = n1 - m1[s];
+        e2[s] = n2 - m2[s];
         m1[s] = n1;
         m2[s] = n2;
       }
     }
     __syncthreads();
+    // potential half: extrapolated flux at (i-1, j) and (i, j-1)
+    T dp[NPT];
 #pragma unroll
     for (int s = 0; s < NPT; ++s) {
       const int e = threadIdx.x + NT * s;
-      if (e < NN) ac[s] = Lb[e] - (e >= N ? Lb[e - N] : T(0));
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < NPT; ++s) {
-      const int e = threadIdx.x + NT * s;
-      if (e < NN) Lb[e] = b2[s];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < NPT; ++s) {
-      const int e = threadIdx.x + NT * s;
+      dp[s] = T(0);
       if (e < NN) {
-        const T pc = Lp[e];
-        const T bl = ((first_col >> s) & 1u) ? T(0) : Lb[e - 1];
-        const T dv = (ac[s] + (b2[s] - bl)) * ih;
-        Lp[e] = fma_(tau, dv - rh[s], pc);
+        const T b1u = e >= N ? Lb[e - N] : T(0);
+        const T b2l = ((first_col >> s) & 1u) ? T(0) : Lc[e - 1];
+        const T pn = plain_potential_(pv[s], b1[s], b1u, b2[s], b2l, rh[s], ih, tau);
+        dp[s] = pn - pv[s];
+        pv[s] = pn;
+        Lp[e] = pn;
       }
     }
     __syncthreads();
     if (!chk) continue;
 
     // ---- stop test ----
-    double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (fpr) {
-      for (int s = 0; s < NPT; ++s) {
-        const int e = threadIdx.x + NT * s;
-        if (e < NN) {
-          e1p[e] = m1[s] - o1[e];
-          e2p[e] = m2[s] - o2[e];
-        }
+    // exchange the flux change (FPR) or the new flux (KKT) through Lb, Lc;
+    // every read of those planes in this iteration is behind the barrier
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      if (e < NN) {
+        Lb[e] = fpr ? e1[s] : m1[s];
+        Lc[e] = fpr ? e2[s] : m2[s];
       }
-      __syncthreads();
-      for (int s = 0; s < NPT; ++s) {
-        const int e = threadIdx.x + NT * s;
-        if (e < NN) {
-          const T f1 = e1p[e], f2 = e2p[e];
-          const T u1 = e >= N ? e1p[e - N] : T(0);
-          const T l2 = ((first_col >> s) & 1u) ? T(0) : e2p[e - 1];
-          const double adm = (double)(((f1 - u1) + (f2 - l2)) * ih);
-          const T pn = Lp[e];
-          const double ep = (double)(pn - op[e]);
-          v[0] += (double)f1 * (double)f1 + (double)f2 * (double)f2;
+    }
+    __syncthreads();
+    double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      if (e < NN) {
+        const T u1 = e >= N ? Lb[e - N] : T(0);
+        const T l2 = ((first_col >> s) & 1u) ? T(0) : Lc[e - 1];
+        if (fpr) {
+          const double adm = (double)(((e1[s] - u1) + (e2[s] - l2)) * ih);
+          const double ep = (double)dp[s];
+          v[0] += (double)e1[s] * (double)e1[s] + (double)e2[s] * (double)e2[s];
           v[1] += ep * ep;
           v[2] += ep * adm;
-          if (!(finite_(m1[s]) && finite_(m2[s]) && finite_(pn))) v[3] += 1.0;
-        }
-      }
-    } else {
-      // KKT: residual A m - rho, Lipschitz excess of grad phi, cost, <phi, rho>
-      for (int s = 0; s < NPT; ++s) {
-        const int e = threadIdx.x + NT * s;
-        if (e < NN) {
-          e1p[e] = m1[s];
-          e2p[e] = m2[s];
-        }
-      }
-      __syncthreads();
-      for (int s = 0; s < NPT; ++s) {
-        const int e = threadIdx.x + NT * s;
-        if (e < NN) {
+          if (!(finite_(m1[s]) && finite_(m2[s]) && finite_(pv[s]))) v[3] += 1.0;
+        } else {
+          // KKT: residual A m - rho, Lipschitz excess of grad phi, cost, <phi, rho>
           const bool hd = e < last_row, hr = !((last_col >> s) & 1u);
-          const T u1 = e >= N ? e1p[e - N] : T(0);
-          const T l2 = ((first_col >> s) & 1u) ? T(0) : e2p[e - 1];
           const double am = (double)(((m1[s] - u1) + (m2[s] - l2)) * ih);
           const double rr = (double)rh[s];
           const double res1 = am - rr;
-          const T pc = Lp[e];
+          const T pc = pv[s];
           const T g1 = hd ? (Lp[e + N] - pc) * ih : T(0);
           const T g2 = hr ? (Lp[e + 1] - pc) * ih : T(0);
           const double gq = (double)norm_q_(g1, g2, metric);
@@ -851,7 +849,6 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
         }
       }
     }
-    __syncthreads();
     block_reduce_<NT>(v, res, red, 0u);
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -882,6 +879,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
     if (status != ST_RUN) break;
   }
 
+#pragma unroll
   for (int s = 0; s < NPT; ++s) {
     const int e = threadIdx.x + NT * s;
     if (e < NN) {
@@ -889,7 +887,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
       const size_t off = (size_t)r * pitch + c;
       d.p[0][off] = m1[s];
       d.p[1][off] = m2[s];
-      d.p[2][off] = Lp[e];
+      d.p[2][off] = pv[s];
     }
   }
   if (threadIdx.x == 0) {
@@ -1133,6 +1131,9 @@ __global__ __launch_bounds__(256) void k_prox_post(const Work* __restrict__ work
 // stop test after a block: reduce the slot's partials, form R^k / G^k or the
 // normalised KKT residual, compare with tol_l and the cap.
 // ---------------------------------------------------------------------------
+// Stop measure from the reduced partials r[0..NQ): R^k (plain) or G^k (prox)
+// of eq. (pd_stop) / eq. (pdhg_stop) for RULE_FPR, else the normalised KKT
+// residual.
 __device__ double measure_from_(const double* r, int kind, int rule, double h2, double mud, double taud, int NN) {
   if (rule == RULE_FPR) {
     if (r[3] > 0.0) return NAN;
@@ -1184,14 +1185,15 @@ __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, cons
 
 // ---------------------------------------------------------------------------
 // FP64 certificate (finest level): needs the Poisson correction
-// corr = (A A*)^{-1}(A m - rho) in plane 6 and, for prox, psi in plane 8.
+// corr = (A A*)^{-1}(A m - rho) in plane 6 (read only with cert) and, for
+// prox, psi in plane 8.
 // q0 sum ||m||_p, q1 sum pot*rho, q2 sum ||m + grad+ corr||_p,
 // q3 sum |grad+ corr|^2, q4 sum excess^2, q5 max ||grad pot||_q (max),
 // q6 sum pot, q7 sum rho.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
-                                                   const SlotScalars* __restrict__ scal, int kind) {
+                                                   const SlotScalars* __restrict__ scal, int kind, int cert) {
   __shared__ double lds[4 * NQ];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
@@ -1213,9 +1215,9 @@ __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work
   double v[NQ] = {0, 0, 0, 0, 0, -INFINITY, 0, 0};
   SIMPLE_TILE_LOOP(d, w, {
     const double a = (double)m1[off], b = (double)m2[off];
-    const double cc = (double)corr[off];
-    const double c1 = i < n ? ((double)corr[off + pitch] - cc) * ih : 0.0;
-    const double c2 = j < n ? ((double)corr[off + 1] - cc) * ih : 0.0;
+    const double cc = cert ? (double)corr[off] : 0.0;
+    const double c1 = cert && i < n ? ((double)corr[off + pitch] - cc) * ih : 0.0;
+    const double c2 = cert && j < n ? ((double)corr[off + 1] - cc) * ih : 0.0;
     const double pc = (double)pot[off];
     const double g1 = i < n ? ((double)pot[off + pitch] - pc) * ih : 0.0;
     const double g2 = j < n ? ((double)pot[off + 1] - pc) * ih : 0.0;
@@ -1238,7 +1240,7 @@ __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval_final(const int* __restrict__ idx, const int* __restrict__ ntiles,
                                                     const SlotDesc<T>* __restrict__ desc,
-                                                    SlotScalars* __restrict__ scal, int kind) {
+                                                    SlotScalars* __restrict__ scal, int kind, int cert) {
   __shared__ double lds[4 * NQ];
   __shared__ double res[NQ];
   const int x = idx[blockIdx.x];
@@ -1273,9 +1275,9 @@ __global__ __launch_bounds__(256) void k_eval_final(const int* __restrict__ idx,
     const double gap = fabs(P - D) / fmax(fmax(fabs(P), fabs(D)), 1e-300);
     sc.eval[0] = P;
     sc.eval[1] = D;
-    sc.eval[2] = lo;
-    sc.eval[3] = hi;
-    sc.eval[4] = fmax(rp, fmax(rd, gap));
+    sc.eval[2] = cert ? lo : NAN;
+    sc.eval[3] = cert ? hi : NAN;
+    sc.eval[4] = cert ? fmax(rp, fmax(rd, gap)) : NAN;
     sc.eval[5] = gmax;
     sc.eval[6] = rp;
     sc.eval[7] = rd;
@@ -1339,6 +1341,9 @@ template <typename T> void K<T>::prep_stats(hipStream_t s, const Work* w, int nw
 template <typename T> void K<T>::prep_scale(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc) {
   if (nw) LAUNCH(k_prep_scale<T>, nw, 256, 0, s, w, d, sc);
 }
+template <typename T> void K<T>::reset_scalars(hipStream_t s, const Work* w, int nw, SlotScalars* sc) {
+  if (nw) LAUNCH(k_reset_scalars, nw, 64, 0, s, w, sc);
+}
 template <typename T> void K<T>::restrict_level(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d) {
   if (nw) LAUNCH(k_restrict<T>, nw, 256, 0, s, w, d);
 }
@@ -1356,14 +1361,34 @@ template <typename T> void K<T>::prolong(hipStream_t s, const Work* w, int nw, c
   if (nw) LAUNCH(k_prolong<T>, nw, 256, 0, s, w, d, sc, kind);
 }
 template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                             const SlotScalars* sc, int li, int steps, int rh, bool check) {
+                                             const SlotScalars* sc, int li, int steps, int rh, bool check,
+                                             int metric, int nwv) {
   if (!nw) return;
-  if (rh != 64 || steps < 1 || 2 * steps >= rh) {
-    fprintf(stderr, "w1: internal error: %d steps in a %d-row region\n", steps, rh);
+  if (rh != TILED_RH || steps < 1 || steps > TILED_MAX_STEPS || (metric != 1 && metric != 2) ||
+      (nwv != 8 && nwv != 16)) {
+    fprintf(stderr, "w1: internal error: %d steps in a %d-row region, metric %d, %d waves\n", steps, rh, metric,
+            nwv);
     return;
   }
-  if (check) LAUNCH((k_plain_tiled<T, true>), nw, 512, 0, s, w, d, sc, li, steps);
-  else LAUNCH((k_plain_tiled<T, false>), nw, 512, 0, s, w, d, sc, li, steps);
+#define W1_TILED_LAUNCH(C, M, NWV) LAUNCH((k_plain_tiled<T, C, M, NWV>), nw, NWV * 64, 0, s, w, d, sc, li, steps)
+  if (nwv == 16) {
+    if (metric == 1) {
+      if (check) W1_TILED_LAUNCH(true, 1, 16);
+      else W1_TILED_LAUNCH(false, 1, 16);
+    } else {
+      if (check) W1_TILED_LAUNCH(true, 2, 16);
+      else W1_TILED_LAUNCH(false, 2, 16);
+    }
+  } else {
+    if (metric == 1) {
+      if (check) W1_TILED_LAUNCH(true, 1, 8);
+      else W1_TILED_LAUNCH(false, 1, 8);
+    } else {
+      if (check) W1_TILED_LAUNCH(true, 2, 8);
+      else W1_TILED_LAUNCH(false, 2, 8);
+    }
+  }
+#undef W1_TILED_LAUNCH
 }
 
 // resident kernel: sides up to 65, 9 nodes per thread of 512
@@ -1371,21 +1396,32 @@ template <typename T> struct ResCfg;
 template <> struct ResCfg<float> { static constexpr int NPT = 9; static constexpr int MAXN = 65; };
 template <> struct ResCfg<double> { static constexpr int NPT = 9; static constexpr int MAXN = 65; };
 
-int resident_lds_bytes(int side, int elem) { return 18 * NQ * 8 + 2 * side * side * elem; }
+int resident_lds_bytes(int side, int elem) { return 18 * NQ * 8 + 3 * side * side * elem; }
 
 template <typename T> int K<T>::plain_resident_max_side() { return ResCfg<T>::MAXN; }
 
 template <typename T> void K<T>::plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d,
-                                                SlotScalars* sc, int max_side, int check_every, int chunk) {
+                                                SlotScalars* sc, int max_side, int check_every, int chunk,
+                                                int metric) {
   if (!ns) return;
+  if (max_side > ResCfg<T>::MAXN || (metric != 1 && metric != 2)) {
+    fprintf(stderr, "w1: internal error: resident side %d, metric %d\n", max_side, metric);
+    return;
+  }
   static bool attr_set = false;
   const int bytes = resident_lds_bytes(max_side, sizeof(T));
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_plain_resident<T, ResCfg<T>::NPT>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, resident_lds_bytes(ResCfg<T>::MAXN, sizeof(T)));
+    const int full = resident_lds_bytes(ResCfg<T>::MAXN, sizeof(T));
+    (void)hipFuncSetAttribute((const void*)k_plain_resident<T, ResCfg<T>::NPT, 1>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, full);
+    (void)hipFuncSetAttribute((const void*)k_plain_resident<T, ResCfg<T>::NPT, 2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, full);
     attr_set = true;
   }
-  LAUNCH((k_plain_resident<T, ResCfg<T>::NPT>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+  if (metric == 1)
+    LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 1>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+  else
+    LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 2>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
 }
 template <typename T> void K<T>::kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                      const SlotScalars* sc, int kind, int set_xor, int gate) {
@@ -1418,12 +1454,12 @@ template <typename T> void K<T>::check(hipStream_t s, const int* idx, const int*
   if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len, launches);
 }
 template <typename T> void K<T>::eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                           const SlotScalars* sc, int kind) {
-  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, sc, kind);
+                                           const SlotScalars* sc, int kind, int cert) {
+  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, sc, kind, cert);
 }
 template <typename T> void K<T>::eval_final(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
-                                            SlotScalars* sc, int kind) {
-  if (ns) LAUNCH(k_eval_final<T>, ns, 256, 0, s, idx, nt, d, sc, kind);
+                                            SlotScalars* sc, int kind, int cert) {
+  if (ns) LAUNCH(k_eval_final<T>, ns, 256, 0, s, idx, nt, d, sc, kind, cert);
 }
 template <typename T> void K<T>::export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                                const SlotScalars* sc, int kind) {

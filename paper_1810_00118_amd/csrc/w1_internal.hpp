@@ -26,6 +26,8 @@ constexpr int ST_H = 16;             // simple per-node tile: 16 rows x 64 cols
 constexpr int ST_W = 64;
 constexpr int GEMM_T = 64;           // DCT GEMM output tile
 constexpr int TILED_RW = 128;        // plain tiled kernel region width
+constexpr int TILED_RH = 64;         // plain tiled kernel region height
+constexpr int TILED_MAX_STEPS = 26;  // most PDHG steps per tiled launch
 constexpr int RES_THREADS = 512;     // resident kernel workgroup size
 
 enum Status : int { ST_RUN = 0, ST_CONV = 1, ST_CAP = 2, ST_DIVERGED = 3, ST_REJECT = 4 };
@@ -87,6 +89,9 @@ struct K {
   static void export_dense(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, int plane, T* dst);
   static void reduce(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
                      SlotScalars* sc, int nq, int out_base, unsigned maxmask);
+  // scalars of every slot in the list (one item per slot has w == 0):
+  // status RUN, iteration 0, iterate in plane set A, sums cleared
+  static void reset_scalars(hipStream_t s, const Work* w, int nw, SlotScalars* sc);
   static void prep_stats(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d);
   static void prep_scale(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc);
   static void restrict_level(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d);
@@ -95,11 +100,14 @@ struct K {
   static void rho_write(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc);
   static void prolong(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
                       int kind);
+  // the plain kernels are compiled per ground metric: every slot of one
+  // launch has `metric` (others in the list are skipped); the tiled
+  // kernel's 64 x 128 region is split over nwv = 8 or 16 wavefronts
   static void plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                          int launch_index, int steps, int rh, bool check);
+                          int launch_index, int steps, int rh, bool check, int metric, int nwv);
   static int plain_resident_max_side();
   static void plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
-                             int max_side, int check_every, int chunk);
+                             int max_side, int check_every, int chunk, int metric);
   static void kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int kind,
                   int set_xor, int gate);
   static void div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int mode,
@@ -110,10 +118,11 @@ struct K {
                         bool check);
   static void check(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
                     SlotScalars* sc, int kind, int block_len, int launches);
+  // cert = 0: no Poisson correction in plane 6; lo, hi and kkt are NaN
   static void eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                        int kind);
+                        int kind, int cert);
   static void eval_final(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
-                         SlotScalars* sc, int kind);
+                         SlotScalars* sc, int kind, int cert);
   static void export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
                             int kind);
 };

@@ -47,3 +47,11 @@ def test_library_loads_and_checks_params_without_a_device():
             setattr(q, k, v)
         assert w1.check_params(q) == w1.W1_EINVAL, bad
     assert w1.strerror(w1.W1_EINVAL) == "invalid argument"
+
+
+def test_tuner_table_is_host_only():
+    if not os.path.exists(LIB):
+        pytest.skip("libw1.so not built")
+    import paper_1810_00118_amd as w1
+    w1.tuner_reset()
+    assert w1.tuner_table() == []

@@ -67,9 +67,9 @@ def test_resident_and_tiled_agree_bitwise(precision, n):
     m1, m2, phi = _rand_state(n, 4)
     dt = tdtype(precision)
     outs = []
-    for block in (-1, 1, 3, 6):
+    for block, waves in ((-1, 0), (1, 8), (3, 8), (6, 16), (5, 16), (1, 16)):
         g = [dev(x, dt) for x in (m1, m2, phi, rho)]
-        w1.op_plain_steps(n, 2, precision, 25, g[0], g[1], g[2], g[3], block_steps=block)
+        w1.op_plain_steps(n, 2, precision, 25, g[0], g[1], g[2], g[3], block_steps=block, waves=waves)
         outs.append([host(x) for x in g[:3]])
     for other in outs[1:]:
         for a, b in zip(outs[0], other):

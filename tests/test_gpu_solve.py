@@ -146,3 +146,42 @@ def test_served_mix_equals_alone():
             alone = s.solve([(p0, p1)])[0]
         assert res["iters"] == alone["iters"]
         assert res["w1"] == pytest.approx(alone["w1"], rel=1e-6)
+
+
+def test_no_certificate_flag():
+    """Without the certificate the solve runs the same iterations and gives
+    the same W1 and dual; only lo, hi and kkt are left as NaN."""
+    w1 = require_gpu()
+    pairs = [w1data.pair_gauss3(60 + i, n=64) for i in range(2)]
+    out = []
+    for flags in (0, w1.FLAG_NO_CERT):
+        for algo in (w1.ALGO_PLAIN, w1.ALGO_PROX):
+            prm = w1.params(n=64, levels=2, metric=2, algo=algo, precision=FP32, stop_rule=w1.STOP_FPR,
+                            tol=0.0, max_iters=2000, check_every=10, flags=flags)
+            with w1.Solver(prm, capacity=2) as s:
+                out.append(s.solve(pairs))
+    for a, b in zip(out[0] + out[1], out[2] + out[3]):
+        assert a["iters"] == b["iters"] and a["w1"] == b["w1"] and a["dual"] == b["dual"]
+        assert np.isfinite(a["lo"]) and np.isfinite(a["hi"]) and np.isfinite(a["kkt"])
+        assert np.isnan(b["lo"]) and np.isnan(b["hi"]) and np.isnan(b["kkt"])
+
+
+def test_autotuner_exploration_keeps_results():
+    """The launch-shape autotuner times candidate shapes on live blocks;
+    results while it explores and after it has settled are identical."""
+    w1 = require_gpu()
+    w1.tuner_reset()
+    pairs = [w1data.pair_gauss3(80 + i, n=128) for i in range(4)]
+    prm = w1.params(n=128, levels=2, metric=2, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_FPR,
+                    tol=0.0, max_iters=3000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+    runs = []
+    with w1.Solver(prm, capacity=4) as s:
+        for _ in range(3):
+            runs.append(s.solve(pairs))
+    table = w1.tuner_table()
+    assert table and all(len(e["arms"]) >= 2 for e in table)
+    assert any(a["blocks"] > 0 for e in table for a in e["arms"])
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert a["iters"] == b["iters"] and a["w1"] == b["w1"]
+
