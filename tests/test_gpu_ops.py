@@ -102,7 +102,7 @@ def test_prox_steps_trajectory(precision, n, metric):
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
-@pytest.mark.parametrize("n", [16, 64, 128, 200])
+@pytest.mark.parametrize("n", [16, 64, 128, 200, 512, 1000])
 def test_poisson(precision, n):
     w1 = require_gpu()
     rng = np.random.default_rng(n)
