@@ -218,9 +218,11 @@ int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision,
 
 /* `steps` iterations of eq. (pdhg) in place on (m1, m2, vphi1, vphi2,
  * vphibar1, vphibar2), mu = tau = step_scale (<= 0: 1/2).  fpr_out
- * receives G^k of the last step (eq. (pdhg_stop)).                        */
+ * receives G^k of the last step (eq. (pdhg_stop)).  resident = 1 runs all
+ * steps in one workgroup with the level in LDS (FP32, n <= 64; W1_EINVAL
+ * otherwise), 0 the batched kernels (one launch sequence per step).       */
 int w1_op_prox_steps(int32_t n, int32_t metric, int32_t precision,
-                     double step_scale, int32_t steps,
+                     double step_scale, int32_t steps, int32_t resident,
                      void* m1, void* m2, void* w1, void* w2,
                      void* wb1, void* wb2, const void* rho,
                      double* fpr_out, void* hip_stream);
@@ -256,9 +258,11 @@ int w1_op_evaluate(int32_t n, int32_t metric, int32_t precision,
  *   elementwise 13 words per node per iteration; DCT pass 2 words per node
  *   per pass; resident 0), out[4] floating-point operations (DCT passes).
  * Families: W1_FAM_PLAIN_TILED, W1_FAM_PLAIN_RESIDENT, W1_FAM_DCT,
- * W1_FAM_PROX_ELEM, W1_FAM_OTHER.                                           */
+ * W1_FAM_PROX_ELEM, W1_FAM_OTHER, W1_FAM_PROX_RESIDENT (whole small prox
+ * levels in one workgroup; resident families count node updates only).    */
 enum { W1_FAM_PLAIN_TILED = 0, W1_FAM_PLAIN_RESIDENT = 1, W1_FAM_DCT = 2,
-       W1_FAM_PROX_ELEM = 3, W1_FAM_OTHER = 4, W1_NFAM = 5 };
+       W1_FAM_PROX_ELEM = 3, W1_FAM_OTHER = 4, W1_FAM_PROX_RESIDENT = 5,
+       W1_NFAM = 6 };
 int w1_profile(w1_handle h, int32_t enable);
 int w1_kernel_stats(w1_handle h, int32_t family, double* out5);
 

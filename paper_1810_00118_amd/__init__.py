@@ -25,7 +25,7 @@ STOP_KKT, STOP_FPR = 1, 2
 FLAG_NO_RESIDENT, FLAG_NO_CERT = 1, 2
 MAX_LEVELS = 12
 FAM_PLAIN_TILED, FAM_PLAIN_RESIDENT, FAM_DCT, FAM_PROX_ELEM, FAM_OTHER = 0, 1, 2, 3, 4
-FAMILIES = {0: "plain_tiled", 1: "plain_resident", 2: "dct", 3: "prox_elem", 4: "other"}
+FAMILIES = {0: "plain_tiled", 1: "plain_resident", 2: "dct", 3: "prox_elem", 4: "other", 5: "prox_resident"}
 
 
 class W1Error(RuntimeError):
@@ -92,7 +92,7 @@ def lib():
         "w1_op_prepare": (C.c_int, [i32, i32, i32, vp, vp, C.POINTER(vp), vp]),
         "w1_op_prolong": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp, vp]),
         "w1_op_plain_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, i32, vp, vp, vp, vp, dp, vp]),
-        "w1_op_prox_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, vp, vp, vp, vp, vp, vp, vp, dp, vp]),
+        "w1_op_prox_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, vp, vp, vp, dp, vp]),
         "w1_op_poisson": (C.c_int, [i32, i32, vp, vp, vp]),
         "w1_op_potential": (C.c_int, [i32, i32, vp, vp, vp, vp]),
         "w1_op_evaluate": (C.c_int, [i32, i32, i32, vp, vp, vp, vp, dp, vp]),
@@ -320,10 +320,10 @@ def tuner_reset():
 
 
 def op_prox_steps(n, metric, precision, steps, m1, m2, w1, w2, wb1, wb2, rho, step_scale=0.0, fpr=False,
-                  stream=None):
+                  stream=None, resident=False):
     d = _dt(precision)
     out = C.c_double(np.nan)
-    _check(lib().w1_op_prox_steps(n, metric, precision, step_scale, steps,
+    _check(lib().w1_op_prox_steps(n, metric, precision, step_scale, steps, 1 if resident else 0,
                                   *[_ptr(x, d)[0] for x in (m1, m2, w1, w2, wb1, wb2, rho)],
                                   C.byref(out) if fpr else None, _stream(stream)), "w1_op_prox_steps")
     return out.value if fpr else None

@@ -596,8 +596,8 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, int nw
 }
 
 template <typename T>
-int op_prox_steps(int n, int metric, double scale, int steps, void* m1, void* m2, void* w1, void* w2, void* wb1,
-                  void* wb2, const void* rho, double* fpr, hipStream_t s) {
+int op_prox_steps(int n, int metric, double scale, int steps, int resident, void* m1, void* m2, void* w1, void* w2,
+                  void* wb1, void* wb2, const void* rho, double* fpr, hipStream_t s) {
   Op<T> op(n, s);
   const double sc = scale > 0 ? scale : 0.5;
   SlotDesc<T>& d = op.hd[0];
@@ -616,6 +616,22 @@ int op_prox_steps(int n, int metric, double scale, int steps, void* m1, void* m2
   d.part = (double*)pp;
   int st = op.dct(d);
   if (st) return st;
+  if (resident) {
+    // every step in one launch; the stop-test sums of the last step give G^k
+    d.cap = steps;
+    st = op.commit(1);
+    if (st) return st;
+    std::vector<int> idx{0};
+    int* di = op.upload(idx);
+    if (!di) return W1_EDEVICE;
+    K<T>::prox_resident(s, di, 1, op.dd, op.dsc, n + 1, steps, 0, metric);
+    HIPCHK(hipGetLastError());
+    SlotScalars h;
+    st = op.read_scalars(&h);
+    if (st) return st;
+    if (fpr) *fpr = h.measure;
+    return W1_OK;
+  }
   st = op.commit(1);
   if (st) return st;
   auto sw = op.simple(0, n);
@@ -822,14 +838,17 @@ extern "C" int w1_tuner_reset(void) {
 }
 
 extern "C" int w1_op_prox_steps(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,
-                                void* m1, void* m2, void* w1, void* w2, void* wb1, void* wb2, const void* rho,
-                                double* fpr_out, void* hip_stream) {
+                                int32_t resident, void* m1, void* m2, void* w1, void* w2, void* wb1, void* wb2,
+                                const void* rho, double* fpr_out, void* hip_stream) {
   if (check_side(n) || steps < 1 || (metric != 1 && metric != 2)) return W1_EINVAL;
   if (!m1 || !m2 || !w1 || !w2 || !wb1 || !wb2 || !rho || step_scale >= 1.0) return W1_EINVAL;
+  if (resident && (precision != W1_FP32 || n + 1 > K<float>::prox_resident_max_side())) return W1_EINVAL;
   hipStream_t s = (hipStream_t)hip_stream;
   return DISPATCH(precision,
-                  op_prox_steps<float>(n, metric, step_scale, steps, m1, m2, w1, w2, wb1, wb2, rho, fpr_out, s),
-                  op_prox_steps<double>(n, metric, step_scale, steps, m1, m2, w1, w2, wb1, wb2, rho, fpr_out, s));
+                  op_prox_steps<float>(n, metric, step_scale, steps, resident, m1, m2, w1, w2, wb1, wb2, rho,
+                                       fpr_out, s),
+                  op_prox_steps<double>(n, metric, step_scale, steps, 0, m1, m2, w1, w2, wb1, wb2, rho, fpr_out,
+                                        s));
 }
 
 extern "C" int w1_op_poisson(int32_t n, int32_t precision, const void* r, void* u, void* hip_stream) {

@@ -616,8 +616,8 @@ class Batch : public BatchBase {
     for (auto* r : slots_) {
       if (!r || r->state != Request::RUN) continue;
       const auto key = std::make_tuple(r->prm.check_every, r->prm.stop_rule, r->prm.metric);
-      if (r->kind == K_PROX) X[key].push_back(r);
-      else if (r->resident_level) R.push_back(r);
+      if (r->resident_level) R.push_back(r);
+      else if (r->kind == K_PROX) X[key].push_back(r);
       else P[key].push_back(r);
     }
     if (R.empty() && P.empty() && X.empty()) return W1_OK;
@@ -641,7 +641,7 @@ class Batch : public BatchBase {
       // chunking a uniform batch spreads the next level over many small
       // launches, which costs more than the wait for the slowest pair
       const bool alone = P.empty() && X.empty();
-      st = launch_resident(R, alone ? 0 : std::max(1, (int)(nblocks * block_us / 3.6)));
+      st = launch_resident(R, alone ? 0 : nblocks * block_us);
       if (st) return fail(st);
     }
     for (int b = 0; b < nblocks; ++b) {
@@ -1017,36 +1017,43 @@ class Batch : public BatchBase {
     r->state = Request::RUN;
     r->t_level = now_seconds();
     const bool allow = !(r->prm.flags & W1_FLAG_NO_RESIDENT);
-    r->resident_level = r->kind == K_PLAIN && allow && (r->sides[l] + 1) <= K<T>::plain_resident_max_side();
+    const int side = r->sides[l] + 1;
+    r->resident_level = allow && (r->kind == K_PLAIN ? side <= K<T>::plain_resident_max_side()
+                                                     : side <= K<T>::prox_resident_max_side());
     // descriptors are fixed at admission; only the work lists change
     ++gen_;
   }
 
-  // -- plain: resident levels ---------------------------------------------
-  // `chunk` bounds the iterations of this launch (0: run to the stop test)
-  int launch_resident(std::vector<Request*>& R, int chunk) {
+  // -- resident levels (both algorithms) -----------------------------------
+  // `budget_us` bounds a launch to about that much device time (0: run to
+  // the stop test); one launch per (kind, check_every, metric)
+  int launch_resident(std::vector<Request*>& R, double budget_us) {
     int st = W1_OK;
-    int maxside = 0;
-    // one launch per (check_every, metric)
-    std::map<std::pair<int, int>, std::vector<int>> by_ce;
-    for (auto* r : R) {
-      by_ce[std::make_pair(r->prm.check_every, r->prm.metric)].push_back(dx(r, r->level));
-      maxside = std::max(maxside, r->sides[r->level] + 1);
-    }
-    for (auto& kv : by_ce) {
-      int* di = arena_.put(kv.second, &st);
+    std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
+    for (auto* r : R) groups[std::make_tuple(r->kind, r->prm.check_every, r->prm.metric)].push_back(r);
+    for (auto& kv : groups) {
+      const int kind = std::get<0>(kv.first), ce = std::get<1>(kv.first), metric = std::get<2>(kv.first);
+      std::vector<int> ids;
+      int maxside = 0;
+      for (auto* r : kv.second) {
+        ids.push_back(dx(r, r->level));
+        maxside = std::max(maxside, r->sides[r->level] + 1);
+      }
+      int* di = arena_.put(ids, &st);
       if (st) return st;
-      const int ce = kv.first.first;
+      // rough cost of one iteration of the largest level in the group
+      const double s3 = std::pow(maxside / 65.0, kind == K_PLAIN ? 2.0 : 3.0);
+      const double it_us = kind == K_PLAIN ? 3.6 * s3 : 8.0 * s3 + 0.5;
+      int chunk = 0;
+      if (budget_us > 0) chunk = std::max(1, (int)(budget_us / it_us));
       const int c = chunk > 0 ? ((chunk + ce - 1) / ce) * ce : 0;
       const int pi = prof_.begin();
-      K<T>::plain_resident(st_, di, (int)kv.second.size(), ddesc_, dsc_, maxside, ce, c, kv.first.second);
-      prof_.end(pi, W1_FAM_PLAIN_RESIDENT, 0, 0, 0);
-      if (pi >= 0) {
-        std::vector<Request*> grp;
-        for (auto* r : R)
-          if (r->prm.check_every == ce && r->prm.metric == kv.first.second) grp.push_back(r);
-        resident_pending_.emplace_back(pi, grp);
-      }
+      if (kind == K_PLAIN)
+        K<T>::plain_resident(st_, di, (int)ids.size(), ddesc_, dsc_, maxside, ce, c, metric);
+      else
+        K<T>::prox_resident(st_, di, (int)ids.size(), ddesc_, dsc_, maxside, ce, c, metric);
+      prof_.end(pi, kind == K_PLAIN ? W1_FAM_PLAIN_RESIDENT : W1_FAM_PROX_RESIDENT, 0, 0, 0);
+      if (pi >= 0) resident_pending_.emplace_back(pi, kv.second);
     }
     HIPCHK(hipGetLastError());
     return W1_OK;

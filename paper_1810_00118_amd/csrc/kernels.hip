@@ -898,6 +898,379 @@ __global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __res
   }
 }
 
+// Stop measure from the reduced partials r[0..NQ): R^k (plain) or G^k (prox)
+// of eq. (pd_stop) / eq. (pdhg_stop) for RULE_FPR, else the normalised KKT
+// residual.
+__device__ double measure_from_(const double* r, int kind, int rule, double h2, double mud, double taud, int NN) {
+  if (rule == RULE_FPR) {
+    if (r[3] > 0.0) return NAN;
+    if (kind == K_PLAIN) return h2 * (r[0] / mud + r[1] / taud - 2.0 * r[2]);
+    return h2 * (r[0] / mud + r[1] / taud + 2.0 * r[2]);
+  }
+  const double rp = sqrt(r[0] / (r[1] > 1e-300 ? r[1] : 1e-300));
+  const double rdl = sqrt(r[2] * h2);
+  const double P = r[3] * h2;
+  const double sgn = kind == K_PLAIN ? -1.0 : 1.0;
+  const double D = sgn * (r[4] - r[6] / (double)NN * r[7]) * h2;
+  const double den = fmax(fmax(fabs(P), fabs(D)), 1e-300);
+  return fmax(rp, fmax(rdl, fabs(P - D) / den));
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2, whole level resident in one workgroup (sides up to 65).
+// The iterate (m, vphi, vphibar) and rho stay in registers (node e of the
+// dense (n+1)^2 grid belongs to thread e mod 512); LDS holds the DCT-II
+// matrix, its eigenvalue parts and three planes for the divergence, the
+// Poisson solve and the gradient.  One iteration: v = m - mu vphibar,
+// r = A v - rho, u = (A A*)^{-1} r by four DCT passes in LDS (each thread a
+// 3 x 3 block of outputs), m+ = v + grad+ u, vphi+ = Proj(vphi + tau m+),
+// vphibar+ = 2 vphi+ - vphi -- the same node arithmetic as the batched
+// kernels.  Stop tests every `check_every` iterations and at the cap: G^k of
+// eq. (pdhg_stop) (pointwise sums) or the normalised KKT residual with
+// psi = (A A*)^{-1} A vphi.  Reads and writes planes 0..5; runs at most
+// `chunk` iterations (0: no limit), resuming from the slot's count.
+// ---------------------------------------------------------------------------
+// one DCT pass in LDS, out = X C^T (PASS 1), C X scaled by h^2 / lambda
+// (PASS 2), C^T X (PASS 3) or X C (PASS 4); dense N x N, ends with a barrier
+template <typename T, int PASS>
+__device__ void res_dct_pass_(const T* __restrict__ Cm, const T* __restrict__ in, T* __restrict__ out,
+                              const double* __restrict__ sk, int N, double h2) {
+  constexpr int RB = 3;
+  const int nb = (N + RB - 1) / RB;
+  for (int bidx = threadIdx.x; bidx < nb * nb; bidx += RES_THREADS) {
+    const int i0 = (bidx / nb) * RB, c0 = (bidx % nb) * RB;
+    int ri[RB], ci[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      ri[r] = i0 + r < N ? i0 + r : N - 1;   // clamped rows / columns are computed and dropped
+      ci[r] = c0 + r < N ? c0 + r : N - 1;
+    }
+    T acc[RB][RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c = 0; c < RB; ++c) acc[r][c] = T(0);
+    for (int p = 0; p < N; ++p) {
+      T a[RB], b[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (PASS == 1 || PASS == 4) a[r] = in[ri[r] * N + p];
+        else if (PASS == 2) a[r] = Cm[ri[r] * N + p];
+        else a[r] = Cm[p * N + ri[r]];
+      }
+#pragma unroll
+      for (int c = 0; c < RB; ++c) {
+        if (PASS == 1) b[c] = Cm[ci[c] * N + p];
+        else if (PASS == 4) b[c] = Cm[p * N + ci[c]];
+        else b[c] = in[p * N + ci[c]];
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < RB; ++c) acc[r][c] = fma_(a[r], b[c], acc[r][c]);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int c = 0; c < RB; ++c) {
+        const int gi = i0 + r, gj = c0 + c;
+        if (gi < N && gj < N) {
+          T v = acc[r][c];
+          if (PASS == 2) v = (gi == 0 && gj == 0) ? T(0) : (T)((double)v * (h2 / (sk[gi] + sk[gj])));
+          out[gi * N + gj] = v;
+        }
+      }
+  }
+  __syncthreads();
+}
+
+// The same pass on the matrix cores (FP32): 16 x 16 output tiles, one per
+// wavefront at a time, accumulated with v_mfma_f32_16x16x4f32 over K in
+// steps of 4 (A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k,
+// accumulator register r of lane l holds row 4 (l / 16) + r, column
+// l % 16); operands outside the N x N matrices read as zero.
+typedef float w1_f32x4 __attribute__((ext_vector_type(4)));
+
+template <int PASS>
+__device__ void res_dct_pass_mfma_(const float* __restrict__ Cm, const float* __restrict__ in,
+                                   float* __restrict__ out, const double* __restrict__ sk, int N, double h2) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nt = (N + 15) >> 4;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int tile = wv; tile < nt * nt; tile += RES_THREADS / 64) {
+    const int i0 = (tile / nt) * 16, j0 = (tile % nt) * 16;
+    const int ia = i0 + li, jb = j0 + li;             // A row and B column of this lane
+    const bool ia_in = ia < N, jb_in = jb < N;
+    const int iac = ia_in ? ia : N - 1, jbc = jb_in ? jb : N - 1;
+    w1_f32x4 acc = {};
+    // four K steps per round: all operand reads are issued before the
+    // matrix-core instructions that consume them
+    for (int k0 = 0; k0 < N; k0 += 16) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + lk;
+        const bool k_in = k < N;
+        const int kc = k_in ? k : N - 1;
+        if (PASS == 1 || PASS == 4) a[u] = in[iac * N + kc];
+        else if (PASS == 2) a[u] = Cm[iac * N + kc];
+        else a[u] = Cm[kc * N + iac];
+        if (PASS == 1) b[u] = Cm[jbc * N + kc];
+        else if (PASS == 4) b[u] = Cm[kc * N + jbc];
+        else b[u] = in[kc * N + jbc];
+        a[u] = (ia_in && k_in) ? a[u] : 0.f;
+        b[u] = (jb_in && k_in) ? b[u] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gi = i0 + 4 * lk + r, gj = j0 + li;
+      if (gi < N && gj < N) {
+        float v = acc[r];
+        if (PASS == 2) v = (gi == 0 && gj == 0) ? 0.f : (float)((double)v * (h2 / (sk[gi] + sk[gj])));
+        out[gi * N + gj] = v;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// u = (A A*)^{-1} r: r in P2 on entry, u in P2 on exit, P0 and P1 scratch
+template <typename T>
+__device__ void res_poisson_(const T* Cm, T* P0, T* P1, T* P2, const double* sk, int N, double h2) {
+  if constexpr (sizeof(T) == 4) {
+    res_dct_pass_mfma_<1>(Cm, P2, P0, sk, N, h2);
+    res_dct_pass_mfma_<2>(Cm, P0, P1, sk, N, h2);
+    res_dct_pass_mfma_<3>(Cm, P1, P0, sk, N, h2);
+    res_dct_pass_mfma_<4>(Cm, P0, P2, sk, N, h2);
+  } else {
+    res_dct_pass_<T, 1>(Cm, P2, P0, sk, N, h2);
+    res_dct_pass_<T, 2>(Cm, P0, P1, sk, N, h2);
+    res_dct_pass_<T, 3>(Cm, P1, P0, sk, N, h2);
+    res_dct_pass_<T, 4>(Cm, P0, P2, sk, N, h2);
+  }
+}
+
+int prox_resident_lds_bytes(int side, int elem) {
+  return 18 * NQ * 8 + side * 8 + 4 * side * side * elem;
+}
+
+template <typename T, int NPT, int METRIC>
+__global__ __launch_bounds__(RES_THREADS) void k_prox_resident(const int* __restrict__ idx,
+                                                               const SlotDesc<T>* __restrict__ desc,
+                                                               SlotScalars* __restrict__ scal, int check_every,
+                                                               int chunk) {
+  extern __shared__ double smem_d[];
+  constexpr int NT = RES_THREADS;
+  constexpr int metric = METRIC;
+  const int x = idx[blockIdx.x];
+  const SlotDesc<T>& d = desc[x];
+  if (d.metric != METRIC) return;
+  SlotScalars& sc = scal[x / MAXL];
+  const int n = d.n, N = n + 1, NN = N * N, pitch = d.pitch;
+  double* red = smem_d;                 // [16 * NQ]
+  double* res = smem_d + 16 * NQ;       // [NQ]
+  int* flag = (int*)(smem_d + 17 * NQ);
+  double* sk = smem_d + 18 * NQ;        // [N] eigenvalue parts 4 sin^2(pi k / 2N)
+  T* Cm = (T*)(sk + N);                 // DCT-II matrix, dense N x N
+  T* P0 = Cm + NN;
+  T* P1 = P0 + NN;
+  T* P2 = P1 + NN;
+  const T ih = d.ih, mu = d.mu, tau = d.tau;
+  const int cap = d.cap;
+  const double h2 = d.h * d.h;
+  for (int e = threadIdx.x; e < NN; e += NT) Cm[e] = d.dctC[e];
+  for (int k = threadIdx.x; k < N; k += NT) sk[k] = d.dcts[k];
+
+  T m1[NPT], m2[NPT], w1[NPT], w2[NPT], b1[NPT], b2[NPT], rh[NPT];
+  unsigned has_d = 0u, has_r = 0u, not_top = 0u, not_left = 0u;   // bit s: neighbour exists
+#pragma unroll
+  for (int s = 0; s < NPT; ++s) {
+    const int e = threadIdx.x + NT * s;
+    m1[s] = m2[s] = w1[s] = w2[s] = b1[s] = b2[s] = rh[s] = T(0);
+    if (e < NN) {
+      const int r = e / N, c = e - r * N;
+      if (r < n) has_d |= 1u << s;
+      if (c < n) has_r |= 1u << s;
+      if (r > 0) not_top |= 1u << s;
+      if (c > 0) not_left |= 1u << s;
+      const size_t off = (size_t)r * pitch + c;
+      m1[s] = d.p[0][off];
+      m2[s] = d.p[1][off];
+      w1[s] = d.p[2][off];
+      w2[s] = d.p[3][off];
+      b1[s] = d.p[4][off];
+      b2[s] = d.p[5][off];
+      rh[s] = d.rho[off];
+    }
+  }
+  __syncthreads();
+
+  int k = sc.iters;
+  const int kend = chunk > 0 ? k + chunk : cap;
+  int status = ST_RUN;
+  double measure = sc.measure;
+  const bool fpr = d.rule == RULE_FPR;
+  while (k < kend) {
+    ++k;
+    const bool chk = (k % check_every == 0) || (k >= cap);
+    // v = m - mu vphibar (zero where the edge leaves the grid)
+    T v1[NPT], v2[NPT];
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      v1[s] = ((has_d >> s) & 1u) ? fma_(-mu, b1[s], m1[s]) : T(0);
+      v2[s] = ((has_r >> s) & 1u) ? fma_(-mu, b2[s], m2[s]) : T(0);
+      if (e < NN) {
+        P0[e] = v1[s];
+        P1[e] = v2[s];
+      }
+    }
+    __syncthreads();
+    // r = A v - rho
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      if (e < NN) {
+        const T v1u = ((not_top >> s) & 1u) ? P0[e - N] : T(0);
+        const T v2l = ((not_left >> s) & 1u) ? P1[e - 1] : T(0);
+        P2[e] = ((v1[s] - v1u) + (v2[s] - v2l)) * ih - rh[s];
+      }
+    }
+    __syncthreads();
+    res_poisson_<T>(Cm, P0, P1, P2, sk, N, h2);
+    // m+ = v + grad+ u; vphi+ = Proj(vphi + tau m+); vphibar+ = 2 vphi+ - vphi
+    double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NPT; ++s) {
+      const int e = threadIdx.x + NT * s;
+      if (e < NN) {
+        const T uc = P2[e];
+        const T g1 = ((has_d >> s) & 1u) ? (P2[e + N] - uc) * ih : T(0);
+        const T g2 = ((has_r >> s) & 1u) ? (P2[e + 1] - uc) * ih : T(0);
+        const T n1 = v1[s] + g1, n2 = v2[s] + g2;
+        T q1, q2;
+        proj_ball_(fma_(tau, n1, w1[s]), fma_(tau, n2, w2[s]), metric, q1, q2);
+        if (!((has_d >> s) & 1u)) q1 = T(0);
+        if (!((has_r >> s) & 1u)) q2 = T(0);
+        if (chk && fpr) {
+          const double e1 = (double)(n1 - m1[s]), e2 = (double)(n2 - m2[s]);
+          const double f1 = (double)(q1 - w1[s]), f2 = (double)(q2 - w2[s]);
+          v[0] += e1 * e1 + e2 * e2;
+          v[1] += f1 * f1 + f2 * f2;
+          v[2] += f1 * e1 + f2 * e2;
+          if (!(finite_(n1) && finite_(n2) && finite_(q1) && finite_(q2))) v[3] += 1.0;
+        }
+        m1[s] = n1;
+        m2[s] = n2;
+        b1[s] = (q1 + q1) - w1[s];
+        b2[s] = (q2 + q2) - w2[s];
+        w1[s] = q1;
+        w2[s] = q2;
+      }
+    }
+    if (!chk) continue;
+
+    // ---- stop test ----
+    if (!fpr) {
+      __syncthreads();
+      // psi = (A A*)^{-1} A vphi, then the KKT partials of (m, psi)
+#pragma unroll
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          P0[e] = w1[s];
+          P1[e] = w2[s];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          const T a1 = w1[s] - (((not_top >> s) & 1u) ? P0[e - N] : T(0));
+          const T a2 = w2[s] - (((not_left >> s) & 1u) ? P1[e - 1] : T(0));
+          P2[e] = (a1 + a2) * ih;
+        }
+      }
+      __syncthreads();
+      res_poisson_<T>(Cm, P0, P1, P2, sk, N, h2);
+#pragma unroll
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          P0[e] = m1[s];
+          P1[e] = m2[s];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          const T a1 = m1[s] - (((not_top >> s) & 1u) ? P0[e - N] : T(0));
+          const T a2 = m2[s] - (((not_left >> s) & 1u) ? P1[e - 1] : T(0));
+          const double am = (double)((a1 + a2) * ih);
+          const double rr = (double)rh[s];
+          const double r1 = am - rr;
+          const T pc = P2[e];
+          const T g1 = ((has_d >> s) & 1u) ? (P2[e + N] - pc) * ih : T(0);
+          const T g2 = ((has_r >> s) & 1u) ? (P2[e + 1] - pc) * ih : T(0);
+          const double gq = (double)norm_q_(g1, g2, metric);
+          const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
+          v[0] += r1 * r1;
+          v[1] += rr * rr;
+          v[2] += ex * ex;
+          v[3] += (double)norm_p_(m1[s], m2[s], metric);
+          v[4] += (double)pc * rr;
+          v[6] += (double)pc;
+          v[7] += rr;
+        }
+      }
+    }
+    // (every LDS plane read above is behind the reduction's barrier)
+    if (fpr) block_reduce_<NT, 4>(v, res, red, 0u);
+    else block_reduce_<NT>(v, res, red, 0u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double m = measure_from_(res, K_PROX, d.rule, h2, d.mud, d.taud, NN);
+      int st = ST_RUN;
+      if (!isfinite(m)) st = ST_DIVERGED;
+      else if (m <= d.tol) st = ST_CONV;
+      else if (k >= cap) st = ST_CAP;
+      flag[0] = st;
+      res[0] = m;
+    }
+    __syncthreads();
+    status = flag[0];
+    measure = res[0];
+    // res and flag are next written after at least six more barriers
+    if (status != ST_RUN) break;
+  }
+
+#pragma unroll
+  for (int s = 0; s < NPT; ++s) {
+    const int e = threadIdx.x + NT * s;
+    if (e < NN) {
+      const int r = e / N, c = e - r * N;
+      const size_t off = (size_t)r * pitch + c;
+      d.p[0][off] = m1[s];
+      d.p[1][off] = m2[s];
+      d.p[2][off] = w1[s];
+      d.p[3][off] = w2[s];
+      d.p[4][off] = b1[s];
+      d.p[5][off] = b2[s];
+    }
+  }
+  if (threadIdx.x == 0) {
+    sc.iters = k;
+    sc.status = status;
+    sc.measure = measure;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // KKT partials of an Algorithm 1 iterate (current set) or of an Algorithm 2
 // iterate with its potential psi in plane 8:
@@ -1239,23 +1612,6 @@ __global__ __launch_bounds__(256) void k_prox_post(const Work* __restrict__ work
 // stop test after a block: reduce the slot's partials, form R^k / G^k or the
 // normalised KKT residual, compare with tol_l and the cap.
 // ---------------------------------------------------------------------------
-// Stop measure from the reduced partials r[0..NQ): R^k (plain) or G^k (prox)
-// of eq. (pd_stop) / eq. (pdhg_stop) for RULE_FPR, else the normalised KKT
-// residual.
-__device__ double measure_from_(const double* r, int kind, int rule, double h2, double mud, double taud, int NN) {
-  if (rule == RULE_FPR) {
-    if (r[3] > 0.0) return NAN;
-    if (kind == K_PLAIN) return h2 * (r[0] / mud + r[1] / taud - 2.0 * r[2]);
-    return h2 * (r[0] / mud + r[1] / taud + 2.0 * r[2]);
-  }
-  const double rp = sqrt(r[0] / (r[1] > 1e-300 ? r[1] : 1e-300));
-  const double rdl = sqrt(r[2] * h2);
-  const double P = r[3] * h2;
-  const double sgn = kind == K_PLAIN ? -1.0 : 1.0;
-  const double D = sgn * (r[4] - r[6] / (double)NN * r[7]) * h2;
-  const double den = fmax(fmax(fabs(P), fabs(D)), 1e-300);
-  return fmax(rp, fmax(rdl, fabs(P - D) / den));
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, const int* __restrict__ ntiles,
@@ -1584,6 +1940,36 @@ template <typename T> void K<T>::eval_final(hipStream_t s, const int* idx, const
 template <typename T> void K<T>::export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                                const SlotScalars* sc, int kind) {
   if (nw) LAUNCH(k_export_fields<T>, nw, 256, 0, s, w, d, sc, kind);
+}
+
+// FP32 only: the FP64 iterate does not fit the register budget
+template <typename T> int K<T>::prox_resident_max_side() { return sizeof(T) == 4 ? 65 : 0; }
+
+template <typename T> void K<T>::prox_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d,
+                                               SlotScalars* sc, int max_side, int check_every, int chunk,
+                                               int metric) {
+  if (!ns) return;
+  if constexpr (sizeof(T) != 4) {
+    fprintf(stderr, "w1: internal error: no resident prox kernel for FP64\n");
+    return;
+  } else {
+  if (max_side > 65 || (metric != 1 && metric != 2)) {
+    fprintf(stderr, "w1: internal error: prox resident side %d, metric %d\n", max_side, metric);
+    return;
+  }
+  static bool attr_set = false;
+  if (!attr_set) {
+    const int full = prox_resident_lds_bytes(65, sizeof(T));
+    (void)hipFuncSetAttribute((const void*)k_prox_resident<T, 9, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              full);
+    (void)hipFuncSetAttribute((const void*)k_prox_resident<T, 9, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              full);
+    attr_set = true;
+  }
+  const int bytes = prox_resident_lds_bytes(max_side, sizeof(T));
+  if (metric == 1) LAUNCH((k_prox_resident<T, 9, 1>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+  else LAUNCH((k_prox_resident<T, 9, 2>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+  }
 }
 
 template struct K<float>;

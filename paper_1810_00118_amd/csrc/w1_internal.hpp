@@ -108,6 +108,11 @@ struct K {
   static int plain_resident_max_side();
   static void plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
                              int max_side, int check_every, int chunk, int metric);
+  // Algorithm 2 levels with sides up to prox_resident_max_side(), one
+  // workgroup per slot (planes 0..5), like plain_resident
+  static int prox_resident_max_side();
+  static void prox_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
+                            int max_side, int check_every, int chunk, int metric);
   static void kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int kind,
                   int set_xor, int gate);
   static void div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int mode,
@@ -128,5 +133,6 @@ struct K {
 };
 
 int resident_lds_bytes(int side, int elem);
+int prox_resident_lds_bytes(int side, int elem);
 
 }  // namespace w1

@@ -101,6 +101,48 @@ def test_prox_steps_trajectory(precision, n, metric):
     assert G == pytest.approx(Gw, rel=1e-8 if precision == FP64 else 1e-2, abs=1e-12)
 
 
+@pytest.mark.parametrize("n", [16, 32, 40, 64])
+@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("k", [1, 10, 60])
+def test_prox_resident_trajectory(n, metric, k):
+    """The whole-level LDS kernel of Algorithm 2 follows the oracle's
+    iterates and G^k (FP32) and agrees with the batched kernels."""
+    w1 = require_gpu()
+    h = 1.0 / n
+    rho = _rho(n, 17 + n)
+    m1, m2, _ = _rand_state(n, 18)
+    rng = np.random.default_rng(19)
+    v1 = rng.uniform(-1, 1, (n + 1, n + 1)); v1[n, :] = 0
+    v2 = rng.uniform(-1, 1, (n + 1, n + 1)); v2[:, n] = 0
+    dt = tdtype(FP32)
+    g = [dev(x, dt) for x in (m1, m2, v1, v2, v1, v2, rho)]
+    G = w1.op_prox_steps(n, metric, FP32, k, *g, fpr=True, resident=True)
+    gb = [dev(x, dt) for x in (m1, m2, v1, v2, v1, v2, rho)]
+    Gb = w1.op_prox_steps(n, metric, FP32, k, *gb, fpr=True)
+    st = (m1, m2, v1, v2, v1.copy(), v2.copy())
+    for _ in range(k):
+        out = o.prox_step(*st, rho, h, 0.5, 0.5, metric)
+        st, Gw = out[:6], out[6]
+    tol = 1e-4 * math.sqrt(k)
+    for got, other, want in zip(g[:6], gb[:6], st):
+        assert rel_err(host(got), want) <= tol
+        assert rel_err(host(got), host(other)) <= tol
+    assert G == pytest.approx(Gw, rel=1e-2, abs=1e-12)
+    assert G == pytest.approx(Gb, rel=1e-2, abs=1e-12)
+
+
+def test_prox_resident_rejects_unsupported():
+    w1 = require_gpu()
+    n = 100
+    dt = tdtype(FP32)
+    z = [dev(np.zeros((n + 1, n + 1)), dt) for _ in range(7)]
+    with pytest.raises(w1.W1Error):
+        w1.op_prox_steps(n, 2, FP32, 1, *z, resident=True)
+    z64 = [dev(np.zeros((33, 33)), tdtype(FP64)) for _ in range(7)]
+    with pytest.raises(w1.W1Error):
+        w1.op_prox_steps(32, 2, FP64, 1, *z64, resident=True)
+
+
 @pytest.mark.parametrize("precision", [FP64, FP32])
 @pytest.mark.parametrize("n", [16, 64, 128, 200, 512, 1000])
 def test_poisson(precision, n):
