@@ -14,6 +14,11 @@ from HIP-event timing inside the timed region, and the FP64 CPU oracle timed
 on this host's cores on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu]
+    python bench.py --workload uneven   # 1024 pairs, n in {64..512}, Algorithm 4
+    python bench.py --workload served   # Poisson arrivals, n in {128..2048}
+    python bench.py --workload single   # one 512-grid pair, both algorithms
+
+Each workload prints one JSON line of the same layout.
 """
 from __future__ import annotations
 
@@ -22,6 +27,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -40,6 +47,276 @@ def workload_pairs(count, n):
     return [w1data.pair_shapes(i, n=n) for i in range(count)]
 
 
+
+FP32_MFMA_TFLOPS = 157.3
+
+
+def _levels(n):
+    return int(round(np.log2(n // 32))) + 1
+
+
+def _mfma_roofline(kstats):
+    """Dominant-kernel roofline for Algorithm 2 runs: the DCT passes are dense
+    products on the matrix cores (flops counted as 4 passes x 2 N^3 per
+    Poisson solve); other families are reported by time only."""
+    dom = max(kstats, key=lambda k: kstats[k]["ms"])
+    st = kstats[dom]
+    if dom == "dct" and st["ms"] > 0:
+        ach = st["flops"] / (st["ms"] * 1e-3) / 1e12
+        return {"kernel": "dct", "bound": "mfma", "achieved": ach, "peak": FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_MFMA_TFLOPS, "traffic": None, "avg_launch_ms": st["ms"] / max(st["launches"], 1),
+                "launches": st["launches"]}
+    return {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None, "avg_launch_ms": st["ms"] / max(st["launches"], 1), "launches": st["launches"]}
+
+
+def _serve_all(w1, srv, items, prm_for):
+    """Submit every (n, metric, p0, p1) item, wait, return results in order."""
+    tickets = [srv.submit(a, b, prm_for(n, m)) for n, m, a, b in items]
+    srv.drain()
+    out = []
+    for t in tickets:
+        r = None
+        while r is None:
+            r = srv.poll(t)
+        out.append(r[0])
+    return out
+
+
+def run_uneven(args, w1):
+    """Uneven batch: 1024 pairs, n in {64,128,256,512} (p = .4,.3,.2,.1), L1 for
+    even pairs and L2 for odd ones, Gaussian mixtures with 2..10 components,
+    FP32 Algorithm 4 with L = log2(n/32)+1 levels and the paper's stop rule;
+    one step = the whole batch through the served entry points."""
+    import torch
+    import w1data
+    P = args.pairs if args.pairs != 256 else 1024
+    log(f"[bench] uneven: generating {P} pairs")
+    items = [w1data.pair_uneven(i) for i in range(P)]
+    dev = [(n, m, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for n, m, a, b in items]
+
+    def prm_for(n, m, precision=w1.FP32):
+        return w1.params(n=n, levels=_levels(n), metric=m, algo=w1.ALGO_PROX, precision=precision,
+                         stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=10)
+
+    srv = w1.Solver(prm_for(512, 2), capacity=P)
+    for k in range(args.warmup):
+        _serve_all(w1, srv, dev, prm_for)
+        log(f"[bench] warmup {k} done")
+    srv.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        res = _serve_all(w1, srv, dev, prm_for)
+        log(f"[bench] step {k} done")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ks = srv.kernel_stats()
+    srv.close()
+    ups = sum(sum(it * ((n >> (len(r["iters"]) - 1 - l)) + 1) ** 2 for l, it in enumerate(r["iters"]))
+              for (n, _, _, _), r in zip(dev, res))
+    # FP64 one-at-a-time reference on a sample (first pairs of each size)
+    sample = []
+    for size in (64, 128, 256, 512):
+        sample += [i for i, it in enumerate(items) if it[0] == size][:max(1, args.fp64_sample // 4)]
+    s64 = w1.Solver(prm_for(512, 2, w1.FP64), capacity=1)
+    rel, t64 = [], 0.0
+    for i in sample:
+        n, m, a, b = dev[i]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r64 = _serve_all(w1, s64, [(n, m, a, b)], lambda n_, m_: prm_for(n_, m_, w1.FP64))[0]
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t
+        rel.append(abs(res[i]["w1"] - r64["w1"]) / abs(r64["w1"]))
+    s64.close()
+    cpu = None
+    if not args.no_cpu:
+        # one pair of each size, weighted by the size mix: expected seconds
+        # per solve of the workload on one host core
+        import oracle.w1_oracle as o
+        probs = {64: 0.4, 128: 0.3, 256: 0.2, 512: 0.1}
+        exp_t, parts = 0.0, []
+        for size, pr in probs.items():
+            i = next(j for j, it in enumerate(items) if it[0] == size)
+            n, m, a, b = items[i]
+            t = time.perf_counter()
+            o.solve(a, b, n, L=_levels(n), p=m, algo=2, stop="fpr", eps_L=o.paper_stop_tolerance(2, n, True),
+                    alpha=-1.0, max_iters=20000, check_every=10, return_fields=False)
+            dt = time.perf_counter() - t
+            exp_t += pr * dt
+            parts.append(f"n={n}: {dt:.2f} s")
+            log(f"[bench] CPU oracle pair {i} n={n}: {dt:.2f} s")
+        cpu = {"value": 1.0 / exp_t, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": "one pair of each size, weighted by the size mix (" + ", ".join(parts) + ")"}
+    sps = P * args.steps / el
+    return {"metric": METRIC, "value": sps, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"uneven batch: {P} pairs, n in {{64,128,256,512}} w.p. {{.4,.3,.2,.1}}, "
+                                   "L1/L2 alternating, Gaussian mixtures K~U{2..10}, Algorithm 4 (DCT Poisson), "
+                                   "L=log2(n/32)+1, paper stop rule, FP32 iterates / FP64 reductions",
+                       "global_batch": P, "parallelism": "batch"},
+            "cell_updates_per_s": ups * args.steps / el,
+            "fp64_single": {"solves_per_s": len(sample) / t64 if t64 else None, "sample": len(sample)},
+            "accuracy": {"checked": len(rel), "within_1e-4": sum(x <= 1e-4 for x in rel),
+                         "max_rel": max(rel) if rel else None},
+            "roofline": _mfma_roofline(ks),
+            "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in ks.items()
+                        if v["launches"]},
+            "cpu_baseline": cpu}
+
+
+def run_served(args, w1):
+    """Served stream: Poisson arrivals at --rate for --duration seconds, grid
+    side uniform over --sizes, densities 50/50 Gaussian mixtures or unions of
+    rectangles/disks, FP32 Algorithm 4 with L = log2(n/32)+1 and the paper's
+    stop rule tested every iteration; each result is checked against the FP64
+    solve of the same request (relative difference 1e-4).  Requests join the
+    running batch as slots and HBM budget free up; latency is submission to
+    completion."""
+    import torch
+    import w1data
+    sizes = tuple(int(x) for x in args.sizes.split(","))
+    count = int(args.rate * args.duration)
+    reqs = w1data.served_requests(count, rate=args.rate, sizes=sizes)
+    # a pool of distinct pairs per size, reused round robin (the solver keeps
+    # no state between requests, so repeats cost the same as new inputs)
+    POOL = 4
+    pool, seen = {}, {}
+    for r in reqs:
+        k = seen.get(r.n, 0)
+        if k < POOL:
+            a, b = w1data.served_pair(r)
+            pool[(r.n, k)] = (torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())
+        seen[r.n] = k + 1
+    torch.cuda.synchronize()
+
+    def prm_for(n, precision=w1.FP32):
+        return w1.params(n=n, levels=_levels(n), metric=w1.METRIC_L2, algo=w1.ALGO_PROX, precision=precision,
+                         stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=1)
+
+    srv = w1.Solver(prm_for(max(sizes)), capacity=256)
+    srv.serve_config(1 << 30)
+    srv.profile(True)
+    out, pend, cnt = [], {}, {}
+    last = [0.0]
+    t0 = time.perf_counter()
+
+    def sweep():
+        for tk in list(pend):
+            r = srv.poll(tk)
+            if r is not None:
+                out.append((pend.pop(tk), r[0]))
+        now = time.perf_counter() - t0
+        if now - last[0] > 2.0:
+            last[0] = now
+            log(f"[bench] served t={now:.1f}s done {len(out)} pending {len(pend)}")
+
+    for r in reqs:
+        while True:
+            now = time.perf_counter() - t0
+            if now >= r.arrival:
+                break
+            sweep()
+            time.sleep(min(0.0005, r.arrival - now))
+        k = cnt.get(r.n, 0)
+        cnt[r.n] = k + 1
+        a, b = pool[(r.n, k % POOL)]
+        pend[srv.submit(a, b, prm_for(r.n))] = (r, k % POOL)
+    deadline = args.duration * 6 + 30
+    while pend and time.perf_counter() - t0 < deadline:
+        sweep()
+        time.sleep(0.001)
+    el = time.perf_counter() - t0
+    unfinished = len(pend)
+    ks = srv.kernel_stats()
+    srv.close()
+    lat = np.array([x[1]["seconds"] for x in out])
+    per = {}
+    for n in sizes:
+        l = np.array([x[1]["seconds"] for x in out if x[0][0].n == n])
+        if len(l):
+            per[str(n)] = {"count": int(len(l)), "p50_ms": float(np.percentile(l, 50) * 1e3),
+                           "p99_ms": float(np.percentile(l, 99) * 1e3)}
+    # FP64 one-at-a-time reference on one request of each size
+    s64 = w1.Solver(prm_for(max(sizes), w1.FP64), capacity=1)
+    rel, t64, n64 = [], 0.0, 0
+    for n in sizes:
+        mine = [x for x in out if x[0][0].n == n]
+        if not mine:
+            continue
+        (r, slot), res = mine[0]
+        a, b = pool[(n, slot)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tk = s64.submit(a, b, prm_for(n, w1.FP64))
+        s64.drain()
+        r64 = None
+        while r64 is None:
+            r64 = s64.poll(tk)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t
+        n64 += 1
+        rel.append(abs(res["w1"] - r64[0]["w1"]) / abs(r64[0]["w1"]))
+    s64.close()
+    return {"metric": METRIC, "value": len(out) / el, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"served stream: Poisson arrivals at {args.rate:g}/s for {args.duration:g} s, "
+                                   f"n uniform over {{{args.sizes}}}, mixtures or rectangles/disks, Algorithm 4, "
+                                   "L=log2(n/32)+1, paper stop rule every iteration, FP32 iterates",
+                       "requests": count, "parallelism": "continuous batching"},
+            "latency": {"p50_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
+                        "p99_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
+                        "per_size": per, "unfinished": unfinished},
+            "fp64_single": {"solves_per_s": n64 / t64 if t64 else None, "sample": n64},
+            "accuracy": {"checked": len(rel), "within_1e-4": sum(x <= 1e-4 for x in rel),
+                         "max_rel": max(rel) if rel else None},
+            "roofline": _mfma_roofline(ks),
+            "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in ks.items()
+                        if v["launches"]},
+            "cpu_baseline": None}
+
+
+def run_single(args, w1):
+    """Single pair at n = 512: eight anisotropic Gaussians and the same
+    mixture shifted by up to 0.1 (W1 close to the shift length), L2, 4-level
+    cascade; plain (Algorithm 3) and prox (Algorithm 4), FP32 and FP64,
+    paper stop rule; seconds per solve."""
+    import torch
+    import w1data
+    n = 512
+    a, b, shift = w1data.pair_shift8(0, n=n)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    out = {}
+    for algo, name in ((w1.ALGO_PLAIN, "plain"), (w1.ALGO_PROX, "prox")):
+        for prec, pn in ((w1.FP32, "f32"), (w1.FP64, "f64")):
+            prm = w1.params(n=n, levels=4, metric=w1.METRIC_L2, algo=algo, precision=prec, stop_rule=w1.STOP_FPR,
+                            tol=0.0, alpha=-1.0, max_iters=20000, check_every=10)
+            with w1.Solver(prm, capacity=1) as s:
+                s.solve([(da, db)])
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                reps = max(1, args.steps)
+                for _ in range(reps):
+                    r = s.solve([(da, db)])[0]
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t) / reps
+            out[f"{name}_{pn}"] = {"seconds": dt, "w1": r["w1"], "iters": r["iters"], "lo": r["lo"], "hi": r["hi"]}
+            log(f"[bench] single {name} {pn}: {dt*1e3:.1f} ms W1 {r['w1']:.6f} iters {r['iters']}")
+    sec = out["prox_f32"]["seconds"]
+    return {"metric": METRIC, "value": 1.0 / sec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "single pair n=512: 8 anisotropic Gaussians and a shifted copy (|s| <= 0.1), "
+                                   "L2, 4 levels, paper stop rule; value = Algorithm 4 FP32",
+                       "global_batch": 1, "parallelism": "none"},
+            "shift_length": float(np.hypot(*shift)), "runs": out,
+            "context": "paper: 0.2-1.5 s per 512x512 W1 on one i7-2600 (MATLAB, Algorithm 4)",
+            "cpu_baseline": None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +330,10 @@ def main():
     ap.add_argument("--block-steps", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "uneven", "served", "single"])
+    ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
+    ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
+    ap.add_argument("--sizes", default="128,256,512,1024,2048", help="served: grid sides")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solves shard across GPUs "
@@ -74,6 +355,10 @@ def main():
     import paper_1810_00118_amd as w1
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.workload != "uniform":
+        run = {"uneven": run_uneven, "served": run_served, "single": run_single}[args.workload]
+        print(json.dumps(run(args, w1)), flush=True)
+        return
     n, L, P = args.n, args.levels, args.pairs
     log(f"[bench] generating {P} pairs n={n}")
     pairs = workload_pairs(P, n)

@@ -94,6 +94,7 @@ struct w1_ctx {
   bool own_stream = false;
   std::unique_ptr<BatchBase> b32, b64;
   std::mutex run_mu;  // one thread drives the batches at a time
+  std::mutex stage_mu;  // submit-side staging copies
   // w1_solve results kept for w1_fields
   std::vector<std::unique_ptr<Request>> last;
   // served mode
@@ -101,8 +102,13 @@ struct w1_ctx {
   std::condition_variable cv;
   std::deque<Request*> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
-  std::vector<std::vector<double>> pending_in;  // unused placeholder
-  std::unordered_map<uint64_t, std::pair<std::vector<double>, std::vector<double>>> staged;
+  // masses of queued requests, in device staging memory (p0 then p1)
+  struct Staged {
+    char* mem = nullptr;
+    size_t bytes = 0;
+  };
+  std::unordered_map<uint64_t, Staged> staged;
+  hipStream_t stage_stream = nullptr;   // submit-side copies, synchronised there
   std::thread worker;
   bool stop = false;
   bool worker_started = false;
@@ -222,15 +228,21 @@ static void worker_loop(w1_ctx* h) {
     }
     std::lock_guard<std::mutex> rg(h->run_mu);
     for (Request* r : to_admit) {
-      std::pair<std::vector<double>, std::vector<double>> in;
+      w1_ctx::Staged in;
       {
         std::lock_guard<std::mutex> lk(h->mu);
         auto it = h->staged.find(r->ticket);
-        in = std::move(it->second);
+        in = it->second;
         h->staged.erase(it);
       }
+      const size_t ne = (size_t)(r->prm.n + 1) * (r->prm.n + 1);
+      const double* s0 = (const double*)in.mem;
       BatchBase* b = h->batch(r->prm.precision);
-      int st = b ? b->admit(r, in.first.data(), in.second.data(), 0) : W1_EDEVICE;
+      int st = b ? b->admit(r, s0, s0 + ne, 1) : W1_EDEVICE;
+      // the copies out of the staging memory are queued on the batch's
+      // stream; the batch returns it to the cache after its next sync
+      if (b) b->retire(in.bytes, in.mem);
+      else stage_free(in.bytes, in.mem);
       if (st) {
         std::lock_guard<std::mutex> lk(h->mu);
         r->res.status = W1_SOLVE_REJECTED;
@@ -279,23 +291,37 @@ extern "C" int w1_submit(w1_handle h, const w1_params* prm, const double* p0, co
   if (w1_params_check(&p)) return W1_EINVAL;
   if (request_bytes(p) > h->budget) return W1_ENOMEM;
   const size_t ne = (size_t)(p.n + 1) * (p.n + 1);
-  std::vector<double> a(ne), b(ne);
-  if (on_device) {
-    HIPCHK(hipMemcpy(a.data(), p0, ne * 8, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(b.data(), p1, ne * 8, hipMemcpyDeviceToHost));
-  } else {
-    std::memcpy(a.data(), p0, ne * 8);
-    std::memcpy(b.data(), p1, ne * 8);
+  // copy the masses into device staging memory on the handle's submit
+  // stream and wait for that stream only: the caller may reuse its buffers
+  // on return, and the solves in flight are not waited for
+  w1_ctx::Staged sg;
+  sg.bytes = 2 * ne * 8;
+  {
+    std::lock_guard<std::mutex> lk(h->stage_mu);
+    if (!h->stage_stream) HIPCHK(hipStreamCreateWithFlags(&h->stage_stream, hipStreamNonBlocking));
+    int st = stage_alloc(sg.bytes, &sg.mem);
+    if (st) return st;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    hipError_t e1 = hipMemcpyAsync(sg.mem, p0, ne * 8, kind, h->stage_stream);
+    hipError_t e2 = hipMemcpyAsync(sg.mem + ne * 8, p1, ne * 8, kind, h->stage_stream);
+    hipError_t e3 = hipStreamSynchronize(h->stage_stream);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+      if (e3 == hipSuccess) stage_free(sg.bytes, sg.mem);
+      return hip_status(e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3), "w1_submit copy");
+    }
   }
   std::unique_ptr<Request> r(new Request());
   fill_request(r.get(), p);
   r->t_submit = now_seconds();
   {
     std::lock_guard<std::mutex> lk(h->mu);
-    if ((int)h->queue.size() >= h->queue_limit) return W1_EBUSY;
+    if ((int)h->queue.size() >= h->queue_limit) {
+      stage_free(sg.bytes, sg.mem);
+      return W1_EBUSY;
+    }
     r->ticket = h->next_ticket++;
     *ticket = r->ticket;
-    h->staged.emplace(r->ticket, std::make_pair(std::move(a), std::move(b)));
+    h->staged.emplace(r->ticket, sg);
     h->queue.push_back(r.get());
     h->all.emplace(r->ticket, std::move(r));
     if (!h->worker_started) {
@@ -361,6 +387,9 @@ extern "C" int w1_destroy(w1_handle h) {
     h->b32.reset();
     h->b64.reset();
   }
+  for (auto& kv : h->staged) stage_free(kv.second.bytes, kv.second.mem);
+  h->staged.clear();
+  if (h->stage_stream) (void)hipStreamDestroy(h->stage_stream);
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return W1_OK;

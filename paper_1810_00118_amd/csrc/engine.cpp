@@ -384,6 +384,8 @@ static BlockCache& g_blocks_ref() {
   return *b;
 }
 #define g_blocks g_blocks_ref()
+int stage_alloc(size_t bytes, char** out) { return g_blocks.get(bytes, out); }
+void stage_free(size_t bytes, char* mem) { g_blocks.put(bytes, mem); }
 
 // ---------------------------------------------------------------------------
 // per-family launch timing with HIP events on the batch's stream
@@ -485,6 +487,7 @@ class Batch : public BatchBase {
   }
   ~Batch() override {
     (void)hipStreamSynchronize(st_);
+    free_retired();
     for (auto& t : tune_pending_) {
       tune_pool_.push_back(t.a);
       tune_pool_.push_back(t.b);
@@ -586,10 +589,11 @@ class Batch : public BatchBase {
     fin.out_m1 = in0;
     fin.out_m2 = in1;
     fin.out_psi = psi;
+    // queued on the batch's stream: the sources stay valid until the next
+    // synchronisation (w1_solve's caller buffers, or staging retired then)
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpyAsync(in0, p0, ne * 8, kind, st_));
     HIPCHK(hipMemcpyAsync(in1, p1, ne * 8, kind, st_));
-    HIPCHK(hipStreamSynchronize(st_));
     r->state = Request::PREP;
     r->level = 0;
     r->res = w1_result{};
@@ -746,6 +750,7 @@ class Batch : public BatchBase {
     prof_.on = on;
     prof_.reset();
   }
+  void retire(size_t bytes, char* mem) override { retire_.emplace_back(bytes, mem); }
   void kernel_stats(int f, double* o) const override { prof_.stats(f, o); }
 
  private:
@@ -772,9 +777,16 @@ class Batch : public BatchBase {
     return W1_OK;
   }
 
+  // after a synchronisation of the stream: staging copies have completed
+  void free_retired() {
+    for (auto& m : retire_) g_blocks.put(m.first, m.second);
+    retire_.clear();
+  }
+
   int read_scalars() {
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
+    free_retired();
     for (auto& t : tune_pending_) {
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) g_tuner().report(t.entry, t.arm, ms, t.units);
@@ -946,6 +958,7 @@ class Batch : public BatchBase {
     }
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
+    free_retired();
     std::vector<Request*> good;
     for (auto* r : prep) {
       const SlotScalars& s = hsc_[r->slot];
@@ -1285,6 +1298,7 @@ class Batch : public BatchBase {
   }
   std::vector<TunePend> tune_pending_;
   std::vector<hipEvent_t> tune_pool_;
+  std::vector<std::pair<size_t, char*>> retire_;
 
   int cap_;
   hipStream_t st_;

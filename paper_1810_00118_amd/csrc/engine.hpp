@@ -65,9 +65,16 @@ class BatchBase {
   // per-family kernel timing (HIP events on the batch's stream)
   virtual void profile(bool on) = 0;
   virtual void kernel_stats(int family, double* out5) const = 0;
+  // device memory that work already queued on the batch's stream may still
+  // read: returned to the cache at the batch's next host synchronisation
+  virtual void retire(size_t bytes, char* mem) = 0;
 };
 
 std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t stream);
+
+// device staging memory for served requests (the solve-state block cache)
+int stage_alloc(size_t bytes, char** out);
+void stage_free(size_t bytes, char* mem);
 
 // Tuning choice for the plain tiled kernel.
 struct TileChoice {
