@@ -375,6 +375,7 @@ def main():
         solver.solve(dev_pairs)
         log(f"[bench] warmup {k} {time.perf_counter() - t:.3f}s")
     solver.profile(True)
+    c0 = solver.counters()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = None
@@ -384,6 +385,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kstats = solver.kernel_stats()
+    counters = {k: (v - c0[k]) / args.steps for k, v in solver.counters().items()}   # per step
     solver.profile(False)
     sides = [n >> (L - 1 - l) for l in range(L)]
     nodes = [(s + 1) ** 2 for s in sides]
@@ -477,7 +479,8 @@ def main():
                         "speedup_batched_fp32": solves_per_s / fp64_sps if fp64_sps else None},
         "accuracy": {"checked": len(rel), "within_1e-4": sum(x <= 1e-4 for x in rel),
                      "max_rel": max(rel) if rel else None},
-        "iterations": iter_stats, "roofline": roof, "kernels": kernels, "autotune": tuned, "cpu_baseline": cpu,
+        "iterations": iter_stats, "roofline": roof, "kernels": kernels, "autotune": tuned,
+        "engine_counters": counters, "cpu_baseline": cpu,
         "context": "paper: 0.2-1.5 s per 512x512 W1 on one i7-2600 (MATLAB, Algorithm 4)",
     }
     solver.close()

@@ -170,6 +170,10 @@ int w1_submit(w1_handle h, const w1_params* per_request, const double* p0,
               const double* p1, int32_t on_device, uint64_t* ticket);
 int w1_poll(w1_handle h, uint64_t ticket, w1_result* out, double* m1,
             double* m2, double* psi);
+/* Engine counters since w1_plan, both precisions: [0] host steps (one
+ * synchronisation each), [1] level starts, [2] work-list uploads,
+ * [3] iteration blocks queued.                                             */
+int w1_engine_counters(w1_handle h, int64_t* out4);
 /* Block until every submitted request is done.                             */
 int w1_drain(w1_handle h);
 /* Served-mode counters: [0] admitted, [1] finished, [2] queued now,

@@ -82,6 +82,7 @@ def lib():
         "w1_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(Result), vp, vp, vp]),
         "w1_drain": (C.c_int, [vp]),
         "w1_serve_stats": (C.c_int, [vp, C.POINTER(C.c_int64)]),
+        "w1_engine_counters": (C.c_int, [vp, C.POINTER(C.c_int64)]),
         "w1_destroy": (C.c_int, [vp]),
         "w1_strerror": (C.c_char_p, [C.c_int]),
         "w1_version": (C.c_char_p, []),
@@ -269,6 +270,11 @@ class Solver:
 
     def drain(self):
         _check(lib().w1_drain(self.h), "w1_drain")
+
+    def counters(self):
+        o = (C.c_int64 * 4)()
+        _check(lib().w1_engine_counters(self.h, o), "w1_engine_counters")
+        return {"host_steps": o[0], "level_starts": o[1], "list_uploads": o[2], "blocks": o[3]}
 
     def stats(self):
         o = (C.c_int64 * 6)()

@@ -612,6 +612,7 @@ class Batch : public BatchBase {
 
   int step() override {
     if (!ok_) return W1_EDEVICE;
+    ++n_steps_;
     arena_.reset();
     int st = W1_OK;
     std::vector<Request*> prep;
@@ -655,6 +656,7 @@ class Batch : public BatchBase {
       st = launch_resident(R, alone ? 0 : nblocks * block_us);
       if (st) return fail(st);
     }
+    n_blocks_ += nblocks;
     for (int b = 0; b < nblocks; ++b) {
       int gi = 0;
       for (auto& kv : P) {
@@ -758,6 +760,12 @@ class Batch : public BatchBase {
     prof_.reset();
   }
   void retire(size_t bytes, char* mem) override { retire_.emplace_back(bytes, mem); }
+  void counters(int64_t* o) const override {
+    o[0] = n_steps_;
+    o[1] = n_levels_;
+    o[2] = n_uploads_;
+    o[3] = n_blocks_;
+  }
   void kernel_stats(int f, double* o) const override { prof_.stats(f, o); }
 
  private:
@@ -926,6 +934,7 @@ class Batch : public BatchBase {
       }
       L.n = (int)v.size();
       L.gen = gen_;
+      ++n_uploads_;
     }
     *count = L.n;
     return (X*)L.d;
@@ -1042,6 +1051,7 @@ class Batch : public BatchBase {
                                                      : side <= K<T>::prox_resident_max_side());
     // descriptors are fixed at admission; only the work lists change
     ++gen_;
+    ++n_levels_;
   }
 
   // -- resident levels (both algorithms) -----------------------------------
@@ -1310,6 +1320,7 @@ class Batch : public BatchBase {
   std::vector<TunePend> tune_pending_;
   std::vector<hipEvent_t> tune_pool_;
   std::vector<std::pair<size_t, char*>> retire_;
+  int64_t n_steps_ = 0, n_levels_ = 0, n_uploads_ = 0, n_blocks_ = 0;
 
   int cap_;
   hipStream_t st_;

@@ -68,6 +68,9 @@ class BatchBase {
   // device memory that work already queued on the batch's stream may still
   // read: returned to the cache at the batch's next host synchronisation
   virtual void retire(size_t bytes, char* mem) = 0;
+  // [0] host steps (one synchronisation each), [1] level starts,
+  // [2] work-list uploads, [3] iteration blocks queued
+  virtual void counters(int64_t* out4) const = 0;
 };
 
 std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t stream);
