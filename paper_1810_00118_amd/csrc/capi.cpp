@@ -762,7 +762,7 @@ int op_evaluate(int n, int metric, const void* m1, const void* m2, const void* p
   if (!dsw || !dgw || !di || !dn) return W1_EDEVICE;
   K<T>::div_pre(s, dsw, (int)sw.size(), op.dd, op.dsc, 2, K_PROX, 0);
   op.poisson(dgw, (int)gw.size(), 6);
-  K<T>::eval_sums(s, dsw, (int)sw.size(), op.dd, op.dsc, K_PROX, 1, 0);
+  K<T>::eval_sums(s, dsw, (int)sw.size(), op.dd, op.dsc, K_PROX, 1);
   K<T>::eval_final(s, di, dn, 1, op.dd, op.dsc, K_PROX, 1);
   HIPCHK(hipGetLastError());
   SlotScalars h;

@@ -572,13 +572,6 @@ class Batch : public BatchBase {
         d.dctCt = (const T*)t.Ct;
         d.dcts = t.s;
       }
-      if (r->kind == K_PROX && l == L - 1 && sizeof(T) == 4) {
-        DctTab t64;
-        st = dct_tables<double>(nl + 1, &t64);
-        if (st) return st;
-        d.dctC64 = (const double*)t64.C;
-        d.dctCt64 = (const double*)t64.Ct;
-      }
     }
     double* part = (double*)p;
     p += align256((size_t)max_tiles(r->prm.n) * NQ * 8);
@@ -1261,11 +1254,7 @@ class Batch : public BatchBase {
       if (st) return st;
       Work* dgw = arena_.put(gw, &st);
       if (st) return st;
-      // the prox potential (Appendix B) is recovered in FP64 for FP32 solves
-      const int pot64 = kind == K_PROX && sizeof(T) == 4 ? 1 : 0;
-      if (pot64) {
-        K<T>::psi64(st_, dsw, (int)sw.size(), dgw, (int)gw.size(), ddesc_);
-      } else if (kind == K_PROX) {
+      if (kind == K_PROX) {
         K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 1, kind, 0);
         poisson(dgw, (int)gw.size(), 8, 0);
       }
@@ -1273,12 +1262,12 @@ class Batch : public BatchBase {
         K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 2, kind, 0);
         poisson(dgw, (int)gw.size(), 6, 0);
       }
-      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, cert, pot64);
+      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, cert);
       int *di, *dn;
       st = reduce_lists(lv, simple_tiles_f, &di, &dn);
       if (st) return st;
       K<T>::eval_final(st_, di, dn, (int)grp.size(), ddesc_, dsc_, kind, cert);
-      K<T>::export_fields(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, pot64);
+      K<T>::export_fields(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));

@@ -1657,8 +1657,7 @@ __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, cons
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
-                                                   const SlotScalars* __restrict__ scal, int kind, int cert,
-                                                   int pot64) {
+                                                   const SlotScalars* __restrict__ scal, int kind, int cert) {
   __shared__ double lds[4 * NQ];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
@@ -1676,7 +1675,6 @@ __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work
     pot = d.p[8];
   }
   const T* corr = d.p[6];
-  const double* __restrict__ P64 = d.out_psi;
   const double ih = 1.0 / d.h;
   double v[NQ] = {0, 0, 0, 0, 0, -INFINITY, 0, 0};
   SIMPLE_TILE_LOOP(d, w, {
@@ -1684,10 +1682,9 @@ __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work
     const double cc = cert ? (double)corr[off] : 0.0;
     const double c1 = cert && i < n ? ((double)corr[off + pitch] - cc) * ih : 0.0;
     const double c2 = cert && j < n ? ((double)corr[off + 1] - cc) * ih : 0.0;
-    const size_t od = (size_t)i * (n + 1) + j;   // dense index of the FP64 potential
-    const double pc = pot64 ? P64[od] : (double)pot[off];
-    const double g1 = i < n ? ((pot64 ? P64[od + n + 1] : (double)pot[off + pitch]) - pc) * ih : 0.0;
-    const double g2 = j < n ? ((pot64 ? P64[od + 1] : (double)pot[off + 1]) - pc) * ih : 0.0;
+    const double pc = (double)pot[off];
+    const double g1 = i < n ? ((double)pot[off + pitch] - pc) * ih : 0.0;
+    const double g2 = j < n ? ((double)pot[off + 1] - pc) * ih : 0.0;
     const double rr = (double)d.rho[off];
     const double gq = d.metric == 1 ? fmax(fabs(g1), fabs(g2)) : sqrt(g1 * g1 + g2 * g2);
     const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
@@ -1757,7 +1754,7 @@ __global__ __launch_bounds__(256) void k_eval_final(const int* __restrict__ idx,
 template <typename T>
 __global__ __launch_bounds__(256) void k_export_fields(const Work* __restrict__ work,
                                                        const SlotDesc<T>* __restrict__ desc,
-                                                       const SlotScalars* __restrict__ scal, int kind, int pot64) {
+                                                       const SlotScalars* __restrict__ scal, int kind) {
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
   const SlotDesc<T>& d = desc[w.x];
@@ -1780,102 +1777,8 @@ __global__ __launch_bounds__(256) void k_export_fields(const Work* __restrict__ 
     const size_t o = (size_t)i * (d.n + 1) + j;
     if (om1) om1[o] = (double)m1[off];
     if (om2) om2[o] = (double)m2[off];
-    if (opsi && !pot64) opsi[o] = kind == K_PLAIN ? -((double)pot[off] - mean) : (double)pot[off];
+    if (opsi) opsi[o] = kind == K_PLAIN ? -((double)pot[off] - mean) : (double)pot[off];
   })
-}
-
-// ---------------------------------------------------------------------------
-// FP64 potential of an FP32 Algorithm 2 iterate (Appendix B): r0 = A vphi in
-// FP64 from the FP32 edge duals, then four FP64 DCT passes r0 -> r1 -> r0 ->
-// r1 -> exported potential (dense pitch n+1).  Recovering psi in FP64 keeps
-// the certificate's Lipschitz test free of the FP32 rounding of psi, whose
-// gradient noise grows with n.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_psi64_div(const Work* __restrict__ work,
-                                                   const SlotDesc<T>* __restrict__ desc) {
-  const Work w = work[blockIdx.x];
-  if (w.x < 0) return;
-  const SlotDesc<T>& d = desc[w.x];
-  const int n = d.n, pitch = d.pitch;
-  const double ih = 1.0 / d.h;
-  const T* a1 = d.p[2];
-  const T* a2 = d.p[3];
-  double* out = d.r0;
-  SIMPLE_TILE_LOOP(d, w, {
-    const double v1c = i < n ? (double)a1[off] : 0.0;
-    const double v1u = i > 0 ? (double)a1[off - pitch] : 0.0;
-    const double v2c = j < n ? (double)a2[off] : 0.0;
-    const double v2l = j > 0 ? (double)a2[off - 1] : 0.0;
-    out[off] = ((v1c - v1u) + (v2c - v2l)) * ih;
-  })
-}
-
-// one FP64 DCT pass; planes: 0 = r0, 1 = r1 (pitch), 2 = exported potential
-// (dense); MODE / SCALE / mat as in the DCT kernels above
-template <typename T, int MODE, bool SCALE>
-__global__ __launch_bounds__(256) void k_psi64_pass(const Work* __restrict__ work,
-                                                    const SlotDesc<T>* __restrict__ desc, int src, int dst,
-                                                    int mat) {
-  __shared__ double As[16][GEMM_T + 1];
-  __shared__ double Bs[16][GEMM_T + 1];
-  const Work w = work[blockIdx.x];
-  if (w.x < 0) return;
-  const SlotDesc<T>& d = desc[w.x];
-  const int N = d.n + 1;
-  const double* M = mat ? d.dctCt64 : d.dctC64;
-  const double* X = src == 0 ? d.r0 : (src == 1 ? d.r1 : d.out_psi);
-  double* Y = dst == 0 ? d.r0 : (dst == 1 ? d.r1 : d.out_psi);
-  const int ldx = src == 2 ? N : d.pitch, ldy = dst == 2 ? N : d.pitch;
-  const double* A = MODE == 0 ? X : M;
-  const double* B = MODE == 0 ? M : X;
-  const int lda = MODE == 0 ? ldx : N;
-  const int ldb = MODE == 0 ? N : ldx;
-  const int i0 = w.y * GEMM_T, j0 = w.z * GEMM_T;
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-  double acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-  for (int p0 = 0; p0 < N; p0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + 256 * q;
-      const int ii = e >> 4, pp = e & 15;
-      const int gi = i0 + ii, gp = p0 + pp;
-      As[pp][ii] = (gi < N && gp < N) ? A[(size_t)gi * lda + gp] : 0.0;
-      const int pb = e >> 6, jj = e & 63;
-      const int gq = p0 + pb, gj = j0 + jj;
-      Bs[pb][jj] = (gq < N && gj < N) ? B[(size_t)gq * ldb + gj] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int pp = 0; pp < 16; ++pp) {
-      double a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[pp][ty * 4 + r];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[pp][tx * 4 + c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = __fma_rn(a[r], b[c], acc[r][c]);
-    }
-    __syncthreads();
-  }
-  const double h2 = d.h * d.h;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int gi = i0 + ty * 4 + r, gj = j0 + tx * 4 + c;
-      if (gi < N && gj < N) {
-        double v = acc[r][c];
-        if (SCALE) v = (gi == 0 && gj == 0) ? 0.0 : v * (h2 / (d.dcts[gi] + d.dcts[gj]));
-        Y[(size_t)gi * ldy + gj] = v;
-      }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2027,25 +1930,16 @@ template <typename T> void K<T>::check(hipStream_t s, const int* idx, const int*
   if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len, launches);
 }
 template <typename T> void K<T>::eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                           const SlotScalars* sc, int kind, int cert, int pot64) {
-  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, sc, kind, cert, pot64);
-}
-template <typename T> void K<T>::psi64(hipStream_t s, const Work* sw, int nsw, const Work* gw, int ngw,
-                                       const SlotDesc<T>* d) {
-  if (!nsw || !ngw) return;
-  LAUNCH(k_psi64_div<T>, nsw, 256, 0, s, sw, d);
-  LAUNCH((k_psi64_pass<T, 0, false>), ngw, 256, 0, s, gw, d, 0, 1, 1);   // rows:    X C^T
-  LAUNCH((k_psi64_pass<T, 1, true>), ngw, 256, 0, s, gw, d, 1, 0, 0);    // columns: C X, / lambda
-  LAUNCH((k_psi64_pass<T, 1, false>), ngw, 256, 0, s, gw, d, 0, 1, 1);   // columns: C^T X
-  LAUNCH((k_psi64_pass<T, 0, false>), ngw, 256, 0, s, gw, d, 1, 2, 0);   // rows:    X C
+                                           const SlotScalars* sc, int kind, int cert) {
+  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, sc, kind, cert);
 }
 template <typename T> void K<T>::eval_final(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
                                             SlotScalars* sc, int kind, int cert) {
   if (ns) LAUNCH(k_eval_final<T>, ns, 256, 0, s, idx, nt, d, sc, kind, cert);
 }
 template <typename T> void K<T>::export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                               const SlotScalars* sc, int kind, int pot64) {
-  if (nw) LAUNCH(k_export_fields<T>, nw, 256, 0, s, w, d, sc, kind, pot64);
+                                               const SlotScalars* sc, int kind) {
+  if (nw) LAUNCH(k_export_fields<T>, nw, 256, 0, s, w, d, sc, kind);
 }
 
 // FP32 only: the FP64 iterate does not fit the register budget

@@ -45,8 +45,6 @@ struct SlotDesc {
   const T* dctC;       // orthonormal DCT-II matrix C[k][j], N x N row-major
   const T* dctCt;      // its transpose
   const double* dcts;  // 4 sin^2(pi k / 2N), k < N
-  const double* dctC64;   // FP64 DCT-II matrix and its transpose (finest prox
-  const double* dctCt64;  // level of an FP32 solve: FP64 potential recovery)
   const double* in0;   // finest level only: input masses, dense pitch n+1
   const double* in1;
   double* out_m1;      // finest level only: exported fields, dense FP64
@@ -125,18 +123,13 @@ struct K {
                         bool check);
   static void check(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
                     SlotScalars* sc, int kind, int block_len, int launches);
-  // FP64 potential psi = (A A*)^{-1} A vphi of an Algorithm 2 iterate into
-  // the slot's exported potential buffer (dense pitch n+1), through the FP64
-  // staging planes r0 / r1; sw = simple tiles, gw = DCT tiles
-  static void psi64(hipStream_t s, const Work* sw, int nsw, const Work* gw, int ngw, const SlotDesc<T>* d);
-  // cert = 0: no Poisson correction in plane 6; lo, hi and kkt are NaN.
-  // pot64: the prox potential is read from the exported FP64 buffer
+  // cert = 0: no Poisson correction in plane 6; lo, hi and kkt are NaN
   static void eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                        int kind, int cert, int pot64);
+                        int kind, int cert);
   static void eval_final(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
                          SlotScalars* sc, int kind, int cert);
   static void export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                            int kind, int pot64);
+                            int kind);
 };
 
 int resident_lds_bytes(int side, int elem);
