@@ -616,11 +616,18 @@ class Batch : public BatchBase {
       if (st) return fail(st);
     }
     std::vector<Request*> R;
-    // grouped by (check_every, rule, metric): one launch sequence per group
-    std::map<std::tuple<int, int, int>, std::vector<Request*>> P, X;
+    // grouped by (check_every, rule, metric, size class): one launch sequence
+    // per group.  Plain levels share one class (one launch covers every
+    // size); prox levels are classed by log2 of the side, so each class
+    // advances at its own pace instead of every small level waiting for the
+    // O(N^3) transforms of the largest one.
+    std::map<std::tuple<int, int, int, int>, std::vector<Request*>> P, X;
     for (auto* r : slots_) {
       if (!r || r->state != Request::RUN) continue;
-      const auto key = std::make_tuple(r->prm.check_every, r->prm.stop_rule, r->prm.metric);
+      int cls = 0;
+      if (r->kind == K_PROX)
+        for (int s = r->sides[r->level]; s > 1; s >>= 1) ++cls;
+      const auto key = std::make_tuple(r->prm.check_every, r->prm.stop_rule, r->prm.metric, cls);
       if (r->resident_level) R.push_back(r);
       else if (r->kind == K_PROX) X[key].push_back(r);
       else P[key].push_back(r);
@@ -629,36 +636,56 @@ class Batch : public BatchBase {
     st = flush_desc();
     if (st) return fail(st);
     // Several iteration blocks per host synchronisation (slots that stop
-    // inside the pipeline are skipped by the gated kernels), sized so one
-    // step is a few milliseconds of device work.  Beside running tiled or
-    // prox levels, LDS-resident levels run in chunks of about that length.
-    double active = 0;
+    // inside the pipeline are skipped by the gated kernels), sized so each
+    // group gets a few milliseconds of device work per step.  Beside running
+    // tiled or prox levels, LDS-resident levels run in chunks of about that
+    // length.
+    struct Grp {
+      std::vector<Request*>* v;
+      bool prox;
+      int nb;
+      double us;
+    };
+    std::vector<Grp> groups;
+    double plain_nodes = 0;
     for (auto& kv : P)
-      for (auto* r : kv.second) active += node_count(r->sides[r->level]) * r->prm.check_every;
-    for (auto& kv : X)
-      for (auto* r : kv.second) active += 6.0 * node_count(r->sides[r->level]) * r->prm.check_every;
-    const double block_us = std::max(30.0, active / 3.0e5);   // ~3e11 node updates / s
-    const int nblocks = (P.empty() && X.empty()) ? 0 : std::max(8, std::min(64, (int)(2000.0 / block_us)));
+      for (auto* r : kv.second) plain_nodes += node_count(r->sides[r->level]) * r->prm.check_every;
+    // plain: ~3e11 node updates / s; one block count for all plain groups
+    const double plain_us = std::max(30.0, plain_nodes / 3.0e5);
+    const int plain_nb = std::max(8, std::min(64, (int)(2000.0 / plain_us)));
+    for (auto& kv : P) groups.push_back(Grp{&kv.second, false, plain_nb, plain_us});
+    for (auto& kv : X) {
+      // per iteration: ~42 us of launch latency for the group, the DCT
+      // passes at ~40 TFLOP/s (8 N^3 flops) and the node-wise kernels
+      double it_us = 42.0;
+      for (auto* r : kv.second) {
+        const double N = r->sides[r->level] + 1.0;
+        it_us += N * N * N / 5.0e6 + N * N / 5.0e4;
+      }
+      const double us = it_us * std::get<0>(kv.first);
+      groups.push_back(Grp{&kv.second, true, std::max(1, std::min(64, (int)(2000.0 / us))), us});
+    }
+    int maxnb = 0;
+    double step_us = 0;
+    for (auto& g : groups) {
+      maxnb = std::max(maxnb, g.nb);
+      step_us = std::max(step_us, g.nb * g.us);
+    }
     if (!R.empty()) {
-      // ~3.6 us per resident iteration: beside other work a chunk lasts about
-      // as long as the blocks queued with it
       // alone (no other level running) the launch runs to its stop tests:
       // chunking a uniform batch spreads the next level over many small
       // launches, which costs more than the wait for the slowest pair
-      const bool alone = P.empty() && X.empty();
-      st = launch_resident(R, alone ? 0 : nblocks * block_us);
+      const bool alone = groups.empty();
+      st = launch_resident(R, alone ? 0 : step_us);
       if (st) return fail(st);
     }
-    n_blocks_ += nblocks;
-    for (int b = 0; b < nblocks; ++b) {
-      int gi = 0;
-      for (auto& kv : P) {
-        st = launch_tiled_block(kv.second, gi++);
-        if (st) return fail(st);
-      }
-      gi = 0;
-      for (auto& kv : X) {
-        st = launch_prox_block(kv.second, gi++);
+    n_blocks_ += maxnb;
+    for (int b = 0; b < maxnb; ++b) {
+      int gp = 0, gx = 0;
+      for (auto& g : groups) {
+        const int gi = g.prox ? gx++ : gp++;
+        if (b >= g.nb) continue;
+        st = g.prox ? launch_prox_block(*g.v, gi) : launch_tiled_block(*g.v, gi);
         if (st) return fail(st);
       }
     }
