@@ -507,6 +507,15 @@ struct Op {
     d.dctC = (const T*)a;
     d.dctCt = (const T*)b;
     d.dcts = (const double*)c;
+    if (sizeof(T) == 4) {
+      std::vector<T> Cp, Ctp;
+      fold_order(M, C, &Cp, &Ctp);
+      if (alloc(Cp.size() * sizeof(T), &a) | alloc(Ctp.size() * sizeof(T), &b)) return W1_EDEVICE;
+      HIPCHK(hipMemcpy(a, Cp.data(), Cp.size() * sizeof(T), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(b, Ctp.data(), Ctp.size() * sizeof(T), hipMemcpyHostToDevice));
+      d.dctCp = (const T*)a;
+      d.dctCtp = (const T*)b;
+    }
     return W1_OK;
   }
   int commit(int count) {
@@ -537,7 +546,7 @@ struct Op {
   }
   std::vector<Work> gemmw(int x, int side) {
     std::vector<Work> w;
-    const int t = cdiv(side + 1, GEMM_T);
+    const int t = sizeof(T) == 4 ? fold_tiles(side + 1) : cdiv(side + 1, GEMM_T);
     for (int a = 0; a < t; ++a)
       for (int b = 0; b < t; ++b) w.push_back(make_int4(x, a, b, a * t + b));
     return w;
@@ -550,6 +559,10 @@ struct Op {
     return w;
   }
   void poisson(Work* gw, int ng, int dst) {
+    if constexpr (sizeof(T) == 4) {
+      K<T>::poisson_fold(st, gw, ng, dd, dsc, dst, 0);
+      return;
+    }
     K<T>::gemm(st, gw, ng, dd, dsc, 0, 6, 7, 1, false, 0);
     K<T>::gemm(st, gw, ng, dd, dsc, 1, 7, 6, 0, true, 0);
     K<T>::gemm(st, gw, ng, dd, dsc, 1, 6, 7, 1, false, 0);

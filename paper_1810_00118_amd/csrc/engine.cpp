@@ -55,12 +55,16 @@ static inline int simple_ti(int n) { return cdiv(n + 1, ST_H); }
 static inline int simple_tj(int n) { return cdiv(n + 1, ST_W); }
 static inline int simple_tiles(int n) { return simple_ti(n) * simple_tj(n); }
 static inline int gemm_t(int n) { return cdiv(n + 1, GEMM_T); }
+// tiles per side of the DCT work list: the folded FP32 passes may need more
+template <typename T>
+static inline int dct_t(int n) { return sizeof(T) == 4 ? fold_tiles(n + 1) : gemm_t(n); }
 static inline int tiled_ti(int n, int rh, int S) { return cdiv(n + 1, rh - 2 * S); }
 static inline int tiled_tj(int n, int S) { return cdiv(n + 1, TILED_RW - 2 * S); }
 static inline int max_tiles(int n) {
   // the tiled kernel has the most tiles at its deepest temporal block
   const int tiled = tiled_ti(n, TILED_RH, TILED_MAX_STEPS) * tiled_tj(n, TILED_MAX_STEPS);
-  return std::max(simple_tiles(n), std::max(gemm_t(n) * gemm_t(n), tiled));
+  const int g = std::max(gemm_t(n), fold_tiles(n + 1));
+  return std::max(simple_tiles(n), std::max(g * g, tiled));
 }
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -278,6 +282,8 @@ class BlockCache {
 struct DctTab {
   void* C = nullptr;
   void* Ct = nullptr;
+  void* Cp = nullptr;    // FP32 only: rows of C in even / odd order
+  void* Ctp = nullptr;   // FP32 only: transpose of Cp
   double* s = nullptr;
 };
 static std::mutex g_dct_mu;
@@ -312,6 +318,14 @@ static int dct_tables(int N, DctTab* out) {
   HIPCHK(hipMemcpy(t.C, C.data(), C.size() * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(t.Ct, Ct.data(), Ct.size() * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(t.s, s.data(), N * sizeof(double), hipMemcpyHostToDevice));
+  if (sizeof(T) == 4) {
+    std::vector<T> Cp, Ctp;
+    fold_order(N, C, &Cp, &Ctp);
+    HIPCHK(hipMalloc(&t.Cp, Cp.size() * sizeof(T)));
+    HIPCHK(hipMalloc(&t.Ctp, Ctp.size() * sizeof(T)));
+    HIPCHK(hipMemcpy(t.Cp, Cp.data(), Cp.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(t.Ctp, Ctp.data(), Ctp.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
   g_dct[key] = t;
   *out = t;
   return W1_OK;
@@ -570,6 +584,8 @@ class Batch : public BatchBase {
         if (st) return st;
         d.dctC = (const T*)t.C;
         d.dctCt = (const T*)t.Ct;
+        d.dctCp = (const T*)t.Cp;
+        d.dctCtp = (const T*)t.Ctp;
         d.dcts = t.s;
       }
     }
@@ -883,7 +899,7 @@ class Batch : public BatchBase {
     });
   }
   std::vector<Work> gemm_work(const std::vector<std::pair<Request*, int>>& lv) {
-    return make_work(lv, [](int n, int* ti, int* tj) { *ti = *tj = gemm_t(n); });
+    return make_work(lv, [](int n, int* ti, int* tj) { *ti = *tj = dct_t<T>(n); });
   }
   std::vector<Work> tiled_work(const std::vector<std::pair<Request*, int>>& lv, int rh, int S) {
     return make_work(lv, [rh, S](int n, int* ti, int* tj) {
@@ -1184,6 +1200,10 @@ class Batch : public BatchBase {
 
   // -- Poisson solve through four DCT passes ------------------------------
   void poisson(Work* gw, int ng, int dst, int gate) {
+    if constexpr (sizeof(T) == 4) {
+      K<T>::poisson_fold(st_, gw, ng, ddesc_, dsc_, dst, gate);
+      return;
+    }
     K<T>::gemm(st_, gw, ng, ddesc_, dsc_, 0, 6, 7, 1, false, gate);   // rows:    X C^T
     K<T>::gemm(st_, gw, ng, ddesc_, dsc_, 1, 7, 6, 0, true, gate);    // columns: C X, / lambda
     K<T>::gemm(st_, gw, ng, ddesc_, dsc_, 1, 6, 7, 1, false, gate);   // columns: C^T X
@@ -1206,7 +1226,9 @@ class Batch : public BatchBase {
     for (auto* r : X) {
       const double N = r->sides[r->level] + 1;
       nodes += N * N;
-      flops += 4.0 * 2.0 * N * N * N;
+      // flops the passes execute: the FP32 passes fold each length-N
+      // product into two of about half the length
+      flops += (sizeof(T) == 4 ? 4.0 : 8.0) * N * N * N;
     }
     for (int it = 0; it < ce; ++it) {
       int pi = prof_.begin();

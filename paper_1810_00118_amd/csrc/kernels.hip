@@ -1564,6 +1564,213 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const Work* __restrict__ work
   }
 }
 
+// ---------------------------------------------------------------------------
+// DCT passes with the even/odd fold (FP32, matrix cores).  The DCT-II basis
+// satisfies C[k][N-1-j] = (-1)^k C[k][j] (and C[k][(N-1)/2] = 0 for odd k
+// when N is odd), so a pass over length N splits into two products of half
+// the length: the even frequencies see x_j + x_{N-1-j}, the odd ones
+// x_j - x_{N-1-j} (forward); for the inverse the even and odd frequency sums
+// give x_j = E + O and x_{N-1-j} = E - O.  Frequency indices are kept in a
+// permuted order between the passes (ne even ones first, then no odd ones;
+// ne = N - N/2, no = N/2), with Cp[k''][j] = C[perm(k'')][j] and Ctp its
+// transpose.  Half the flops of the plain dense passes.
+//   pass 1 (rows, forward):   Y1[i][k''] = sum_j X[i][j] C[perm k''][j]
+//   pass 2 (columns, forward, divided by lambda):
+//                             Y2[k''][l''] = sum_i C[perm k''][i] Y1[i][l'']
+//   pass 3 (columns, inverse): Y3[i][l''] = sum_k'' C[perm k''][i] Y2[k''][l'']
+//   pass 4 (rows, inverse):    U[i][j] = sum_l'' Y3[i][l''] C[perm l''][j]
+// Work items: one square list per slot, T x T tiles with
+// T = max(cdiv(N, 64), cdiv(ne, 64) + cdiv(no, 64)); each pass reads (y, z)
+// in its own orientation and tiles outside its output return at once.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int dct_perm_(int x, int ne) { return x < ne ? 2 * x : 2 * (x - ne) + 1; }
+
+// one 64 x 64 output tile (this wavefront's 32 x 32 quarter into out[16],
+// same lane layout as k_gemm_mfma) of sum_k A(i, k) B(k, j), k < K; the
+// loaders take tile-local row / column and return 0 outside the operands
+template <class LA, class LB>
+__device__ __forceinline__ void mfma_tile64_(const LA& la, const LB& lb, int K, float (*As)[64][33],
+                                             float (*Bs)[32][68], float (&out)[16]) {
+  constexpr int KT = 32;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+  const int ak = t & 31, ai0 = t >> 5;
+  const int bj = t & 63, bk0 = t >> 6;
+  float ra[8], rb[8];
+  auto load = [&](int p0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      ra[q] = p0 + ak < K ? la(ai0 + 8 * q, p0 + ak) : 0.f;
+      rb[q] = p0 + bk0 + 4 * q < K ? lb(p0 + bk0 + 4 * q, bj) : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[buf][ai0 + 8 * q][ak] = ra[q];
+      Bs[buf][bk0 + 4 * q][bj] = rb[q];
+    }
+  };
+  w1_f32x16 tot = {}, comp = {};
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int p0 = 0; p0 < K; p0 += KT) {
+    const bool more = p0 + KT < K;
+    if (more) load(p0 + KT);
+    w1_f32x16 acc = {};
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 2) {
+      const float a = As[buf][wr + (lane & 31)][kk + (lane >> 5)];
+      const float b = Bs[buf][kk + (lane >> 5)][wc + (lane & 31)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float x = acc[r], s0 = tot[r], s1 = s0 + x;
+      comp[r] += fabsf(s0) >= fabsf(x) ? (s0 - s1) + x : (x - s1) + s0;
+      tot[r] = s1;
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) out[r] = tot[r] + comp[r];
+}
+
+// tile-local row / column of accumulator register r of this lane
+__device__ __forceinline__ int mfma_row_(int r) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  return (wv >> 1) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+}
+__device__ __forceinline__ int mfma_col_() {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  return (wv & 1) * 32 + (lane & 31);
+}
+
+template <int PASS>
+__global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
+                                                  const SlotDesc<float>* __restrict__ desc,
+                                                  const SlotScalars* __restrict__ scal, int src, int dst, int gate) {
+  __shared__ float As[2][64][33];
+  __shared__ float Bs[2][32][68];
+  const Work w = work[blockIdx.x];
+  if (w.x < 0) return;
+  if (gate && scal[w.x / MAXL].status != ST_RUN) return;
+  const SlotDesc<float>& d = desc[w.x];
+  const int N = d.n + 1, ld = d.pitch, h = N / 2, ne = N - h, no = h;
+  const float* __restrict__ X = d.p[src];
+  float* __restrict__ Y = d.p[dst];
+  const float* __restrict__ Cp = d.dctCp;
+  const float* __restrict__ Ctp = d.dctCtp;
+  const int nte = (ne + 63) / 64, nto = (no + 63) / 64;
+  float out[16];
+  if (PASS == 1 || PASS == 2) {
+    // the tile along the parity blocks and the tile along the N side
+    const int zb = PASS == 1 ? w.z : w.y, zn = PASS == 1 ? w.y : w.z;
+    if (zb >= nte + nto || zn * 64 >= N) return;
+    const bool odd = zb >= nte;
+    const int cnt = odd ? no : ne, base = odd ? ne : 0, b0 = (odd ? zb - nte : zb) * 64, n0 = zn * 64;
+    const int K = cnt;   // fold: ne terms (with the middle node when N is odd) or no terms
+    if (PASS == 1) {
+      // Y1[i][base + k2] = sum_j' fold_j'(X[i][.]) Ctp[j'][base + k2]
+      auto la = [&](int il, int jp) -> float {
+        const int i = n0 + il;
+        if (i >= N) return 0.f;
+        const float* row = X + (size_t)i * ld;
+        if (odd) return row[jp] - row[N - 1 - jp];
+        return jp < h ? row[jp] + row[N - 1 - jp] : row[jp];
+      };
+      auto lb = [&](int jp, int cl) -> float {
+        const int k2 = b0 + cl;
+        return k2 < cnt ? Ctp[(size_t)jp * N + base + k2] : 0.f;
+      };
+      mfma_tile64_(la, lb, K, As, Bs, out);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = n0 + mfma_row_(r), k2 = b0 + mfma_col_();
+        if (i < N && k2 < cnt) Y[(size_t)i * ld + base + k2] = out[r];
+      }
+    } else {
+      // Y2[base + k2][l] = sum_i' Cp[base + k2][i'] fold_i'(X[.][l]) / lambda
+      auto la = [&](int kl, int ip) -> float {
+        const int k2 = b0 + kl;
+        return k2 < cnt ? Cp[(size_t)(base + k2) * N + ip] : 0.f;
+      };
+      auto lb = [&](int ip, int cl) -> float {
+        const int l = n0 + cl;
+        if (l >= N) return 0.f;
+        const float a = X[(size_t)ip * ld + l];
+        if (odd) return a - X[(size_t)(N - 1 - ip) * ld + l];
+        return ip < h ? a + X[(size_t)(N - 1 - ip) * ld + l] : a;
+      };
+      mfma_tile64_(la, lb, K, As, Bs, out);
+      const double h2 = d.h * d.h;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int k2 = b0 + mfma_row_(r), l = n0 + mfma_col_();
+        if (k2 < cnt && l < N) {
+          const int kk = base + k2, tk = dct_perm_(kk, ne), tl = dct_perm_(l, ne);
+          const float v = (tk == 0 && tl == 0) ? 0.f : (float)((double)out[r] * (h2 / (d.dcts[tk] + d.dcts[tl])));
+          Y[(size_t)kk * ld + l] = v;
+        }
+      }
+    }
+  } else {
+    // inverse: the ne leading rows (pass 3) or columns (pass 4) from the even
+    // and odd frequency sums, mirrored to N-1-i / N-1-j
+    const int zh = PASS == 3 ? w.y : w.z, zn = PASS == 3 ? w.z : w.y;
+    const int h0 = zh * 64, n0 = zn * 64;
+    if (h0 >= ne || n0 >= N) return;
+    float ev[16];
+    for (int par = 0; par < 2; ++par) {
+      const int K = par ? no : ne, base = par ? ne : 0;
+      if (PASS == 3) {
+        // rows i < ne: sum_k'' Ctp[i][base + k''] X[base + k''][l]
+        auto la = [&](int il, int kk) -> float {
+          const int i = h0 + il;
+          return i < ne ? Ctp[(size_t)i * N + base + kk] : 0.f;
+        };
+        auto lb = [&](int kk, int cl) -> float {
+          const int l = n0 + cl;
+          return l < N ? X[(size_t)(base + kk) * ld + l] : 0.f;
+        };
+        mfma_tile64_(la, lb, K, As, Bs, par ? out : ev);
+      } else {
+        // columns j < ne: sum_l'' X[i][base + l''] Cp[base + l''][j]
+        auto la = [&](int il, int kk) -> float {
+          const int i = n0 + il;
+          return i < N ? X[(size_t)i * ld + base + kk] : 0.f;
+        };
+        auto lb = [&](int kk, int cl) -> float {
+          const int j = h0 + cl;
+          return j < ne ? Cp[(size_t)(base + kk) * N + j] : 0.f;
+        };
+        mfma_tile64_(la, lb, K, As, Bs, par ? out : ev);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int a = (PASS == 3 ? h0 : n0) + mfma_row_(r), b = (PASS == 3 ? n0 : h0) + mfma_col_();
+      const int i = a, j = b;   // pass 3: i < ne mirrored; pass 4: j < ne mirrored
+      const float e = ev[r], o = out[r];
+      if (PASS == 3) {
+        if (i < ne && j < N) {
+          Y[(size_t)i * ld + j] = e + o;
+          if (N - 1 - i != i) Y[(size_t)(N - 1 - i) * ld + j] = e - o;
+        }
+      } else {
+        if (i < N && j < ne) {
+          Y[(size_t)i * ld + j] = e + o;
+          if (N - 1 - j != j) Y[(size_t)i * ld + (N - 1 - j)] = e - o;
+        }
+      }
+    }
+  }
+}
+
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(256) void k_prox_post(const Work* __restrict__ work,
                                                    const SlotDesc<T>* __restrict__ desc,
@@ -1917,6 +2124,19 @@ template <typename T> void K<T>::gemm(hipStream_t s, const Work* w, int nw, cons
   } else {
     if (scale) LAUNCH((k_gemm<T, 1, true>), nw, 256, 0, s, w, d, sc, src, dst, mat, gate);
     else LAUNCH((k_gemm<T, 1, false>), nw, 256, 0, s, w, d, sc, src, dst, mat, gate);
+  }
+}
+template <typename T> void K<T>::poisson_fold(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
+                                              const SlotScalars* sc, int dst, int gate) {
+  if constexpr (sizeof(T) != 4) {
+    fprintf(stderr, "w1: internal error: the folded DCT passes are FP32 only\n");
+    return;
+  } else {
+    if (!nw) return;
+    LAUNCH((k_dct_fold<1>), nw, 256, 0, s, w, d, sc, 6, 7, gate);
+    LAUNCH((k_dct_fold<2>), nw, 256, 0, s, w, d, sc, 7, 6, gate);
+    LAUNCH((k_dct_fold<3>), nw, 256, 0, s, w, d, sc, 6, 7, gate);
+    LAUNCH((k_dct_fold<4>), nw, 256, 0, s, w, d, sc, 7, dst, gate);
   }
 }
 template <typename T> void K<T>::prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,

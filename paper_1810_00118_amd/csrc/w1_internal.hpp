@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <vector>
 
 namespace w1 {
 
@@ -45,6 +46,8 @@ struct SlotDesc {
   const T* dctC;       // orthonormal DCT-II matrix C[k][j], N x N row-major
   const T* dctCt;      // its transpose
   const double* dcts;  // 4 sin^2(pi k / 2N), k < N
+  const T* dctCp;      // C with its rows in even-then-odd frequency order
+  const T* dctCtp;     // and its transpose (folded FP32 passes)
   const double* in0;   // finest level only: input masses, dense pitch n+1
   const double* in1;
   double* out_m1;      // finest level only: exported fields, dense FP64
@@ -119,6 +122,10 @@ struct K {
                       int kind, int gate);
   static void gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int mode,
                    int src, int dst, int mat, bool scale, int gate);
+  // (A A*)^{-1} of plane 6 into plane dst with the folded FP32 passes
+  // (plane 7 scratch); w: T x T tiles per slot, fold_tiles(N)
+  static void poisson_fold(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
+                           int dst, int gate);
   static void prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
                         bool check);
   static void check(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
@@ -133,6 +140,30 @@ struct K {
 };
 
 int resident_lds_bytes(int side, int elem);
+// frequency order of the folded DCT: ne = N - N/2 even frequencies first,
+// then the N/2 odd ones
+inline int fold_perm(int x, int N) {
+  const int ne = N - N / 2;
+  return x < ne ? 2 * x : 2 * (x - ne) + 1;
+}
+// Cp[k''][j] = C[fold_perm(k'')][j] and Ctp = Cp^T from the row-major N x N C
+template <typename T>
+inline void fold_order(int N, const std::vector<T>& C, std::vector<T>* Cp, std::vector<T>* Ctp) {
+  Cp->assign((size_t)N * N, T(0));
+  Ctp->assign((size_t)N * N, T(0));
+  for (int k = 0; k < N; ++k) {
+    const int src = fold_perm(k, N);
+    for (int j = 0; j < N; ++j) {
+      (*Cp)[(size_t)k * N + j] = C[(size_t)src * N + j];
+      (*Ctp)[(size_t)j * N + k] = C[(size_t)src * N + j];
+    }
+  }
+}
+// tiles per side of the folded DCT work list for transform length N
+inline int fold_tiles(int N) {
+  const int ne = N - N / 2, no = N / 2, a = (N + 63) / 64, b = (ne + 63) / 64 + (no + 63) / 64;
+  return a > b ? a : b;
+}
 int prox_resident_lds_bytes(int side, int elem);
 
 }  // namespace w1

@@ -144,7 +144,7 @@ def test_prox_resident_rejects_unsupported():
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
-@pytest.mark.parametrize("n", [16, 64, 128, 200, 512, 1000])
+@pytest.mark.parametrize("n", [4, 16, 63, 64, 99, 128, 129, 200, 512, 1000])
 def test_poisson(precision, n):
     w1 = require_gpu()
     rng = np.random.default_rng(n)
