@@ -919,151 +919,202 @@ __device__ double measure_from_(const double* r, int kind, int rule, double h2, 
 // ---------------------------------------------------------------------------
 // Algorithm 2, whole level resident in one workgroup (sides up to 65).
 // The iterate (m, vphi, vphibar) and rho stay in registers (node e of the
-// dense (n+1)^2 grid belongs to thread e mod 512); LDS holds the DCT-II
-// matrix, its eigenvalue parts and three planes for the divergence, the
-// Poisson solve and the gradient.  One iteration: v = m - mu vphibar,
-// r = A v - rho, u = (A A*)^{-1} r by four DCT passes in LDS (each thread a
-// 3 x 3 block of outputs), m+ = v + grad+ u, vphi+ = Proj(vphi + tau m+),
+// dense (n+1)^2 grid belongs to thread e mod 1024); LDS holds the even and
+// odd DCT-II blocks, the FP64 factors h^2 / lambda, three node planes for
+// the divergence, the Poisson solve and the gradient, and two folded planes.
+// One iteration: v = m - mu vphibar, r = A v - rho, u = (A A*)^{-1} r by the
+// folded transform below, m+ = v + grad+ u, vphi+ = Proj(vphi + tau m+),
 // vphibar+ = 2 vphi+ - vphi -- the same node arithmetic as the batched
 // kernels.  Stop tests every `check_every` iterations and at the cap: G^k of
 // eq. (pdhg_stop) (pointwise sums) or the normalised KKT residual with
 // psi = (A A*)^{-1} A vphi.  Reads and writes planes 0..5; runs at most
 // `chunk` iterations (0: no limit), resuming from the slot's count.
 // ---------------------------------------------------------------------------
-// one DCT pass in LDS, out = X C^T (PASS 1), C X scaled by h^2 / lambda
-// (PASS 2), C^T X (PASS 3) or X C (PASS 4); dense N x N, ends with a barrier
-template <typename T, int PASS>
-__device__ void res_dct_pass_(const T* __restrict__ Cm, const T* __restrict__ in, T* __restrict__ out,
-                              const double* __restrict__ sk, int N, double h2) {
-  constexpr int RB = 3;
-  const int nb = (N + RB - 1) / RB;
-  for (int bidx = threadIdx.x; bidx < nb * nb; bidx += RES_THREADS) {
-    const int i0 = (bidx / nb) * RB, c0 = (bidx % nb) * RB;
-    int ri[RB], ci[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      ri[r] = i0 + r < N ? i0 + r : N - 1;   // clamped rows / columns are computed and dropped
-      ci[r] = c0 + r < N ? c0 + r : N - 1;
-    }
-    T acc[RB][RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int c = 0; c < RB; ++c) acc[r][c] = T(0);
-    for (int p = 0; p < N; ++p) {
-      T a[RB], b[RB];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        if (PASS == 1 || PASS == 4) a[r] = in[ri[r] * N + p];
-        else if (PASS == 2) a[r] = Cm[ri[r] * N + p];
-        else a[r] = Cm[p * N + ri[r]];
-      }
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        if (PASS == 1) b[c] = Cm[ci[c] * N + p];
-        else if (PASS == 4) b[c] = Cm[p * N + ci[c]];
-        else b[c] = in[p * N + ci[c]];
-      }
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int c = 0; c < RB; ++c) acc[r][c] = fma_(a[r], b[c], acc[r][c]);
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int c = 0; c < RB; ++c) {
-        const int gi = i0 + r, gj = c0 + c;
-        if (gi < N && gj < N) {
-          T v = acc[r][c];
-          if (PASS == 2) v = (gi == 0 && gj == 0) ? T(0) : (T)((double)v * (h2 / (sk[gi] + sk[gj])));
-          out[gi * N + gj] = v;
-        }
-      }
-  }
-  __syncthreads();
-}
-
-// The same pass on the matrix cores (FP32): 16 x 16 output tiles, one per
-// wavefront at a time, accumulated with v_mfma_f32_16x16x4f32 over K in
-// steps of 4 (A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k,
-// accumulator register r of lane l holds row 4 (l / 16) + r, column
-// l % 16); operands outside the N x N matrices read as zero.
+// The Poisson solve in LDS uses the even/odd symmetry of the DCT-II basis
+// (C[k][N-1-j] = (-1)^k C[k][j], and C[k][(N-1)/2] = 0 for odd k when N is
+// odd) along both axes.  With h = N/2, ne = N - h even and no = h odd
+// frequencies, a butterfly over the node quads (p, q), (p, N-1-q),
+// (N-1-p, q), (N-1-p, N-1-q) (p, q < ne) gives four folded blocks
+// XF_ab (a, b in {even, odd}); the 2D transform is then block diagonal:
+// Y_ab = C_a XF_ab C_b^T with C_e[k][p] = C[2k][p] (ne x ne) and
+// C_o[k][p] = C[2k+1][p] (no x no).  The eigenvalue division runs on the
+// blocks with the frequencies 2k / 2k+1, the inverse is U_ab = C_a^T Z_ab C_b
+// and an inverse butterfly restores the nodes.  Four times fewer products
+// per block, half the flops of the dense passes, and every pass a plain
+// matrix product on the matrix cores (v_mfma_f32_16x16x4f32: A[i][k] at lane
+// i + 16 k, B[k][j] at lane j + 16 k, accumulator register r of lane l holds
+// row 4 (l / 16) + r, column l % 16).
+//
+// LDS layout of the folded planes: rows and columns in the folded index
+// (even block [0, ne), odd block [ne, N)), stride fs, zero beyond N.  C_e and
+// C_o are stored zero padded to 16-row multiples, so that the contraction
+// runs in steps of 4 with no bounds tests: the padded terms multiply a zero
+// coefficient by a finite plane entry.
+// ---------------------------------------------------------------------------
 typedef float w1_f32x4 __attribute__((ext_vector_type(4)));
 
+struct FoldLay {
+  int N, h, ne, no, re, ro, fs, fr, sde, sdo;
+  __host__ __device__ explicit FoldLay(int n1) : N(n1) {
+    h = N / 2;
+    ne = N - h;
+    no = h;
+    re = (ne + 15) & ~15;   // C_e rows (16-padded)
+    ro = (no + 15) & ~15;   // C_o rows
+    fs = (N + 16) | 1;      // folded plane stride (odd: no bank aliasing down a column)
+    fr = N + 16;            // folded plane rows
+    sde = re + 1;
+    sdo = ro + 1;
+  }
+};
+
+// node planes (dense N x N) <-> folded planes (stride fs); end with a barrier
+__device__ void res_fold_in_(const float* __restrict__ X, float* __restrict__ F, const FoldLay& L) {
+  const int N = L.N, ne = L.ne, fs = L.fs;
+  const float rne = 1.f / (float)ne;
+  for (int Q = threadIdx.x; Q < ne * ne; Q += PRES_THREADS) {
+    // Q / ne by a float reciprocal: Q < ne^2 <= 33^2, so (Q + 0.5) / ne stays
+    // at least 0.5 / ne from an integer, far beyond the rounding error
+    const int p = (int)(((float)Q + 0.5f) * rne), q = Q - p * ne;
+    const bool pr = p < L.h, qr = q < L.h;   // the mirrored row / column is a different node
+    const int pm = N - 1 - p, qm = N - 1 - q;
+    const float x00 = X[p * N + q];
+    const float x01 = qr ? X[p * N + qm] : 0.f;
+    const float x10 = pr ? X[pm * N + q] : 0.f;
+    const float x11 = (pr && qr) ? X[pm * N + qm] : 0.f;
+    const float se = x00 + x01, so = x00 - x01, te = x10 + x11, to = x10 - x11;
+    F[p * fs + q] = se + te;
+    if (qr) F[p * fs + ne + q] = so + to;
+    if (pr) F[(ne + p) * fs + q] = se - te;
+    if (pr && qr) F[(ne + p) * fs + ne + q] = so - to;
+  }
+  __syncthreads();
+}
+__device__ void res_fold_out_(const float* __restrict__ F, float* __restrict__ U, const FoldLay& L) {
+  const int N = L.N, ne = L.ne, fs = L.fs;
+  const float rne = 1.f / (float)ne;
+  for (int Q = threadIdx.x; Q < ne * ne; Q += PRES_THREADS) {
+    // Q / ne by a float reciprocal: Q < ne^2 <= 33^2, so (Q + 0.5) / ne stays
+    // at least 0.5 / ne from an integer, far beyond the rounding error
+    const int p = (int)(((float)Q + 0.5f) * rne), q = Q - p * ne;
+    const bool pr = p < L.h, qr = q < L.h;
+    const int pm = N - 1 - p, qm = N - 1 - q;
+    const float ee = F[p * fs + q];
+    const float eo = qr ? F[p * fs + ne + q] : 0.f;
+    const float oe = pr ? F[(ne + p) * fs + q] : 0.f;
+    const float oo = (pr && qr) ? F[(ne + p) * fs + ne + q] : 0.f;
+    const float a = ee + oe, b = eo + oo, c = ee - oe, e = eo - oo;
+    U[p * N + q] = a + b;
+    if (qr) U[p * N + qm] = a - b;
+    if (pr) U[pm * N + q] = c + e;
+    if (pr && qr) U[pm * N + qm] = c - e;
+  }
+  __syncthreads();
+}
+
+// one pass over the four blocks, 16 x 16 output tiles, one per wavefront at
+// a time; ends with a barrier.
+//   PASS 1: out_ab = in_ab C_b^T    PASS 2: out_ab = C_a in_ab, scaled by h^2 / lambda
+//   PASS 3: out_ab = C_a^T in_ab    PASS 4: out_ab = in_ab C_b
 template <int PASS>
-__device__ void res_dct_pass_mfma_(const float* __restrict__ Cm, const float* __restrict__ in,
-                                   float* __restrict__ out, const double* __restrict__ sk, int N, double h2) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nt = (N + 15) >> 4;
+__device__ void res_fold_pass_(const float* __restrict__ CE, const float* __restrict__ CO,
+                               const float* __restrict__ in, float* __restrict__ out,
+                               const double* __restrict__ lam, const FoldLay& L) {
+  constexpr int MAXS = 9;   // contraction steps of 4 for ne <= 33 (N <= 65)
+  constexpr bool colk = PASS == 1 || PASS == 4;   // contraction over the column block
+  // the wavefront index through a scalar register: every tile quantity below
+  // is then wave-uniform and the contraction runs without lane masking
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  for (int tile = wv; tile < nt * nt; tile += RES_THREADS / 64) {
-    const int i0 = (tile / nt) * 16, j0 = (tile % nt) * 16;
-    const int ia = i0 + li, jb = j0 + li;             // A row and B column of this lane
-    const bool ia_in = ia < N, jb_in = jb < N;
-    const int iac = ia_in ? ia : N - 1, jbc = jb_in ? jb : N - 1;
-    w1_f32x4 acc = {};
-    // four K steps per round: all operand reads are issued before the
-    // matrix-core instructions that consume them
-    for (int k0 = 0; k0 < N; k0 += 16) {
-      float a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = k0 + 4 * u + lk;
-        const bool k_in = k < N;
-        const int kc = k_in ? k : N - 1;
-        if (PASS == 1 || PASS == 4) a[u] = in[iac * N + kc];
-        else if (PASS == 2) a[u] = Cm[iac * N + kc];
-        else a[u] = Cm[kc * N + iac];
-        if (PASS == 1) b[u] = Cm[jbc * N + kc];
-        else if (PASS == 4) b[u] = Cm[kc * N + jbc];
-        else b[u] = in[kc * N + jbc];
-        a[u] = (ia_in && k_in) ? a[u] : 0.f;
-        b[u] = (jb_in && k_in) ? b[u] : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+  const int rte = L.re >> 4, RT = rte + (L.ro >> 4);
+  for (int tile = wv; tile < RT * RT; tile += PRES_THREADS / 64) {
+    const int rt = tile / RT, ct = tile - rt * RT;
+    const bool ao = rt >= rte, bo = ct >= rte;            // odd row / column block
+    const int ra = ao ? L.ne : 0, rb = bo ? L.ne : 0;     // block origin in the folded index
+    const int na = ao ? L.no : L.ne, nb = bo ? L.no : L.ne;
+    const int i0 = (ao ? rt - rte : rt) * 16, j0 = (bo ? ct - rte : ct) * 16;   // in-block tile origin
+    const bool kodd = colk ? bo : ao;
+    const int K = colk ? nb : na, ko = kodd ? L.ne : 0;
+    const float* Cb = kodd ? CO : CE;
+    const int cs = kodd ? L.sdo : L.sde;
+    // this lane's A row and B column: element k at p[k * stride]
+    const float* pa;
+    const float* pb;
+    int sa, sb;
+    if (colk) {
+      pa = in + (ra + i0 + li) * L.fs + ko;
+      sa = 1;
+    } else if (PASS == 2) {
+      pa = Cb + (i0 + li) * cs;
+      sa = 1;
+    } else {
+      pa = Cb + i0 + li;
+      sa = cs;
     }
+    if (PASS == 1) {
+      pb = Cb + (j0 + li) * cs;
+      sb = 1;
+    } else if (PASS == 4) {
+      pb = Cb + j0 + li;
+      sb = cs;
+    } else {
+      pb = in + ko * L.fs + rb + j0 + li;
+      sb = L.fs;
+    }
+    const int ks = (K + 3) >> 2;
+    // all operand reads first, then the matrix-core chain
+    float av[MAXS], bv[MAXS];
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      av[s] = 0.f;
+      bv[s] = 0.f;
+      if (s < ks) {
+        av[s] = pa[(4 * s + lk) * sa];
+        bv[s] = pb[(4 * s + lk) * sb];
+      }
+    }
+    w1_f32x4 acc = {};
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s)
+      if (s < ks) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int gi = i0 + 4 * lk + r, gj = j0 + li;
-      if (gi < N && gj < N) {
+      const int il = i0 + 4 * lk + r, jl = j0 + li;
+      if (il < na && jl < nb) {
         float v = acc[r];
-        if (PASS == 2) v = (gi == 0 && gj == 0) ? 0.f : (float)((double)v * (h2 / (sk[gi] + sk[gj])));
-        out[gi * N + gj] = v;
+        if (PASS == 2) v = (float)((double)v * lam[(ra + il) * L.N + rb + jl]);
+        out[(ra + il) * L.fs + rb + jl] = v;
       }
     }
   }
   __syncthreads();
 }
 
-// u = (A A*)^{-1} r: r in P2 on entry, u in P2 on exit, P0 and P1 scratch
-template <typename T>
-__device__ void res_poisson_(const T* Cm, T* P0, T* P1, T* P2, const double* sk, int N, double h2) {
-  if constexpr (sizeof(T) == 4) {
-    res_dct_pass_mfma_<1>(Cm, P2, P0, sk, N, h2);
-    res_dct_pass_mfma_<2>(Cm, P0, P1, sk, N, h2);
-    res_dct_pass_mfma_<3>(Cm, P1, P0, sk, N, h2);
-    res_dct_pass_mfma_<4>(Cm, P0, P2, sk, N, h2);
-  } else {
-    res_dct_pass_<T, 1>(Cm, P2, P0, sk, N, h2);
-    res_dct_pass_<T, 2>(Cm, P0, P1, sk, N, h2);
-    res_dct_pass_<T, 3>(Cm, P1, P0, sk, N, h2);
-    res_dct_pass_<T, 4>(Cm, P0, P2, sk, N, h2);
-  }
+// u = (A A*)^{-1} r: r in X on entry, u in X on exit; F0, F1 folded scratch;
+// lam[k''][l''] = h^2 / (s_k + s_l) of the frequencies of the folded indices
+// (0 at the constant mode), FP64
+__device__ void res_poisson_(const float* CE, const float* CO, float* X, float* F0, float* F1,
+                             const double* lam, const FoldLay& L) {
+  res_fold_in_(X, F0, L);
+  res_fold_pass_<1>(CE, CO, F0, F1, lam, L);
+  res_fold_pass_<2>(CE, CO, F1, F0, lam, L);
+  res_fold_pass_<3>(CE, CO, F0, F1, lam, L);
+  res_fold_pass_<4>(CE, CO, F1, F0, lam, L);
+  res_fold_out_(F0, X, L);
 }
 
 int prox_resident_lds_bytes(int side, int elem) {
-  return 18 * NQ * 8 + side * 8 + 4 * side * side * elem;
+  const FoldLay L(side);
+  return 18 * NQ * 8 + side * side * 8 + (3 * side * side + 2 * L.fr * L.fs + L.re * L.sde + L.ro * L.sdo) * elem;
 }
 
 template <typename T, int NPT, int METRIC>
-__global__ __launch_bounds__(RES_THREADS) void k_prox_resident(const int* __restrict__ idx,
+__global__ __launch_bounds__(PRES_THREADS) void k_prox_resident(const int* __restrict__ idx,
                                                                const SlotDesc<T>* __restrict__ desc,
                                                                SlotScalars* __restrict__ scal, int check_every,
                                                                int chunk) {
   extern __shared__ double smem_d[];
-  constexpr int NT = RES_THREADS;
+  constexpr int NT = PRES_THREADS;
   constexpr int metric = METRIC;
   const int x = idx[blockIdx.x];
   const SlotDesc<T>& d = desc[x];
@@ -1073,16 +1124,33 @@ __global__ __launch_bounds__(RES_THREADS) void k_prox_resident(const int* __rest
   double* red = smem_d;                 // [16 * NQ]
   double* res = smem_d + 16 * NQ;       // [NQ]
   int* flag = (int*)(smem_d + 17 * NQ);
-  double* sk = smem_d + 18 * NQ;        // [N] eigenvalue parts 4 sin^2(pi k / 2N)
-  T* Cm = (T*)(sk + N);                 // DCT-II matrix, dense N x N
-  T* P0 = Cm + NN;
+  static_assert(sizeof(T) == 4, "the resident Algorithm 2 kernel is FP32");
+  const FoldLay L(N);
+  double* lam = smem_d + 18 * NQ;       // [N x N] h^2 / lambda in the folded order
+  T* P0 = (T*)(lam + NN);               // node planes, dense N x N
   T* P1 = P0 + NN;
   T* P2 = P1 + NN;
+  T* F0 = P2 + NN;                      // folded planes, fr x fs
+  T* F1 = F0 + L.fr * L.fs;
+  T* CE = F1 + L.fr * L.fs;             // C_e, re x sde
+  T* CO = CE + L.re * L.sde;            // C_o, ro x sdo
   const T ih = d.ih, mu = d.mu, tau = d.tau;
   const int cap = d.cap;
   const double h2 = d.h * d.h;
-  for (int e = threadIdx.x; e < NN; e += NT) Cm[e] = d.dctC[e];
-  for (int k = threadIdx.x; k < N; k += NT) sk[k] = d.dcts[k];
+  for (int e = threadIdx.x; e < L.re * L.sde; e += NT) {
+    const int k = e / L.sde, p = e - k * L.sde;
+    CE[e] = (k < L.ne && p < L.ne) ? d.dctC[(2 * k) * N + p] : T(0);
+  }
+  for (int e = threadIdx.x; e < L.ro * L.sdo; e += NT) {
+    const int k = e / L.sdo, p = e - k * L.sdo;
+    CO[e] = (k < L.no && p < L.no) ? d.dctC[(2 * k + 1) * N + p] : T(0);
+  }
+  for (int e = threadIdx.x; e < 2 * L.fr * L.fs; e += NT) F0[e] = T(0);
+  for (int e = threadIdx.x; e < NN; e += NT) {
+    const int k = e / N, l = e - k * N;
+    const int tk = k < L.ne ? 2 * k : 2 * (k - L.ne) + 1, tl = l < L.ne ? 2 * l : 2 * (l - L.ne) + 1;
+    lam[e] = (tk == 0 && tl == 0) ? 0.0 : h2 / (d.dcts[tk] + d.dcts[tl]);
+  }
 
   T m1[NPT], m2[NPT], w1[NPT], w2[NPT], b1[NPT], b2[NPT], rh[NPT];
   unsigned has_d = 0u, has_r = 0u, not_top = 0u, not_left = 0u;   // bit s: neighbour exists
@@ -1140,7 +1208,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_prox_resident(const int* __rest
       }
     }
     __syncthreads();
-    res_poisson_<T>(Cm, P0, P1, P2, sk, N, h2);
+    res_poisson_(CE, CO, P2, F0, F1, lam, L);
     // m+ = v + grad+ u; vphi+ = Proj(vphi + tau m+); vphibar+ = 2 vphi+ - vphi
     double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -1196,7 +1264,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_prox_resident(const int* __rest
         }
       }
       __syncthreads();
-      res_poisson_<T>(Cm, P0, P1, P2, sk, N, h2);
+      res_poisson_(CE, CO, P2, F0, F1, lam, L);
 #pragma unroll
       for (int s = 0; s < NPT; ++s) {
         const int e = threadIdx.x + NT * s;
@@ -2180,15 +2248,15 @@ template <typename T> void K<T>::prox_resident(hipStream_t s, const int* idx, in
   static bool attr_set = false;
   if (!attr_set) {
     const int full = prox_resident_lds_bytes(65, sizeof(T));
-    (void)hipFuncSetAttribute((const void*)k_prox_resident<T, 9, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_prox_resident<T, 5, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               full);
-    (void)hipFuncSetAttribute((const void*)k_prox_resident<T, 9, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_prox_resident<T, 5, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               full);
     attr_set = true;
   }
   const int bytes = prox_resident_lds_bytes(max_side, sizeof(T));
-  if (metric == 1) LAUNCH((k_prox_resident<T, 9, 1>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
-  else LAUNCH((k_prox_resident<T, 9, 2>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+  if (metric == 1) LAUNCH((k_prox_resident<T, 5, 1>), ns, PRES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+  else LAUNCH((k_prox_resident<T, 5, 2>), ns, PRES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
   }
 }
 

@@ -101,7 +101,7 @@ def test_prox_steps_trajectory(precision, n, metric):
     assert G == pytest.approx(Gw, rel=1e-8 if precision == FP64 else 1e-2, abs=1e-12)
 
 
-@pytest.mark.parametrize("n", [16, 32, 40, 64])
+@pytest.mark.parametrize("n", [4, 7, 16, 32, 40, 63, 64])
 @pytest.mark.parametrize("metric", [1, 2])
 @pytest.mark.parametrize("k", [1, 10, 60])
 def test_prox_resident_trajectory(n, metric, k):
