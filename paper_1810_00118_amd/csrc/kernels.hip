@@ -694,9 +694,9 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
 // ---------------------------------------------------------------------------
 // Algorithm 1, whole level resident in one workgroup.
 // For grids whose potential and both extrapolated-flux planes fit in LDS
-// (3 (n+1)^2 sizeof(T) bytes), one 512-thread workgroup per pair runs the
-// level to its stop test or cap without touching HBM in between.  Node e
-// (row-major, dense) belongs to thread e mod 512; the flux, rho and the
+// (3 (n+1)^2 sizeof(T) bytes), one workgroup per pair runs the level to its
+// stop test or cap without touching HBM in between.  Node e (row-major,
+// dense) belongs to thread e mod the workgroup size; the flux, rho and the
 // node's own potential and extrapolated flux stay in registers, the planes
 // in LDS carry the neighbours: an iteration is two phases with one barrier
 // each (flux half writing 2 m+ - m, potential half reading it at (i-1, j)
@@ -706,13 +706,19 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
 // A launch runs at most `chunk` iterations (0: no limit) and resumes from
 // the slot's iteration count, so long levels can run in bounded pieces.
 // ---------------------------------------------------------------------------
+// workgroup size and nodes per thread of the resident Algorithm 1 kernel:
+// 16 wavefronts for FP32, 8 for FP64 (its iterate needs twice the registers)
+template <typename T> struct ResCfg;
+template <> struct ResCfg<float> { static constexpr int NT = 1024, NPT = 5, MAXN = 65; };
+template <> struct ResCfg<double> { static constexpr int NT = 512, NPT = 9, MAXN = 65; };
+
 template <typename T, int NPT, int METRIC>
-__global__ __launch_bounds__(RES_THREADS) void k_plain_resident(const int* __restrict__ idx,
+__global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __restrict__ idx,
                                                                 const SlotDesc<T>* __restrict__ desc,
                                                                 SlotScalars* __restrict__ scal, int check_every,
                                                                 int chunk) {
   extern __shared__ double smem_d[];
-  constexpr int NT = RES_THREADS;
+  constexpr int NT = ResCfg<T>::NT;
   static_assert(NPT <= 32, "column masks hold 32 nodes");
   const int x = idx[blockIdx.x];
   const SlotDesc<T>& d = desc[x];
@@ -2131,9 +2137,6 @@ template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int n
 }
 
 // resident kernel: sides up to 65, 9 nodes per thread of 512
-template <typename T> struct ResCfg;
-template <> struct ResCfg<float> { static constexpr int NPT = 9; static constexpr int MAXN = 65; };
-template <> struct ResCfg<double> { static constexpr int NPT = 9; static constexpr int MAXN = 65; };
 
 int resident_lds_bytes(int side, int elem) { return 18 * NQ * 8 + 3 * side * side * elem; }
 
@@ -2158,9 +2161,9 @@ template <typename T> void K<T>::plain_resident(hipStream_t s, const int* idx, i
     attr_set = true;
   }
   if (metric == 1)
-    LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 1>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+    LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 1>), ns, ResCfg<T>::NT, bytes, s, idx, d, sc, check_every, chunk);
   else
-    LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 2>), ns, RES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+    LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 2>), ns, ResCfg<T>::NT, bytes, s, idx, d, sc, check_every, chunk);
 }
 template <typename T> void K<T>::kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                      const SlotScalars* sc, int kind, int set_xor, int gate) {

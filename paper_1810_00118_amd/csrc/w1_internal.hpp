@@ -29,7 +29,6 @@ constexpr int GEMM_T = 64;           // DCT GEMM output tile
 constexpr int TILED_RW = 128;        // plain tiled kernel region width
 constexpr int TILED_RH = 64;         // plain tiled kernel region height
 constexpr int TILED_MAX_STEPS = 26;  // most PDHG steps per tiled launch
-constexpr int RES_THREADS = 512;     // resident kernel workgroup size (Algorithm 1)
 constexpr int PRES_THREADS = 1024;   // resident kernel workgroup size (Algorithm 2)
 
 enum Status : int { ST_RUN = 0, ST_CONV = 1, ST_CAP = 2, ST_DIVERGED = 3, ST_REJECT = 4 };
