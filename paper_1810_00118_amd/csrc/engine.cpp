@@ -418,20 +418,21 @@ class Prof {
   void reset() {
     for (int f = 0; f < W1_NFAM; ++f) tot_[f][0] = tot_[f][1] = tot_[f][2] = tot_[f][3] = tot_[f][4] = 0;
   }
-  // returns the pending index (or -1 when off)
-  int begin() {
+  // returns the pending index (or -1 when off); `s`: the launch's stream
+  // when it is not the batch's own
+  int begin(hipStream_t s = nullptr) {
     if (!on) return -1;
     Pend p;
     p.a = ev();
     p.b = ev();
-    (void)hipEventRecord(p.a, st_);
+    (void)hipEventRecord(p.a, s ? s : st_);
     pend_.push_back(p);
     return (int)pend_.size() - 1;
   }
-  void end(int i, int fam, double units, double bytes, double flops) {
+  void end(int i, int fam, double units, double bytes, double flops, hipStream_t s = nullptr) {
     if (i < 0) return;
     Pend& p = pend_[i];
-    (void)hipEventRecord(p.b, st_);
+    (void)hipEventRecord(p.b, s ? s : st_);
     p.fam = fam;
     p.units = units;
     p.bytes = bytes;
@@ -498,9 +499,15 @@ class Batch : public BatchBase {
           hipHostMalloc((void**)&hsc_, sizeof(SlotScalars) * cap_, hipHostMallocDefault) == hipSuccess;
     if (ok_) ok_ = hipMemsetAsync(dsc_, 0, sizeof(SlotScalars) * cap_, st_) == hipSuccess;
     if (ok_) ok_ = hipStreamSynchronize(st_) == hipSuccess;
+    // side stream for LDS-resident levels (default priority), so that their
+    // few busy compute units overlap the batched launches of other levels
+    if (ok_) ok_ = hipStreamCreateWithFlags(&rs_, hipStreamNonBlocking) == hipSuccess;
+    if (ok_) ok_ = hipEventCreateWithFlags(&ev_up_, hipEventDisableTiming) == hipSuccess &&
+                   hipEventCreateWithFlags(&ev_res_, hipEventDisableTiming) == hipSuccess;
   }
   ~Batch() override {
     (void)hipStreamSynchronize(st_);
+    if (rs_) (void)hipStreamSynchronize(rs_);
     free_retired();
     for (auto& t : tune_pending_) {
       tune_pool_.push_back(t.a);
@@ -517,6 +524,9 @@ class Batch : public BatchBase {
     (void)hipFree(ddesc_);
     (void)hipFree(dsc_);
     (void)hipHostFree(hsc_);
+    if (ev_up_) (void)hipEventDestroy(ev_up_);
+    if (ev_res_) (void)hipEventDestroy(ev_res_);
+    if (rs_) (void)hipStreamDestroy(rs_);
   }
 
   int active() const override {
@@ -692,7 +702,10 @@ class Batch : public BatchBase {
       // chunking a uniform batch spreads the next level over many small
       // launches, which costs more than the wait for the slowest pair
       const bool alone = groups.empty();
-      st = launch_resident(R, alone ? 0 : step_us);
+      // beside other levels, a few resident slots (each holds one compute
+      // unit) run on the side stream; a large set fills the device anyway
+      const bool side = !alone && (int)R.size() <= 64;
+      st = launch_resident(R, alone ? 0 : step_us, side);
       if (st) return fail(st);
     }
     n_blocks_ += maxnb;
@@ -835,6 +848,11 @@ class Batch : public BatchBase {
   }
 
   int read_scalars() {
+    if (res_side_) {
+      // resident levels launched on the side stream finish before the copy
+      HIPCHK(hipStreamWaitEvent(st_, ev_res_, 0));
+      res_side_ = false;
+    }
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
     free_retired();
@@ -1092,36 +1110,54 @@ class Batch : public BatchBase {
 
   // -- resident levels (both algorithms) -----------------------------------
   // `budget_us` bounds a launch to about that much device time (0: run to
-  // the stop test); one launch per (kind, check_every, metric)
-  int launch_resident(std::vector<Request*>& R, double budget_us) {
+  // the stop test); one launch per (kind, check_every, metric).  With
+  // `side`, the launches run on the side stream (after this step's uploads)
+  // and the next read of the slot scalars waits for them: resident levels
+  // and the batched launches touch disjoint slots, descriptors are not
+  // rewritten before that read, and the upload arena is reset only after it.
+  int launch_resident(std::vector<Request*>& R, double budget_us, bool side) {
     int st = W1_OK;
     std::map<std::tuple<int, int, int>, std::vector<Request*>> groups;
     for (auto* r : R) groups[std::make_tuple(r->kind, r->prm.check_every, r->prm.metric)].push_back(r);
+    std::vector<int*> lists;
+    for (auto& kv : groups) {
+      std::vector<int> ids;
+      for (auto* r : kv.second) ids.push_back(dx(r, r->level));
+      lists.push_back(arena_.put(ids, &st));
+      if (st) return st;
+    }
+    hipStream_t ls = st_;
+    if (side) {
+      HIPCHK(hipEventRecord(ev_up_, st_));
+      HIPCHK(hipStreamWaitEvent(rs_, ev_up_, 0));
+      ls = rs_;
+    }
+    size_t gi = 0;
     for (auto& kv : groups) {
       const int kind = std::get<0>(kv.first), ce = std::get<1>(kv.first), metric = std::get<2>(kv.first);
-      std::vector<int> ids;
+      int* di = lists[gi++];
       int maxside = 0;
-      for (auto* r : kv.second) {
-        ids.push_back(dx(r, r->level));
-        maxside = std::max(maxside, r->sides[r->level] + 1);
-      }
-      int* di = arena_.put(ids, &st);
-      if (st) return st;
+      for (auto* r : kv.second) maxside = std::max(maxside, r->sides[r->level] + 1);
+      const int nids = (int)kv.second.size();
       // rough cost of one iteration of the largest level in the group
       const double s3 = std::pow(maxside / 65.0, kind == K_PLAIN ? 2.0 : 3.0);
       const double it_us = kind == K_PLAIN ? 3.6 * s3 : 8.0 * s3 + 0.5;
       int chunk = 0;
       if (budget_us > 0) chunk = std::max(1, (int)(budget_us / it_us));
       const int c = chunk > 0 ? ((chunk + ce - 1) / ce) * ce : 0;
-      const int pi = prof_.begin();
+      const int pi = prof_.begin(ls);
       if (kind == K_PLAIN)
-        K<T>::plain_resident(st_, di, (int)ids.size(), ddesc_, dsc_, maxside, ce, c, metric);
+        K<T>::plain_resident(ls, di, nids, ddesc_, dsc_, maxside, ce, c, metric);
       else
-        K<T>::prox_resident(st_, di, (int)ids.size(), ddesc_, dsc_, maxside, ce, c, metric);
-      prof_.end(pi, kind == K_PLAIN ? W1_FAM_PLAIN_RESIDENT : W1_FAM_PROX_RESIDENT, 0, 0, 0);
+        K<T>::prox_resident(ls, di, nids, ddesc_, dsc_, maxside, ce, c, metric);
+      prof_.end(pi, kind == K_PLAIN ? W1_FAM_PLAIN_RESIDENT : W1_FAM_PROX_RESIDENT, 0, 0, 0, ls);
       if (pi >= 0) resident_pending_.emplace_back(pi, kv.second);
     }
     HIPCHK(hipGetLastError());
+    if (side) {
+      HIPCHK(hipEventRecord(ev_res_, rs_));
+      res_side_ = true;
+    }
     return W1_OK;
   }
 
@@ -1362,6 +1398,10 @@ class Batch : public BatchBase {
 
   int cap_;
   hipStream_t st_;
+  hipStream_t rs_ = nullptr;        // side stream of the resident levels
+  hipEvent_t ev_up_ = nullptr;      // this step's uploads, for the side stream
+  hipEvent_t ev_res_ = nullptr;     // the side stream's launches of this step
+  bool res_side_ = false;
   Arena arena_;
   bool ok_ = false;
   std::vector<Request*> slots_;
