@@ -826,17 +826,18 @@ class Batch : public BatchBase {
   int dx(const Request* r, int l) const { return r->slot * MAXL + l; }
   static double node_count(int n) { return (double)(n + 1) * (double)(n + 1); }
 
+  // descriptors of the changed slots to the device: the span from the lowest
+  // to the highest changed slot in one staged copy (slots in between are
+  // rewritten with their unchanged host copy), so a step costs two copies
+  // however many slots changed
   int flush_desc() {
+    if (dirty_.empty()) return W1_OK;
     int st = W1_OK;
-    std::sort(dirty_.begin(), dirty_.end());
-    dirty_.erase(std::unique(dirty_.begin(), dirty_.end()), dirty_.end());
-    for (int s : dirty_) {
-      std::vector<SlotDesc<T>> v(hdesc_.begin() + (size_t)s * MAXL, hdesc_.begin() + (size_t)(s + 1) * MAXL);
-      SlotDesc<T>* src = arena_.put(v, &st);
-      if (st) return st;
-      HIPCHK(hipMemcpyAsync(ddesc_ + (size_t)s * MAXL, src, sizeof(SlotDesc<T>) * MAXL, hipMemcpyDeviceToDevice,
-                            st_));
-    }
+    const auto mm = std::minmax_element(dirty_.begin(), dirty_.end());
+    const size_t lo = (size_t)*mm.first * MAXL, hi = (size_t)(*mm.second + 1) * MAXL;
+    SlotDesc<T>* src = (SlotDesc<T>*)arena_.put_bytes(hdesc_.data() + lo, sizeof(SlotDesc<T>) * (hi - lo), &st);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(ddesc_ + lo, src, sizeof(SlotDesc<T>) * (hi - lo), hipMemcpyDeviceToDevice, st_));
     dirty_.clear();
     return W1_OK;
   }
