@@ -39,6 +39,15 @@ template <> __device__ __forceinline__ double sqrt_(double a) { return sqrt(a); 
 
 template <typename T> __device__ __forceinline__ T abs_(T a) { return a < T(0) ? -a : a; }
 
+// Plane and table pointers come from the slot descriptors in memory, so the
+// compiler sees generic pointers and emits flat loads, which also count
+// against the LDS wait counter: every wait for an LDS read then waits for
+// the global prefetches in flight too.  The planes and tables are device
+// global memory; through these views the loads and stores are global ones.
+#define W1_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ const W1_GLOBAL T* gld_(const T* p) { return (const W1_GLOBAL T*)p; }
+template <typename T> __device__ __forceinline__ W1_GLOBAL T* gst_(T* p) { return (W1_GLOBAL T*)p; }
+
 // prox of mu ||.||_p at one node: p = 1 soft-threshold per component,
 // p = 2 isotropic shrink (0 when ||v|| <= mu).  The FP32 isotropic factor
 // 1 - mu/||v|| uses the hardware reciprocal square root (about 1 ulp);
@@ -522,10 +531,10 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
   const int OH = RH - 2 * S, OW = RW - 2 * S;
   const int gi0 = w.y * OH - S, gj0 = w.z * OW - S;
   const int rs = (sc.cur ^ li) & 1, ws = rs ^ 1;
-  const T* __restrict__ sm1 = d.p[3 * rs];
-  const T* __restrict__ sm2 = d.p[3 * rs + 1];
-  const T* __restrict__ sph = d.p[3 * rs + 2];
-  const T* __restrict__ srho = d.rho;
+  const W1_GLOBAL T* __restrict__ sm1 = gld_(d.p[3 * rs]);
+  const W1_GLOBAL T* __restrict__ sm2 = gld_(d.p[3 * rs + 1]);
+  const W1_GLOBAL T* __restrict__ sph = gld_(d.p[3 * rs + 2]);
+  const W1_GLOBAL T* __restrict__ srho = gld_(d.rho);
   const T ih = d.ih, mu = d.mu, tau = d.tau;
   constexpr int metric = METRIC;   // one launch per ground metric
   // the wavefront index is uniform across the wavefront: held in a scalar
@@ -674,9 +683,9 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
     step(std::false_type{});
   }
 
-  T* __restrict__ om1 = d.p[3 * ws];
-  T* __restrict__ om2 = d.p[3 * ws + 1];
-  T* __restrict__ oph = d.p[3 * ws + 2];
+  W1_GLOBAL T* __restrict__ om1 = gst_(d.p[3 * ws]);
+  W1_GLOBAL T* __restrict__ om2 = gst_(d.p[3 * ws + 1]);
+  W1_GLOBAL T* __restrict__ oph = gst_(d.p[3 * ws + 2]);
 #pragma unroll
   for (int a = 0; a < NR; ++a)
 #pragma unroll
@@ -1660,8 +1669,11 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const Work* __restrict__ work
 __device__ __forceinline__ int dct_perm_(int x, int ne) { return x < ne ? 2 * x : 2 * (x - ne) + 1; }
 
 // one 64 x 64 output tile (this wavefront's 32 x 32 quarter into out[16],
-// same lane layout as k_gemm_mfma) of sum_k A(i, k) B(k, j), k < K; the
-// loaders take tile-local row / column and return 0 outside the operands
+// same lane layout as k_gemm_mfma) of sum_k A(i, k) B(k, j), k < K.  The
+// loaders take a tile-local row / column and a contraction index k < K, read
+// only in-bounds addresses (clamping internally) and return 0 outside the
+// operands; terms with k >= K are masked here, so no load is conditional
+// and the slice loads compile without branches
 template <class LA, class LB>
 __device__ __forceinline__ void mfma_tile64_(const LA& la, const LB& lb, int K, float (*As)[64][33],
                                              float (*Bs)[32][68], float (&out)[16]) {
@@ -1672,10 +1684,13 @@ __device__ __forceinline__ void mfma_tile64_(const LA& la, const LB& lb, int K, 
   const int bj = t & 63, bk0 = t >> 6;
   float ra[8], rb[8];
   auto load = [&](int p0) {
+    const int ka = p0 + ak, kac = ka < K ? ka : K - 1;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      ra[q] = p0 + ak < K ? la(ai0 + 8 * q, p0 + ak) : 0.f;
-      rb[q] = p0 + bk0 + 4 * q < K ? lb(p0 + bk0 + 4 * q, bj) : 0.f;
+      const int kb = p0 + bk0 + 4 * q, kbc = kb < K ? kb : K - 1;
+      const float va = la(ai0 + 8 * q, kac), vb = lb(kbc, bj);
+      ra[q] = ka < K ? va : 0.f;
+      rb[q] = kb < K ? vb : 0.f;
     }
   };
   auto store = [&](int buf) {
@@ -1724,6 +1739,8 @@ __device__ __forceinline__ int mfma_col_() {
   return (wv & 1) * 32 + (lane & 31);
 }
 
+// (offsets in 32 bits: N <= 4097, so every plane and table offset fits, and
+// the loads take a scalar base with an unsigned 32-bit lane offset)
 template <int PASS>
 __global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
                                                   const SlotDesc<float>* __restrict__ desc,
@@ -1735,10 +1752,10 @@ __global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
   if (gate && scal[w.x / MAXL].status != ST_RUN) return;
   const SlotDesc<float>& d = desc[w.x];
   const int N = d.n + 1, ld = d.pitch, h = N / 2, ne = N - h, no = h;
-  const float* __restrict__ X = d.p[src];
-  float* __restrict__ Y = d.p[dst];
-  const float* __restrict__ Cp = d.dctCp;
-  const float* __restrict__ Ctp = d.dctCtp;
+  const W1_GLOBAL float* __restrict__ X = gld_(d.p[src]);
+  W1_GLOBAL float* __restrict__ Y = gst_(d.p[dst]);
+  const W1_GLOBAL float* __restrict__ Cp = gld_(d.dctCp);
+  const W1_GLOBAL float* __restrict__ Ctp = gld_(d.dctCtp);
   const int nte = (ne + 63) / 64, nto = (no + 63) / 64;
   float out[16];
   if (PASS == 1 || PASS == 2) {
@@ -1751,44 +1768,45 @@ __global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
     if (PASS == 1) {
       // Y1[i][base + k2] = sum_j' fold_j'(X[i][.]) Ctp[j'][base + k2]
       auto la = [&](int il, int jp) -> float {
-        const int i = n0 + il;
-        if (i >= N) return 0.f;
-        const float* row = X + (size_t)i * ld;
-        if (odd) return row[jp] - row[N - 1 - jp];
-        return jp < h ? row[jp] + row[N - 1 - jp] : row[jp];
+        const int i = n0 + il, ic = i < N ? i : N - 1;
+        const float a = X[unsigned(ic * ld + jp)], b = X[unsigned(ic * ld + N - 1 - jp)];
+        const float v = odd ? a - b : (jp < h ? a + b : a);
+        return i < N ? v : 0.f;
       };
       auto lb = [&](int jp, int cl) -> float {
-        const int k2 = b0 + cl;
-        return k2 < cnt ? Ctp[(size_t)jp * N + base + k2] : 0.f;
+        const int k2 = b0 + cl, k2c = k2 < cnt ? k2 : cnt - 1;
+        const float v = Ctp[unsigned(jp * N + base + k2c)];
+        return k2 < cnt ? v : 0.f;
       };
       mfma_tile64_(la, lb, K, As, Bs, out);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = n0 + mfma_row_(r), k2 = b0 + mfma_col_();
-        if (i < N && k2 < cnt) Y[(size_t)i * ld + base + k2] = out[r];
+        if (i < N && k2 < cnt) Y[unsigned(i * ld + base + k2)] = out[r];
       }
     } else {
       // Y2[base + k2][l] = sum_i' Cp[base + k2][i'] fold_i'(X[.][l]) / lambda
       auto la = [&](int kl, int ip) -> float {
-        const int k2 = b0 + kl;
-        return k2 < cnt ? Cp[(size_t)(base + k2) * N + ip] : 0.f;
+        const int k2 = b0 + kl, k2c = k2 < cnt ? k2 : cnt - 1;
+        const float v = Cp[unsigned((base + k2c) * N + ip)];
+        return k2 < cnt ? v : 0.f;
       };
       auto lb = [&](int ip, int cl) -> float {
-        const int l = n0 + cl;
-        if (l >= N) return 0.f;
-        const float a = X[(size_t)ip * ld + l];
-        if (odd) return a - X[(size_t)(N - 1 - ip) * ld + l];
-        return ip < h ? a + X[(size_t)(N - 1 - ip) * ld + l] : a;
+        const int l = n0 + cl, lc = l < N ? l : N - 1;
+        const float a = X[unsigned(ip * ld + lc)], b = X[unsigned((N - 1 - ip) * ld + lc)];
+        const float v = odd ? a - b : (ip < h ? a + b : a);
+        return l < N ? v : 0.f;
       };
       mfma_tile64_(la, lb, K, As, Bs, out);
       const double h2 = d.h * d.h;
+      const W1_GLOBAL double* __restrict__ dcts = gld_(d.dcts);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int k2 = b0 + mfma_row_(r), l = n0 + mfma_col_();
         if (k2 < cnt && l < N) {
           const int kk = base + k2, tk = dct_perm_(kk, ne), tl = dct_perm_(l, ne);
-          const float v = (tk == 0 && tl == 0) ? 0.f : (float)((double)out[r] * (h2 / (d.dcts[tk] + d.dcts[tl])));
-          Y[(size_t)kk * ld + l] = v;
+          const float v = (tk == 0 && tl == 0) ? 0.f : (float)((double)out[r] * (h2 / (dcts[tk] + dcts[tl])));
+          Y[unsigned(kk * ld + l)] = v;
         }
       }
     }
@@ -1804,23 +1822,27 @@ __global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
       if (PASS == 3) {
         // rows i < ne: sum_k'' Ctp[i][base + k''] X[base + k''][l]
         auto la = [&](int il, int kk) -> float {
-          const int i = h0 + il;
-          return i < ne ? Ctp[(size_t)i * N + base + kk] : 0.f;
+          const int i = h0 + il, ic = i < ne ? i : ne - 1;
+          const float v = Ctp[unsigned(ic * N + base + kk)];
+          return i < ne ? v : 0.f;
         };
         auto lb = [&](int kk, int cl) -> float {
-          const int l = n0 + cl;
-          return l < N ? X[(size_t)(base + kk) * ld + l] : 0.f;
+          const int l = n0 + cl, lc = l < N ? l : N - 1;
+          const float v = X[unsigned((base + kk) * ld + lc)];
+          return l < N ? v : 0.f;
         };
         mfma_tile64_(la, lb, K, As, Bs, par ? out : ev);
       } else {
         // columns j < ne: sum_l'' X[i][base + l''] Cp[base + l''][j]
         auto la = [&](int il, int kk) -> float {
-          const int i = n0 + il;
-          return i < N ? X[(size_t)i * ld + base + kk] : 0.f;
+          const int i = n0 + il, ic = i < N ? i : N - 1;
+          const float v = X[unsigned(ic * ld + base + kk)];
+          return i < N ? v : 0.f;
         };
         auto lb = [&](int kk, int cl) -> float {
-          const int j = h0 + cl;
-          return j < ne ? Cp[(size_t)(base + kk) * N + j] : 0.f;
+          const int j = h0 + cl, jc = j < ne ? j : ne - 1;
+          const float v = Cp[unsigned((base + kk) * N + jc)];
+          return j < ne ? v : 0.f;
         };
         mfma_tile64_(la, lb, K, As, Bs, par ? out : ev);
       }
@@ -1832,13 +1854,13 @@ __global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
       const float e = ev[r], o = out[r];
       if (PASS == 3) {
         if (i < ne && j < N) {
-          Y[(size_t)i * ld + j] = e + o;
-          if (N - 1 - i != i) Y[(size_t)(N - 1 - i) * ld + j] = e - o;
+          Y[unsigned(i * ld + j)] = e + o;
+          if (N - 1 - i != i) Y[unsigned((N - 1 - i) * ld + j)] = e - o;
         }
       } else {
         if (i < N && j < ne) {
-          Y[(size_t)i * ld + j] = e + o;
-          if (N - 1 - j != j) Y[(size_t)i * ld + (N - 1 - j)] = e - o;
+          Y[unsigned(i * ld + j)] = e + o;
+          if (N - 1 - j != j) Y[unsigned(i * ld + (N - 1 - j))] = e - o;
         }
       }
     }
