@@ -1533,119 +1533,10 @@ __global__ __launch_bounds__(256) void k_gemm(const Work* __restrict__ work, con
     }
 }
 
-// ---------------------------------------------------------------------------
-// Algorithm 2 update after the Poisson solve (u in plane 6), in place:
-// m+ = v + grad+ u, vphi+ = Proj(vphi + tau m+), vphibar+ = 2 vphi+ - vphi.
-// With CHECK: partials of G^k (eq. (pdhg_stop)): sum |dm|^2, sum |dvphi|^2,
-// sum dvphi . dm, count of non-finite values.
-// ---------------------------------------------------------------------------
-// ---------------------------------------------------------------------------
-// One DCT pass on the matrix cores (FP32): Y = X M (MODE 0, along rows) or
-// Y = M X (MODE 1, along columns) for one 64 x 64 output tile, M the N x N
-// orthonormal DCT-II matrix or its transpose.  Four wavefronts each own a
-// 32 x 32 quarter and accumulate it with v_mfma_f32_32x32x2f32 over K in
-// slices of 32 staged through LDS; out-of-range rows, columns and K are
-// zero in the staged slices.  The lane layout of that instruction: A[i][k]
-// at lane i + 32 k, B[k][j] at lane j + 32 k, and accumulator register r of
-// lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
-// SCALE divides by lambda_kl = s_k + s_l (and zeroes the constant mode) as
-// the scalar kernel does.
-// ---------------------------------------------------------------------------
+// v_mfma_f32_32x32x2f32 lane layout: A[i][k] at lane i + 32 k, B[k][j] at
+// lane j + 32 k, and accumulator register r of lane l holds row
+// 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
 typedef float w1_f32x16 __attribute__((ext_vector_type(16)));
-
-template <int MODE, bool SCALE>
-__global__ __launch_bounds__(256) void k_gemm_mfma(const Work* __restrict__ work,
-                                                   const SlotDesc<float>* __restrict__ desc,
-                                                   const SlotScalars* __restrict__ scal, int src, int dst, int mat,
-                                                   int gate) {
-  constexpr int KT = 32;
-  // two LDS stages: the next K slice is loaded into registers while the
-  // matrix cores work on the current one
-  __shared__ float As[2][64][KT + 1];   // A slice: output rows x K
-  __shared__ float Bs[2][KT][64 + 4];   // B slice: K x output columns
-  const Work w = work[blockIdx.x];
-  if (w.x < 0) return;
-  if (gate && scal[w.x / MAXL].status != ST_RUN) return;
-  const SlotDesc<float>& d = desc[w.x];
-  const int N = d.n + 1, ld = d.pitch;
-  const float* M = mat ? d.dctCt : d.dctC;
-  const float* X = d.p[src];
-  float* Y = d.p[dst];
-  const float* A = MODE == 0 ? X : M;
-  const float* B = MODE == 0 ? M : X;
-  const int lda = MODE == 0 ? ld : N;
-  const int ldb = MODE == 0 ? N : ld;
-  const int i0 = w.y * GEMM_T, j0 = w.z * GEMM_T;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
-  // this thread's 8 elements of each slice: A rows ai0 + 8q, column ak;
-  // B rows bk0 + 4q, column bj
-  const int ak = t & 31, ai0 = t >> 5;
-  const int bj = t & 63, bk0 = t >> 6;
-  float ra[8], rb[8];
-  auto load = [&](int p0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int gi = i0 + ai0 + 8 * q, gk = p0 + ak;
-      ra[q] = (gi < N && gk < N) ? A[(size_t)gi * lda + gk] : 0.f;
-      const int gq = p0 + bk0 + 4 * q, gj = j0 + bj;
-      rb[q] = (gq < N && gj < N) ? B[(size_t)gq * ldb + gj] : 0.f;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[buf][ai0 + 8 * q][ak] = ra[q];
-      Bs[buf][bk0 + 4 * q][bj] = rb[q];
-    }
-  };
-  // each K slice is summed on the matrix cores into a fresh accumulator and
-  // added to the running total with Neumaier compensation, so the rounding
-  // error of a length-N dot product grows with the slice length (32), not
-  // with N (up to 2049)
-  w1_f32x16 tot = {}, comp = {};
-  load(0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (int p0 = 0; p0 < N; p0 += KT) {
-    const bool more = p0 + KT < N;
-    if (more) load(p0 + KT);
-    w1_f32x16 acc = {};
-#pragma unroll
-    for (int kk = 0; kk < KT; kk += 2) {
-      const float a = As[buf][wr + (lane & 31)][kk + (lane >> 5)];
-      const float b = Bs[buf][kk + (lane >> 5)][wc + (lane & 31)];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float x = acc[r], s0 = tot[r], s1 = s0 + x;
-      comp[r] += fabsf(s0) >= fabsf(x) ? (s0 - s1) + x : (x - s1) + s0;
-      tot[r] = s1;
-    }
-    if (more) store(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-  w1_f32x16 acc;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = tot[r] + comp[r];
-  const double h2 = d.h * d.h;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int gi = i0 + wr + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    const int gj = j0 + wc + (lane & 31);
-    if (gi < N && gj < N) {
-      float v = acc[r];
-      if (SCALE) {
-        const double lam = d.dcts[gi] + d.dcts[gj];
-        v = (gi == 0 && gj == 0) ? 0.f : (float)((double)v * (h2 / lam));
-      }
-      Y[(size_t)gi * ld + gj] = v;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // DCT passes with the even/odd fold (FP32, matrix cores).  The DCT-II basis
@@ -1669,7 +1560,7 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(const Work* __restrict__ work
 __device__ __forceinline__ int dct_perm_(int x, int ne) { return x < ne ? 2 * x : 2 * (x - ne) + 1; }
 
 // one 64 x 64 output tile (this wavefront's 32 x 32 quarter into out[16],
-// same lane layout as k_gemm_mfma) of sum_k A(i, k) B(k, j), k < K.  The
+// four wavefronts) of sum_k A(i, k) B(k, j), k < K.  The
 // loaders take a tile-local row / column and a contraction index k < K, read
 // only in-bounds addresses (clamping internally) and return 0 outside the
 // operands; terms with k >= K are masked here, so no load is conditional
@@ -1867,6 +1758,12 @@ __global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Algorithm 2 update after the Poisson solve (u in plane 6), in place:
+// m+ = v + grad+ u, vphi+ = Proj(vphi + tau m+), vphibar+ = 2 vphi+ - vphi.
+// With CHECK: partials of G^k (eq. (pdhg_stop)): sum |dm|^2, sum |dvphi|^2,
+// sum dvphi . dm, count of non-finite values.
+// ---------------------------------------------------------------------------
 template <typename T, bool CHECK>
 __global__ __launch_bounds__(256) void k_prox_post(const Work* __restrict__ work,
                                                    const SlotDesc<T>* __restrict__ desc,
@@ -2199,18 +2096,6 @@ template <typename T> void K<T>::gemm(hipStream_t s, const Work* w, int nw, cons
                                       const SlotScalars* sc, int mode, int src, int dst, int mat, bool scale,
                                       int gate) {
   if (!nw) return;
-  if constexpr (sizeof(T) == 4) {
-    // FP32 passes run on the matrix cores
-    const SlotDesc<float>* df = reinterpret_cast<const SlotDesc<float>*>(d);
-    if (mode == 0) {
-      if (scale) LAUNCH((k_gemm_mfma<0, true>), nw, 256, 0, s, w, df, sc, src, dst, mat, gate);
-      else LAUNCH((k_gemm_mfma<0, false>), nw, 256, 0, s, w, df, sc, src, dst, mat, gate);
-    } else {
-      if (scale) LAUNCH((k_gemm_mfma<1, true>), nw, 256, 0, s, w, df, sc, src, dst, mat, gate);
-      else LAUNCH((k_gemm_mfma<1, false>), nw, 256, 0, s, w, df, sc, src, dst, mat, gate);
-    }
-    return;
-  }
   if (mode == 0) {
     if (scale) LAUNCH((k_gemm<T, 0, true>), nw, 256, 0, s, w, d, sc, src, dst, mat, gate);
     else LAUNCH((k_gemm<T, 0, false>), nw, 256, 0, s, w, d, sc, src, dst, mat, gate);
