@@ -945,54 +945,76 @@ class Batch : public BatchBase {
     void* h = nullptr;
     size_t cap = 0;
     int n = 0;
+    std::vector<size_t> off, cnt;   // packed lists: offsets and counts
     uint64_t gen = ~0ull;
     hipEvent_t ev = nullptr;
   };
+  // upload into a list's device buffer from its own pinned copy (grown as
+  // needed); the copy is rewritten only after its previous upload completed
+  int upload_list(DevList& L, const void* src, size_t nbytes) {
+    const size_t bytes = std::max<size_t>(nbytes, 16);
+    if (L.ev && hipEventSynchronize(L.ev) != hipSuccess) return W1_EDEVICE;
+    if (bytes > L.cap) {
+      // kernels queued earlier may still read the old list
+      if (L.d && hipStreamSynchronize(st_) != hipSuccess) return W1_EDEVICE;
+      (void)hipFree(L.d);
+      (void)hipHostFree(L.h);
+      L.d = L.h = nullptr;
+      L.cap = bytes * 2;
+      if (hipMalloc(&L.d, L.cap) != hipSuccess || hipHostMalloc(&L.h, L.cap, hipHostMallocDefault) != hipSuccess) {
+        L.cap = 0;
+        g_err = "work list allocation failed";
+        return W1_ENOMEM;
+      }
+    }
+    if (!L.ev && hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess) return W1_EDEVICE;
+    if (nbytes) std::memcpy(L.h, src, nbytes);
+    if (hipMemcpyAsync(L.d, L.h, std::max<size_t>(nbytes, 1), hipMemcpyHostToDevice, st_) != hipSuccess ||
+        hipEventRecord(L.ev, st_) != hipSuccess)
+      return W1_EDEVICE;
+    L.gen = gen_;
+    ++n_uploads_;
+    return W1_OK;
+  }
   template <typename X, typename F>
   X* cached(const std::string& key, F build, int* count, int* status) {
     DevList& L = lists_[key];
     if (L.gen != gen_) {
       std::vector<X> v = build();
-      const size_t bytes = std::max<size_t>(v.size() * sizeof(X), 16);
-      if (L.ev && hipEventSynchronize(L.ev) != hipSuccess) {
-        *status = W1_EDEVICE;
-        return nullptr;
-      }
-      if (bytes > L.cap) {
-        // kernels queued earlier may still read the old list
-        if (L.d && hipStreamSynchronize(st_) != hipSuccess) {
-          *status = W1_EDEVICE;
-          return nullptr;
-        }
-        (void)hipFree(L.d);
-        (void)hipHostFree(L.h);
-        L.d = L.h = nullptr;
-        L.cap = bytes * 2;
-        if (hipMalloc(&L.d, L.cap) != hipSuccess ||
-            hipHostMalloc(&L.h, L.cap, hipHostMallocDefault) != hipSuccess) {
-          L.cap = 0;
-          *status = W1_ENOMEM;
-          g_err = "work list allocation failed";
-          return nullptr;
-        }
-      }
-      if (!L.ev && hipEventCreateWithFlags(&L.ev, hipEventDisableTiming) != hipSuccess) {
-        *status = W1_EDEVICE;
-        return nullptr;
-      }
-      if (!v.empty()) std::memcpy(L.h, v.data(), v.size() * sizeof(X));
-      if (hipMemcpyAsync(L.d, L.h, std::max<size_t>(v.size() * sizeof(X), 1), hipMemcpyHostToDevice, st_) !=
-              hipSuccess ||
-          hipEventRecord(L.ev, st_) != hipSuccess) {
-        *status = W1_EDEVICE;
-        return nullptr;
-      }
+      *status = upload_list(L, v.data(), v.size() * sizeof(X));
+      if (*status) return nullptr;
       L.n = (int)v.size();
-      L.gen = gen_;
-      ++n_uploads_;
     }
     *count = L.n;
     return (X*)L.d;
+  }
+  // several lists of one launch sequence in one buffer: one upload per group
+  struct Packed {
+    std::vector<char> b;
+    std::vector<size_t> off, cnt;
+    template <typename X>
+    void add(const std::vector<X>& v) {
+      const size_t o = align256(b.size());
+      b.resize(o + std::max<size_t>(v.size() * sizeof(X), 1));
+      if (!v.empty()) std::memcpy(b.data() + o, v.data(), v.size() * sizeof(X));
+      off.push_back(o);
+      cnt.push_back(v.size());
+    }
+  };
+  template <typename F>
+  char* cached_packed(const std::string& key, F build, std::vector<size_t>* off, std::vector<size_t>* cnt,
+                      int* status) {
+    DevList& L = lists_[key];
+    if (L.gen != gen_) {
+      Packed p = build();
+      *status = upload_list(L, p.b.data(), p.b.size());
+      if (*status) return nullptr;
+      L.off = p.off;
+      L.cnt = p.cnt;
+    }
+    *off = L.off;
+    *cnt = L.cnt;
+    return (char*)L.d;
   }
 
   int reduce_lists(const std::vector<std::pair<Request*, int>>& lv, int (*tiles)(int), int** didx_out,
@@ -1181,9 +1203,29 @@ class Batch : public BatchBase {
       t0 = tune_event();
       t1 = tune_event();
     }
-    int nw = 0;
-    Work* w = cached<Work>(key, [&] { return tiled_work(lv, tc.rh, tc.steps); }, &nw, &st);
+    // tiled work, slot ids, per-slot tile counts of the stop-test partials
+    // (and the node tiles of the KKT evaluation)
+    std::vector<size_t> off, cnt;
+    char* base = cached_packed(key, [&] {
+      Packed p;
+      p.add(tiled_work(lv, tc.rh, tc.steps));
+      std::vector<int> ids, nt;
+      for (auto* r : P) {
+        const int n = r->sides[r->level];
+        ids.push_back(dx(r, r->level));
+        nt.push_back(fpr ? tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.steps) : simple_tiles(n));
+      }
+      p.add(ids);
+      p.add(nt);
+      if (!fpr) p.add(simple_work(lv));
+      return p;
+    }, &off, &cnt, &st);
     if (st) return st;
+    Work* w = (Work*)(base + off[0]);
+    const int nw = (int)cnt[0];
+    int* di = (int*)(base + off[1]);
+    int* dn = (int*)(base + off[2]);
+    const int ns = (int)cnt[1];
     const double wb = 7.0 * sizeof(T);  // read m1 m2 phi rho, write m1 m2 phi
     if (t0 && t1) HIPCHK(hipEventRecord(t0, st_));
     for (int li = 0; li < nl; ++li) {
@@ -1196,40 +1238,7 @@ class Batch : public BatchBase {
       HIPCHK(hipEventRecord(t1, st_));
       tune_pending_.push_back(TunePend{t0, t1, entry, arm, nodes * ce});
     }
-    int ns = 0;
-    int* di;
-    int* dn;
-    if (!fpr) {
-      int nsw = 0;
-      Work* sw = cached<Work>(key + "_s", [&] { return simple_work(lv); }, &nsw, &st);
-      if (st) return st;
-      K<T>::kkt(st_, sw, nsw, ddesc_, dsc_, K_PLAIN, nl & 1, 1);
-      di = cached<int>(key + "_i", [&] {
-        std::vector<int> v;
-        for (auto* r : P) v.push_back(dx(r, r->level));
-        return v;
-      }, &ns, &st);
-      dn = cached<int>(key + "_ns", [&] {
-        std::vector<int> v;
-        for (auto* r : P) v.push_back(simple_tiles(r->sides[r->level]));
-        return v;
-      }, &ns, &st);
-    } else {
-      di = cached<int>(key + "_i", [&] {
-        std::vector<int> v;
-        for (auto* r : P) v.push_back(dx(r, r->level));
-        return v;
-      }, &ns, &st);
-      dn = cached<int>(key + "_nt", [&] {
-        std::vector<int> v;
-        for (auto* r : P) {
-          const int n = r->sides[r->level];
-          v.push_back(tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.steps));
-        }
-        return v;
-      }, &ns, &st);
-    }
-    if (st) return st;
+    if (!fpr) K<T>::kkt(st_, (Work*)(base + off[3]), (int)cnt[3], ddesc_, dsc_, K_PLAIN, nl & 1, 1);
     K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PLAIN, ce, nl);
     HIPCHK(hipGetLastError());
     return W1_OK;
@@ -1254,11 +1263,26 @@ class Batch : public BatchBase {
     const bool fpr = X[0]->prm.stop_rule == W1_STOP_FPR;
     auto lv = at_level(X);
     const std::string key = "X" + std::to_string(group);
-    int nsw = 0, ngw = 0, ns = 0;
-    Work* dsw = cached<Work>(key + "_s", [&] { return simple_work(lv); }, &nsw, &st);
+    std::vector<size_t> off, cnt;
+    char* base = cached_packed(key, [&] {
+      Packed p;
+      p.add(simple_work(lv));
+      p.add(gemm_work(lv));
+      std::vector<int> ids, nt;
+      for (auto* r : X) {
+        ids.push_back(dx(r, r->level));
+        nt.push_back(simple_tiles(r->sides[r->level]));
+      }
+      p.add(ids);
+      p.add(nt);
+      return p;
+    }, &off, &cnt, &st);
     if (st) return st;
-    Work* dgw = cached<Work>(key + "_g", [&] { return gemm_work(lv); }, &ngw, &st);
-    if (st) return st;
+    Work* dsw = (Work*)(base + off[0]);
+    Work* dgw = (Work*)(base + off[1]);
+    int* di = (int*)(base + off[2]);
+    int* dn = (int*)(base + off[3]);
+    const int nsw = (int)cnt[0], ngw = (int)cnt[1], ns = (int)cnt[2];
     double nodes = 0, flops = 0;
     for (auto* r : X) {
       const double N = r->sides[r->level] + 1;
@@ -1283,18 +1307,6 @@ class Batch : public BatchBase {
       poisson(dgw, ngw, 8, 1);
       K<T>::kkt(st_, dsw, nsw, ddesc_, dsc_, K_PROX, 0, 1);
     }
-    int* di = cached<int>(key + "_i", [&] {
-      std::vector<int> v;
-      for (auto* r : X) v.push_back(dx(r, r->level));
-      return v;
-    }, &ns, &st);
-    if (st) return st;
-    int* dn = cached<int>(key + "_n", [&] {
-      std::vector<int> v;
-      for (auto* r : X) v.push_back(simple_tiles(r->sides[r->level]));
-      return v;
-    }, &ns, &st);
-    if (st) return st;
     K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PROX, ce, 0);
     HIPCHK(hipGetLastError());
     return W1_OK;
