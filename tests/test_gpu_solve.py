@@ -80,11 +80,12 @@ def test_prox_kkt_rule_resident_levels(precision):
         _check_parity(w1, res, fields, ref, n, metric, rho, precision)
         return
     # FP32: the rounding noise of the FP32 Poisson solves (~1e-7 relative,
-    # white) enters m+ through grad u and raises the gap part of the
-    # in-loop KKT residual to a floor (~1.7e-4 at 65^2, ~7e-4 at 129^2
-    # here) above this schedule's level tolerances, so the levels run to
-    # the cap; W1 and the FP64 evaluation of the returned fields still meet
-    # the tolerance
+    # white) enters m+ through grad u, so A m+ - rho is the discrete
+    # Laplacian of that noise: the primal part of the in-loop KKT residual
+    # has a floor (~1.7e-4 at 65^2, ~7e-4 at 129^2 here) above this
+    # schedule's level tolerances, and the levels run to the cap; W1 and
+    # the FP64 evaluation of the returned (feasibility-corrected) fields
+    # still meet the tolerance
     assert res["iters"] == [20000, 20000, 20000]
     assert res["w1"] == pytest.approx(ref["w1"], rel=1e-4)
     m1, m2, psi = fields
