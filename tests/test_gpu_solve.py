@@ -183,6 +183,43 @@ def test_served_mix_equals_alone():
         assert res["w1"] == pytest.approx(alone["w1"], rel=1e-6)
 
 
+def test_served_resident_beside_batched():
+    """Served mix where LDS-resident levels (sides 33 and 65, on the side
+    stream) run while other requests' batched levels (side 129 and up) run
+    on the batch's stream, under an HBM budget that admits only part of
+    the queue at once: each result equals the request solved alone."""
+    w1 = require_gpu()
+    reqs = []
+    for i in range(8):
+        n = (64, 256)[i % 2]
+        L = {64: 2, 256: 3}[n]
+        p0, p1 = w1data.pair_gauss3(200 + i, n=n)
+        algo = 2 if i % 4 < 2 else 1
+        prm = w1.params(n=n, levels=L, metric=2, algo=algo, precision=FP32, stop_rule=w1.STOP_FPR,
+                        tol=0.0, max_iters=4000, check_every=10)
+        reqs.append((prm, p0, p1))
+    need = max(w1.bytes_per_solve(prm) for prm, _, _ in reqs)
+    small = min(w1.bytes_per_solve(prm) for prm, _, _ in reqs)
+    assert 8 * small <= 3 * need   # the plan (capacity x base request) fits the budget
+    with w1.Solver(reqs[0][0], capacity=8, hbm_budget=3 * need) as srv:
+        tickets = [srv.submit(p0, p1, prm) for prm, p0, p1 in reqs]
+        srv.drain()
+        served = []
+        for t, (prm, _, _) in zip(tickets, reqs):
+            r = None
+            while r is None:
+                r = srv.poll(t)
+            served.append(r[0])
+        st = srv.stats()
+        assert st["finished"] == len(reqs) and st["running"] == 0
+        assert st["peak_bytes"] <= 3 * need
+    for (prm, p0, p1), res in zip(reqs, served):
+        with w1.Solver(prm) as s:
+            alone = s.solve([(p0, p1)])[0]
+        assert res["iters"] == alone["iters"]
+        assert res["w1"] == pytest.approx(alone["w1"], rel=1e-6)
+
+
 def test_no_certificate_flag():
     """Without the certificate the solve runs the same iterations and gives
     the same W1 and dual; only lo, hi and kkt are left as NaN."""
