@@ -613,8 +613,8 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
         T n1, n2;
         plain_flux_(m1[a][b], m2[a][b], pc, pd, pr, rhd[a], chr[b], ih, mu, metric, n1, n2);
         if (!(rin[a] && cin[b])) { n1 = T(0); n2 = T(0); }
-        b1[a][b] = (n1 + n1) - m1[a][b];
-        b2[a][b] = (n2 + n2) - m2[a][b];
+        b1[a][b] = fma_(T(2), n1, -m1[a][b]);   // 2 n1 is exact: the same rounding as (n1 + n1) - m1
+        b2[a][b] = fma_(T(2), n2, -m2[a][b]);
         if constexpr (KEEP) {
           const int r = r0 + a, c = lane + 64 * b;
           const T e1 = n1 - m1[a][b], e2 = n2 - m2[a][b];
@@ -788,8 +788,8 @@ __global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __r
         const T pr = hr ? Lp[e + 1] : pc;
         T n1, n2;
         plain_flux_(m1[s], m2[s], pc, pd, pr, hd, hr, ih, mu, metric, n1, n2);
-        b1[s] = (n1 + n1) - m1[s];
-        b2[s] = (n2 + n2) - m2[s];
+        b1[s] = fma_(T(2), n1, -m1[s]);
+        b2[s] = fma_(T(2), n2, -m2[s]);
         Lb[e] = b1[s];
         Lc[e] = b2[s];
         e1[s] = n1 - m1[s];
@@ -1248,8 +1248,8 @@ __global__ __launch_bounds__(PRES_THREADS) void k_prox_resident(const int* __res
         }
         m1[s] = n1;
         m2[s] = n2;
-        b1[s] = (q1 + q1) - w1[s];
-        b2[s] = (q2 + q2) - w2[s];
+        b1[s] = fma_(T(2), q1, -w1[s]);
+        b2[s] = fma_(T(2), q2, -w2[s]);
         w1[s] = q1;
         w2[s] = q2;
       }
@@ -1794,8 +1794,8 @@ __global__ __launch_bounds__(256) void k_prox_post(const Work* __restrict__ work
     d.p[1][off] = n2;
     d.p[2][off] = q1;
     d.p[3][off] = q2;
-    d.p[4][off] = (q1 + q1) - w1;
-    d.p[5][off] = (q2 + q2) - w2;
+    d.p[4][off] = fma_(T(2), q1, -w1);
+    d.p[5][off] = fma_(T(2), q2, -w2);
     if (CHECK) {
       const double e1 = (double)(n1 - m1), e2 = (double)(n2 - m2);
       const double f1 = (double)(q1 - w1), f2 = (double)(q2 - w2);
