@@ -50,9 +50,11 @@ enum {
     W1_ENOTFOUND = -6  /* unknown ticket                                   */
 };
 
-/* per-solve outcome in w1_result.status (not an error)                      */
+/* per-solve outcome in w1_result.status (not an error); W1_SOLVE_FAILED:
+ * served mode only, the batch the request ran in stopped on a runtime
+ * error (no values; w1_drain returns that error)                          */
 enum { W1_SOLVE_OK = 0, W1_SOLVE_MAXITER = 1, W1_SOLVE_DIVERGED = 2,
-       W1_SOLVE_REJECTED = 3 };
+       W1_SOLVE_REJECTED = 3, W1_SOLVE_FAILED = 4 };
 
 enum { W1_METRIC_L1 = 1, W1_METRIC_L2 = 2 };   /* ground metric ||.||_p   */
 enum { W1_ALGO_PLAIN = 1,  /* Algorithm 1 / 3 (eq. (primaldual))           */

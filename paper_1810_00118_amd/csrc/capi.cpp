@@ -259,13 +259,17 @@ static void worker_loop(w1_ctx* h) {
       if (!bp || bp->active() == 0) continue;
       int st = bp->step();
       if (st) {
+        // the batch is unusable: its requests end as failed instead of
+        // waiting for steps that no longer run
+        bp->abort_all();
         std::lock_guard<std::mutex> lk(h->mu);
         h->worker_error = st;
       }
       std::vector<Request*> done;
       bp->collect(done);
       for (Request* r : done) {
-        if (r->want_fields && r->res.status != W1_SOLVE_REJECTED) bp->fetch_fields(r);
+        if (r->want_fields && r->res.status != W1_SOLVE_REJECTED && r->res.status != W1_SOLVE_FAILED)
+          bp->fetch_fields(r);
         bp->release(r);
         std::lock_guard<std::mutex> lk(h->mu);
         h->in_use -= request_bytes(r->prm);

@@ -504,6 +504,10 @@ class Batch : public BatchBase {
     if (ok_) ok_ = hipStreamCreateWithFlags(&rs_, hipStreamNonBlocking) == hipSuccess;
     if (ok_) ok_ = hipEventCreateWithFlags(&ev_up_, hipEventDisableTiming) == hipSuccess &&
                    hipEventCreateWithFlags(&ev_res_, hipEventDisableTiming) == hipSuccess;
+    // failure injection for tests of the error paths: W1_FAIL_AT_STEP=k
+    // makes the k-th step of every batch of the process fail from the host
+    // (no device work is affected)
+    if (const char* e = std::getenv("W1_FAIL_AT_STEP")) fail_at_ = std::atol(e);
   }
   ~Batch() override {
     (void)hipStreamSynchronize(st_);
@@ -632,6 +636,10 @@ class Batch : public BatchBase {
   int step() override {
     if (!ok_) return W1_EDEVICE;
     ++n_steps_;
+    if (fail_at_ > 0 && n_steps_ == fail_at_) {
+      g_err = "step failure injected by W1_FAIL_AT_STEP";
+      return fail(W1_EDEVICE);
+    }
     arena_.reset();
     int st = W1_OK;
     std::vector<Request*> prep;
@@ -758,6 +766,17 @@ class Batch : public BatchBase {
       if (r && r->state == Request::DONE) done.push_back(r);
   }
 
+  void abort_all() override {
+    for (auto* r : slots_) {
+      if (!r || r->state == Request::DONE) continue;
+      r->res.status = W1_SOLVE_FAILED;
+      r->res.w1 = r->res.dual = r->res.lo = r->res.hi = r->res.kkt = NAN;
+      r->state = Request::DONE;
+      r->res.seconds = now_seconds() - r->t_submit;
+    }
+    ++gen_;
+  }
+
   int fetch_fields(Request* r) override {
     if (r->fields_ready) return W1_OK;
     const size_t ne = (size_t)(r->prm.n + 1) * (r->prm.n + 1);
@@ -775,7 +794,16 @@ class Batch : public BatchBase {
 
   int release(Request* r) override {
     if (r->slot >= 0 && r->slot < cap_ && slots_[r->slot] == r) {
-      HIPCHK(hipStreamSynchronize(st_));
+      // after a failed step the stream may report the error again: the
+      // slot is released all the same (its memory is not reused then)
+      if (hipStreamSynchronize(st_) != hipSuccess) {
+        (void)hipGetLastError();
+        slots_[r->slot] = nullptr;
+        r->mem = nullptr;
+        r->slot = -1;
+        ++gen_;
+        return W1_EDEVICE;
+      }
       g_blocks.put(r->bytes, r->mem);
       r->mem = nullptr;
       slots_[r->slot] = nullptr;
@@ -1415,6 +1443,7 @@ class Batch : public BatchBase {
   hipEvent_t ev_up_ = nullptr;      // this step's uploads, for the side stream
   hipEvent_t ev_res_ = nullptr;     // the side stream's launches of this step
   bool res_side_ = false;
+  int64_t fail_at_ = 0;              // W1_FAIL_AT_STEP (tests only)
   Arena arena_;
   bool ok_ = false;
   std::vector<Request*> slots_;

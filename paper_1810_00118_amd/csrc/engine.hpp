@@ -58,6 +58,8 @@ class BatchBase {
   virtual int step() = 0;                 // advance every slot by one block
   virtual int active() const = 0;
   virtual void collect(std::vector<Request*>& done) = 0;
+  // after a failed step: every unfinished request ends as W1_SOLVE_FAILED
+  virtual void abort_all() = 0;
   virtual int fetch_fields(Request* r) = 0;   // copy finest fields to host
   virtual int release(Request* r) = 0;        // free a finished slot
   // input preparation only: rho of every level to dense caller buffers

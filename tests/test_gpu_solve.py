@@ -257,3 +257,49 @@ def test_autotuner_exploration_keeps_results():
         for a, b in zip(runs[0], other):
             assert a["iters"] == b["iters"] and a["w1"] == b["w1"]
 
+
+_FAIL_CHILD = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import paper_1810_00118_amd as w1, w1data
+prm = w1.params(n=64, levels=2, metric=2, algo=w1.ALGO_PROX, precision=w1.FP32, stop_rule=w1.STOP_FPR,
+                tol=0.0, max_iters=4000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+srv = w1.Solver(prm, capacity=4)
+tickets = [srv.submit(*w1data.pair_gauss3(300 + i, n=64), prm) for i in range(4)]
+try:
+    srv.drain()
+    err = 0
+except w1.W1Error as e:
+    err = e.status
+out = []
+for t in tickets:
+    r = None
+    while r is None:
+        r = srv.poll(t)
+    out.append(r[0]["status"])
+st = srv.stats()
+srv.close()
+print(json.dumps({"err": err, "status": out, "running": st["running"], "finished": st["finished"]}))
+"""
+
+
+def test_served_batch_failure_ends_requests():
+    """A batch whose step fails (forced from the host by W1_FAIL_AT_STEP, in
+    a child process) ends its unfinished requests as W1_SOLVE_FAILED, and
+    w1_drain returns the error instead of waiting for ever."""
+    require_gpu()
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, W1_FAIL_AT_STEP="3")
+    out = subprocess.run([sys.executable, "-c", _FAIL_CHILD, root], env=env, capture_output=True, text=True,
+                         timeout=100)
+    assert out.returncode == 0, out.stderr[-2000:]
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    import paper_1810_00118_amd as w1lib
+    assert res["err"] == w1lib.W1_EDEVICE
+    assert res["running"] == 0 and res["finished"] == 4
+    assert all(s == w1lib.SOLVE_FAILED for s in res["status"]), res
+
