@@ -123,8 +123,39 @@ def flux_cost(m1, m2, h, p):
 # {||vphi(x)||_q <= 1} (the conjugate defined before eq. (minmax_pdhg)).
 # --------------------------------------------------------------------------
 
+def _project_l1_ball(v1, v2, r):
+    """Euclidean projection of every node's (v1, v2) onto {|y1| + |y2| <= r}.
+
+    The sort-and-threshold method of Duchi et al. (2008), which the paper
+    names for the p = inf case (Sec. 4.2, complexity of Algorithms 1 and 3),
+    over the d = 2 components of a node: with |v| sorted decreasingly into u
+    and partial sums c_j, k is the largest j with u_j > (c_j - r)/j, the
+    threshold is theta = (c_k - r)/k and y = sign(v) max(|v| - theta, 0).
+    Vectors already in the ball are returned unchanged.
+    """
+    V = np.stack([np.asarray(v1, dtype=np.float64), np.asarray(v2, dtype=np.float64)], axis=-1)
+    A = np.abs(V)
+    u = -np.sort(-A, axis=-1)
+    c = np.cumsum(u, axis=-1)
+    j = np.arange(1, V.shape[-1] + 1, dtype=np.float64)
+    k = np.maximum(np.sum(u > (c - r) / j, axis=-1), 1)
+    theta = (np.take_along_axis(c, (k - 1)[..., None], axis=-1)[..., 0] - r) / k
+    Y = np.sign(V) * np.maximum(A - theta[..., None], 0.0)
+    inside = A.sum(axis=-1) <= r
+    Y = np.where(inside[..., None], V, Y)
+    return Y[..., 0], Y[..., 1]
+
+
 def shrink(v1, v2, mu, p):
-    """argmin_m ||m||_p + ||m - v||^2/(2 mu), per node."""
+    """argmin_m ||m||_p + ||m - v||^2/(2 mu), per node.
+
+    p = inf by the Moreau decomposition the paper uses for that case
+    (Sec. 4.2): prox of mu ||.||_inf at v is v minus the projection of v onto
+    the l_1 ball of radius mu.
+    """
+    if p == math.inf:
+        q1, q2 = _project_l1_ball(v1, v2, mu)
+        return v1 - q1, v2 - q2
     if p == 1:
         return (np.sign(v1) * np.maximum(np.abs(v1) - mu, 0.0),
                 np.sign(v2) * np.maximum(np.abs(v2) - mu, 0.0))
@@ -133,7 +164,7 @@ def shrink(v1, v2, mu, p):
         with np.errstate(divide="ignore", invalid="ignore"):
             s = np.where(nv > mu, 1.0 - mu / np.where(nv > 0, nv, 1.0), 0.0)
         return v1 * s, v2 * s
-    raise ValueError("shrink implemented for p in {1, 2}")
+    raise ValueError("shrink implemented for p in {1, 2, inf}")
 
 
 def project_dual_ball(w1, w2, p):
@@ -144,7 +175,9 @@ def project_dual_ball(w1, w2, p):
         nw = np.sqrt(w1 * w1 + w2 * w2)
         s = 1.0 / np.maximum(1.0, nw)
         return w1 * s, w2 * s
-    raise ValueError("projection implemented for p in {1, 2}")
+    if p == math.inf:   # q = 1: the l_1 unit ball
+        return _project_l1_ball(w1, w2, 1.0)
+    raise ValueError("projection implemented for p in {1, 2, inf}")
 
 
 # --------------------------------------------------------------------------

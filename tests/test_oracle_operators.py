@@ -92,9 +92,9 @@ def test_operator_norm_closed_form_by_power_iteration(n):
     assert mu * tau * o.norm_A_exact(n, h) ** 2 < 0.25 + 1e-15
 
 
-@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, math.inf])
 def test_moreau_decomposition(p):
-    rng = np.random.default_rng(p)
+    rng = np.random.default_rng(3 if p == math.inf else p)
     v1 = rng.standard_normal(2000) * 2
     v2 = rng.standard_normal(2000) * 2
     mu = 0.7
@@ -103,13 +103,13 @@ def test_moreau_decomposition(p):
     np.testing.assert_allclose(s1 + mu * q1, v1, atol=1e-12)
     np.testing.assert_allclose(s2 + mu * q2, v2, atol=1e-12)
     # projections land in the dual-norm ball
-    qn = o.pointwise_norm(q1, q2, {1: math.inf, 2: 2}[p])
+    qn = o.pointwise_norm(q1, q2, {1: math.inf, 2: 2, math.inf: 1}[p])
     assert qn.max() <= 1 + 1e-12
 
 
-@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, math.inf])
 def test_shrink_is_the_prox_minimiser(p):
-    rng = np.random.default_rng(5 + p)
+    rng = np.random.default_rng(8 if p == math.inf else 5 + p)
     mu = 0.3
     for _ in range(50):
         v = rng.standard_normal(2)
@@ -117,13 +117,56 @@ def test_shrink_is_the_prox_minimiser(p):
         best = np.array([s1[0], s2[0]])
 
         def obj(m):
-            nm = np.abs(m).sum() if p == 1 else np.linalg.norm(m)
+            nm = np.abs(m).sum() if p == 1 else (np.abs(m).max() if p == math.inf else np.linalg.norm(m))
             return nm + np.sum((m - v) ** 2) / (2 * mu)
 
         f0 = obj(best)
         for _ in range(200):
             trial = best + rng.standard_normal(2) * 10 ** rng.uniform(-6, 0)
             assert obj(trial) >= f0 - 1e-12
+
+
+def test_l1_ball_projection_variational_inequality():
+    # p = inf: the dual ball is the l_1 unit ball, a polytope with vertices
+    # +-e1, +-e2.  y = P(w) is the projection iff y lies in the ball and
+    # <w - y, z - y> <= 0 for every z of the ball, which for a polytope it
+    # suffices to check at the vertices.
+    rng = np.random.default_rng(17)
+    w1 = rng.standard_normal(4000) * 1.5
+    w2 = rng.standard_normal(4000) * 1.5
+    w1[:4] = [0.3, 2.0, 0.0, -0.5]
+    w2[:4] = [-0.2, 0.0, 0.0, 1.5]       # inside, on an axis, zero, an edge case
+    y1, y2 = o.project_dual_ball(w1, w2, math.inf)
+    assert (np.abs(y1) + np.abs(y2)).max() <= 1 + 1e-12
+    for z1, z2 in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        vi = (w1 - y1) * (z1 - y1) + (w2 - y2) * (z2 - y2)
+        assert vi.max() <= 1e-12
+    inside = np.abs(w1) + np.abs(w2) <= 1
+    np.testing.assert_array_equal(y1[inside], w1[inside])
+    np.testing.assert_array_equal(y2[inside], w2[inside])
+    np.testing.assert_allclose([y1[1], y2[1]], [1.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose([y1[3], y2[3]], [0.0, 1.0], atol=1e-15)
+
+
+def test_linf_shrink_optimality_condition():
+    # x = prox of mu ||.||_inf at v iff g = (v - x)/mu is a subgradient of
+    # ||.||_inf at x: ||g||_1 <= 1 and <g, x> = ||x||_inf (Fenchel equality
+    # of a norm and its dual)
+    rng = np.random.default_rng(23)
+    mu = 0.4
+    v1 = rng.standard_normal(4000)
+    v2 = rng.standard_normal(4000)
+    v1[:3] = [0.1, 1.0, 0.5]
+    v2[:3] = [0.2, 0.9, -0.05]           # inside the ball, both move, one moves
+    x1, x2 = o.shrink(v1, v2, mu, math.inf)
+    g1, g2 = (v1 - x1) / mu, (v2 - x2) / mu
+    assert (np.abs(g1) + np.abs(g2)).max() <= 1 + 1e-12
+    np.testing.assert_allclose(g1 * x1 + g2 * x2, np.maximum(np.abs(x1), np.abs(x2)), atol=1e-12)
+    np.testing.assert_allclose([x1[0], x2[0]], [0.0, 0.0], atol=1e-15)
+    # equal magnitudes (a + b - mu)/2 when |a - b| < mu; only the larger
+    # component moves, by mu, when |a - b| >= mu
+    np.testing.assert_allclose([x1[1], x2[1]], [0.75, 0.75], atol=1e-15)
+    np.testing.assert_allclose([x1[2], x2[2]], [0.1, -0.05], atol=1e-15)
 
 
 def test_dual_exponent_and_norms():

@@ -70,6 +70,80 @@ def _assignment_l1(ia, ib, n):
     return C[r, c].sum() / ia.sum()
 
 
+def _grid_edges(n):
+    """Forward edges of the (n+1)^2 node grid: (node, next node, axis)."""
+    out = []
+    for i in range(n + 1):
+        for j in range(n + 1):
+            if i < n:
+                out.append((i * (n + 1) + j, (i + 1) * (n + 1) + j, 0))
+            if j < n:
+                out.append((i * (n + 1) + j, i * (n + 1) + j + 1, 1))
+    return out
+
+
+def _flux_lp_linf(a, b, n):
+    """The discrete problem (opt_flux_dis) for p = inf as an LP: each node x
+    carries the flux of its two forward edges and a bound t_x >= |m1(x)|,
+    |m2(x)|; minimise sum t_x h^2 subject to div m = rho."""
+    h = 1.0 / n
+    N = (n + 1) ** 2
+    edges = _grid_edges(n)
+    E = len(edges)
+    A_eq = np.zeros((N, E + N))
+    A_ub = np.zeros((2 * E, E + N))
+    for e, (s, t, _) in enumerate(edges):
+        A_eq[s, e] += 1 / h
+        A_eq[t, e] -= 1 / h
+        A_ub[2 * e, e] = 1.0
+        A_ub[2 * e + 1, e] = -1.0
+        A_ub[2 * e, E + s] = -1.0        # the edge's flux is bounded by t of its tail node
+        A_ub[2 * e + 1, E + s] = -1.0
+    c = np.concatenate([np.zeros(E), np.full(N, h * h)])
+    bounds = [(None, None)] * E + [(0, None)] * N
+    res = linprog(c, A_ub=A_ub, b_ub=np.zeros(2 * E), A_eq=A_eq, b_eq=((a - b) / h ** 2).ravel(),
+                  bounds=bounds, method="highs")
+    assert res.status == 0
+    return res.fun
+
+
+def _potential_lp_q1(a, b, n):
+    """Its dual: maximise sum psi (a - b) over node potentials whose forward
+    differences satisfy |g1(x)| + |g2(x)| <= 1 at every node (q = 1), a
+    missing edge counting as g = 0."""
+    h = 1.0 / n
+    N = (n + 1) ** 2
+    G = {}
+    for s, t, ax in _grid_edges(n):
+        G.setdefault(s, {})[ax] = t
+    rows = []
+    for s, nb in G.items():
+        for sg1 in (1, -1):
+            for sg2 in (1, -1):
+                r = np.zeros(N)
+                for ax, sg in ((0, sg1), (1, sg2)):
+                    if ax in nb:
+                        r[nb[ax]] += sg / h
+                        r[s] -= sg / h
+                rows.append(r)
+    res = linprog(-(a - b).ravel(), A_ub=np.array(rows), b_ub=np.ones(len(rows)), bounds=(None, None),
+                  method="highs")
+    assert res.status == 0
+    return -res.fun
+
+
+@pytest.mark.parametrize("n,seed", [(4, 3), (6, 4), (8, 5)])
+def test_brute_force_lp_pinf(n, seed):
+    a, b = w1data.random_pair(n, 40 + seed)
+    exact = _flux_lp_linf(a, b, n)
+    assert exact == pytest.approx(_potential_lp_q1(a, b, n), rel=1e-9, abs=1e-12)
+    for algo in (1, 2):
+        r = _solve(a, b, n, math.inf, algo=algo)
+        assert r["lo"] <= exact * (1 + 1e-9) + 1e-12
+        assert r["hi"] >= exact * (1 - 1e-9) - 1e-12
+        assert r["w1"] == pytest.approx(exact, rel=2e-6), algo
+
+
 @pytest.mark.parametrize("n,seed", [(4, 0), (6, 1), (8, 2)])
 def test_brute_force_min_cost_flow_p1(n, seed):
     ia, ib = w1data.integer_mass_pair(n, 24, seed)
@@ -85,22 +159,25 @@ def test_brute_force_min_cost_flow_p1(n, seed):
     assert r["w1"] == pytest.approx(exact_tp, rel=2e-6)
 
 
-@pytest.mark.parametrize("n,p", [(8, 1), (16, 2), (9, 2)])
+@pytest.mark.parametrize("n,p", [(8, 1), (16, 2), (9, 2), (8, math.inf), (9, math.inf)])
 def test_stripes_closed_form(n, p):
     a, b = w1data.stripes_pair(n, seed=n)
     F0 = np.cumsum(a.sum(axis=1))
     F1 = np.cumsum(b.sum(axis=1))
     closed = float(np.sum(np.abs(F0 - F1)) / n)
-    r = _solve(a, b, n, p, algo=2 if p == 2 else 1)
+    r = _solve(a, b, n, p, algo=1 if p == 1 else 2)
     assert r["w1"] == pytest.approx(closed, rel=1e-6)
     assert r["lo"] <= closed * (1 + 1e-9) <= r["hi"] * (1 + 2e-9)
 
 
-@pytest.mark.parametrize("n,shift,p", [(12, (2, 3), 1), (12, (-3, 1), 1), (8, (2, 0), 2), (8, (0, -3), 2)])
+@pytest.mark.parametrize("n,shift,p", [(12, (2, 3), 1), (12, (-3, 1), 1), (8, (2, 0), 2), (8, (0, -3), 2),
+                                       (8, (3, 0), math.inf), (8, (0, -2), math.inf)])
 def test_translation_closed_form(n, shift, p):
+    # axis-aligned shifts for p = 2 and p = inf: the grid's edges carry the
+    # continuous optimal flux exactly only along an axis
     a, b, mass = w1data.translated_bump_pair(n, shift, floor_mass=0.2, seed=sum(shift) + 7)
     s = np.array(shift, dtype=float) / n
-    closed = (np.abs(s).sum() if p == 1 else np.linalg.norm(s)) * mass
+    closed = np.linalg.norm(s, ord=p) * mass
     r = _solve(a, b, n, p, algo=1 if p == 1 else 2)
     assert r["w1"] == pytest.approx(closed, rel=2e-6)
     assert r["lo"] <= closed * (1 + 1e-9)
@@ -117,6 +194,18 @@ def test_p2_sandwich_and_moment_bound():
     mom = np.array([np.sum((a - b) * x1), np.sum((a - b) * x2)])
     assert r2["w1"] >= np.linalg.norm(mom) - 1e-9
     assert r2["lo"] <= r2["hi"]
+
+
+def test_pinf_sandwich():
+    # ||x||_inf <= ||x||_2 <= ||x||_1 <= 2 ||x||_inf node by node, so the
+    # discrete optima obey W_inf <= W_2 <= W_1 <= 2 W_inf
+    n = 10
+    a, b = w1data.random_pair(n, 12)
+    w_1 = _solve(a, b, n, 1, algo=1)["w1"]
+    w_2 = _solve(a, b, n, 2, algo=2)["w1"]
+    w_i = _solve(a, b, n, math.inf, algo=2)["w1"]
+    assert w_i <= w_2 + 1e-8 and w_2 <= w_1 + 1e-8 and w_1 <= 2 * w_i + 1e-8
+    assert w_i < w_2 < w_1        # a generic pair moves mass off the axes
 
 
 def test_invariants():
