@@ -14,6 +14,7 @@ from HIP-event timing inside the timed region, and the FP64 CPU oracle timed
 on this host's cores on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu]
+    python bench.py --ground linf       # the uniform batch under another ground metric
     python bench.py --workload uneven   # 1024 pairs, n in {64..512}, Algorithm 4
     python bench.py --workload served   # Poisson arrivals, n in {128..2048}
     python bench.py --workload single   # one 512-grid pair, both algorithms
@@ -24,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -331,6 +333,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
     ap.add_argument("--workload", default="uniform", choices=["uniform", "uneven", "served", "single"])
+    ap.add_argument("--ground", default="l2", choices=["l1", "l2", "linf"],
+                    help="uniform: ground metric of the flux cost (the headline figure is l2)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--sizes", default="128,256,512,1024,2048", help="served: grid sides")
@@ -366,7 +370,9 @@ def main():
     torch.cuda.synchronize()
 
     w1.lib()
-    prm = w1.params(n=n, levels=L, metric=w1.METRIC_L2, algo=w1.ALGO_PLAIN, precision=w1.FP32,
+    gm = {"l1": w1.METRIC_L1, "l2": w1.METRIC_L2, "linf": w1.METRIC_LINF}[args.ground]
+    p_or = {"l1": 1, "l2": 2, "linf": math.inf}[args.ground]
+    prm = w1.params(n=n, levels=L, metric=gm, algo=w1.ALGO_PLAIN, precision=w1.FP32,
                     stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=10,
                     block_steps=args.block_steps)
     solver = w1.Solver(prm, capacity=P)
@@ -400,7 +406,7 @@ def main():
         f"{ms_per_step:.1f} ms/step, iters pair0 {results[0]['iters']}")
 
     # ---- plain FP64 one-pair-at-a-time GPU path on a sample ----
-    prm64 = w1.params(n=n, levels=L, metric=w1.METRIC_L2, algo=w1.ALGO_PLAIN, precision=w1.FP64,
+    prm64 = w1.params(n=n, levels=L, metric=gm, algo=w1.ALGO_PLAIN, precision=w1.FP64,
                       stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=10,
                       block_steps=1, flags=w1.FLAG_NO_RESIDENT)
     s64 = w1.Solver(prm64, capacity=1)
@@ -456,7 +462,7 @@ def main():
         import oracle.w1_oracle as o
         a, b = pairs[0]
         t = time.perf_counter()
-        r = o.solve(a, b, n, L=L, p=2, algo=1, stop="fpr", eps_L=o.paper_stop_tolerance(1, n, True), alpha=-1.0,
+        r = o.solve(a, b, n, L=L, p=p_or, algo=1, stop="fpr", eps_L=o.paper_stop_tolerance(1, n, True), alpha=-1.0,
                     max_iters=20000, check_every=10, return_fields=False)
         dt = time.perf_counter() - t
         cu = sum(it * nd for it, nd in zip(r["iters"], nodes))
@@ -471,7 +477,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"uniform batch: {P} pairs, n={n} ({n + 1}^2 nodes), rectangles/disks on 1e-4 "
-                               f"floor, L2 metric, {L}-level cascade, plain PDHG (Algorithm 3), paper stop rule "
+                               f"floor, {args.ground.upper()} metric, {L}-level cascade, plain PDHG (Algorithm 3), paper stop rule "
                                "eq. (stop_tol) alpha=-1, FP32 iterates / FP64 reductions",
                    "global_batch": P, "grid": n, "levels": L, "parallelism": "batch"},
         "cell_updates_per_s": cups,

@@ -56,7 +56,10 @@ enum {
 enum { W1_SOLVE_OK = 0, W1_SOLVE_MAXITER = 1, W1_SOLVE_DIVERGED = 2,
        W1_SOLVE_REJECTED = 3, W1_SOLVE_FAILED = 4 };
 
-enum { W1_METRIC_L1 = 1, W1_METRIC_L2 = 2 };   /* ground metric ||.||_p   */
+/* ground metric ||.||_p of the flux cost (Sec. 2.1); the dual norm q of the
+ * potential's constraint is inf, 2 and 1.  W1_METRIC_LINF: the l_inf prox is
+ * the Moreau complement of an l_1-ball projection (Sec. 4.2, p = inf)     */
+enum { W1_METRIC_L1 = 1, W1_METRIC_L2 = 2, W1_METRIC_LINF = 3 };
 enum { W1_ALGO_PLAIN = 1,  /* Algorithm 1 / 3 (eq. (primaldual))           */
        W1_ALGO_PROX = 2 }; /* Algorithm 2 / 4 (eq. (pdhg))                 */
 enum { W1_FP32 = 1,        /* FP32 iterates, FP64 reductions               */

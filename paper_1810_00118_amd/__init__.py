@@ -18,7 +18,7 @@ LIB_PATH = os.environ.get("W1_LIB_PATH") or os.path.join(HERE, "libw1.so")
 W1_OK, W1_EAGAIN = 0, 1
 W1_EINVAL, W1_ENOMEM, W1_EBUSY, W1_EDEVICE, W1_ESTATE, W1_ENOTFOUND = -1, -2, -3, -4, -5, -6
 SOLVE_OK, SOLVE_MAXITER, SOLVE_DIVERGED, SOLVE_REJECTED, SOLVE_FAILED = 0, 1, 2, 3, 4
-METRIC_L1, METRIC_L2 = 1, 2
+METRIC_L1, METRIC_L2, METRIC_LINF = 1, 2, 3
 ALGO_PLAIN, ALGO_PROX = 1, 2
 FP32, FP64 = 1, 2
 STOP_KKT, STOP_FPR = 1, 2

@@ -41,7 +41,7 @@ extern "C" int w1_params_check(const w1_params* p) {
   if (p->levels < 1 || p->levels > W1_MAX_LEVELS) return W1_EINVAL;
   if (p->n < 2 || p->n > 8192) return W1_EINVAL;
   if (p->n % (1 << (p->levels - 1)) != 0 || (p->n >> (p->levels - 1)) < 2) return W1_EINVAL;
-  if (p->metric != W1_METRIC_L1 && p->metric != W1_METRIC_L2) return W1_EINVAL;
+  if (p->metric < W1_METRIC_L1 || p->metric > W1_METRIC_LINF) return W1_EINVAL;
   if (p->algo != W1_ALGO_PLAIN && p->algo != W1_ALGO_PROX) return W1_EINVAL;
   if (p->precision != W1_FP32 && p->precision != W1_FP64) return W1_EINVAL;
   if (p->stop_rule != W1_STOP_KKT && p->stop_rule != W1_STOP_FPR) return W1_EINVAL;
@@ -870,7 +870,8 @@ extern "C" int w1_op_prolong(int32_t nc, int32_t precision, const void* c_m1, co
 extern "C" int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,
                                  int32_t block_steps, int32_t waves, void* m1, void* m2, void* phi, const void* rho,
                                  double* fpr_out, void* hip_stream) {
-  if (check_side(n) || steps < 1 || (metric != 1 && metric != 2) || !m1 || !m2 || !phi || !rho) return W1_EINVAL;
+  if (check_side(n) || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF || !m1 || !m2 || !phi || !rho)
+    return W1_EINVAL;
   if (step_scale >= 1.0 || block_steps > TILED_MAX_STEPS || (waves != 0 && waves != 8 && waves != 16))
     return W1_EINVAL;
   const int nwv = waves ? waves : 8;
@@ -899,7 +900,7 @@ extern "C" int w1_tuner_reset(void) {
 extern "C" int w1_op_prox_steps(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,
                                 int32_t resident, void* m1, void* m2, void* w1, void* w2, void* wb1, void* wb2,
                                 const void* rho, double* fpr_out, void* hip_stream) {
-  if (check_side(n) || steps < 1 || (metric != 1 && metric != 2)) return W1_EINVAL;
+  if (check_side(n) || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF) return W1_EINVAL;
   if (!m1 || !m2 || !w1 || !w2 || !wb1 || !wb2 || !rho || step_scale >= 1.0) return W1_EINVAL;
   if (resident && (precision != W1_FP32 || n + 1 > K<float>::prox_resident_max_side())) return W1_EINVAL;
   hipStream_t s = (hipStream_t)hip_stream;
@@ -927,7 +928,8 @@ extern "C" int w1_op_potential(int32_t n, int32_t precision, const void* w1, con
 
 extern "C" int w1_op_evaluate(int32_t n, int32_t metric, int32_t precision, const void* m1, const void* m2,
                               const void* psi, const void* rho, double* out, void* hip_stream) {
-  if (check_side(n) || (metric != 1 && metric != 2) || !m1 || !m2 || !psi || !rho || !out) return W1_EINVAL;
+  if (check_side(n) || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF || !m1 || !m2 || !psi || !rho || !out)
+    return W1_EINVAL;
   hipStream_t s = (hipStream_t)hip_stream;
   return DISPATCH(precision, op_evaluate<float>(n, metric, m1, m2, psi, rho, out, s),
                   op_evaluate<double>(n, metric, m1, m2, psi, rho, out, s));

@@ -48,15 +48,43 @@ template <typename T> __device__ __forceinline__ T abs_(T a) { return a < T(0) ?
 template <typename T> __device__ __forceinline__ const W1_GLOBAL T* gld_(const T* p) { return (const W1_GLOBAL T*)p; }
 template <typename T> __device__ __forceinline__ W1_GLOBAL T* gst_(T* p) { return (W1_GLOBAL T*)p; }
 
+// Ground metric codes: 1 = l_1, 2 = l_2, 3 = l_inf (dual norms inf, 2, 1).
+//
+// prox of mu ||.||_inf at one node (Sec. 4.2, the p = inf case): v minus
+// the projection of v onto the l_1 ball of radius mu (Moreau).  With two
+// components that projection has a closed form: when one magnitude exceeds
+// the other by mu or more only the larger one moves, by mu; otherwise both
+// become (|v1| + |v2| - mu)/2 (0 when |v|_1 <= mu).  Signs are kept.
+template <typename T>
+__device__ __forceinline__ void shrink_inf_(T v1, T v2, T mu, T& o1, T& o2) {
+  const T a = abs_(v1), b = abs_(v2);
+  T x1, x2;
+  if (a - b >= mu) {
+    x1 = a - mu;
+    x2 = b;
+  } else if (b - a >= mu) {
+    x1 = a;
+    x2 = b - mu;
+  } else {
+    const T t = (a + b - mu) * T(0.5);
+    x1 = t > T(0) ? t : T(0);
+    x2 = x1;
+  }
+  o1 = v1 < T(0) ? -x1 : x1;
+  o2 = v2 < T(0) ? -x2 : x2;
+}
+
 // prox of mu ||.||_p at one node: p = 1 soft-threshold per component,
-// p = 2 isotropic shrink (0 when ||v|| <= mu).  The FP32 isotropic factor
-// 1 - mu/||v|| uses the hardware reciprocal square root (about 1 ulp);
-// FP64 keeps the correctly rounded square root and division.
+// p = 2 isotropic shrink (0 when ||v|| <= mu), p = inf as above.  The FP32
+// isotropic factor 1 - mu/||v|| uses the hardware reciprocal square root
+// (about 1 ulp); FP64 keeps the correctly rounded square root and division.
 template <typename T>
 __device__ __forceinline__ void shrink_(T v1, T v2, T mu, int metric, T& o1, T& o2);
 template <>
 __device__ __forceinline__ void shrink_(float v1, float v2, float mu, int metric, float& o1, float& o2) {
-  if (metric == 1) {
+  if (metric == 3) {
+    shrink_inf_(v1, v2, mu, o1, o2);
+  } else if (metric == 1) {
     float a1 = fabsf(v1) - mu, a2 = fabsf(v2) - mu;
     a1 = a1 > 0.f ? a1 : 0.f;
     a2 = a2 > 0.f ? a2 : 0.f;
@@ -71,7 +99,9 @@ __device__ __forceinline__ void shrink_(float v1, float v2, float mu, int metric
 }
 template <>
 __device__ __forceinline__ void shrink_(double v1, double v2, double mu, int metric, double& o1, double& o2) {
-  if (metric == 1) {
+  if (metric == 3) {
+    shrink_inf_(v1, v2, mu, o1, o2);
+  } else if (metric == 1) {
     double a1 = fabs(v1) - mu, a2 = fabs(v2) - mu;
     a1 = a1 > 0.0 ? a1 : 0.0;
     a2 = a2 > 0.0 ? a2 : 0.0;
@@ -87,10 +117,29 @@ __device__ __forceinline__ void shrink_(double v1, double v2, double mu, int met
 }
 
 // projection onto the unit ball of the dual norm q (q = inf for p = 1,
-// q = 2 for p = 2)
+// q = 2 for p = 2, q = 1 for p = inf: the l_1 ball, a vector outside it
+// loses (|w1| + |w2| - 1)/2 from both magnitudes, or keeps only its larger
+// component, as sign 1, when that exceeds the other by 1 or more)
 template <typename T>
 __device__ __forceinline__ void proj_ball_(T w1, T w2, int metric, T& o1, T& o2) {
-  if (metric == 1) {
+  if (metric == 3) {
+    const T a = abs_(w1), b = abs_(w2);
+    T x1 = a, x2 = b;
+    if (a + b > T(1)) {
+      if (a - b >= T(1)) {
+        x1 = T(1);
+        x2 = T(0);
+      } else if (b - a >= T(1)) {
+        x1 = T(0);
+        x2 = T(1);
+      } else {
+        x1 = (a - b + T(1)) * T(0.5);
+        x2 = (b - a + T(1)) * T(0.5);
+      }
+    }
+    o1 = w1 < T(0) ? -x1 : x1;
+    o2 = w2 < T(0) ? -x2 : x2;
+  } else if (metric == 1) {
     o1 = w1 > T(1) ? T(1) : (w1 < T(-1) ? T(-1) : w1);
     o2 = w2 > T(1) ? T(1) : (w2 < T(-1) ? T(-1) : w2);
   } else {
@@ -108,13 +157,14 @@ __device__ __forceinline__ void proj_ball_(T w1, T w2, int metric, T& o1, T& o2)
 
 template <typename T>
 __device__ __forceinline__ T norm_p_(T a, T b, int metric) {
-  return metric == 1 ? abs_(a) + abs_(b) : sqrt_(a * a + b * b);
+  const T x = abs_(a), y = abs_(b);
+  return metric == 1 ? x + y : (metric == 3 ? (x > y ? x : y) : sqrt_(a * a + b * b));
 }
 // dual norm q of a gradient
 template <typename T>
 __device__ __forceinline__ T norm_q_(T a, T b, int metric) {
-  T x = abs_(a), y = abs_(b);
-  return metric == 1 ? (x > y ? x : y) : sqrt_(a * a + b * b);
+  const T x = abs_(a), y = abs_(b);
+  return metric == 1 ? (x > y ? x : y) : (metric == 3 ? x + y : sqrt_(a * a + b * b));
 }
 
 // flux half of the plain iterate; hd / hr say whether the node has a
@@ -1886,12 +1936,12 @@ __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work
     const double g1 = i < n ? ((double)pot[off + pitch] - pc) * ih : 0.0;
     const double g2 = j < n ? ((double)pot[off + 1] - pc) * ih : 0.0;
     const double rr = (double)d.rho[off];
-    const double gq = d.metric == 1 ? fmax(fabs(g1), fabs(g2)) : sqrt(g1 * g1 + g2 * g2);
+    const double gq = norm_q_(g1, g2, d.metric);
     const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
-    v[0] += d.metric == 1 ? fabs(a) + fabs(b) : sqrt(a * a + b * b);
+    v[0] += norm_p_(a, b, d.metric);
     v[1] += pc * rr;
     const double f1 = a + c1, f2 = b + c2;
-    v[2] += d.metric == 1 ? fabs(f1) + fabs(f2) : sqrt(f1 * f1 + f2 * f2);
+    v[2] += norm_p_(f1, f2, d.metric);
     v[3] += c1 * c1 + c2 * c2;
     v[4] += ex * ex;
     v[5] = gq > v[5] ? gq : v[5];
@@ -2028,30 +2078,33 @@ template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int n
                                              const SlotScalars* sc, int li, int steps, int rh, bool check,
                                              int metric, int nwv) {
   if (!nw) return;
-  if (rh != TILED_RH || steps < 1 || steps > TILED_MAX_STEPS || (metric != 1 && metric != 2) ||
+  if (rh != TILED_RH || steps < 1 || steps > TILED_MAX_STEPS || (metric < 1 || metric > 3) ||
       (nwv != 8 && nwv != 16)) {
     fprintf(stderr, "w1: internal error: %d steps in a %d-row region, metric %d, %d waves\n", steps, rh, metric,
             nwv);
     return;
   }
 #define W1_TILED_LAUNCH(C, M, NWV) LAUNCH((k_plain_tiled<T, C, M, NWV>), nw, NWV * 64, 0, s, w, d, sc, li, steps)
-  if (nwv == 16) {
-    if (metric == 1) {
-      if (check) W1_TILED_LAUNCH(true, 1, 16);
-      else W1_TILED_LAUNCH(false, 1, 16);
-    } else {
-      if (check) W1_TILED_LAUNCH(true, 2, 16);
-      else W1_TILED_LAUNCH(false, 2, 16);
-    }
-  } else {
-    if (metric == 1) {
-      if (check) W1_TILED_LAUNCH(true, 1, 8);
-      else W1_TILED_LAUNCH(false, 1, 8);
-    } else {
-      if (check) W1_TILED_LAUNCH(true, 2, 8);
-      else W1_TILED_LAUNCH(false, 2, 8);
-    }
+#define W1_TILED_METRIC(NWV)                   \
+  switch (metric) {                            \
+    case 1:                                    \
+      if (check) W1_TILED_LAUNCH(true, 1, NWV); \
+      else W1_TILED_LAUNCH(false, 1, NWV);      \
+      break;                                   \
+    case 2:                                    \
+      if (check) W1_TILED_LAUNCH(true, 2, NWV); \
+      else W1_TILED_LAUNCH(false, 2, NWV);      \
+      break;                                   \
+    default:                                   \
+      if (check) W1_TILED_LAUNCH(true, 3, NWV); \
+      else W1_TILED_LAUNCH(false, 3, NWV);      \
   }
+  if (nwv == 16) {
+    W1_TILED_METRIC(16)
+  } else {
+    W1_TILED_METRIC(8)
+  }
+#undef W1_TILED_METRIC
 #undef W1_TILED_LAUNCH
 }
 
@@ -2065,7 +2118,7 @@ template <typename T> void K<T>::plain_resident(hipStream_t s, const int* idx, i
                                                 SlotScalars* sc, int max_side, int check_every, int chunk,
                                                 int metric) {
   if (!ns) return;
-  if (max_side > ResCfg<T>::MAXN || (metric != 1 && metric != 2)) {
+  if (max_side > ResCfg<T>::MAXN || metric < 1 || metric > 3) {
     fprintf(stderr, "w1: internal error: resident side %d, metric %d\n", max_side, metric);
     return;
   }
@@ -2077,12 +2130,16 @@ template <typename T> void K<T>::plain_resident(hipStream_t s, const int* idx, i
                               hipFuncAttributeMaxDynamicSharedMemorySize, full);
     (void)hipFuncSetAttribute((const void*)k_plain_resident<T, ResCfg<T>::NPT, 2>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, full);
+    (void)hipFuncSetAttribute((const void*)k_plain_resident<T, ResCfg<T>::NPT, 3>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, full);
     attr_set = true;
   }
   if (metric == 1)
     LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 1>), ns, ResCfg<T>::NT, bytes, s, idx, d, sc, check_every, chunk);
-  else
+  else if (metric == 2)
     LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 2>), ns, ResCfg<T>::NT, bytes, s, idx, d, sc, check_every, chunk);
+  else
+    LAUNCH((k_plain_resident<T, ResCfg<T>::NPT, 3>), ns, ResCfg<T>::NT, bytes, s, idx, d, sc, check_every, chunk);
 }
 template <typename T> void K<T>::kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                      const SlotScalars* sc, int kind, int set_xor, int gate) {
@@ -2151,7 +2208,7 @@ template <typename T> void K<T>::prox_resident(hipStream_t s, const int* idx, in
     fprintf(stderr, "w1: internal error: no resident prox kernel for FP64\n");
     return;
   } else {
-  if (max_side > 65 || (metric != 1 && metric != 2)) {
+  if (max_side > 65 || metric < 1 || metric > 3) {
     fprintf(stderr, "w1: internal error: prox resident side %d, metric %d\n", max_side, metric);
     return;
   }
@@ -2162,11 +2219,14 @@ template <typename T> void K<T>::prox_resident(hipStream_t s, const int* idx, in
                               full);
     (void)hipFuncSetAttribute((const void*)k_prox_resident<T, 5, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               full);
+    (void)hipFuncSetAttribute((const void*)k_prox_resident<T, 5, 3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              full);
     attr_set = true;
   }
   const int bytes = prox_resident_lds_bytes(max_side, sizeof(T));
   if (metric == 1) LAUNCH((k_prox_resident<T, 5, 1>), ns, PRES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
-  else LAUNCH((k_prox_resident<T, 5, 2>), ns, PRES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+  else if (metric == 2) LAUNCH((k_prox_resident<T, 5, 2>), ns, PRES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
+  else LAUNCH((k_prox_resident<T, 5, 3>), ns, PRES_THREADS, bytes, s, idx, d, sc, check_every, chunk);
   }
 }
 

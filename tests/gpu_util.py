@@ -1,4 +1,6 @@
 """Helpers shared by the GPU tests: device buffers through torch."""
+import math
+
 import numpy as np
 import pytest
 
@@ -29,3 +31,7 @@ def rel_err(a, b):
 
 def tdtype(precision):
     return torch.float32 if precision == 1 else torch.float64
+
+
+# ground metric code of the C ABI -> the oracle's p
+P_OF = {1: 1, 2: 2, 3: math.inf}

@@ -8,7 +8,7 @@ import pytest
 
 import oracle.w1_oracle as o
 import w1data
-from tests.gpu_util import dev, host, rel_err, require_gpu, tdtype
+from tests.gpu_util import P_OF, dev, host, rel_err, require_gpu, tdtype
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,7 @@ def _rand_state(n, seed, scale=1.0):
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
 @pytest.mark.parametrize("n", [33, 100, 200])
-@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("metric", [1, 2, 3])
 @pytest.mark.parametrize("block", [1, 4, -1])
 def test_plain_steps_trajectory(precision, n, metric, block):
     w1 = require_gpu()
@@ -46,7 +46,7 @@ def test_plain_steps_trajectory(precision, n, metric, block):
         R = w1.op_plain_steps(n, metric, precision, k, g[0], g[1], g[2], g[3], block_steps=block, fpr=True)
         a1, a2, ap = m1.copy(), m2.copy(), phi.copy()
         for _ in range(k):
-            a1, a2, ap, Rw = o.pd_step(a1, a2, ap, rho, h, mu, tau, metric)
+            a1, a2, ap, Rw = o.pd_step(a1, a2, ap, rho, h, mu, tau, P_OF[metric])
         tol = 1e-12 if precision == FP64 else 2e-5 * math.sqrt(k)
         assert rel_err(host(g[0]), a1) <= tol
         assert rel_err(host(g[1]), a2) <= tol
@@ -59,7 +59,8 @@ def test_plain_steps_trajectory(precision, n, metric, block):
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
 @pytest.mark.parametrize("n", [32, 64, 100])
-def test_resident_and_tiled_agree_bitwise(precision, n):
+@pytest.mark.parametrize("metric", [2, 3])
+def test_resident_and_tiled_agree_bitwise(precision, n, metric):
     w1 = require_gpu()
     if n + 1 > 65:
         pytest.skip("resident kernel holds sides up to 65")
@@ -69,7 +70,7 @@ def test_resident_and_tiled_agree_bitwise(precision, n):
     outs = []
     for block, waves in ((-1, 0), (1, 8), (3, 8), (6, 16), (5, 16), (1, 16)):
         g = [dev(x, dt) for x in (m1, m2, phi, rho)]
-        w1.op_plain_steps(n, 2, precision, 25, g[0], g[1], g[2], g[3], block_steps=block, waves=waves)
+        w1.op_plain_steps(n, metric, precision, 25, g[0], g[1], g[2], g[3], block_steps=block, waves=waves)
         outs.append([host(x) for x in g[:3]])
     for other in outs[1:]:
         for a, b in zip(outs[0], other):
@@ -78,7 +79,7 @@ def test_resident_and_tiled_agree_bitwise(precision, n):
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
 @pytest.mark.parametrize("n", [32, 64, 100])
-@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("metric", [1, 2, 3])
 def test_prox_steps_trajectory(precision, n, metric):
     w1 = require_gpu()
     h = 1.0 / n
@@ -93,7 +94,7 @@ def test_prox_steps_trajectory(precision, n, metric):
     G = w1.op_prox_steps(n, metric, precision, k, *g, fpr=True)
     st = (m1, m2, v1, v2, v1.copy(), v2.copy())
     for _ in range(k):
-        out = o.prox_step(*st, rho, h, 0.5, 0.5, metric)
+        out = o.prox_step(*st, rho, h, 0.5, 0.5, P_OF[metric])
         st, Gw = out[:6], out[6]
     tol = 1e-10 if precision == FP64 else 1e-4
     for got, want in zip(g[:6], st):
@@ -102,7 +103,7 @@ def test_prox_steps_trajectory(precision, n, metric):
 
 
 @pytest.mark.parametrize("n", [4, 7, 16, 32, 40, 63, 64])
-@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("metric", [1, 2, 3])
 @pytest.mark.parametrize("k", [1, 10, 60])
 def test_prox_resident_trajectory(n, metric, k):
     """The whole-level LDS kernel of Algorithm 2 follows the oracle's
@@ -121,7 +122,7 @@ def test_prox_resident_trajectory(n, metric, k):
     Gb = w1.op_prox_steps(n, metric, FP32, k, *gb, fpr=True)
     st = (m1, m2, v1, v2, v1.copy(), v2.copy())
     for _ in range(k):
-        out = o.prox_step(*st, rho, h, 0.5, 0.5, metric)
+        out = o.prox_step(*st, rho, h, 0.5, 0.5, P_OF[metric])
         st, Gw = out[:6], out[6]
     tol = 1e-4 * math.sqrt(k)
     for got, other, want in zip(g[:6], gb[:6], st):
@@ -225,15 +226,15 @@ def test_prepare_rejects_bad_masses():
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
-@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("metric", [1, 2, 3])
 @pytest.mark.parametrize("n", [24, 100])
 def test_evaluate(precision, metric, n):
     w1 = require_gpu()
     rho = _rho(n, 11)
-    r = o.solve(*w1data.random_pair(n, 11), n, L=1, p=metric, algo=1, stop="kkt", tol=0.0, max_iters=200,
+    r = o.solve(*w1data.random_pair(n, 11), n, L=1, p=P_OF[metric], algo=1, stop="kkt", tol=0.0, max_iters=200,
                 check_every=200)
     m1, m2, psi = r["m1"], r["m2"], r["psi"]
-    want = o.evaluate(m1, m2, psi, rho, 1.0 / n, metric)
+    want = o.evaluate(m1, m2, psi, rho, 1.0 / n, P_OF[metric])
     dt = tdtype(precision)
     got = w1.op_evaluate(n, metric, precision, *[dev(x, dt) for x in (m1, m2, psi, rho)])
     rt = 1e-10 if precision == FP64 else 2e-5

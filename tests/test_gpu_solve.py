@@ -7,7 +7,7 @@ import pytest
 
 import oracle.w1_oracle as o
 import w1data
-from tests.gpu_util import require_gpu
+from tests.gpu_util import P_OF, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -15,7 +15,7 @@ FP32, FP64 = 1, 2
 
 
 def _oracle(p0, p1, n, L, metric, algo, rule, tol, cap, ce):
-    return o.solve(p0, p1, n, L=L, p=metric, algo=algo, stop="fpr" if rule == 2 else "kkt",
+    return o.solve(p0, p1, n, L=L, p=P_OF[metric], algo=algo, stop="fpr" if rule == 2 else "kkt",
                    tol=tol, eps_L=tol if rule == 2 and tol > 0 else None, max_iters=cap, check_every=ce,
                    alpha=-1.0)
 
@@ -24,8 +24,8 @@ def _check_parity(w1, res, fields, ref, n, metric, rho, precision=FP64):
     assert res["status"] in (0, 1)
     assert res["w1"] == pytest.approx(ref["w1"], rel=1e-4)
     m1, m2, psi = fields
-    ev_gpu = o.evaluate(m1, m2, psi, rho, 1.0 / n, metric)
-    ev_ref = o.evaluate(ref["m1"], ref["m2"], ref["psi"], rho, 1.0 / n, metric)
+    ev_gpu = o.evaluate(m1, m2, psi, rho, 1.0 / n, P_OF[metric])
+    ev_ref = o.evaluate(ref["m1"], ref["m2"], ref["psi"], rho, 1.0 / n, P_OF[metric])
     assert abs(ev_gpu["kkt"] - ev_ref["kkt"]) <= 1e-5
     # W1_h lies in both certified brackets, so they overlap; the oracle's own
     # f(m^K) need not lie in the GPU bracket when m^K is not yet feasible
@@ -89,14 +89,14 @@ def test_prox_kkt_rule_resident_levels(precision):
     assert res["iters"] == [20000, 20000, 20000]
     assert res["w1"] == pytest.approx(ref["w1"], rel=1e-4)
     m1, m2, psi = fields
-    ev_gpu = o.evaluate(m1, m2, psi, rho, 1.0 / n, metric)
+    ev_gpu = o.evaluate(m1, m2, psi, rho, 1.0 / n, P_OF[metric])
     assert ev_gpu["kkt"] <= 1e-4
     assert max(res["lo"], ref["lo"]) <= min(res["hi"], ref["hi"]) * (1 + 1e-6)
 
 
 @pytest.mark.parametrize("algo", [1, 2])
 @pytest.mark.parametrize("precision", [FP64, FP32])
-@pytest.mark.parametrize("metric", [1, 2])
+@pytest.mark.parametrize("metric", [1, 2, 3])
 def test_multilevel_paper_rule(algo, precision, metric):
     """Algorithm 3 / 4 with the paper's tolerance rule eq. (stop_tol),
     alpha = -1, on a 128-grid, 3 levels (tiled plain levels beyond 65)."""
@@ -159,7 +159,7 @@ def test_served_mix_equals_alone():
         p0, p1 = w1data.pair_gauss3(100 + i, n=n)
         algo = 2 if i % 2 == 0 else 1
         L = {32: 1, 64: 2, 128: 3}[n]
-        prm = w1.params(n=n, levels=L, metric=1 + (i % 2), algo=algo, precision=FP32, stop_rule=w1.STOP_FPR,
+        prm = w1.params(n=n, levels=L, metric=1 + (i // 2) % 3, algo=algo, precision=FP32, stop_rule=w1.STOP_FPR,
                         tol=0.0, max_iters=3000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
         reqs.append((prm, p0, p1))
     base = reqs[0][0]
