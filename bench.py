@@ -18,6 +18,7 @@ on this host's cores on a bounded sample.
     python bench.py --workload uneven   # 1024 pairs, n in {64..512}, Algorithm 4
     python bench.py --workload served   # Poisson arrivals, n in {128..2048}
     python bench.py --workload single   # one 512-grid pair, both algorithms
+    python bench.py --workload tolerance  # the tolerance-rule / level-count study
 
 Each workload prints one JSON line of the same layout.
 """
@@ -319,6 +320,121 @@ def run_single(args, w1):
             "cpu_baseline": None}
 
 
+def run_tolerance(args, w1):
+    """The tolerance-rule study of Sec. 5.2 (Tables tab:1m and tab:2m) and
+    the level-count comparison of Sec. 5.1 (Table tab:pd_comparel) on
+    synthetic pairs: Algorithm 3 at n = 256 and Algorithm 4 at n = 512, six
+    levels, l_1 ground metric, FP32 iterates.
+
+    Per level, the optimum f(m*_{h_l}) is taken from an FP64 Algorithm 4
+    cascade run to a normalised KKT residual of 1e-8 at every level.  For
+    each alpha in {1, 0, -1, -5}, eps_L walks down the paper's grid
+    (1e-6 2^p, p = 0..-10 for Algorithm 3; 1e-4 2^p, p = 5..-10 for
+    Algorithm 4; both extended upwards, to p = 6 and p = 10, so that the
+    largest passing value is inside the grid), with an iteration cap of
+    200000 per level, until condition (cond_f) holds at levels 2..L:
+    |f(m*_{h_l}) - f(m^{K_l}_{h_l})| < |f(m*_{h_l}) - f(m*_{h_{l-1}})|.
+    The single-level baseline takes the largest eps on the same grid whose
+    error on the finest level is below the finest grid error.  Times are
+    wall seconds of one w1_solve (median of three; per level: host steps
+    that saw the level end); K_l, errors and the speedup over the baseline
+    are reported, then L = 1..6 at the alpha = -1 tolerance (Sec. 5.1)."""
+    import torch
+    import w1data
+    L = 6
+    study = {}
+    cap = 200000
+    for algo, n, grid in ((w1.ALGO_PLAIN, 256, [1e-6 * 2.0 ** p for p in range(6, -11, -1)]),
+                          (w1.ALGO_PROX, 512, [1e-4 * 2.0 ** p for p in range(10, -11, -1)])):
+        a, b = w1data.pair_shapes(0, n=n)
+        pair = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda())]
+        ref_prm = w1.params(n=n, levels=L, metric=w1.METRIC_L1, algo=w1.ALGO_PROX, precision=w1.FP64,
+                            stop_rule=w1.STOP_KKT, tol=1e-8, alpha=0.0, max_iters=100000, check_every=10,
+                            flags=w1.FLAG_LEVEL_COST)
+        with w1.Solver(ref_prm, capacity=1) as s:
+            ref = s.solve(pair)[0]
+        # stop tests every iteration for Algorithm 4, whose finer levels stop
+        # after one or two (as in the paper); every 10 for Algorithm 3
+        ce = 10 if algo == w1.ALGO_PLAIN else 1
+        fstar = ref["level_w1"]
+        gerr = [None] + [abs(fstar[l] - fstar[l - 1]) for l in range(1, L)]
+        log(f"[bench] tolerance study algo {algo} n={n}: level optima {['%.7f' % f for f in fstar]} "
+            f"(reference iters {ref['iters']}, level KKT {['%.1e' % x for x in ref['measure']]}, "
+            f"bracket [{ref['lo']:.8f}, {ref['hi']:.8f}])")
+
+        def run(levels, eps, alpha):
+            prm = w1.params(n=n, levels=levels, metric=w1.METRIC_L1, algo=algo, precision=w1.FP32,
+                            stop_rule=w1.STOP_FPR, tol=eps, alpha=alpha, max_iters=cap, check_every=ce,
+                            flags=w1.FLAG_LEVEL_COST)
+            with w1.Solver(prm, capacity=1) as s:
+                s.solve(pair)                        # shapes settled by the autotuner
+                walls = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    r = s.solve(pair)[0]
+                    torch.cuda.synchronize()
+                    walls.append(time.perf_counter() - t)
+                r["wall"] = float(np.median(walls))
+            off = L - levels
+            r["err"] = [abs(fstar[off + l] - r["level_w1"][l]) for l in range(levels)]
+            ls = r["level_seconds"]
+            r["level_time"] = [ls[0]] + [ls[l] - ls[l - 1] for l in range(1, levels)]
+            return r
+
+        def row(r, eps, alpha, levels):
+            # eps_l = eps_L (h_l / h)^alpha, h_l = 2^(levels - 1 - l) h (l = 0 coarsest)
+            return {"eps_L": eps, "alpha": alpha, "levels": levels,
+                    "eps_l": [eps * 2.0 ** ((levels - 1 - l) * alpha) for l in range(levels)],
+                    "K": r["iters"], "error": r["err"], "level_seconds": r["level_time"], "seconds": r["wall"],
+                    "w1": r["w1"]}
+
+        base = None
+        for eps in grid:
+            r = run(1, eps, 0.0)
+            if r["err"][0] < gerr[L - 1]:
+                base = row(r, eps, 0.0, 1)
+                break
+        if base:
+            log(f"[bench]   baseline (L=1): eps {base['eps_L']:.3g} K {base['K']} {base['seconds']:.3f}s")
+        else:
+            log("[bench]   baseline (L=1): no eps on the grid reaches the finest grid error")
+        rules = []
+        for alpha in (1.0, 0.0, -1.0, -5.0):
+            best = None
+            for eps in grid:
+                r = run(L, eps, alpha)
+                if all(r["err"][l] < gerr[l] for l in range(1, L)):
+                    best = row(r, eps, alpha, L)
+                    break
+            if best is not None:
+                best["speedup"] = base["seconds"] / best["seconds"] if base else None
+                log(f"[bench]   alpha {alpha:+.0f}: eps_L {best['eps_L']:.3g} K {best['K']} "
+                    f"{best['seconds']:.3f}s speedup {best['speedup']}")
+            else:
+                log(f"[bench]   alpha {alpha:+.0f}: no eps_L on the grid meets (cond_f)")
+            rules.append({"alpha": alpha, "best": best})
+        levels_rows = []
+        eps_m1 = next((x["best"]["eps_L"] for x in rules if x["alpha"] == -1.0 and x["best"]), grid[-1])
+        for levels in range(1, L + 1):
+            r = run(levels, eps_m1, -1.0)
+            levels_rows.append(row(r, eps_m1, -1.0, levels))
+            log(f"[bench]   L={levels}: K {r['iters']} {r['wall']:.3f}s")
+        study["plain" if algo == w1.ALGO_PLAIN else "prox"] = {
+            "n": n, "grid_error": gerr[1:], "level_optima": fstar,
+            "reference": {"iters": ref["iters"], "level_kkt": ref["measure"], "lo": ref["lo"], "hi": ref["hi"]},
+            "eps_grid": [grid[0], grid[-1]], "cap": cap, "check_every": ce, "baseline": base, "rules": rules, "levels": levels_rows}
+    sp = [x["best"]["speedup"] for x in study["prox"]["rules"] if x["alpha"] == -1.0 and x["best"]]
+    return {"metric": "speedup of the multilevel cascade over one level at equal accuracy (Sec. 5.2 protocol)",
+            "value": sp[0] if sp else None, "unit": "x", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "tolerance-rule study: one rectangles/disks pair, Algorithm 3 at n=256 and "
+                                   "Algorithm 4 at n=512, 6 levels, l_1 metric, FP32, alpha in {1, 0, -1, -5}, "
+                                   "eps_L on the paper's grids; value = Algorithm 4 speedup at alpha = -1"},
+            "study": study}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,7 +448,7 @@ def main():
     ap.add_argument("--block-steps", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
-    ap.add_argument("--workload", default="uniform", choices=["uniform", "uneven", "served", "single"])
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "uneven", "served", "single", "tolerance"])
     ap.add_argument("--ground", default="l2", choices=["l1", "l2", "linf"],
                     help="uniform: ground metric of the flux cost (the headline figure is l2)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
@@ -360,7 +476,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     if args.workload != "uniform":
-        run = {"uneven": run_uneven, "served": run_served, "single": run_single}[args.workload]
+        run = {"uneven": run_uneven, "served": run_served, "single": run_single,
+               "tolerance": run_tolerance}[args.workload]
         print(json.dumps(run(args, w1)), flush=True)
         return
     n, L, P = args.n, args.levels, args.pairs

@@ -97,6 +97,11 @@ typedef struct {
 /* W1_FLAG_NO_CERT: skip the FP64 certificate at the end (w1 and dual are   */
 /* still computed; lo, hi and kkt are returned as NaN)                       */
 #define W1_FLAG_NO_CERT 2
+/* W1_FLAG_LEVEL_COST: also evaluate f(m^{K_l}) = sum ||m||_p h_l^2 at the */
+/* end of every coarser level (one FP64 reduction and a host wait per level */
+/* transition; the quantity the tolerance study of Sec. 5.2 compares with   */
+/* the level optimum); without it level_w1 holds NaN below the finest level */
+#define W1_FLAG_LEVEL_COST 4
 
 typedef struct {
     double  w1;           /* f(m^K) = sum ||m||_p h^2 on the finest level     */
@@ -109,6 +114,10 @@ typedef struct {
     double  measure[W1_MAX_LEVELS]; /* stop measure at each level's end      */
     double  seconds;      /* wall time from admission to completion           */
     double  queue_seconds;/* served requests: time waiting for admission     */
+    double  level_w1[W1_MAX_LEVELS];      /* f(m^{K_l}) at each level's end
+                             (W1_FLAG_LEVEL_COST; the finest always), or NaN */
+    double  level_seconds[W1_MAX_LEVELS]; /* wall time from admission to the
+                             host step that saw each level end            */
 } w1_result;
 
 typedef struct w1_ctx* w1_handle;

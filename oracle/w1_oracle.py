@@ -489,7 +489,7 @@ def solve(p0, p1, n, L=1, p=1, algo=1, stop="kkt", tol=1e-6, alpha=-1.0,
     rhos = prepare_levels(p0, p1, n, L)
     base = eps_L if (stop == "fpr" and eps_L is not None) else tol
     tols = level_tolerances(base, alpha, n, L)
-    out = {"iters": [], "level_seconds": [], "status": "ok", "measure": []}
+    out = {"iters": [], "level_seconds": [], "status": "ok", "measure": [], "level_w1": []}
     state = None
     for l in range(L):
         nl = sides[l]
@@ -544,6 +544,9 @@ def solve(p0, p1, n, L=1, p=1, algo=1, stop="kkt", tol=1e-6, alpha=-1.0,
             state = (m1, m2, w1, w2)
         out["iters"].append(k)
         out["measure"].append(float(meas))
+        # f(m^{K_l}) on this level, the quantity condition (cond_f) of
+        # Sec. 5.2 compares with the level optimum
+        out["level_w1"].append(flux_cost(state[0], state[1], h, p))
         out["level_seconds"].append(time.perf_counter() - t0)
     h = 1.0 / n
     rho = rhos[-1]

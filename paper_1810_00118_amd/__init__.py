@@ -22,7 +22,7 @@ METRIC_L1, METRIC_L2, METRIC_LINF = 1, 2, 3
 ALGO_PLAIN, ALGO_PROX = 1, 2
 FP32, FP64 = 1, 2
 STOP_KKT, STOP_FPR = 1, 2
-FLAG_NO_RESIDENT, FLAG_NO_CERT = 1, 2
+FLAG_NO_RESIDENT, FLAG_NO_CERT, FLAG_LEVEL_COST = 1, 2, 4
 MAX_LEVELS = 12
 FAM_PLAIN_TILED, FAM_PLAIN_RESIDENT, FAM_DCT, FAM_PROX_ELEM, FAM_OTHER = 0, 1, 2, 3, 4
 FAMILIES = {0: "plain_tiled", 1: "plain_resident", 2: "dct", 3: "prox_elem", 4: "other", 5: "prox_resident"}
@@ -48,6 +48,7 @@ class Result(C.Structure):
         ("w1", C.c_double), ("dual", C.c_double), ("lo", C.c_double), ("hi", C.c_double), ("kkt", C.c_double),
         ("status", C.c_int32), ("levels_run", C.c_int32), ("iters", C.c_int32 * MAX_LEVELS),
         ("measure", C.c_double * MAX_LEVELS), ("seconds", C.c_double), ("queue_seconds", C.c_double),
+        ("level_w1", C.c_double * MAX_LEVELS), ("level_seconds", C.c_double * MAX_LEVELS),
     ]
 
     def as_dict(self):
@@ -55,7 +56,8 @@ class Result(C.Structure):
         return {"w1": self.w1, "dual": self.dual, "lo": self.lo, "hi": self.hi, "kkt": self.kkt,
                 "status": self.status, "levels_run": L, "iters": list(self.iters[:L]),
                 "measure": list(self.measure[:L]), "seconds": self.seconds,
-                "queue_seconds": self.queue_seconds}
+                "queue_seconds": self.queue_seconds, "level_w1": list(self.level_w1[:L]),
+                "level_seconds": list(self.level_seconds[:L])}
 
 
 _lib = None

@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <tuple>
 
@@ -627,6 +628,7 @@ class Batch : public BatchBase {
     r->state = Request::PREP;
     r->level = 0;
     r->res = w1_result{};
+    for (int l = 0; l < W1_MAX_LEVELS; ++l) r->res.level_w1[l] = std::numeric_limits<double>::quiet_NaN();
     r->t_admit = now_seconds();
     dirty_.push_back(slot);
     ++gen_;
@@ -736,6 +738,7 @@ class Batch : public BatchBase {
       r->res.iters[l] = s.iters;
       r->res.measure[l] = s.measure;
       r->res.levels_run = l + 1;
+      r->res.level_seconds[l] = now_seconds() - r->t_admit;
       if (s.status == ST_DIVERGED) {
         r->res.status = W1_SOLVE_DIVERGED;
         fin.push_back(r);
@@ -1345,6 +1348,8 @@ class Batch : public BatchBase {
     int st = W1_OK;
     std::vector<Request*> plain, prox;
     for (auto* r : up) (r->kind == K_PLAIN ? plain : prox).push_back(r);
+    st = level_costs(up);
+    if (st) return st;
     for (auto* r : up) start_level(r, r->level + 1);
     st = flush_desc();
     if (st) return st;
@@ -1359,6 +1364,38 @@ class Batch : public BatchBase {
       K<T>::reset_scalars(st_, dw, (int)w.size(), dsc_);
     }
     HIPCHK(hipGetLastError());
+    return W1_OK;
+  }
+
+  // f(m^{K_l}) of the level just finished, for requests that ask for it:
+  // the certificate's sums without the Poisson correction, read back at
+  // once (the slot's partial-sum area and eval scalars are free between
+  // levels; prox slots' potential plane is stale here, only P is kept)
+  int level_costs(const std::vector<Request*>& up) {
+    int st = W1_OK;
+    bool any = false;
+    for (int kind : {K_PLAIN, K_PROX}) {
+      std::vector<Request*> grp;
+      for (auto* r : up)
+        if (r->kind == kind && (r->prm.flags & W1_FLAG_LEVEL_COST)) grp.push_back(r);
+      if (grp.empty()) continue;
+      any = true;
+      auto lv = at_level(grp);
+      auto sw = simple_work(lv);
+      Work* dsw = arena_.put(sw, &st);
+      if (st) return st;
+      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, 0);
+      int *di, *dn;
+      st = reduce_lists(lv, simple_tiles_f, &di, &dn);
+      if (st) return st;
+      K<T>::eval_final(st_, di, dn, (int)grp.size(), ddesc_, dsc_, kind, 0);
+      HIPCHK(hipGetLastError());
+    }
+    if (!any) return W1_OK;
+    HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
+    HIPCHK(hipStreamSynchronize(st_));
+    for (auto* r : up)
+      if (r->prm.flags & W1_FLAG_LEVEL_COST) r->res.level_w1[r->level] = hsc_[r->slot].eval[0];
     return W1_OK;
   }
 
@@ -1402,6 +1439,7 @@ class Batch : public BatchBase {
     for (auto* r : fin) {
       const SlotScalars& s = hsc_[r->slot];
       r->res.w1 = s.eval[0];
+      r->res.level_w1[r->level] = s.eval[0];
       r->res.dual = s.eval[1];
       r->res.lo = s.eval[2];
       r->res.hi = s.eval[3];

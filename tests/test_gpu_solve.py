@@ -116,6 +116,45 @@ def test_multilevel_paper_rule(algo, precision, metric):
     _check_parity(w1, res, fields, ref, n, metric, rho, precision)
 
 
+@pytest.mark.parametrize("algo", [1, 2])
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_level_costs(algo, precision):
+    """f(m^{K_l}) at every level's end (W1_FLAG_LEVEL_COST) against the
+    oracle's, on a 128-grid, 3 levels (resident and batched levels); the
+    flag changes no iterate."""
+    w1 = require_gpu()
+    n, L, metric = 128, 3, 1
+    p0, p1 = w1data.pair_gauss3(5, n=n)
+    eps = o.paper_stop_tolerance(algo, n, True)
+    out = {}
+    for flags in (0, w1.FLAG_LEVEL_COST):
+        prm = w1.params(n=n, levels=L, metric=metric, algo=algo, precision=precision, stop_rule=w1.STOP_FPR,
+                        tol=eps, max_iters=20000, check_every=10, flags=flags)
+        with w1.Solver(prm) as s:
+            out[flags] = s.solve([(p0, p1)])[0]
+    plain, costs = out[0], out[w1.FLAG_LEVEL_COST]
+    assert plain["iters"] == costs["iters"] and plain["w1"] == costs["w1"]
+    assert all(np.isnan(x) for x in plain["level_w1"][:-1]) and plain["level_w1"][-1] == plain["w1"]
+    assert costs["level_w1"][-1] == costs["w1"]
+    assert all(b >= a for a, b in zip(costs["level_seconds"], costs["level_seconds"][1:]))
+    if precision == FP64:
+        ref = _oracle(p0, p1, n, L, metric, algo, 2, eps, 20000, 10)
+        assert costs["iters"] == ref["iters"]
+        np.testing.assert_allclose(costs["level_w1"], ref["level_w1"], rtol=1e-9)
+        return
+    # FP32 decides the paper's stop test on its own rounded iterates and may
+    # stop a still-moving level some iterations away from the oracle; with
+    # the KKT rule at tolerance 0 every level runs to the same cap on both
+    # sides, and the level values are compared at equal iteration counts
+    prm = w1.params(n=n, levels=L, metric=metric, algo=algo, precision=FP32, stop_rule=w1.STOP_KKT,
+                    tol=0.0, max_iters=400, check_every=10, flags=w1.FLAG_LEVEL_COST)
+    with w1.Solver(prm) as s:
+        capped = s.solve([(p0, p1)])[0]
+    ref = _oracle(p0, p1, n, L, metric, algo, 1, 0.0, 400, 10)
+    assert capped["iters"] == ref["iters"] == [400] * L
+    np.testing.assert_allclose(capped["level_w1"], ref["level_w1"], rtol=2e-5)
+
+
 def test_batch_equals_alone_bitwise():
     w1 = require_gpu()
     n, L = 64, 2

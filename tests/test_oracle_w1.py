@@ -238,6 +238,24 @@ def test_plain_and_prox_agree_and_cascade_preserves_limit():
     assert len(r["iters"]) == 3
 
 
+def test_level_costs_are_level_optima():
+    # with a tight stop at every level, f(m^{K_l}) recorded at a level's end
+    # is the optimum of that level's problem: the restricted density solved
+    # alone on its grid (split into its positive and negative parts, which
+    # the input preparation scales to unit mass, so W1 scales by that mass)
+    n, L = 8, 3
+    a, b = w1data.random_pair(n, 5)
+    r = _solve(a, b, n, 2, algo=2, L=L)
+    assert r["level_w1"][-1] == r["w1"]
+    rhos = o.prepare_levels(a, b, n, L)
+    for l, nl in enumerate(o.level_sides(n, L)):
+        d = rhos[l] / nl ** 2
+        pos, neg = np.maximum(d, 0.0), np.maximum(-d, 0.0)
+        S = pos.sum()
+        alone = _solve(pos, neg, nl, 2, algo=2)["w1"] * S
+        assert r["level_w1"][l] == pytest.approx(alone, rel=1e-6), l
+
+
 def test_certificate_brackets_the_limit():
     n = 8
     a, b = w1data.random_pair(n, 31)
