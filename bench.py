@@ -451,6 +451,8 @@ def main():
     ap.add_argument("--workload", default="uniform", choices=["uniform", "uneven", "served", "single", "tolerance"])
     ap.add_argument("--ground", default="l2", choices=["l1", "l2", "linf"],
                     help="uniform: ground metric of the flux cost (the headline figure is l2)")
+    ap.add_argument("--step-scale", type=float, default=0.0,
+                    help="uniform: step_scale of every solve (0: the paper's 1/2; 1: its practical steps)")
     ap.add_argument("--rate", type=float, default=200.0, help="served: arrivals per second")
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--sizes", default="128,256,512,1024,2048", help="served: grid sides")
@@ -491,7 +493,7 @@ def main():
     p_or = {"l1": 1, "l2": 2, "linf": math.inf}[args.ground]
     prm = w1.params(n=n, levels=L, metric=gm, algo=w1.ALGO_PLAIN, precision=w1.FP32,
                     stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=10,
-                    block_steps=args.block_steps)
+                    block_steps=args.block_steps, step_scale=args.step_scale)
     solver = w1.Solver(prm, capacity=P)
     for k in range(args.warmup):
         t = time.perf_counter()
@@ -523,7 +525,7 @@ def main():
         f"{ms_per_step:.1f} ms/step, iters pair0 {results[0]['iters']}")
 
     # ---- plain FP64 one-pair-at-a-time GPU path on a sample ----
-    prm64 = w1.params(n=n, levels=L, metric=gm, algo=w1.ALGO_PLAIN, precision=w1.FP64,
+    prm64 = w1.params(n=n, levels=L, metric=gm, algo=w1.ALGO_PLAIN, precision=w1.FP64, step_scale=args.step_scale,
                       stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=10,
                       block_steps=1, flags=w1.FLAG_NO_RESIDENT)
     s64 = w1.Solver(prm64, capacity=1)
@@ -579,7 +581,7 @@ def main():
         import oracle.w1_oracle as o
         a, b = pairs[0]
         t = time.perf_counter()
-        r = o.solve(a, b, n, L=L, p=p_or, algo=1, stop="fpr", eps_L=o.paper_stop_tolerance(1, n, True), alpha=-1.0,
+        r = o.solve(a, b, n, L=L, p=p_or, algo=1, stop="fpr", step_scale=args.step_scale or None, eps_L=o.paper_stop_tolerance(1, n, True), alpha=-1.0,
                     max_iters=20000, check_every=10, return_fields=False)
         dt = time.perf_counter() - t
         cu = sum(it * nd for it, nd in zip(r["iters"], nodes))
@@ -594,7 +596,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"uniform batch: {P} pairs, n={n} ({n + 1}^2 nodes), rectangles/disks on 1e-4 "
-                               f"floor, {args.ground.upper()} metric, {L}-level cascade, plain PDHG (Algorithm 3), paper stop rule "
+                               f"floor, {args.ground.upper()} metric, {L}-level cascade{' step_scale ' + str(args.step_scale) if args.step_scale else ''}, plain PDHG (Algorithm 3), paper stop rule "
                                "eq. (stop_tol) alpha=-1, FP32 iterates / FP64 reductions",
                    "global_batch": P, "grid": n, "levels": L, "parallelism": "batch"},
         "cell_updates_per_s": cups,

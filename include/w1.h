@@ -83,7 +83,10 @@ typedef struct {
                              (tol_formula_propose); paper's choice -1        */
     double  step_scale;   /* plain: mu = tau = step_scale / (2 sqrt 2 / h);
                              prox: mu = tau = step_scale;  <= 0 selects the
-                             paper's 1/2 for both                             */
+                             paper's 1/2 for both; at most 1 (1 is the
+                             practical choice of the footnotes to Sec. 3.1:
+                             mu = tau = 1/||A|| with the bound 2 sqrt 2 / h
+                             for ||A||, and 1 for Algorithm 2)              */
     int32_t max_iters;    /* per-level iteration cap (> 0)                    */
     int32_t check_every;  /* stop-test cadence in iterations (> 0)           */
     int32_t block_steps;  /* plain: PDHG steps fused per launch (temporal
@@ -223,8 +226,8 @@ int w1_op_prolong(int32_t nc, int32_t precision,
                   void* f_m1, void* f_m2, void* f_phi, void* hip_stream);
 
 /* `steps` iterations of eq. (primaldual) in place on (m1, m2, phi), with
- * mu = tau = step_scale * h / (2 sqrt 2) (step_scale <= 0: 1/2).
- * fpr_out (host, may be NULL) receives R^k of the last step
+ * mu = tau = step_scale * h / (2 sqrt 2) (step_scale <= 0: 1/2; at most 1,
+ * else W1_EINVAL).  fpr_out (host, may be NULL) receives R^k of the last step
  * (eq. (pd_stop)).  block_steps > 0 (at most 26) fuses that many steps per
  * tiled launch, block_steps < 0 runs the whole-level LDS kernel (n <= 64);
  * waves (0, 8 or 16) splits each tiled 64 x 128 region over that many
@@ -235,7 +238,7 @@ int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision,
                       const void* rho, double* fpr_out, void* hip_stream);
 
 /* `steps` iterations of eq. (pdhg) in place on (m1, m2, vphi1, vphi2,
- * vphibar1, vphibar2), mu = tau = step_scale (<= 0: 1/2).  fpr_out
+ * vphibar1, vphibar2), mu = tau = step_scale (<= 0: 1/2; at most 1).  fpr_out
  * receives G^k of the last step (eq. (pdhg_stop)).  resident = 1 runs all
  * steps in one workgroup with the level in LDS (FP32, n <= 64; W1_EINVAL
  * otherwise), 0 the batched kernels (one launch sequence per step).       */

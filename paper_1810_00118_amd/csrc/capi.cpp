@@ -51,7 +51,11 @@ extern "C" int w1_params_check(const w1_params* p) {
   // checks fall on multiples of check_every; the cap must be one of them
   if (p->max_iters % p->check_every != 0) return W1_EINVAL;
   if (p->block_steps < 0 || p->block_steps > TILED_MAX_STEPS) return W1_EINVAL;
-  if (p->step_scale >= 1.0) return W1_EINVAL;  // mu tau ||A||^2 < 1 (plain), mu tau < 1 (prox)
+  // plain: mu tau ||A||^2 < 1 holds up to step_scale 1 (the bound 2 sqrt 2 / h
+  // exceeds ||A||); prox: mu tau <= 1, the practical choice of the paper.
+  // Beyond, the fixed-point residual is no longer a norm of the iterate
+  // change and can pass the stop test on a diverging iterate
+  if (p->step_scale > 1.0) return W1_EINVAL;
   return W1_OK;
 }
 
@@ -872,7 +876,7 @@ extern "C" int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision, d
                                  double* fpr_out, void* hip_stream) {
   if (check_side(n) || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF || !m1 || !m2 || !phi || !rho)
     return W1_EINVAL;
-  if (step_scale >= 1.0 || block_steps > TILED_MAX_STEPS || (waves != 0 && waves != 8 && waves != 16))
+  if (step_scale > 1.0 || block_steps > TILED_MAX_STEPS || (waves != 0 && waves != 8 && waves != 16))
     return W1_EINVAL;
   const int nwv = waves ? waves : 8;
   hipStream_t s = (hipStream_t)hip_stream;
@@ -901,7 +905,7 @@ extern "C" int w1_op_prox_steps(int32_t n, int32_t metric, int32_t precision, do
                                 int32_t resident, void* m1, void* m2, void* w1, void* w2, void* wb1, void* wb2,
                                 const void* rho, double* fpr_out, void* hip_stream) {
   if (check_side(n) || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF) return W1_EINVAL;
-  if (!m1 || !m2 || !w1 || !w2 || !wb1 || !wb2 || !rho || step_scale >= 1.0) return W1_EINVAL;
+  if (!m1 || !m2 || !w1 || !w2 || !wb1 || !wb2 || !rho || step_scale > 1.0) return W1_EINVAL;
   if (resident && (precision != W1_FP32 || n + 1 > K<float>::prox_resident_max_side())) return W1_EINVAL;
   hipStream_t s = (hipStream_t)hip_stream;
   return DISPATCH(precision,

@@ -576,17 +576,7 @@ class Batch : public BatchBase {
       d.pitch = pitch_of(nl);
       d.h = 1.0 / nl;
       d.ih = (T)((double)nl);
-      double mu, tau;
-      const double sc = r->prm.step_scale > 0 ? r->prm.step_scale : 0.5;
-      if (r->kind == K_PLAIN) {
-        mu = tau = sc / (2.0 * std::sqrt(2.0) / d.h);   // scale / (Gershgorin bound of ||A||)
-      } else {
-        mu = tau = sc;
-      }
-      d.mud = mu;
-      d.taud = tau;
-      d.mu = (T)mu;
-      d.tau = (T)tau;
+      set_steps(r, d);
       d.metric = r->prm.metric;
       d.rule = r->prm.stop_rule == W1_STOP_FPR ? RULE_FPR : RULE_KKT;
       double tolL = r->prm.tol;
@@ -633,6 +623,15 @@ class Batch : public BatchBase {
     dirty_.push_back(slot);
     ++gen_;
     return W1_OK;
+  }
+
+  // step sizes of a level (R4): plain mu = tau = scale / (2 sqrt 2 / h), the
+  // Gershgorin bound of ||A||; prox mu = tau = scale
+  static void set_steps(const Request* r, SlotDesc<T>& d) {
+    const double sc = r->prm.step_scale > 0 ? r->prm.step_scale : 0.5;
+    const double mu = r->kind == K_PLAIN ? sc / (2.0 * std::sqrt(2.0) / d.h) : sc;
+    d.mud = d.taud = mu;
+    d.mu = d.tau = (T)mu;
   }
 
   int step() override {
@@ -1130,20 +1129,23 @@ class Batch : public BatchBase {
       K<T>::rho_write(st_, dw, (int)w.size(), ddesc_, dsc_);
     }
     HIPCHK(hipGetLastError());
-    // level 1 starts from zero (Algorithms 3 and 4)
-    for (auto* r : good) start_level(r, 0);
+    return start_first_level(good);
+  }
+
+  // level 1 starts from zero (Algorithms 3 and 4)
+  int start_first_level(const std::vector<Request*>& rs) {
+    int st = W1_OK;
+    for (auto* r : rs) start_level(r, 0);
     st = flush_desc();
     if (st) return st;
-    {
-      auto lv = at_level(good);
-      auto w = simple_work(lv);
-      Work* dw = arena_.put(w, &st);
-      if (st) return st;
-      unsigned mask = 0;
-      for (auto* r : good) mask |= r->kind == K_PLAIN ? 0x7u : 0x3Fu;
-      K<T>::zero(st_, dw, (int)w.size(), ddesc_, mask);
-      K<T>::reset_scalars(st_, dw, (int)w.size(), dsc_);
-    }
+    auto lv = at_level(rs);
+    auto w = simple_work(lv);
+    Work* dw = arena_.put(w, &st);
+    if (st) return st;
+    unsigned mask = 0;
+    for (auto* r : rs) mask |= r->kind == K_PLAIN ? 0x7u : 0x3Fu;
+    K<T>::zero(st_, dw, (int)w.size(), ddesc_, mask);
+    K<T>::reset_scalars(st_, dw, (int)w.size(), dsc_);
     HIPCHK(hipGetLastError());
     return W1_OK;
   }

@@ -42,8 +42,10 @@ def test_library_loads_and_checks_params_without_a_device():
     assert w1.bytes_per_solve(p) > 0
     for m in (1, 2, 3):
         assert w1.check_params(w1.params(n=512, levels=4, metric=m)) == 0
+    # the paper's practical step sizes (scale 1) are accepted, larger ones not
+    assert w1.check_params(w1.params(n=512, levels=4, step_scale=1.0)) == 0
     for bad in (dict(n=100, levels=4), dict(levels=0), dict(metric=4), dict(metric=0),
-                dict(max_iters=15, check_every=10), dict(step_scale=1.0), dict(algo=7)):
+                dict(max_iters=15, check_every=10), dict(step_scale=1.5), dict(algo=7)):
         q = w1.params(n=512, levels=4)
         for k, v in bad.items():
             setattr(q, k, v)

@@ -58,6 +58,44 @@ def test_plain_steps_trajectory(precision, n, metric, block):
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("block", [4, -1])
+def test_practical_step_sizes(precision, block):
+    """The footnoted practical steps of Sec. 3.1 (step_scale 1: mu = tau =
+    1/||A|| with the Gershgorin bound; mu = tau = 1 for Algorithm 2) follow
+    the oracle's iterates like the default steps."""
+    w1 = require_gpu()
+    n = 64 if block < 0 else 100
+    h = 1.0 / n
+    rho = _rho(n, 5)
+    m1, m2, phi = _rand_state(n, 6)
+    mu, tau = o.plain_step_sizes(h, 1.0)
+    dt = tdtype(precision)
+    g = [dev(x, dt) for x in (m1, m2, phi, rho)]
+    k = 30
+    R = w1.op_plain_steps(n, 2, precision, k, g[0], g[1], g[2], g[3], step_scale=1.0, block_steps=block, fpr=True)
+    a1, a2, ap = m1, m2, phi
+    for _ in range(k):
+        a1, a2, ap, Rw = o.pd_step(a1, a2, ap, rho, h, mu, tau, 2)
+    tol = 1e-12 if precision == FP64 else 2e-5 * math.sqrt(k)
+    for got, want in zip(g[:3], (a1, a2, ap)):
+        assert rel_err(host(got), want) <= tol
+    assert R == pytest.approx(Rw, rel=1e-9 if precision == FP64 else 1e-3)
+    rng = np.random.default_rng(7)
+    v1 = rng.uniform(-1, 1, (n + 1, n + 1)); v1[n, :] = 0
+    v2 = rng.uniform(-1, 1, (n + 1, n + 1)); v2[:, n] = 0
+    g = [dev(x, dt) for x in (m1, m2, v1, v2, v1, v2, rho)]
+    G = w1.op_prox_steps(n, 2, precision, 10, *g, step_scale=1.0, fpr=True,
+                         resident=block < 0 and precision == FP32)
+    st = (m1, m2, v1, v2, v1.copy(), v2.copy())
+    for _ in range(10):
+        out = o.prox_step(*st, rho, h, 1.0, 1.0, 2)
+        st, Gw = out[:6], out[6]
+    for got, want in zip(g[:6], st):
+        assert rel_err(host(got), want) <= (1e-10 if precision == FP64 else 2e-4)
+    assert G == pytest.approx(Gw, rel=1e-8 if precision == FP64 else 1e-2, abs=1e-12)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
 @pytest.mark.parametrize("n", [32, 64, 100])
 @pytest.mark.parametrize("metric", [2, 3])
 def test_resident_and_tiled_agree_bitwise(precision, n, metric):

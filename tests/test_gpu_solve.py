@@ -155,6 +155,27 @@ def test_level_costs(algo, precision):
     np.testing.assert_allclose(capped["level_w1"], ref["level_w1"], rtol=2e-5)
 
 
+@pytest.mark.parametrize("algo", [1, 2])
+def test_practical_steps_follow_the_oracle(algo):
+    """step_scale 1 (the footnoted practical steps of Sec. 3.1) through the
+    whole cascade: FP64 takes the oracle's stop decisions, W1 and KKT at the
+    usual bar."""
+    w1 = require_gpu()
+    n, L, metric = 128, 3, 2
+    p0, p1 = w1data.pair_gauss3(3, n=n)
+    eps = o.paper_stop_tolerance(algo, n, True)
+    prm = w1.params(n=n, levels=L, metric=metric, algo=algo, precision=FP64, stop_rule=w1.STOP_FPR,
+                    tol=eps, max_iters=20000, check_every=10, step_scale=1.0)
+    with w1.Solver(prm) as s:
+        res = s.solve([(p0, p1)])[0]
+        fields = s.fields(0)
+    ref = o.solve(p0, p1, n, L=L, p=2, algo=algo, stop="fpr", eps_L=eps, tol=eps, max_iters=20000,
+                  check_every=10, alpha=-1.0, step_scale=1.0)
+    assert res["iters"] == ref["iters"]
+    rho = o.prepare_levels(p0, p1, n, L)[-1]
+    _check_parity(w1, res, fields, ref, n, metric, rho, FP64)
+
+
 def test_batch_equals_alone_bitwise():
     w1 = require_gpu()
     n, L = 64, 2
