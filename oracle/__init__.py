@@ -9,9 +9,11 @@ oracle shares no code with the HIP path: the only common dependency is the
 seeded input generator module ``w1data``, which holds none of the method's
 arithmetic.
 
-Parity status: every public function of ``oracle.w1_oracle`` is pinned by the
-tests under ``tests/test_oracle_*.py`` against closed forms, exact identities,
-printed values of the paper or brute force.  One quantity is "parity
+Parity status: every public function of ``oracle.w1_oracle`` (d = 2) and of
+``oracle.w1_oracle3d`` (the same method written for any d, used at d = 3) is
+pinned by the tests under ``tests/test_oracle_*.py`` against closed forms,
+exact identities, printed values of the paper, brute force, or (for the
+d-general module) the d = 2 module it reduces to.  One quantity is "parity
 unpinned": the W1 values the paper prints for its DOTmark / cat experiments,
 because those inputs are absent.
 """

@@ -28,7 +28,7 @@ __all__ = [
     "rng_for", "nodes", "gaussian_mixture", "shapes_density", "normalise",
     "pair_gauss3", "pair_shift8", "pair_shapes", "pair_uneven", "served_requests",
     "stripes_pair", "translated_bump_pair", "integer_mass_pair", "random_pair",
-    "Request",
+    "Request", "random_pair_nd", "pair_gauss_3d",
 ]
 
 CONFIG_GAUSS3 = 1      # single pair, n=64, 3 isotropic Gaussians
@@ -36,6 +36,7 @@ CONFIG_SHIFT8 = 2      # single pair, n=512, 8 anisotropic Gaussians and a shift
 CONFIG_SHAPES = 3      # uniform batch, n=256, unions of rectangles and disks
 CONFIG_UNEVEN = 4      # uneven batch, n in {64,128,256,512}
 CONFIG_SERVED = 5      # served stream, n in {128..2048}
+CONFIG_GAUSS_3D = 6    # d = 3 pairs: isotropic Gaussian mixtures on the unit cube
 
 
 def rng_for(config_id: int, index: int) -> np.random.Generator:
@@ -241,3 +242,30 @@ def random_pair(n: int, seed: int = 0, floor: float = 0.05):
     p0 = rng.uniform(0.0, 1.0, size=(n + 1, n + 1)) + floor
     p1 = rng.uniform(0.0, 1.0, size=(n + 1, n + 1)) + floor
     return normalise(p0), normalise(p1)
+
+
+def random_pair_nd(n: int, d: int, seed: int = 0, floor: float = 0.05):
+    """Random positive masses on the (n+1)^d vertex grid of [0,1]^d."""
+    rng = np.random.default_rng(seed)
+    p0 = rng.uniform(0.0, 1.0, size=(n + 1,) * d) + floor
+    p1 = rng.uniform(0.0, 1.0, size=(n + 1,) * d) + floor
+    return normalise(p0), normalise(p1)
+
+
+def pair_gauss_3d(index: int, n: int = 64, K: int = 3, floor: float = 1e-3):
+    """d = 3 pair: each density a mixture of K isotropic Gaussians on the unit
+    cube (centres U[0.2, 0.8]^3, sigma U[0.05, 0.15]) plus a floor, node
+    masses of shape (n+1, n+1, n+1), index [i1, i2, i3] with i3 contiguous."""
+    rng = rng_for(CONFIG_GAUSS_3D, index)
+    t = np.arange(n + 1, dtype=np.float64) / n
+    x = np.meshgrid(t, t, t, indexing="ij")
+    out = []
+    for _ in range(2):
+        c = rng.uniform(0.2, 0.8, size=(K, 3))
+        sig = rng.uniform(0.05, 0.15, size=K)
+        g = np.zeros_like(x[0])
+        for k in range(K):
+            r2 = sum((x[a] - c[k, a]) ** 2 for a in range(3))
+            g += np.exp(-0.5 * r2 / sig[k] ** 2) / ((2 * math.pi) ** 1.5 * sig[k] ** 3) / K
+        out.append(normalise(g + floor))
+    return out[0], out[1]
