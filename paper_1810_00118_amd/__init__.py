@@ -99,6 +99,8 @@ def lib():
         "w1_op_poisson": (C.c_int, [i32, i32, vp, vp, vp]),
         "w1_op_potential": (C.c_int, [i32, i32, vp, vp, vp, vp]),
         "w1_op_evaluate": (C.c_int, [i32, i32, i32, vp, vp, vp, vp, dp, vp]),
+        "w1_solve3d": (C.c_int, [C.POINTER(Params), vp, vp, i32, C.POINTER(Result), vp, vp, vp]),
+        "w1_op_plain_steps3d": (C.c_int, [i32, i32, i32, C.c_double, i32, vp, vp, vp, vp, vp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -354,3 +356,33 @@ def op_evaluate(n, metric, precision, m1, m2, psi, rho, stream=None):
     _check(lib().w1_op_evaluate(n, metric, precision, *[_ptr(x, d)[0] for x in (m1, m2, psi, rho)], out,
                                 _stream(stream)), "w1_op_evaluate")
     return {"P": out[0], "D": out[1], "lo": out[2], "hi": out[3], "kkt": out[4], "grad_max": out[5]}
+
+
+def solve3d(p: Params, p0, p1, fields=False, stream=None):
+    """Algorithm 3 in d = 3 on one pair of (n+1)^3 float64 masses (numpy or
+    cuda tensors).  Returns the result dict, and with fields=True also
+    (m, psi): m of shape (3, n+1, n+1, n+1) and psi (n+1, n+1, n+1), host."""
+    pa, da = _ptr(p0, "float64")
+    pb, db = _ptr(p1, "float64")
+    if da != db:
+        raise ValueError("both masses must be on the same side (host or device)")
+    out = Result()
+    n = p.n
+    m = psi = None
+    if fields:
+        m = np.empty((3, n + 1, n + 1, n + 1))
+        psi = np.empty((n + 1, n + 1, n + 1))
+    _check(lib().w1_solve3d(C.byref(p), pa, pb, 1 if da else 0, C.byref(out),
+                            m.ctypes.data if fields else None, psi.ctypes.data if fields else None,
+                            _stream(stream)), "w1_solve3d")
+    r = out.as_dict()
+    return (r, m, psi) if fields else r
+
+
+def op_plain_steps3d(n, metric, precision, steps, m1, m2, m3, phi, rho, step_scale=0.0, fpr=False, stream=None):
+    d = _dt(precision)
+    out = C.c_double(np.nan)
+    _check(lib().w1_op_plain_steps3d(n, metric, precision, step_scale, steps,
+                                     *[_ptr(x, d)[0] for x in (m1, m2, m3, phi, rho)],
+                                     C.byref(out) if fpr else None, _stream(stream)), "w1_op_plain_steps3d")
+    return out.value if fpr else None

@@ -1,0 +1,706 @@
+// Algorithm 1 / 3 in d = 3 (the paper states the method for any d: the
+// divergence of Sec. 2.2 summed over three axes, the interpolations of
+// Sec. 3.3 as products of 1-D factors).  One pair per call, levels run one
+// after the other from the host.
+//
+// Layout: a level of side n holds (n+1)^3 nodes, index
+// e = (i1 (n+1) + i2) (n+1) + i3 with i3 contiguous; flux components m1, m2,
+// m3 (m_a on the last node of axis a is not a variable and stays 0), the
+// extrapolated flux b = 2 m+ - m, the potential phi and rho, all in the
+// iterate precision T, plus two FP64 planes for the density pyramid.
+//
+// An iteration is two node-parallel kernels: the flux half (reads phi at the
+// node and its three forward neighbours, writes m+ and b) and the potential
+// half (reads b at the node and its three backward neighbours, updates phi in
+// place).  The stop test's sums (R^k of eq. (pd_stop), or the normalised KKT
+// residual) are block partials in FP64, summed by a one-block kernel and
+// read by the host every `check_every` iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "engine.hpp"
+#include "w1.h"
+
+namespace w1 {
+namespace cube {
+
+constexpr int NT = 256;     // threads per block of every kernel here
+constexpr int NQ3 = 8;      // FP64 partial sums per block
+constexpr int MAXB = 2048;  // blocks of the node-parallel kernels (grid-stride)
+
+#define CHK(x)                                      \
+  do {                                              \
+    hipError_t _e = (x);                            \
+    if (_e != hipSuccess) return hip_status(_e, #x); \
+  } while (0)
+
+template <typename T> __device__ __forceinline__ T abs3_(T a) { return a < T(0) ? -a : a; }
+template <typename T> __device__ __forceinline__ T max3_(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ __forceinline__ T min3_(T a, T b) { return a < b ? a : b; }
+__device__ __forceinline__ float fma3_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma3_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float sqrt3_(float a) { return sqrtf(a); }
+__device__ __forceinline__ double sqrt3_(double a) { return sqrt(a); }
+
+// prox of mu ||.||_p at a node with three components.  p = 1: soft threshold
+// per component; p = 2: isotropic shrink; p = inf: v minus its projection
+// onto the l_1 ball of radius mu (Moreau, Sec. 4.2), the projection by the
+// sort-and-threshold rule of Duchi et al.: with the magnitudes sorted
+// decreasingly into u and partial sums c_j, k counts the j with
+// u_j > (c_j - mu)/j and theta = (c_k - mu)/k; then each component keeps its
+// sign and min(|v_i|, theta), and a vector inside the ball maps to 0.
+template <typename T, int METRIC>
+__device__ __forceinline__ void shrink3_(const T v[3], T mu, T o[3]) {
+  if constexpr (METRIC == 1) {
+    for (int a = 0; a < 3; ++a) {
+      const T r = max3_(abs3_(v[a]) - mu, T(0));
+      o[a] = v[a] < T(0) ? -r : r;
+    }
+  } else if constexpr (METRIC == 2) {
+    const T s2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const T s = s2 > mu * mu ? T(1) - mu / sqrt3_(s2) : T(0);
+    for (int a = 0; a < 3; ++a) o[a] = v[a] * s;
+  } else {
+    const T x = abs3_(v[0]), y = abs3_(v[1]), z = abs3_(v[2]);
+    const T u0 = max3_(max3_(x, y), z), u2 = min3_(min3_(x, y), z);
+    const T u1 = max3_(min3_(x, y), min3_(max3_(x, y), z));
+    const T c2 = u0 + u1, c3 = c2 + u2;
+    if (x + y + z <= mu) {
+      o[0] = o[1] = o[2] = T(0);
+      return;
+    }
+    const int k = 1 + (u1 > (c2 - mu) / T(2) ? 1 : 0) + (u2 > (c3 - mu) / T(3) ? 1 : 0);
+    const T theta = k == 1 ? u0 - mu : (k == 2 ? (c2 - mu) / T(2) : (c3 - mu) / T(3));
+    for (int a = 0; a < 3; ++a) {
+      const T r = min3_(abs3_(v[a]), theta);
+      o[a] = v[a] < T(0) ? -r : r;
+    }
+  }
+}
+
+template <typename T, int METRIC>
+__device__ __forceinline__ T norm_p3_(T a, T b, T c) {
+  const T x = abs3_(a), y = abs3_(b), z = abs3_(c);
+  if constexpr (METRIC == 1) return x + y + z;
+  else if constexpr (METRIC == 2) return sqrt3_(a * a + b * b + c * c);
+  else return max3_(max3_(x, y), z);
+}
+// dual norm q of a gradient (inf, 2, 1 for p = 1, 2, inf)
+template <typename T, int METRIC>
+__device__ __forceinline__ T norm_q3_(T a, T b, T c) {
+  const T x = abs3_(a), y = abs3_(b), z = abs3_(c);
+  if constexpr (METRIC == 1) return max3_(max3_(x, y), z);
+  else if constexpr (METRIC == 2) return sqrt3_(a * a + b * b + c * c);
+  else return x + y + z;
+}
+
+struct Idx {
+  int i1, i2, i3;
+};
+__device__ __forceinline__ Idx split_(long long e, int N1) {
+  Idx r;
+  r.i3 = (int)(e % N1);
+  const long long q = e / N1;
+  r.i2 = (int)(q % N1);
+  r.i1 = (int)(q / N1);
+  return r;
+}
+
+// block sum of NQ3 doubles into part[blockIdx.x * NQ3 + q]; q = 5 is a max
+__device__ __forceinline__ void block_out_(double v[NQ3], double* part) {
+  __shared__ double sh[NQ3][NT];
+  for (int q = 0; q < NQ3; ++q) sh[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < NQ3; ++q) {
+        const double a = sh[q][threadIdx.x], b = sh[q][threadIdx.x + w];
+        sh[q][threadIdx.x] = q == 5 ? (a > b ? a : b) : a + b;
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < NQ3) part[(size_t)blockIdx.x * NQ3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
+// flux half: m+ = shrink(m + mu grad+ phi), b = 2 m+ - m
+// ---------------------------------------------------------------------------
+template <typename T, int METRIC>
+__global__ __launch_bounds__(NT) void k3_flux(int n, T* __restrict__ m0, T* __restrict__ m1, T* __restrict__ m2,
+                                              T* __restrict__ b0, T* __restrict__ b1, T* __restrict__ b2,
+                                              const T* __restrict__ phi, T ih, T mu) {
+  const int N1 = n + 1;
+  const long long S1 = (long long)N1 * N1, N = S1 * N1;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, N1);
+    const T pc = phi[e];
+    const T g0 = x.i1 < n ? (phi[e + S1] - pc) * ih : T(0);
+    const T g1 = x.i2 < n ? (phi[e + N1] - pc) * ih : T(0);
+    const T g2 = x.i3 < n ? (phi[e + 1] - pc) * ih : T(0);
+    const T m[3] = {m0[e], m1[e], m2[e]};
+    const T v[3] = {fma3_(mu, g0, m[0]), fma3_(mu, g1, m[1]), fma3_(mu, g2, m[2])};
+    T o[3];
+    shrink3_<T, METRIC>(v, mu, o);
+    m0[e] = o[0];
+    m1[e] = o[1];
+    m2[e] = o[2];
+    b0[e] = fma3_(T(2), o[0], -m[0]);
+    b1[e] = fma3_(T(2), o[1], -m[1]);
+    b2[e] = fma3_(T(2), o[2], -m[2]);
+  }
+}
+
+// divergence of a flux at node e (Sec. 2.2 summed over the three axes),
+// without the 1/h factor
+template <typename T>
+__device__ __forceinline__ T div3_(const T* f0, const T* f1, const T* f2, long long e, Idx x, int n, int N1,
+                                   long long S1) {
+  T s = (x.i1 < n ? f0[e] : T(0)) - (x.i1 > 0 ? f0[e - S1] : T(0));
+  s += (x.i2 < n ? f1[e] : T(0)) - (x.i2 > 0 ? f1[e - N1] : T(0));
+  s += (x.i3 < n ? f2[e] : T(0)) - (x.i3 > 0 ? f2[e - 1] : T(0));
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// potential half: phi+ = phi + tau (A b - rho); CHECK adds the sums of
+// R^k: sum |dm|^2, sum dphi^2, sum dphi A dm (dm = b - m+)
+// ---------------------------------------------------------------------------
+template <typename T, bool CHECK>
+__global__ __launch_bounds__(NT) void k3_pot(int n, const T* __restrict__ b0, const T* __restrict__ b1,
+                                             const T* __restrict__ b2, const T* __restrict__ m0,
+                                             const T* __restrict__ m1, const T* __restrict__ m2,
+                                             T* __restrict__ phi, const T* __restrict__ rho, T ih, T tau,
+                                             double* __restrict__ part) {
+  const int N1 = n + 1;
+  const long long S1 = (long long)N1 * N1, N = S1 * N1;
+  double v[NQ3] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, N1);
+    const T db = div3_(b0, b1, b2, e, x, n, N1, S1);
+    const T pc = phi[e];
+    const T pn = fma3_(tau, db * ih - rho[e], pc);
+    phi[e] = pn;
+    if constexpr (CHECK) {
+      // dm at the node and at the backward neighbours: b - m+ there
+      const T d0 = b0[e] - m0[e], d1 = b1[e] - m1[e], d2 = b2[e] - m2[e];
+      T adm = (x.i1 < n ? d0 : T(0)) - (x.i1 > 0 ? b0[e - S1] - m0[e - S1] : T(0));
+      adm += (x.i2 < n ? d1 : T(0)) - (x.i2 > 0 ? b1[e - N1] - m1[e - N1] : T(0));
+      adm += (x.i3 < n ? d2 : T(0)) - (x.i3 > 0 ? b2[e - 1] - m2[e - 1] : T(0));
+      const T dp = pn - pc;
+      v[0] += (double)(d0 * d0) + (double)(d1 * d1) + (double)(d2 * d2);
+      v[1] += (double)(dp * dp);
+      v[2] += (double)(dp * (adm * ih));
+    }
+  }
+  if constexpr (CHECK) block_out_(v, part);
+}
+
+// ---------------------------------------------------------------------------
+// evaluation sums: q0 sum ||m||_p, q1 sum phi rho, q2 sum (A m - rho)^2,
+// q3 sum rho^2, q4 sum (||grad(-phi)||_q - 1)_+^2, q5 max ||grad phi||_q,
+// q6 sum phi
+// ---------------------------------------------------------------------------
+template <typename T, int METRIC>
+__global__ __launch_bounds__(NT) void k3_eval(int n, const T* __restrict__ m0, const T* __restrict__ m1,
+                                              const T* __restrict__ m2, const T* __restrict__ phi,
+                                              const T* __restrict__ rho, double* __restrict__ part) {
+  const int N1 = n + 1;
+  const long long S1 = (long long)N1 * N1, N = S1 * N1;
+  const double ih = (double)n;
+  double v[NQ3] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, N1);
+    const double a = (double)m0[e], b = (double)m1[e], c = (double)m2[e];
+    const double pc = (double)phi[e], rr = (double)rho[e];
+    const double g0 = x.i1 < n ? ((double)phi[e + S1] - pc) * ih : 0.0;
+    const double g1 = x.i2 < n ? ((double)phi[e + N1] - pc) * ih : 0.0;
+    const double g2 = x.i3 < n ? ((double)phi[e + 1] - pc) * ih : 0.0;
+    double dv = (x.i1 < n ? a : 0.0) - (x.i1 > 0 ? (double)m0[e - S1] : 0.0);
+    dv += (x.i2 < n ? b : 0.0) - (x.i2 > 0 ? (double)m1[e - N1] : 0.0);
+    dv += (x.i3 < n ? c : 0.0) - (x.i3 > 0 ? (double)m2[e - 1] : 0.0);
+    const double r = dv * ih - rr;
+    const double gq = norm_q3_<double, METRIC>(g0, g1, g2);
+    const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
+    v[0] += norm_p3_<double, METRIC>(a, b, c);
+    v[1] += pc * rr;
+    v[2] += r * r;
+    v[3] += rr * rr;
+    v[4] += ex * ex;
+    v[5] = gq > v[5] ? gq : v[5];
+    v[6] += pc;
+  }
+  block_out_(v, part);
+}
+
+// sums the nb block partials (compensated; q5 a max) into out[0..NQ3)
+__global__ __launch_bounds__(NT) void k3_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sh[NQ3][NT];
+  for (int q = 0; q < NQ3; ++q) {
+    double s = 0.0, comp = 0.0, mx = -INFINITY;
+    for (int i = threadIdx.x; i < nb; i += NT) {
+      const double x = part[(size_t)i * NQ3 + q];
+      const double t = s + x;
+      comp += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+      s = t;
+      mx = x > mx ? x : mx;
+    }
+    sh[q][threadIdx.x] = q == 5 ? mx : s + comp;
+  }
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < NQ3; ++q) {
+        const double a = sh[q][threadIdx.x], b = sh[q][threadIdx.x + w];
+        sh[q][threadIdx.x] = q == 5 ? (a > b ? a : b) : a + b;
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < NQ3) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
+// density pyramid (FP64): input checks, scaling, restriction, rho
+// ---------------------------------------------------------------------------
+// q0 sum p0, q1 sum p1, q2 count of negative or non-finite masses
+__global__ __launch_bounds__(NT) void k3_mass(long long N, const double* __restrict__ p0,
+                                              const double* __restrict__ p1, double* __restrict__ part) {
+  double v[NQ3] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const double a = p0[e], b = p1[e];
+    v[0] += a;
+    v[1] += b;
+    v[2] += (isfinite(a) && isfinite(b) && a >= 0.0 && b >= 0.0) ? 0.0 : 1.0;
+  }
+  block_out_(v, part);
+}
+
+__global__ __launch_bounds__(NT) void k3_scale2(long long N, double* __restrict__ x, double sx,
+                                                double* __restrict__ y, double sy) {
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    x[e] *= sx;
+    y[e] *= sy;
+  }
+}
+
+// coarse = D^-1 P^T fine per axis (the potential interpolation's weights
+// 1 at the coinciding fine node and 1/2 at its two neighbours, divided by
+// their sum), for both densities
+__global__ __launch_bounds__(NT) void k3_restrict(int nc, const double* __restrict__ f0,
+                                                  const double* __restrict__ f1, double* __restrict__ c0,
+                                                  double* __restrict__ c1) {
+  const int C1 = nc + 1, nf = 2 * nc, F1 = nf + 1;
+  const long long N = (long long)C1 * C1 * C1;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, C1);
+    const int c[3] = {x.i1, x.i2, x.i3};
+    double wsum[3];
+    for (int a = 0; a < 3; ++a) wsum[a] = 1.0 + (c[a] > 0 ? 0.5 : 0.0) + (c[a] < nc ? 0.5 : 0.0);
+    double s0 = 0.0, s1 = 0.0;
+    for (int d1 = -1; d1 <= 1; ++d1) {
+      const int I1 = 2 * c[0] + d1;
+      if (I1 < 0 || I1 > nf) continue;
+      const double w1 = d1 == 0 ? 1.0 : 0.5;
+      for (int d2 = -1; d2 <= 1; ++d2) {
+        const int I2 = 2 * c[1] + d2;
+        if (I2 < 0 || I2 > nf) continue;
+        const double w2 = w1 * (d2 == 0 ? 1.0 : 0.5);
+        for (int d3 = -1; d3 <= 1; ++d3) {
+          const int I3 = 2 * c[2] + d3;
+          if (I3 < 0 || I3 > nf) continue;
+          const double w = w2 * (d3 == 0 ? 1.0 : 0.5);
+          const long long f = ((long long)I1 * F1 + I2) * F1 + I3;
+          s0 += w * f0[f];
+          s1 += w * f1[f];
+        }
+      }
+    }
+    const double dn = wsum[0] * wsum[1] * wsum[2];
+    c0[e] = s0 / dn;
+    c1[e] = s1 / dn;
+  }
+}
+
+// q0 sum (r0 - r1)
+__global__ __launch_bounds__(NT) void k3_diffsum(long long N, const double* __restrict__ r0,
+                                                 const double* __restrict__ r1, double* __restrict__ part) {
+  double v[NQ3] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT)
+    v[0] += r0[e] - r1[e];
+  block_out_(v, part);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k3_rho(long long N, const double* __restrict__ r0,
+                                             const double* __restrict__ r1, double mean, T* __restrict__ rho) {
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT)
+    rho[e] = (T)((r0[e] - r1[e]) - mean);
+}
+
+// ---------------------------------------------------------------------------
+// prolongation (Sec. 3.3): potential linear along every axis; flux
+// component a nearest-neighbour along axis a (coarse index floor(I/2), the
+// coarse edge containing the fine one) and linear across, 0 on the last
+// fine node of axis a
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k3_prolong(int nc, int comp, const T* __restrict__ c, T* __restrict__ f) {
+  const int C1 = nc + 1, nf = 2 * nc, F1 = nf + 1;
+  const long long N = (long long)F1 * F1 * F1;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, F1);
+    const int I[3] = {x.i1, x.i2, x.i3};
+    if (comp >= 0 && I[comp] == nf) {
+      f[e] = T(0);
+      continue;
+    }
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      if (a == comp || (I[a] & 1) == 0) {
+        lo[a] = hi[a] = I[a] >> 1;
+      } else {
+        lo[a] = (I[a] - 1) >> 1;
+        hi[a] = (I[a] + 1) >> 1;
+      }
+    }
+    // mean over the (at most 8) coarse nodes of the product neighbourhood
+    double s = 0.0;
+    int cnt = 0;
+    for (int j1 = lo[0]; j1 <= hi[0]; ++j1)
+      for (int j2 = lo[1]; j2 <= hi[1]; ++j2)
+        for (int j3 = lo[2]; j3 <= hi[2]; ++j3) {
+          s += (double)c[((long long)j1 * C1 + j2) * C1 + j3];
+          ++cnt;
+        }
+    f[e] = (T)(s / cnt);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k3_export(long long N, const T* __restrict__ m0, const T* __restrict__ m1,
+                                                const T* __restrict__ m2, const T* __restrict__ phi, double mean,
+                                                double* __restrict__ om, double* __restrict__ opsi) {
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    if (om) {
+      om[e] = (double)m0[e];
+      om[N + e] = (double)m1[e];
+      om[2 * N + e] = (double)m2[e];
+    }
+    if (opsi) opsi[e] = -((double)phi[e] - mean);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+inline int blocks_for(long long N) {
+  const long long b = (N + NT - 1) / NT;
+  return (int)(b < MAXB ? (b > 0 ? b : 1) : MAXB);
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+template <typename T>
+struct Level {
+  int n = 0;
+  long long N = 0;
+  T *m[3] = {}, *b[3] = {}, *phi = nullptr, *rho = nullptr;
+  double *r0 = nullptr, *r1 = nullptr;
+};
+
+template <typename T>
+int launch_steps(hipStream_t s, const Level<T>& L, int metric, T mu, T tau, int steps, bool check_last,
+                 double* part) {
+  const int nb = blocks_for(L.N);
+  const T ih = (T)L.n;
+  for (int k = 0; k < steps; ++k) {
+    switch (metric) {
+      case 1: k3_flux<T, 1><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu); break;
+      case 2: k3_flux<T, 2><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu); break;
+      default: k3_flux<T, 3><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu);
+    }
+    if (check_last && k == steps - 1)
+      k3_pot<T, true><<<nb, NT, 0, s>>>(L.n, L.b[0], L.b[1], L.b[2], L.m[0], L.m[1], L.m[2], L.phi, L.rho, ih, tau,
+                                        part);
+    else
+      k3_pot<T, false><<<nb, NT, 0, s>>>(L.n, L.b[0], L.b[1], L.b[2], L.m[0], L.m[1], L.m[2], L.phi, L.rho, ih,
+                                         tau, part);
+  }
+  CHK(hipGetLastError());
+  return W1_OK;
+}
+
+// final sums of `nb` partials, copied to host `out`
+inline int finish_sums(hipStream_t s, const double* part, int nb, double* dout, double* out) {
+  k3_final<<<1, NT, 0, s>>>(part, nb, dout);
+  CHK(hipGetLastError());
+  CHK(hipMemcpyAsync(out, dout, NQ3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  CHK(hipStreamSynchronize(s));
+  return W1_OK;
+}
+
+template <typename T>
+int eval_level(hipStream_t s, const Level<T>& L, int metric, double* part, double* dout, double* out) {
+  const int nb = blocks_for(L.N);
+  switch (metric) {
+    case 1: k3_eval<T, 1><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part); break;
+    case 2: k3_eval<T, 2><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part); break;
+    default: k3_eval<T, 3><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part);
+  }
+  CHK(hipGetLastError());
+  return finish_sums(s, part, nb, dout, out);
+}
+
+// P, D, lo, kkt from the evaluation sums of a level of side n
+struct Eval {
+  double P, D, lo, kkt, mean;
+};
+inline Eval eval_of(const double* q, int n) {
+  const double h3 = 1.0 / ((double)n * n * n);
+  const double N = (double)(n + 1) * (n + 1) * (n + 1);
+  Eval e;
+  e.P = q[0] * h3;
+  e.D = -q[1] * h3;
+  const double rp = std::sqrt(q[2] * h3) / std::fmax(std::sqrt(q[3] * h3), 1e-300);
+  const double rd = std::sqrt(q[4] * h3);
+  const double gap = std::fabs(e.P - e.D) / std::fmax(std::fmax(std::fabs(e.P), std::fabs(e.D)), 1e-300);
+  e.kkt = std::fmax(rp, std::fmax(rd, gap));
+  e.lo = e.D / (q[5] > 1.0 ? q[5] : 1.0);
+  e.mean = q[6] / N;
+  return e;
+}
+
+inline double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+int solve(const w1_params& prm, const double* p0, const double* p1, int on_device, w1_result* out, double* m_out,
+          double* psi_out, hipStream_t s) {
+  const double t0 = now_s();
+  const int L = prm.levels;
+  std::vector<Level<T>> lv(L);
+  size_t bytes = 0;
+  for (int l = 0; l < L; ++l) {
+    lv[l].n = prm.n >> (L - 1 - l);
+    lv[l].N = (long long)(lv[l].n + 1) * (lv[l].n + 1) * (lv[l].n + 1);
+    bytes += (size_t)lv[l].N * (8 * sizeof(T) + 2 * sizeof(double)) + 16 * 256;
+  }
+  bytes += (size_t)MAXB * NQ3 * sizeof(double) + 256 + NQ3 * sizeof(double) + 256;
+  DevBuf mem;
+  CHK(hipMalloc(&mem.p, bytes));
+  char* p = (char*)mem.p;
+  auto take = [&](size_t b) {
+    char* r = p;
+    p += (b + 255) / 256 * 256;
+    return r;
+  };
+  for (int l = 0; l < L; ++l) {
+    const size_t pe = (size_t)lv[l].N;
+    for (int a = 0; a < 3; ++a) lv[l].m[a] = (T*)take(pe * sizeof(T));
+    for (int a = 0; a < 3; ++a) lv[l].b[a] = (T*)take(pe * sizeof(T));
+    lv[l].phi = (T*)take(pe * sizeof(T));
+    lv[l].rho = (T*)take(pe * sizeof(T));
+    lv[l].r0 = (double*)take(pe * 8);
+    lv[l].r1 = (double*)take(pe * 8);
+  }
+  double* part = (double*)take((size_t)MAXB * NQ3 * sizeof(double));
+  double* dout = (double*)take(NQ3 * sizeof(double));
+  double q[NQ3];
+
+  // input masses -> finest r0, r1; checks (Sec. 2.2 samples the densities on
+  // the nodes; both renormalised to unit mass)
+  Level<T>& F = lv[L - 1];
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  CHK(hipMemcpyAsync(F.r0, p0, (size_t)F.N * 8, kind, s));
+  CHK(hipMemcpyAsync(F.r1, p1, (size_t)F.N * 8, kind, s));
+  {
+    const int nb = blocks_for(F.N);
+    k3_mass<<<nb, NT, 0, s>>>(F.N, F.r0, F.r1, part);
+    CHK(hipGetLastError());
+    int st = finish_sums(s, part, nb, dout, q);
+    if (st) return st;
+    if (q[2] > 0 || !(q[0] > 0) || !(std::fabs(q[0] - q[1]) <= 1e-9 * q[0])) return W1_EINVAL;
+    const double h3 = 1.0 / ((double)F.n * F.n * F.n);
+    k3_scale2<<<nb, NT, 0, s>>>(F.N, F.r0, 1.0 / (q[0] * h3), F.r1, 1.0 / (q[1] * h3));
+    CHK(hipGetLastError());
+  }
+  // coarse densities: D^-1 P^T per axis, each renormalised to unit mass (R6)
+  for (int l = L - 2; l >= 0; --l) {
+    const int nb = blocks_for(lv[l].N);
+    k3_restrict<<<nb, NT, 0, s>>>(lv[l].n, lv[l + 1].r0, lv[l + 1].r1, lv[l].r0, lv[l].r1);
+    k3_mass<<<nb, NT, 0, s>>>(lv[l].N, lv[l].r0, lv[l].r1, part);
+    CHK(hipGetLastError());
+    int st = finish_sums(s, part, nb, dout, q);
+    if (st) return st;
+    const double h3 = 1.0 / ((double)lv[l].n * lv[l].n * lv[l].n);
+    k3_scale2<<<nb, NT, 0, s>>>(lv[l].N, lv[l].r0, 1.0 / (q[0] * h3), lv[l].r1, 1.0 / (q[1] * h3));
+    CHK(hipGetLastError());
+  }
+  for (int l = 0; l < L; ++l) {
+    const int nb = blocks_for(lv[l].N);
+    k3_diffsum<<<nb, NT, 0, s>>>(lv[l].N, lv[l].r0, lv[l].r1, part);
+    CHK(hipGetLastError());
+    int st = finish_sums(s, part, nb, dout, q);
+    if (st) return st;
+    k3_rho<T><<<nb, NT, 0, s>>>(lv[l].N, lv[l].r0, lv[l].r1, q[0] / (double)lv[l].N, lv[l].rho);
+    CHK(hipGetLastError());
+  }
+
+  *out = w1_result{};
+  for (int l = 0; l < W1_MAX_LEVELS; ++l) out->level_w1[l] = std::numeric_limits<double>::quiet_NaN();
+  out->status = W1_SOLVE_OK;
+  const double sc = prm.step_scale > 0 ? prm.step_scale : 0.5;
+  const int ce = prm.check_every;
+  for (int l = 0; l < L; ++l) {
+    Level<T>& V = lv[l];
+    const int nb = blocks_for(V.N);
+    if (l == 0) {
+      for (int a = 0; a < 3; ++a) CHK(hipMemsetAsync(V.m[a], 0, (size_t)V.N * sizeof(T), s));
+      CHK(hipMemsetAsync(V.phi, 0, (size_t)V.N * sizeof(T), s));
+    } else {
+      const Level<T>& C = lv[l - 1];
+      const int fb = blocks_for(V.N);
+      for (int a = 0; a < 3; ++a) k3_prolong<T><<<fb, NT, 0, s>>>(C.n, a, C.m[a], V.m[a]);
+      k3_prolong<T><<<fb, NT, 0, s>>>(C.n, -1, C.phi, V.phi);
+      CHK(hipGetLastError());
+    }
+    // R4 with d = 3: mu = tau = scale / ||A||, ||A|| <= 2 sqrt(3) / h
+    const double mu = sc / (2.0 * std::sqrt(3.0) * V.n);
+    const double tol = prm.tol * std::pow(2.0, (double)(L - 1 - l) * prm.alpha);
+    int k = 0;
+    double meas = 0;
+    for (;;) {
+      const int steps = std::min(ce, prm.max_iters - k);
+      const bool fpr = prm.stop_rule == W1_STOP_FPR;
+      int st = launch_steps<T>(s, V, prm.metric, (T)mu, (T)mu, steps, fpr, part);
+      if (st) return st;
+      k += steps;
+      if (fpr) {
+        st = finish_sums(s, part, nb, dout, q);
+        if (st) return st;
+        const double h3 = 1.0 / ((double)V.n * V.n * V.n);
+        meas = (q[0] / mu + q[1] / mu - 2.0 * q[2]) * h3;
+      } else {
+        st = eval_level<T>(s, V, prm.metric, part, dout, q);
+        if (st) return st;
+        meas = eval_of(q, V.n).kkt;
+      }
+      if (!std::isfinite(meas)) {
+        out->status = W1_SOLVE_DIVERGED;
+        break;
+      }
+      if (meas <= tol) break;
+      if (k >= prm.max_iters) {
+        out->status = W1_SOLVE_MAXITER;
+        break;
+      }
+    }
+    out->iters[l] = k;
+    out->measure[l] = meas;
+    out->levels_run = l + 1;
+    int st = eval_level<T>(s, V, prm.metric, part, dout, q);
+    if (st) return st;
+    out->level_w1[l] = eval_of(q, V.n).P;
+    out->level_seconds[l] = now_s() - t0;
+    if (out->status == W1_SOLVE_DIVERGED) break;
+  }
+  const Level<T>& V = lv[out->levels_run - 1];
+  int st = eval_level<T>(s, V, prm.metric, part, dout, q);
+  if (st) return st;
+  const Eval ev = eval_of(q, V.n);
+  out->w1 = ev.P;
+  out->dual = ev.D;
+  out->lo = ev.lo;
+  out->hi = std::numeric_limits<double>::quiet_NaN();
+  out->kkt = ev.kkt;
+  if ((m_out || psi_out) && out->levels_run == L) {
+    DevBuf ex;
+    const size_t need = (m_out ? 3 : 0) * (size_t)V.N * 8 + (psi_out ? (size_t)V.N * 8 : 0);
+    CHK(hipMalloc(&ex.p, need));
+    double* om = m_out ? (double*)ex.p : nullptr;
+    double* op = psi_out ? (double*)ex.p + (m_out ? 3 * V.N : 0) : nullptr;
+    k3_export<T><<<blocks_for(V.N), NT, 0, s>>>(V.N, V.m[0], V.m[1], V.m[2], V.phi, ev.mean, om, op);
+    CHK(hipGetLastError());
+    if (m_out) CHK(hipMemcpyAsync(m_out, om, 3 * (size_t)V.N * 8, hipMemcpyDeviceToHost, s));
+    if (psi_out) CHK(hipMemcpyAsync(psi_out, op, (size_t)V.N * 8, hipMemcpyDeviceToHost, s));
+    CHK(hipStreamSynchronize(s));
+  }
+  out->seconds = now_s() - t0;
+  return W1_OK;
+}
+
+template <typename T>
+int plain_steps(int n, int metric, double scale, int steps, void* m1, void* m2, void* m3, void* phi,
+                const void* rho, double* fpr_out, hipStream_t s) {
+  Level<T> V;
+  V.n = n;
+  V.N = (long long)(n + 1) * (n + 1) * (n + 1);
+  V.m[0] = (T*)m1;
+  V.m[1] = (T*)m2;
+  V.m[2] = (T*)m3;
+  V.phi = (T*)phi;
+  V.rho = (T*)rho;
+  DevBuf mem;
+  const size_t pe = ((size_t)V.N * sizeof(T) + 255) / 256 * 256;
+  CHK(hipMalloc(&mem.p, 3 * pe + (size_t)MAXB * NQ3 * 8 + 256 + NQ3 * 8));
+  char* p = (char*)mem.p;
+  for (int a = 0; a < 3; ++a) V.b[a] = (T*)(p + a * pe);
+  double* part = (double*)(p + 3 * pe);
+  double* dout = part + (size_t)MAXB * NQ3 + 32;
+  const double mu = (scale > 0 ? scale : 0.5) / (2.0 * std::sqrt(3.0) * n);
+  int st = launch_steps<T>(s, V, metric, (T)mu, (T)mu, steps, fpr_out != nullptr, part);
+  if (st) return st;
+  if (fpr_out) {
+    double q[NQ3];
+    st = finish_sums(s, part, blocks_for(V.N), dout, q);
+    if (st) return st;
+    *fpr_out = (q[0] / mu + q[1] / mu - 2.0 * q[2]) / ((double)n * n * n);
+  } else {
+    CHK(hipStreamSynchronize(s));
+  }
+  return W1_OK;
+}
+
+}  // namespace cube
+}  // namespace w1
+
+using namespace w1;
+
+extern "C" int w1_solve3d(const w1_params* p, const double* p0, const double* p1, int32_t on_device,
+                          w1_result* out, double* m_out, double* psi_out, void* hip_stream) {
+  if (!p || !p0 || !p1 || !out) return W1_EINVAL;
+  if (p->n < 2 || p->n > 1024 || p->levels < 1 || p->levels > W1_MAX_LEVELS) return W1_EINVAL;
+  if (p->n % (1 << (p->levels - 1)) != 0 || (p->n >> (p->levels - 1)) < 2) return W1_EINVAL;
+  if (p->metric < W1_METRIC_L1 || p->metric > W1_METRIC_LINF || p->algo != W1_ALGO_PLAIN) return W1_EINVAL;
+  if (p->precision != W1_FP32 && p->precision != W1_FP64) return W1_EINVAL;
+  if (p->stop_rule != W1_STOP_KKT && p->stop_rule != W1_STOP_FPR) return W1_EINVAL;
+  if (!(p->tol > 0) || !std::isfinite(p->tol) || !std::isfinite(p->alpha)) return W1_EINVAL;
+  if (!std::isfinite(p->step_scale) || p->step_scale > 1.0) return W1_EINVAL;
+  if (p->max_iters < 1 || p->check_every < 1 || p->max_iters % p->check_every != 0) return W1_EINVAL;
+  hipStream_t s = (hipStream_t)hip_stream;
+  return p->precision == W1_FP32 ? cube::solve<float>(*p, p0, p1, on_device, out, m_out, psi_out, s)
+                                 : cube::solve<double>(*p, p0, p1, on_device, out, m_out, psi_out, s);
+}
+
+extern "C" int w1_op_plain_steps3d(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,
+                                   void* m1, void* m2, void* m3, void* phi, const void* rho, double* fpr_out,
+                                   void* hip_stream) {
+  if (n < 1 || n > 1024 || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF) return W1_EINVAL;
+  if (!m1 || !m2 || !m3 || !phi || !rho || !(step_scale <= 1.0)) return W1_EINVAL;
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (precision == W1_FP32) return cube::plain_steps<float>(n, metric, step_scale, steps, m1, m2, m3, phi, rho, fpr_out, s);
+  if (precision == W1_FP64) return cube::plain_steps<double>(n, metric, step_scale, steps, m1, m2, m3, phi, rho, fpr_out, s);
+  return W1_EINVAL;
+}

@@ -1,0 +1,138 @@
+"""GPU parity of the d = 3 path (w1_op_plain_steps3d, w1_solve3d) against the
+d-general FP64 oracle on identical seeded inputs: single steps, the cascade
+under both stop rules, the exported fields, argument errors, and a 65^3
+case against the FP64 GPU path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle.w1_oracle3d as o3
+import w1data
+from tests.gpu_util import P_OF, dev, host, rel_err, require_gpu, tdtype
+
+pytestmark = pytest.mark.gpu
+
+FP32, FP64 = 1, 2
+
+
+def _state(n, seed):
+    rng = np.random.default_rng(seed)
+    m = [rng.standard_normal((n + 1,) * 3) for _ in range(3)]
+    for a in range(3):
+        idx = [slice(None)] * 3
+        idx[a] = -1
+        m[a][tuple(idx)] = 0.0
+    return m, rng.standard_normal((n + 1,) * 3) * 0.1
+
+
+def _rho(n, seed):
+    p0, p1 = w1data.random_pair_nd(n, 3, seed=seed)
+    return o3.prepare_levels(p0, p1, n, 1)[0]
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [5, 17, 40])
+@pytest.mark.parametrize("metric", [1, 2, 3])
+def test_plain_steps_trajectory_3d(precision, n, metric):
+    w1 = require_gpu()
+    h = 1.0 / n
+    rho = _rho(n, n)
+    m, phi = _state(n, n + 1)
+    mu, tau = o3.plain_step_sizes(h, 3)
+    dt = tdtype(precision)
+    g = [dev(x, dt) for x in (*m, phi, rho)]
+    k = 12
+    R = w1.op_plain_steps3d(n, metric, precision, k, *g, fpr=True)
+    mm, pp = tuple(m), phi
+    for _ in range(k):
+        mm, pp, Rw = o3.pd_step(mm, pp, rho, h, mu, tau, P_OF[metric])
+    tol = 1e-12 if precision == FP64 else 2e-5 * math.sqrt(k)
+    for got, want in zip(g[:4], (*mm, pp)):
+        assert rel_err(host(got), want) <= tol
+    assert R == pytest.approx(Rw, rel=1e-9 if precision == FP64 else 1e-3)
+
+
+def _oracle(p0, p1, n, L, metric, rule, tol, cap, ce):
+    return o3.solve_plain(p0, p1, n, L=L, p=P_OF[metric], stop="fpr" if rule == 2 else "kkt", tol=tol,
+                          alpha=-1.0, max_iters=cap, check_every=ce)
+
+
+@pytest.mark.parametrize("metric", [1, 2, 3])
+@pytest.mark.parametrize("rule", [2, 1])
+def test_cascade_fp64_follows_the_oracle(metric, rule):
+    w1 = require_gpu()
+    n, L = 16, 2
+    p0, p1 = w1data.pair_gauss_3d(0, n=n)
+    tol = 2e-6 if rule == 2 else 1e-3
+    prm = w1.params(n=n, levels=L, metric=metric, algo=w1.ALGO_PLAIN, precision=FP64, stop_rule=rule, tol=tol,
+                    alpha=-1.0, max_iters=20000, check_every=10)
+    res, m, psi = w1.solve3d(prm, p0, p1, fields=True)
+    ref = _oracle(p0, p1, n, L, metric, rule, tol, 20000, 10)
+    assert res["iters"] == ref["iters"]
+    assert res["w1"] == pytest.approx(ref["w1"], rel=1e-9)
+    np.testing.assert_allclose(res["level_w1"], ref["level_w1"], rtol=1e-9)
+    assert res["lo"] == pytest.approx(ref["lo"], rel=1e-9)
+    assert res["dual"] == pytest.approx(-o3.inner_h(ref["phi"], ref["rho"], 1.0 / n), rel=1e-9, abs=1e-12)
+    assert math.isnan(res["hi"]) and ref["lo"] <= ref["hi"] * (1 + 1e-9)
+    for a in range(3):
+        assert rel_err(m[a], ref["m"][a]) <= 1e-9
+    assert rel_err(psi, -(ref["phi"] - ref["phi"].mean())) <= 1e-9
+    kkt, _, _ = o3.kkt_plain(tuple(m), -psi, ref["rho"], 1.0 / n, P_OF[metric])
+    assert res["kkt"] == pytest.approx(kkt, rel=1e-6)
+
+
+@pytest.mark.parametrize("metric", [1, 2, 3])
+def test_cascade_fp32_at_equal_iteration_counts(metric):
+    """FP32 decides the stop tests on rounded iterates; with the KKT rule at a
+    tolerance no level reaches, both sides run every level to the same cap
+    and the level values are compared there."""
+    w1 = require_gpu()
+    n, L = 24, 3
+    p0, p1 = w1data.pair_gauss_3d(1, n=n)
+    prm = w1.params(n=n, levels=L, metric=metric, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_KKT,
+                    tol=1e-300, alpha=0.0, max_iters=300, check_every=10)
+    res = w1.solve3d(prm, p0, p1)
+    ref = _oracle(p0, p1, n, L, metric, 1, 1e-300, 300, 10)
+    assert res["iters"] == ref["iters"] == [300] * L
+    np.testing.assert_allclose(res["level_w1"], ref["level_w1"], rtol=2e-5)
+    assert res["lo"] == pytest.approx(ref["lo"], rel=1e-3)
+
+
+def test_errors_3d():
+    w1 = require_gpu()
+    n = 8
+    p0, p1 = w1data.random_pair_nd(n, 3, seed=2)
+    base = dict(n=n, levels=2, metric=2, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_FPR, tol=1e-6,
+                max_iters=100, check_every=10)
+    for bad in (dict(algo=w1.ALGO_PROX), dict(tol=0.0), dict(levels=4), dict(metric=4), dict(step_scale=1.5)):
+        prm = w1.params(**dict(base, **bad))
+        with pytest.raises(w1.W1Error):
+            w1.solve3d(prm, p0, p1)
+    neg = p0.copy()
+    neg[0, 0, 0] = -1e-3
+    with pytest.raises(w1.W1Error):
+        w1.solve3d(w1.params(**base), neg, p1)
+    with pytest.raises(w1.W1Error):
+        w1.solve3d(w1.params(**base), p0, p1 * 1.01)
+
+
+def test_cube65_fp32_against_fp64():
+    """65^3 nodes, 3 levels (17^3, 33^3, 65^3), paper-style FPR rule: the
+    FP32 result within 1e-4 of the FP64 GPU result, the lower bound below
+    both, masses on the device."""
+    w1 = require_gpu()
+    import torch
+    n, L = 64, 3
+    p0, p1 = w1data.pair_gauss_3d(2, n=n)
+    d0, d1 = torch.from_numpy(p0).cuda(), torch.from_numpy(p1).cuda()
+    out = {}
+    for prec in (FP32, FP64):
+        prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PLAIN, precision=prec, stop_rule=w1.STOP_FPR,
+                        tol=1e-7, alpha=-1.0, max_iters=20000, check_every=10)
+        out[prec] = w1.solve3d(prm, d0, d1)
+    a, b = out[FP32], out[FP64]
+    assert a["status"] in (0, 1) and b["status"] in (0, 1)
+    assert a["w1"] == pytest.approx(b["w1"], rel=1e-4)
+    assert a["lo"] <= a["w1"] * (1 + 1e-6) and b["lo"] <= b["w1"] * (1 + 1e-6)
+    assert all(x > 0 for x in a["iters"])
