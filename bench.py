@@ -19,6 +19,7 @@ on this host's cores on a bounded sample.
     python bench.py --workload served   # Poisson arrivals, n in {128..2048}
     python bench.py --workload single   # one 512-grid pair, both algorithms
     python bench.py --workload tolerance  # the tolerance-rule / level-count study
+    python bench.py --workload cube     # d = 3, one 129^3 pair
 
 Each workload prints one JSON line of the same layout.
 """
@@ -435,6 +436,71 @@ def run_tolerance(args, w1):
             "study": study}
 
 
+def run_cube(args, w1):
+    """d = 3 (the method for general d, Sec. 2.2 / 3.3): one pair of
+    isotropic Gaussian mixtures on the unit cube at n = 128 (129^3 nodes),
+    3 levels (33^3, 65^3, 129^3), l_2 metric, Algorithm 3, FPR rule with
+    eps_L = 1e-7 and alpha = -1, FP32 iterates; against the same solve in
+    FP64 on the GPU, and the FP64 oracle's node-update rate on this host."""
+    import torch
+    import w1data
+    n, L = 128, 3
+    p0, p1 = w1data.pair_gauss_3d(0, n=n)
+    d0, d1 = torch.from_numpy(p0).cuda(), torch.from_numpy(p1).cuda()
+    out = {}
+    for prec, name in ((w1.FP32, "f32"), (w1.FP64, "f64")):
+        prm = w1.params(n=n, levels=L, metric=w1.METRIC_L2, algo=w1.ALGO_PLAIN, precision=prec,
+                        stop_rule=w1.STOP_FPR, tol=1e-7, alpha=-1.0, max_iters=20000, check_every=10)
+        w1.solve3d(prm, d0, d1)
+        torch.cuda.synchronize()
+        reps = max(1, args.steps) if prec == w1.FP32 else 1
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = w1.solve3d(prm, d0, d1)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        out[name] = {"seconds": dt, "w1": r["w1"], "iters": r["iters"], "lo": r["lo"], "kkt": r["kkt"]}
+        log(f"[bench] cube {name}: {dt*1e3:.1f} ms W1 {r['w1']:.7f} iters {r['iters']}")
+    sides = [n >> (L - 1 - l) for l in range(L)]
+    nodes = [(s_ + 1) ** 3 for s_ in sides]
+    upd = sum(k * nd for k, nd in zip(out["f32"]["iters"], nodes))
+    sec = out["f32"]["seconds"]
+    cups = upd / sec
+    # 9 words per node update: read m1, m2, m3, phi, rho; write m1, m2, m3, phi
+    alg = 36.0
+    roof = {"kernel": "k3_flux + k3_pot (whole solve, wall time)", "bound": "hbm", "achieved": cups * alg / 1e9,
+            "peak": 8000.0, "unit": "GB/s", "frac": cups * alg / 8e12, "traffic": None,
+            "alg_bytes_per_node_update": alg}
+    cpu = None
+    if not args.no_cpu:
+        os.environ.setdefault("OMP_NUM_THREADS", "1")
+        import oracle.w1_oracle3d as o3
+        rho = o3.prepare_levels(p0, p1, n, 1)[0]
+        h = 1.0 / n
+        mu, tau = o3.plain_step_sizes(h, 3)
+        m = tuple(np.zeros((n + 1,) * 3) for _ in range(3))
+        phi = np.zeros((n + 1,) * 3)
+        k, t = 0, time.perf_counter()
+        while time.perf_counter() - t < 15.0:
+            m, phi, _ = o3.pd_step(m, phi, rho, h, mu, tau, 2)
+            k += 1
+        dt = time.perf_counter() - t
+        rate = k * (n + 1) ** 3 / dt
+        cpu = {"value": rate / upd, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} iterations of eq. (primaldual) on the 129^3 level in {dt:.1f} s, scaled by the "
+                         "node updates of the GPU solve", "node_updates_per_s": rate}
+        log(f"[bench] cube CPU oracle: {rate:.3e} node updates/s")
+    rel = abs(out["f32"]["w1"] - out["f64"]["w1"]) / out["f64"]["w1"]
+    return {"metric": METRIC, "value": 1.0 / sec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": 1, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "d=3: one pair of 3-Gaussian mixtures on the unit cube, n=128 (129^3 nodes), "
+                                   "3 levels, L2 metric, Algorithm 3, FPR eps_L 1e-7 alpha -1, FP32"},
+            "cell_updates_per_s": cups, "fp64_single": {"solves_per_s": 1.0 / out["f64"]["seconds"],
+                                                        "speedup_fp32": out["f64"]["seconds"] / sec},
+            "accuracy": {"rel_w1_fp32_vs_fp64": rel}, "solves": out, "roofline": roof, "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,7 +514,8 @@ def main():
     ap.add_argument("--block-steps", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
-    ap.add_argument("--workload", default="uniform", choices=["uniform", "uneven", "served", "single", "tolerance"])
+    ap.add_argument("--workload", default="uniform",
+                    choices=["uniform", "uneven", "served", "single", "tolerance", "cube"])
     ap.add_argument("--ground", default="l2", choices=["l1", "l2", "linf"],
                     help="uniform: ground metric of the flux cost (the headline figure is l2)")
     ap.add_argument("--step-scale", type=float, default=0.0,
@@ -479,7 +546,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     if args.workload != "uniform":
         run = {"uneven": run_uneven, "served": run_served, "single": run_single,
-               "tolerance": run_tolerance}[args.workload]
+               "tolerance": run_tolerance, "cube": run_cube}[args.workload]
         print(json.dumps(run(args, w1)), flush=True)
         return
     n, L, P = args.n, args.levels, args.pairs

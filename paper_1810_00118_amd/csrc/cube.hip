@@ -35,6 +35,16 @@ constexpr int NT = 256;     // threads per block of every kernel here
 constexpr int NQ3 = 8;      // FP64 partial sums per block
 constexpr int MAXB = 2048;  // blocks of the node-parallel kernels (grid-stride)
 
+// stop-test state of the running level in device memory: the iteration
+// kernels of a block skip all work once `status` leaves G_RUN, so the host
+// queues several blocks of `check_every` iterations between reads
+enum { G_RUN = 0, G_CONV = 1, G_CAP = 2, G_DIVERGED = 3 };
+struct Gate {
+  int status;
+  int iters;
+  double measure;
+};
+
 #define CHK(x)                                      \
   do {                                              \
     hipError_t _e = (x);                            \
@@ -135,7 +145,9 @@ __device__ __forceinline__ void block_out_(double v[NQ3], double* part) {
 template <typename T, int METRIC>
 __global__ __launch_bounds__(NT) void k3_flux(int n, T* __restrict__ m0, T* __restrict__ m1, T* __restrict__ m2,
                                               T* __restrict__ b0, T* __restrict__ b1, T* __restrict__ b2,
-                                              const T* __restrict__ phi, T ih, T mu) {
+                                              const T* __restrict__ phi, T ih, T mu,
+                                              const int* __restrict__ gate) {
+  if (gate && *gate != G_RUN) return;
   const int N1 = n + 1;
   const long long S1 = (long long)N1 * N1, N = S1 * N1;
   for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
@@ -177,7 +189,8 @@ __global__ __launch_bounds__(NT) void k3_pot(int n, const T* __restrict__ b0, co
                                              const T* __restrict__ b2, const T* __restrict__ m0,
                                              const T* __restrict__ m1, const T* __restrict__ m2,
                                              T* __restrict__ phi, const T* __restrict__ rho, T ih, T tau,
-                                             double* __restrict__ part) {
+                                             double* __restrict__ part, const int* __restrict__ gate) {
+  if (gate && *gate != G_RUN) return;   // the same value for every thread of the launch
   const int N1 = n + 1;
   const long long S1 = (long long)N1 * N1, N = S1 * N1;
   double v[NQ3] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -210,7 +223,9 @@ __global__ __launch_bounds__(NT) void k3_pot(int n, const T* __restrict__ b0, co
 template <typename T, int METRIC>
 __global__ __launch_bounds__(NT) void k3_eval(int n, const T* __restrict__ m0, const T* __restrict__ m1,
                                               const T* __restrict__ m2, const T* __restrict__ phi,
-                                              const T* __restrict__ rho, double* __restrict__ part) {
+                                              const T* __restrict__ rho, double* __restrict__ part,
+                                              const int* __restrict__ gate) {
+  if (gate && *gate != G_RUN) return;
   const int N1 = n + 1;
   const long long S1 = (long long)N1 * N1, N = S1 * N1;
   const double ih = (double)n;
@@ -240,7 +255,46 @@ __global__ __launch_bounds__(NT) void k3_eval(int n, const T* __restrict__ m0, c
 }
 
 // sums the nb block partials (compensated; q5 a max) into out[0..NQ3)
+// (thread 0 also receives them in q0)
+__device__ __forceinline__ void final_sums_(const double* __restrict__ part, int nb, double* __restrict__ out,
+                                            double q0[NQ3]);
 __global__ __launch_bounds__(NT) void k3_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  double q[NQ3];
+  final_sums_(part, nb, out, q);
+}
+
+// the stop test of a block of `steps` iterations (one block of threads):
+// rule 2 R^k of eq. (pd_stop) from the potential half's sums, rule 1 the
+// normalised KKT residual from the evaluation sums (as the oracle defines
+// them); the level stops at meas <= tol, on a non-finite measure, or at
+// the cap
+__global__ __launch_bounds__(NT) void k3_check(const double* __restrict__ part, int nb, double* __restrict__ sums,
+                                               Gate* __restrict__ gate, int rule, double mu, double tau, int n,
+                                               double tol, int steps, int cap) {
+  if (gate->status != G_RUN) return;   // read by every thread before any write below
+  double q[NQ3];
+  final_sums_(part, nb, sums, q);
+  if (threadIdx.x == 0) {
+    const double h3 = 1.0 / ((double)n * n * n);
+    double meas;
+    if (rule == W1_STOP_FPR) {
+      meas = (q[0] / mu + q[1] / tau - 2.0 * q[2]) * h3;
+    } else {
+      const double P = q[0] * h3, D = -q[1] * h3;
+      const double rp = sqrt(q[2] * h3) / fmax(sqrt(q[3] * h3), 1e-300);
+      const double rd = sqrt(q[4] * h3);
+      const double gap = fabs(P - D) / fmax(fmax(fabs(P), fabs(D)), 1e-300);
+      meas = fmax(rp, fmax(rd, gap));
+    }
+    const int it = gate->iters + steps;
+    gate->iters = it;
+    gate->measure = meas;
+    gate->status = !isfinite(meas) ? G_DIVERGED : (meas <= tol ? G_CONV : (it >= cap ? G_CAP : G_RUN));
+  }
+}
+
+__device__ __forceinline__ void final_sums_(const double* __restrict__ part, int nb, double* __restrict__ out,
+                                            double q0[NQ3]) {
   __shared__ double sh[NQ3][NT];
   for (int q = 0; q < NQ3; ++q) {
     double s = 0.0, comp = 0.0, mx = -INFINITY;
@@ -263,6 +317,8 @@ __global__ __launch_bounds__(NT) void k3_final(const double* __restrict__ part, 
     __syncthreads();
   }
   if (threadIdx.x < NQ3) out[threadIdx.x] = sh[threadIdx.x][0];
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NQ3; ++q) q0[q] = sh[q][0];
 }
 
 // ---------------------------------------------------------------------------
@@ -421,21 +477,26 @@ struct Level {
 
 template <typename T>
 int launch_steps(hipStream_t s, const Level<T>& L, int metric, T mu, T tau, int steps, bool check_last,
-                 double* part) {
+                 double* part, const int* gate) {
   const int nb = blocks_for(L.N);
   const T ih = (T)L.n;
   for (int k = 0; k < steps; ++k) {
     switch (metric) {
-      case 1: k3_flux<T, 1><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu); break;
-      case 2: k3_flux<T, 2><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu); break;
-      default: k3_flux<T, 3><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu);
+      case 1:
+        k3_flux<T, 1><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu, gate);
+        break;
+      case 2:
+        k3_flux<T, 2><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu, gate);
+        break;
+      default:
+        k3_flux<T, 3><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.b[0], L.b[1], L.b[2], L.phi, ih, mu, gate);
     }
     if (check_last && k == steps - 1)
       k3_pot<T, true><<<nb, NT, 0, s>>>(L.n, L.b[0], L.b[1], L.b[2], L.m[0], L.m[1], L.m[2], L.phi, L.rho, ih, tau,
-                                        part);
+                                        part, gate);
     else
       k3_pot<T, false><<<nb, NT, 0, s>>>(L.n, L.b[0], L.b[1], L.b[2], L.m[0], L.m[1], L.m[2], L.phi, L.rho, ih,
-                                         tau, part);
+                                         tau, part, gate);
   }
   CHK(hipGetLastError());
   return W1_OK;
@@ -451,15 +512,22 @@ inline int finish_sums(hipStream_t s, const double* part, int nb, double* dout, 
 }
 
 template <typename T>
-int eval_level(hipStream_t s, const Level<T>& L, int metric, double* part, double* dout, double* out) {
+int eval_sums(hipStream_t s, const Level<T>& L, int metric, double* part, const int* gate) {
   const int nb = blocks_for(L.N);
   switch (metric) {
-    case 1: k3_eval<T, 1><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part); break;
-    case 2: k3_eval<T, 2><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part); break;
-    default: k3_eval<T, 3><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part);
+    case 1: k3_eval<T, 1><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part, gate); break;
+    case 2: k3_eval<T, 2><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part, gate); break;
+    default: k3_eval<T, 3><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part, gate);
   }
   CHK(hipGetLastError());
-  return finish_sums(s, part, nb, dout, out);
+  return W1_OK;
+}
+
+template <typename T>
+int eval_level(hipStream_t s, const Level<T>& L, int metric, double* part, double* dout, double* out) {
+  int st = eval_sums<T>(s, L, metric, part, nullptr);
+  if (st) return st;
+  return finish_sums(s, part, blocks_for(L.N), dout, out);
 }
 
 // P, D, lo, kkt from the evaluation sums of a level of side n
@@ -497,7 +565,7 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
     lv[l].N = (long long)(lv[l].n + 1) * (lv[l].n + 1) * (lv[l].n + 1);
     bytes += (size_t)lv[l].N * (8 * sizeof(T) + 2 * sizeof(double)) + 16 * 256;
   }
-  bytes += (size_t)MAXB * NQ3 * sizeof(double) + 256 + NQ3 * sizeof(double) + 256;
+  bytes += (size_t)MAXB * NQ3 * sizeof(double) + 256 + NQ3 * sizeof(double) + 256 + sizeof(Gate) + 256;
   DevBuf mem;
   CHK(hipMalloc(&mem.p, bytes));
   char* p = (char*)mem.p;
@@ -517,6 +585,7 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
   }
   double* part = (double*)take((size_t)MAXB * NQ3 * sizeof(double));
   double* dout = (double*)take(NQ3 * sizeof(double));
+  Gate* gate = (Gate*)take(sizeof(Gate));
   double q[NQ3];
 
   // input masses -> finest r0, r1; checks (Sec. 2.2 samples the densities on
@@ -579,36 +648,35 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
     // R4 with d = 3: mu = tau = scale / ||A||, ||A|| <= 2 sqrt(3) / h
     const double mu = sc / (2.0 * std::sqrt(3.0) * V.n);
     const double tol = prm.tol * std::pow(2.0, (double)(L - 1 - l) * prm.alpha);
-    int k = 0;
-    double meas = 0;
-    for (;;) {
-      const int steps = std::min(ce, prm.max_iters - k);
-      const bool fpr = prm.stop_rule == W1_STOP_FPR;
-      int st = launch_steps<T>(s, V, prm.metric, (T)mu, (T)mu, steps, fpr, part);
-      if (st) return st;
-      k += steps;
-      if (fpr) {
-        st = finish_sums(s, part, nb, dout, q);
+    // blocks of check_every iterations, each ending in the stop test on the
+    // device; the host reads the gate after 4, 8, ... 64 queued blocks (the
+    // blocks queued past the stop skip their work)
+    CHK(hipMemsetAsync(gate, 0, sizeof(Gate), s));
+    const bool fpr = prm.stop_rule == W1_STOP_FPR;
+    const int total = prm.max_iters / ce;
+    int queued = 0, burst = 4;
+    Gate g{G_RUN, 0, 0.0};
+    while (g.status == G_RUN && queued < total) {
+      const int B = std::min(burst, total - queued);
+      for (int b = 0; b < B; ++b) {
+        int st = launch_steps<T>(s, V, prm.metric, (T)mu, (T)mu, ce, fpr, part, &gate->status);
         if (st) return st;
-        const double h3 = 1.0 / ((double)V.n * V.n * V.n);
-        meas = (q[0] / mu + q[1] / mu - 2.0 * q[2]) * h3;
-      } else {
-        st = eval_level<T>(s, V, prm.metric, part, dout, q);
-        if (st) return st;
-        meas = eval_of(q, V.n).kkt;
+        if (!fpr) {
+          st = eval_sums<T>(s, V, prm.metric, part, &gate->status);
+          if (st) return st;
+        }
+        k3_check<<<1, NT, 0, s>>>(part, nb, dout, gate, prm.stop_rule, mu, mu, V.n, tol, ce, prm.max_iters);
+        CHK(hipGetLastError());
       }
-      if (!std::isfinite(meas)) {
-        out->status = W1_SOLVE_DIVERGED;
-        break;
-      }
-      if (meas <= tol) break;
-      if (k >= prm.max_iters) {
-        out->status = W1_SOLVE_MAXITER;
-        break;
-      }
+      queued += B;
+      burst = std::min(2 * burst, 64);
+      CHK(hipMemcpyAsync(&g, gate, sizeof(Gate), hipMemcpyDeviceToHost, s));
+      CHK(hipStreamSynchronize(s));
     }
-    out->iters[l] = k;
-    out->measure[l] = meas;
+    if (g.status == G_DIVERGED) out->status = W1_SOLVE_DIVERGED;
+    if (g.status == G_CAP) out->status = W1_SOLVE_MAXITER;
+    out->iters[l] = g.iters;
+    out->measure[l] = g.measure;
     out->levels_run = l + 1;
     int st = eval_level<T>(s, V, prm.metric, part, dout, q);
     if (st) return st;
@@ -660,7 +728,7 @@ int plain_steps(int n, int metric, double scale, int steps, void* m1, void* m2, 
   double* part = (double*)(p + 3 * pe);
   double* dout = part + (size_t)MAXB * NQ3 + 32;
   const double mu = (scale > 0 ? scale : 0.5) / (2.0 * std::sqrt(3.0) * n);
-  int st = launch_steps<T>(s, V, metric, (T)mu, (T)mu, steps, fpr_out != nullptr, part);
+  int st = launch_steps<T>(s, V, metric, (T)mu, (T)mu, steps, fpr_out != nullptr, part, nullptr);
   if (st) return st;
   if (fpr_out) {
     double q[NQ3];
