@@ -23,7 +23,7 @@ __all__ = [
     "div", "div_adj", "grad_fwd", "pointwise_norm", "flux_cost", "inner_h", "shrink",
     "project_dual_ball", "poisson_neumann", "norm_A_bound", "plain_step_sizes", "pd_step",
     "prolong_potential", "prolong_flux", "restrict_density", "prepare_levels", "kkt_plain",
-    "evaluate_plain", "solve_plain",
+    "evaluate_plain", "solve_plain", "prox_step", "potential_from_dual", "kkt_prox", "evaluate", "solve_prox",
 ]
 
 
@@ -210,6 +210,103 @@ def pd_step(m, phi, rho, h, mu, tau, p):
     dp = phin - phi
     R = inner_h(dm, dm, h) / mu + inner_h(dp, dp, h) / tau - 2.0 * inner_h(dp, div(dm, h), h)
     return n_, phin, R
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2 (eq. (pdhg)), G^k (eq. (pdhg_stop)) and Appendix B.
+# --------------------------------------------------------------------------
+
+def prox_step(m, w, wb, rho, h, mu, tau, p):
+    """One iteration of eq. (pdhg) with vphi^k = w and the extrapolated
+    vphi-bar^k = wb (tuples of d arrays).  Returns (m', w', wb', G^k)."""
+    v = tuple(mi - mu * bi for mi, bi in zip(m, wb))
+    u = poisson_neumann(div(v, h) - rho, h)
+    a = div_adj(u, h)
+    n_ = tuple(vi - ai for vi, ai in zip(v, a))           # projection onto {A m = rho}
+    q = project_dual_ball(tuple(wi + tau * ni for wi, ni in zip(w, n_)), p)
+    qb = tuple(2.0 * qi - wi for qi, wi in zip(q, w))
+    d = tuple(ni - mi for ni, mi in zip(n_, m))
+    e = tuple(qi - wi for qi, wi in zip(q, w))
+    G = inner_h(d, d, h) / mu + inner_h(e, e, h) / tau + 2.0 * inner_h(e, d, h)
+    return n_, q, qb, G
+
+
+def potential_from_dual(w, h):
+    """Appendix B: psi = (A A*)^{-1} A vphi, zero-mean (R8)."""
+    return poisson_neumann(div(w, h), h)
+
+
+def kkt_prox(m, w, rho, h, p):
+    """The normalised KKT residual of an Algorithm 2 iterate with the
+    potential of Appendix B: D = <psi, rho>_h."""
+    psi = potential_from_dual(w, h)
+    res = div(m, h) - rho
+    r_pri = math.sqrt(inner_h(res, res, h)) / max(math.sqrt(inner_h(rho, rho, h)), 1e-300)
+    r_dual, _ = _dual_excess(psi, h, p)
+    P = flux_cost(m, h, p)
+    D = inner_h(psi, rho, h)
+    return max(r_pri, r_dual, abs(P - D) / max(abs(P), abs(D), 1e-300)), P, D
+
+
+def evaluate(m, psi, rho, h, p):
+    """The certificate for a flux m and usual-sign potential psi: P = f(m),
+    D = <psi, rho>_h, lo = D / max(1, max ||grad psi||_q), hi = f of the flux
+    made feasible by the minimum-norm correction."""
+    res = div(m, h) - rho
+    corr = div_adj(poisson_neumann(res, h), h)
+    P = flux_cost(m, h, p)
+    D = inner_h(psi, rho, h)
+    _, gmax = _dual_excess(psi, h, p)
+    hi = flux_cost(tuple(mi - ci for mi, ci in zip(m, corr)), h, p)
+    return {"P": P, "D": D, "lo": D / max(1.0, gmax), "hi": hi, "grad_max": gmax}
+
+
+def solve_prox(p0, p1, n, L=1, p=1, stop="fpr", tol=1e-4, alpha=-1.0, max_iters=20000, check_every=1,
+               step_scale=0.5):
+    """Algorithm 4 in d dimensions: mu = tau = step_scale (R4), vphi-bar =
+    vphi at every level start (R5), level 1 from zero, the others from eq.
+    (inter_m) for both m and vphi; G^k (stop = "fpr") or the normalised KKT
+    residual (stop = "kkt") against tol (h_l/h)^alpha."""
+    d = np.asarray(p0).ndim
+    sides = level_sides(n, L)
+    rhos = prepare_levels(p0, p1, n, L)
+    tols = [tol * float(1 << (L - l)) ** alpha for l in range(1, L + 1)]
+    out = {"iters": [], "measure": [], "level_w1": [], "status": "ok", "level_seconds": []}
+    m = w = None
+    mu = tau = step_scale
+    for l in range(L):
+        nl = sides[l]
+        h = 1.0 / nl
+        rho = rhos[l]
+        t0 = time.perf_counter()
+        if m is None:
+            m = tuple(np.zeros((nl + 1,) * d) for _ in range(d))
+            w = tuple(np.zeros((nl + 1,) * d) for _ in range(d))
+        else:
+            m = prolong_flux(m)
+            w = prolong_flux(w)
+        wb = tuple(x.copy() for x in w)
+        k = 0
+        while True:
+            m, w, wb, G = prox_step(m, w, wb, rho, h, mu, tau, p)
+            k += 1
+            if k % check_every == 0 or k >= max_iters:
+                meas = G if stop == "fpr" else kkt_prox(m, w, rho, h, p)[0]
+                if meas <= tols[l]:
+                    break
+                if k >= max_iters:
+                    out["status"] = "maxiter"
+                    break
+        out["iters"].append(k)
+        out["measure"].append(float(meas))
+        out["level_w1"].append(flux_cost(m, h, p))
+        out["level_seconds"].append(time.perf_counter() - t0)
+    h = 1.0 / n
+    psi = potential_from_dual(w, h)
+    ev = evaluate(m, psi, rhos[-1], h, p)
+    out.update({"w1": ev["P"], "dual": ev["D"], "lo": ev["lo"], "hi": ev["hi"], "m": m, "vphi": w, "psi": psi,
+                "rho": rhos[-1], "tolerances": tols})
+    return out
 
 
 # --------------------------------------------------------------------------

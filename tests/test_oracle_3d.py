@@ -62,6 +62,28 @@ def test_reduces_to_the_2d_module_solve(p):
     assert r3["hi"] == pytest.approx(ev["hi"], rel=1e-10)
 
 
+@pytest.mark.parametrize("p", [1, 2, math.inf])
+def test_reduces_to_the_2d_module_prox(p):
+    n, L = 8, 2
+    a, b = w1data.random_pair(n, 6)
+    rng = np.random.default_rng(8)
+    m1, m2, w1_, w2_ = (rng.standard_normal((n + 1, n + 1)) for _ in range(4))
+    rho = o2.prepare_levels(a, b, n, 1)[0]
+    h = 1.0 / n
+    got = o3.prox_step((m1, m2), (w1_, w2_), (w1_, w2_), rho, h, 0.5, 0.5, p)
+    want = o2.prox_step(m1, m2, w1_, w2_, w1_, w2_, rho, h, 0.5, 0.5, p)
+    for x, y in zip((*got[0], *got[1], *got[2]), want[:6]):
+        np.testing.assert_allclose(x, y, atol=1e-12)
+    assert got[3] == pytest.approx(want[6], rel=1e-12)
+    eps = 1e-5
+    r3 = o3.solve_prox(a, b, n, L=L, p=p, stop="fpr", tol=eps, check_every=1)
+    r2 = o2.solve(a, b, n, L=L, p=p, algo=2, stop="fpr", tol=eps, eps_L=eps, check_every=1)
+    assert r3["iters"] == r2["iters"]
+    assert r3["w1"] == pytest.approx(r2["w1"], rel=1e-11)
+    assert r3["lo"] == pytest.approx(r2["lo"], rel=1e-10) and r3["hi"] == pytest.approx(r2["hi"], rel=1e-10)
+    np.testing.assert_allclose(r3["psi"], r2["psi"], atol=1e-11)
+
+
 # ---------------------------------------------------------------- d = 3 ----
 
 def test_adjoint_and_telescoping_3d():
@@ -232,3 +254,38 @@ def test_cascade_preserves_the_limit_3d():
     two = o3.solve_plain(a, b, n, L=2, p=2, **TIGHT)
     assert two["w1"] == pytest.approx(one["w1"], rel=1e-6)
     assert len(two["iters"]) == 2
+
+
+def test_prox_step_projects_onto_the_constraint_3d():
+    n, h = 5, 0.2
+    rng = np.random.default_rng(21)
+    rho = _rho3(n, 22)
+    m = tuple(rng.standard_normal((n + 1,) * 3) for _ in range(3))
+    w = tuple(rng.uniform(-1, 1, (n + 1,) * 3) for _ in range(3))
+    for p in P_ALL:
+        nm, q, qb, _ = o3.prox_step(m, w, w, rho, h, 0.5, 0.5, p)
+        np.testing.assert_allclose(o3.div(nm, h), rho, atol=1e-9)   # A m+ = rho
+        assert o3.pointwise_norm(q, o3.dual_exponent(p)).max() <= 1 + 1e-12
+
+
+def _rho3(n, seed):
+    a, b = w1data.random_pair_nd(n, 3, seed=seed)
+    return o3.prepare_levels(a, b, n, 1)[0]
+
+
+@pytest.mark.parametrize("n,seed", [(2, 0), (3, 1)])
+def test_prox_reaches_the_transport_lp_3d(n, seed):
+    a, b = w1data.random_pair_nd(n, 3, seed=30 + seed)
+    exact = _transport_lp_l1_3d(a, b, n)
+    r = o3.solve_prox(a, b, n, p=1, stop="kkt", tol=1e-9, check_every=10, max_iters=200000)
+    assert r["w1"] == pytest.approx(exact, rel=5e-6)
+    assert r["lo"] <= exact * (1 + 1e-9) and r["hi"] >= exact * (1 - 1e-9)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_prox_and_plain_share_the_limit_3d(p):
+    n = 4
+    a, b = w1data.random_pair_nd(n, 3, seed=23)
+    plain = o3.solve_plain(a, b, n, L=2, p=p, **dict(TIGHT, tol=1e-7))
+    prox = o3.solve_prox(a, b, n, L=2, p=p, stop="kkt", tol=1e-9, check_every=10, max_iters=200000)
+    assert prox["w1"] == pytest.approx(plain["w1"], rel=2e-6)
