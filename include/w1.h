@@ -272,25 +272,26 @@ int w1_op_evaluate(int32_t n, int32_t metric, int32_t precision,
 /* ---- d = 3 ---------------------------------------------------------------
  * The method is stated for any d (Sec. 2.2: the divergence sums D_{h,i} over
  * the d axes; Sec. 3.3: the interpolations are products of 1-D factors).
- * These run Algorithm 1 / 3 on the (n+1)^3 vertex grid of [0,1]^3, one pair
+ * These run Algorithms 1 / 3 and 2 / 4 on the (n+1)^3 vertex grid of [0,1]^3, one pair
  * per call, synchronously on `hip_stream` (NULL = default stream).  Arrays
  * are dense, index (i1 (n+1) + i2) (n+1) + i3, i3 contiguous.
  */
 
-/* Algorithm 3 in d = 3.  p0, p1: node masses ((n+1)^3 doubles each, host
- * or device by on_device; copied before use, caller-owned).  Parameters as
- * for w1_plan, with these limits: algo W1_ALGO_PLAIN only (W1_EINVAL
- * otherwise), tol > 0 (the paper's eq. (stop_tol) is fitted to its d = 2
- * experiments; no default), n <= 1024, step sizes mu = tau = step_scale /
- * (2 sqrt 3 / h).  out: w1 = f(m^K) = sum ||m||_p h^3, dual = -<phi, rho>_h,
- * lo = a certified lower bound (the dual value of phi scaled to the
- * Lipschitz constraint), hi = NaN (no Poisson correction in d = 3),
- * kkt = max(||A m - rho|| / ||rho||, RMS Lipschitz excess, relative gap),
- * per-level iterations, measures, f(m^{K_l}) and times.  m_out (3 (n+1)^3
- * doubles: m1, m2, m3) and psi_out ((n+1)^3 doubles, the zero-mean
- * potential with W1 = <psi, rho>_h) are optional host buffers.  W1_EINVAL
- * also for unbalanced, negative or non-finite masses; W1_ENOMEM when the
- * (n+1)^3 (8 sizeof(iterate) + 16) bytes per level do not fit.           */
+/* Algorithm 3 (algo W1_ALGO_PLAIN) or 4 (W1_ALGO_PROX) in d = 3.  p0, p1:
+ * node masses ((n+1)^3 doubles each, host or device by on_device; copied
+ * before use, caller-owned).  Parameters as for w1_plan, with these limits:
+ * tol > 0 (the paper's eq. (stop_tol) is fitted to its d = 2 experiments;
+ * no default), n <= 1024; steps mu = tau = step_scale / (2 sqrt 3 / h)
+ * (Algorithm 3) or step_scale (Algorithm 4).  out: w1 = f(m^K) =
+ * sum ||m||_p h^3, dual = <psi, rho>_h with psi = -phi (Algorithm 3) or
+ * (A A*)^{-1} A vphi (Appendix B), the certified bracket lo <= W1_h <= hi
+ * (psi scaled to the Lipschitz constraint; m made feasible by the
+ * minimum-norm correction), kkt = max(||A m - rho|| / ||rho||, RMS
+ * Lipschitz excess, relative gap), per-level iterations, measures,
+ * f(m^{K_l}) and times.  m_out (3 (n+1)^3 doubles: m1, m2, m3) and psi_out
+ * ((n+1)^3 doubles) are optional host buffers.  W1_EINVAL also for
+ * unbalanced, negative or non-finite masses; W1_ENOMEM when the
+ * (n+1)^3 (16 sizeof(iterate) + 16) bytes per level do not fit.          */
 int w1_solve3d(const w1_params* params, const double* p0, const double* p1,
                int32_t on_device, w1_result* out, double* m_out,
                double* psi_out, void* hip_stream);
@@ -303,6 +304,16 @@ int w1_op_plain_steps3d(int32_t n, int32_t metric, int32_t precision,
                         double step_scale, int32_t steps, void* m1, void* m2,
                         void* m3, void* phi, const void* rho, double* fpr_out,
                         void* hip_stream);
+
+/* `steps` iterations of eq. (pdhg) in d = 3 in place on device arrays
+ * (m1..m3, vphi1..vphi3, vphibar1..vphibar3), rho read only, mu = tau =
+ * step_scale (<= 0: 1/2; at most 1).  fpr_out (host, may be NULL)
+ * receives G^k of the last step (eq. (pdhg_stop)).                        */
+int w1_op_prox_steps3d(int32_t n, int32_t metric, int32_t precision,
+                       double step_scale, int32_t steps, void* m1, void* m2,
+                       void* m3, void* w1, void* w2, void* w3, void* wb1,
+                       void* wb2, void* wb3, const void* rho, double* fpr_out,
+                       void* hip_stream);
 
 /* ---- kernel timing ------------------------------------------------------
  * w1_profile(h, 1) resets and enables per-launch HIP-event timing on the

@@ -101,6 +101,7 @@ def lib():
         "w1_op_evaluate": (C.c_int, [i32, i32, i32, vp, vp, vp, vp, dp, vp]),
         "w1_solve3d": (C.c_int, [C.POINTER(Params), vp, vp, i32, C.POINTER(Result), vp, vp, vp]),
         "w1_op_plain_steps3d": (C.c_int, [i32, i32, i32, C.c_double, i32, vp, vp, vp, vp, vp, dp, vp]),
+        "w1_op_prox_steps3d": (C.c_int, [i32, i32, i32, C.c_double, i32] + [vp] * 10 + [dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -359,7 +360,7 @@ def op_evaluate(n, metric, precision, m1, m2, psi, rho, stream=None):
 
 
 def solve3d(p: Params, p0, p1, fields=False, stream=None):
-    """Algorithm 3 in d = 3 on one pair of (n+1)^3 float64 masses (numpy or
+    """Algorithm 3 or 4 (p.algo) in d = 3 on one pair of (n+1)^3 float64 masses (numpy or
     cuda tensors).  Returns the result dict, and with fields=True also
     (m, psi): m of shape (3, n+1, n+1, n+1) and psi (n+1, n+1, n+1), host."""
     pa, da = _ptr(p0, "float64")
@@ -385,4 +386,14 @@ def op_plain_steps3d(n, metric, precision, steps, m1, m2, m3, phi, rho, step_sca
     _check(lib().w1_op_plain_steps3d(n, metric, precision, step_scale, steps,
                                      *[_ptr(x, d)[0] for x in (m1, m2, m3, phi, rho)],
                                      C.byref(out) if fpr else None, _stream(stream)), "w1_op_plain_steps3d")
+    return out.value if fpr else None
+
+
+def op_prox_steps3d(n, metric, precision, steps, m1, m2, m3, w1, w2, w3, wb1, wb2, wb3, rho, step_scale=0.0,
+                    fpr=False, stream=None):
+    d = _dt(precision)
+    out = C.c_double(np.nan)
+    _check(lib().w1_op_prox_steps3d(n, metric, precision, step_scale, steps,
+                                    *[_ptr(x, d)[0] for x in (m1, m2, m3, w1, w2, w3, wb1, wb2, wb3, rho)],
+                                    C.byref(out) if fpr else None, _stream(stream)), "w1_op_prox_steps3d")
     return out.value if fpr else None

@@ -1,4 +1,4 @@
-// Algorithm 1 / 3 in d = 3 (the paper states the method for any d: the
+// Algorithms 1 / 3 and 2 / 4 in d = 3 (the paper states the method for any d: the
 // divergence of Sec. 2.2 summed over three axes, the interpolations of
 // Sec. 3.3 as products of 1-D factors).  One pair per call, levels run one
 // after the other from the host.
@@ -9,10 +9,14 @@
 // extrapolated flux b = 2 m+ - m, the potential phi and rho, all in the
 // iterate precision T, plus two FP64 planes for the density pyramid.
 //
-// An iteration is two node-parallel kernels: the flux half (reads phi at the
-// node and its three forward neighbours, writes m+ and b) and the potential
-// half (reads b at the node and its three backward neighbours, updates phi in
-// place).  The stop test's sums (R^k of eq. (pd_stop), or the normalised KKT
+// An Algorithm 1 iteration is two node-parallel kernels: the flux half (reads
+// phi at the node and its three forward neighbours, writes m+ and b) and the
+// potential half (reads b at the node and its three backward neighbours,
+// updates phi in place).  An Algorithm 2 iteration is a pre kernel
+// (v = m - mu vphibar and r = A v - rho), the Neumann Poisson solve as six
+// one-axis DCT passes (products with the orthonormal DCT matrix, the
+// eigenvalue division fused into the third), and a post kernel (m+, vphi+,
+// vphibar+).  The stop test's sums (R^k of eq. (pd_stop), or the normalised KKT
 // residual) are block partials in FP64, summed by a one-block kernel and
 // read by the host every `check_every` iterations.
 #include <hip/hip_runtime.h>
@@ -216,15 +220,18 @@ __global__ __launch_bounds__(NT) void k3_pot(int n, const T* __restrict__ b0, co
 }
 
 // ---------------------------------------------------------------------------
-// evaluation sums: q0 sum ||m||_p, q1 sum phi rho, q2 sum (A m - rho)^2,
-// q3 sum rho^2, q4 sum (||grad(-phi)||_q - 1)_+^2, q5 max ||grad phi||_q,
-// q6 sum phi
+// evaluation sums for a flux m and a potential pot taken with sign sgn
+// (psi = sgn pot: -phi for Algorithm 1, the Appendix B potential for
+// Algorithm 2): q0 sum ||m||_p, q1 sum psi rho, q2 sum (A m - rho)^2,
+// q3 sum rho^2, q4 sum (||grad psi||_q - 1)_+^2, q5 max ||grad psi||_q,
+// q6 sum pot, and with a correction potential c (may be NULL) q7 sum of
+// ||m - A* c||_p, the flux made feasible when c = (A A*)^{-1}(A m - rho)
 // ---------------------------------------------------------------------------
 template <typename T, int METRIC>
 __global__ __launch_bounds__(NT) void k3_eval(int n, const T* __restrict__ m0, const T* __restrict__ m1,
-                                              const T* __restrict__ m2, const T* __restrict__ phi,
-                                              const T* __restrict__ rho, double* __restrict__ part,
-                                              const int* __restrict__ gate) {
+                                              const T* __restrict__ m2, const T* __restrict__ pot, double sgn,
+                                              const T* __restrict__ rho, const T* __restrict__ corr,
+                                              double* __restrict__ part, const int* __restrict__ gate) {
   if (gate && *gate != G_RUN) return;
   const int N1 = n + 1;
   const long long S1 = (long long)N1 * N1, N = S1 * N1;
@@ -233,10 +240,10 @@ __global__ __launch_bounds__(NT) void k3_eval(int n, const T* __restrict__ m0, c
   for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
     const Idx x = split_(e, N1);
     const double a = (double)m0[e], b = (double)m1[e], c = (double)m2[e];
-    const double pc = (double)phi[e], rr = (double)rho[e];
-    const double g0 = x.i1 < n ? ((double)phi[e + S1] - pc) * ih : 0.0;
-    const double g1 = x.i2 < n ? ((double)phi[e + N1] - pc) * ih : 0.0;
-    const double g2 = x.i3 < n ? ((double)phi[e + 1] - pc) * ih : 0.0;
+    const double pr = (double)pot[e], pc = sgn * pr, rr = (double)rho[e];
+    const double g0 = x.i1 < n ? (sgn * (double)pot[e + S1] - pc) * ih : 0.0;
+    const double g1 = x.i2 < n ? (sgn * (double)pot[e + N1] - pc) * ih : 0.0;
+    const double g2 = x.i3 < n ? (sgn * (double)pot[e + 1] - pc) * ih : 0.0;
     double dv = (x.i1 < n ? a : 0.0) - (x.i1 > 0 ? (double)m0[e - S1] : 0.0);
     dv += (x.i2 < n ? b : 0.0) - (x.i2 > 0 ? (double)m1[e - N1] : 0.0);
     dv += (x.i3 < n ? c : 0.0) - (x.i3 > 0 ? (double)m2[e - 1] : 0.0);
@@ -249,7 +256,14 @@ __global__ __launch_bounds__(NT) void k3_eval(int n, const T* __restrict__ m0, c
     v[3] += rr * rr;
     v[4] += ex * ex;
     v[5] = gq > v[5] ? gq : v[5];
-    v[6] += pc;
+    v[6] += pr;
+    if (corr) {
+      const double cc = (double)corr[e];
+      const double f0 = x.i1 < n ? a - (cc - (double)corr[e + S1]) * ih : a;
+      const double f1 = x.i2 < n ? b - (cc - (double)corr[e + N1]) * ih : b;
+      const double f2 = x.i3 < n ? c - (cc - (double)corr[e + 1]) * ih : c;
+      v[7] += norm_p3_<double, METRIC>(f0, f1, f2);
+    }
   }
   block_out_(v, part);
 }
@@ -264,13 +278,14 @@ __global__ __launch_bounds__(NT) void k3_final(const double* __restrict__ part, 
 }
 
 // the stop test of a block of `steps` iterations (one block of threads):
-// rule 2 R^k of eq. (pd_stop) from the potential half's sums, rule 1 the
-// normalised KKT residual from the evaluation sums (as the oracle defines
-// them); the level stops at meas <= tol, on a non-finite measure, or at
-// the cap
+// rule 2 R^k of eq. (pd_stop) (Algorithm 1, from the potential half's sums)
+// or G^k of eq. (pdhg_stop) (Algorithm 2, from the post kernel's sums),
+// rule 1 the normalised KKT residual from the evaluation sums (as the
+// oracle defines it); the level stops at meas <= tol, on a non-finite
+// measure, or at the cap
 __global__ __launch_bounds__(NT) void k3_check(const double* __restrict__ part, int nb, double* __restrict__ sums,
-                                               Gate* __restrict__ gate, int rule, double mu, double tau, int n,
-                                               double tol, int steps, int cap) {
+                                               Gate* __restrict__ gate, int kind, int rule, double mu, double tau,
+                                               int n, double tol, int steps, int cap) {
   if (gate->status != G_RUN) return;   // read by every thread before any write below
   double q[NQ3];
   final_sums_(part, nb, sums, q);
@@ -278,9 +293,11 @@ __global__ __launch_bounds__(NT) void k3_check(const double* __restrict__ part, 
     const double h3 = 1.0 / ((double)n * n * n);
     double meas;
     if (rule == W1_STOP_FPR) {
-      meas = (q[0] / mu + q[1] / tau - 2.0 * q[2]) * h3;
+      // R^k (eq. (pd_stop)) or G^k (eq. (pdhg_stop))
+      meas = kind == W1_ALGO_PLAIN ? (q[0] / mu + q[1] / tau - 2.0 * q[2]) * h3
+                                   : (q[0] / mu + q[1] / tau + 2.0 * q[2]) * h3;
     } else {
-      const double P = q[0] * h3, D = -q[1] * h3;
+      const double P = q[0] * h3, D = q[1] * h3;
       const double rp = sqrt(q[2] * h3) / fmax(sqrt(q[3] * h3), 1e-300);
       const double rd = sqrt(q[4] * h3);
       const double gap = fabs(P - D) / fmax(fmax(fabs(P), fabs(D)), 1e-300);
@@ -319,6 +336,152 @@ __device__ __forceinline__ void final_sums_(const double* __restrict__ part, int
   if (threadIdx.x < NQ3) out[threadIdx.x] = sh[threadIdx.x][0];
   if (threadIdx.x == 0)
     for (int q = 0; q < NQ3; ++q) q0[q] = sh[q][0];
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 2 (eq. (pdhg)): v = m - mu vphibar and r = A v - rho (pre), the
+// Neumann Poisson solve u = (A A*)^{-1} r by DCT (R3), then m+ = v - A* u,
+// vphi+ = Proj(vphi + tau m+), vphibar+ = 2 vphi+ - vphi (post)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k3_prox_pre(int n, const T* __restrict__ m0, const T* __restrict__ m1,
+                                                  const T* __restrict__ m2, const T* __restrict__ wb0,
+                                                  const T* __restrict__ wb1, const T* __restrict__ wb2,
+                                                  const T* __restrict__ rho, T* __restrict__ v0, T* __restrict__ v1,
+                                                  T* __restrict__ v2, T* __restrict__ r, T ih, T mu,
+                                                  const int* __restrict__ gate) {
+  if (gate && *gate != G_RUN) return;
+  const int N1 = n + 1;
+  const long long S1 = (long long)N1 * N1, N = S1 * N1;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, N1);
+    const T a0 = fma3_(-mu, wb0[e], m0[e]), a1 = fma3_(-mu, wb1[e], m1[e]), a2 = fma3_(-mu, wb2[e], m2[e]);
+    T d = (x.i1 < n ? a0 : T(0)) - (x.i1 > 0 ? fma3_(-mu, wb0[e - S1], m0[e - S1]) : T(0));
+    d += (x.i2 < n ? a1 : T(0)) - (x.i2 > 0 ? fma3_(-mu, wb1[e - N1], m1[e - N1]) : T(0));
+    d += (x.i3 < n ? a2 : T(0)) - (x.i3 > 0 ? fma3_(-mu, wb2[e - 1], m2[e - 1]) : T(0));
+    v0[e] = a0;
+    v1[e] = a1;
+    v2[e] = a2;
+    r[e] = d * ih - rho[e];
+  }
+}
+
+// projection onto the unit ball of the dual norm q (inf, 2, 1 for
+// p = 1, 2, inf; the l_1 ball by the same sort-and-threshold rule)
+template <typename T, int METRIC>
+__device__ __forceinline__ void proj3_(const T w[3], T o[3]) {
+  if constexpr (METRIC == 1) {
+    for (int a = 0; a < 3; ++a) o[a] = w[a] > T(1) ? T(1) : (w[a] < T(-1) ? T(-1) : w[a]);
+  } else if constexpr (METRIC == 2) {
+    const T nw = sqrt3_(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    for (int a = 0; a < 3; ++a) o[a] = nw > T(1) ? w[a] / nw : w[a];
+  } else {
+    const T x = abs3_(w[0]), y = abs3_(w[1]), z = abs3_(w[2]);
+    if (x + y + z <= T(1)) {
+      for (int a = 0; a < 3; ++a) o[a] = w[a];
+      return;
+    }
+    const T u0 = max3_(max3_(x, y), z), u2 = min3_(min3_(x, y), z);
+    const T u1 = max3_(min3_(x, y), min3_(max3_(x, y), z));
+    const T c2 = u0 + u1, c3 = c2 + u2;
+    const int k = 1 + (u1 > (c2 - T(1)) / T(2) ? 1 : 0) + (u2 > (c3 - T(1)) / T(3) ? 1 : 0);
+    const T theta = k == 1 ? u0 - T(1) : (k == 2 ? (c2 - T(1)) / T(2) : (c3 - T(1)) / T(3));
+    for (int a = 0; a < 3; ++a) {
+      const T r = max3_(abs3_(w[a]) - theta, T(0));
+      o[a] = w[a] < T(0) ? -r : r;
+    }
+  }
+}
+
+template <typename T, int METRIC, bool CHECK>
+__global__ __launch_bounds__(NT) void k3_prox_post(int n, const T* __restrict__ v0, const T* __restrict__ v1,
+                                                   const T* __restrict__ v2, const T* __restrict__ u,
+                                                   T* __restrict__ m0, T* __restrict__ m1, T* __restrict__ m2,
+                                                   T* __restrict__ w0, T* __restrict__ w1, T* __restrict__ w2,
+                                                   T* __restrict__ wb0, T* __restrict__ wb1, T* __restrict__ wb2,
+                                                   T ih, T tau, double* __restrict__ part,
+                                                   const int* __restrict__ gate) {
+  if (gate && *gate != G_RUN) return;
+  const int N1 = n + 1;
+  const long long S1 = (long long)N1 * N1, N = S1 * N1;
+  double acc[NQ3] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, N1);
+    const T uc = u[e];
+    // A* u: (u(x) - u(x + h e_a)) / h, 0 on the last node of axis a
+    const T n0 = v0[e] - (x.i1 < n ? (uc - u[e + S1]) * ih : T(0));
+    const T n1 = v1[e] - (x.i2 < n ? (uc - u[e + N1]) * ih : T(0));
+    const T n2 = v2[e] - (x.i3 < n ? (uc - u[e + 1]) * ih : T(0));
+    const T wo[3] = {w0[e], w1[e], w2[e]};
+    const T q[3] = {fma3_(tau, n0, wo[0]), fma3_(tau, n1, wo[1]), fma3_(tau, n2, wo[2])};
+    T pw[3];
+    proj3_<T, METRIC>(q, pw);
+    if constexpr (CHECK) {
+      const T d0 = n0 - m0[e], d1 = n1 - m1[e], d2 = n2 - m2[e];
+      const T e0 = pw[0] - wo[0], e1 = pw[1] - wo[1], e2 = pw[2] - wo[2];
+      acc[0] += (double)(d0 * d0) + (double)(d1 * d1) + (double)(d2 * d2);
+      acc[1] += (double)(e0 * e0) + (double)(e1 * e1) + (double)(e2 * e2);
+      acc[2] += (double)(e0 * d0) + (double)(e1 * d1) + (double)(e2 * d2);
+    }
+    m0[e] = n0;
+    m1[e] = n1;
+    m2[e] = n2;
+    w0[e] = pw[0];
+    w1[e] = pw[1];
+    w2[e] = pw[2];
+    wb0[e] = fma3_(T(2), pw[0], -wo[0]);
+    wb1[e] = fma3_(T(2), pw[1], -wo[1]);
+    wb2[e] = fma3_(T(2), pw[2], -wo[2]);
+  }
+  if constexpr (CHECK) block_out_(acc, part);
+}
+
+// r = A f - rho (rho may be NULL: r = A f)
+template <typename T>
+__global__ __launch_bounds__(NT) void k3_div(int n, const T* __restrict__ f0, const T* __restrict__ f1,
+                                             const T* __restrict__ f2, const T* __restrict__ rho,
+                                             T* __restrict__ r, const int* __restrict__ gate) {
+  if (gate && *gate != G_RUN) return;
+  const int N1 = n + 1;
+  const long long S1 = (long long)N1 * N1, N = S1 * N1;
+  const T ih = (T)n;
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, N1);
+    const T d = div3_(f0, f1, f2, e, x, n, N1, S1) * ih;
+    r[e] = rho ? d - rho[e] : d;
+  }
+}
+
+// One axis of the orthonormal DCT of length N = n+1 on every line along
+// AXIS (0: i1, 1: i2, 2: i3): MODE 0 forward (C), MODE 1 forward and then
+// the spectral division by the FP64 eigenvalues of A A*
+// (4/h^2) sum_a sin^2(pi k_a / 2N), the constant mode set to 0, MODE 2
+// inverse (C^T).  C is N x N row-major, s[k] = sin^2(pi k / 2N).
+template <typename T, int AXIS, int MODE>
+__global__ __launch_bounds__(NT) void k3_dct(int n, const T* __restrict__ in, T* __restrict__ out,
+                                             const T* __restrict__ C, const double* __restrict__ s,
+                                             const int* __restrict__ gate) {
+  if (gate && *gate != G_RUN) return;
+  const int N1 = n + 1;
+  const long long S1 = (long long)N1 * N1, N = S1 * N1;
+  const long long stride = AXIS == 0 ? S1 : (AXIS == 1 ? N1 : 1);
+  for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
+    const Idx x = split_(e, N1);
+    const int k = AXIS == 0 ? x.i1 : (AXIS == 1 ? x.i2 : x.i3);
+    const long long base = e - (long long)k * stride;
+    T acc = T(0);
+    if constexpr (MODE == 2) {
+      for (int j = 0; j < N1; ++j) acc = fma3_(C[(size_t)j * N1 + k], in[base + j * stride], acc);
+    } else {
+      const T* row = C + (size_t)k * N1;
+      for (int j = 0; j < N1; ++j) acc = fma3_(row[j], in[base + j * stride], acc);
+    }
+    if constexpr (MODE == 1) {
+      const double lam = 4.0 * (double)n * (double)n * (s[x.i1] + s[x.i2] + s[x.i3]);
+      acc = (x.i1 | x.i2 | x.i3) == 0 ? T(0) : (T)((double)acc / lam);
+    }
+    out[e] = acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -440,15 +603,15 @@ __global__ __launch_bounds__(NT) void k3_prolong(int nc, int comp, const T* __re
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k3_export(long long N, const T* __restrict__ m0, const T* __restrict__ m1,
-                                                const T* __restrict__ m2, const T* __restrict__ phi, double mean,
-                                                double* __restrict__ om, double* __restrict__ opsi) {
+                                                const T* __restrict__ m2, const T* __restrict__ pot, double mean,
+                                                double sgn, double* __restrict__ om, double* __restrict__ opsi) {
   for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < N; e += (long long)gridDim.x * NT) {
     if (om) {
       om[e] = (double)m0[e];
       om[N + e] = (double)m1[e];
       om[2 * N + e] = (double)m2[e];
     }
-    if (opsi) opsi[e] = -((double)phi[e] - mean);
+    if (opsi) opsi[e] = sgn * ((double)pot[e] - mean);
   }
 }
 
@@ -467,13 +630,59 @@ struct DevBuf {
   }
 };
 
+// planes of one level: Algorithm 1 uses m, b (= 2 m+ - m), phi; Algorithm 2
+// uses m, w (vphi), wb (vphibar), b (= v), r (residual, then u) and t (DCT
+// scratch); rho, the FP64 density pair and the DCT tables always
+constexpr int NPL3 = 16;
 template <typename T>
 struct Level {
   int n = 0;
   long long N = 0;
-  T *m[3] = {}, *b[3] = {}, *phi = nullptr, *rho = nullptr;
+  T *m[3] = {}, *b[3] = {}, *w[3] = {}, *wb[3] = {}, *phi = nullptr, *rho = nullptr, *r = nullptr, *t = nullptr;
   double *r0 = nullptr, *r1 = nullptr;
+  T* C = nullptr;        // orthonormal DCT-II matrix, N x N
+  double* s = nullptr;   // sin^2(pi k / 2N)
 };
+
+template <typename T>
+size_t level_bytes(int n) {
+  const size_t N = (size_t)(n + 1) * (n + 1) * (n + 1), L = (size_t)(n + 1);
+  return N * (NPL3 * sizeof(T) + 2 * sizeof(double)) + L * L * sizeof(T) + L * sizeof(double) + 20 * 256;
+}
+
+// orthonormal DCT-II of length N: C[k][j] = sqrt((k ? 2 : 1)/N) cos(pi k (2j+1) / 2N)
+template <typename T>
+int upload_dct(hipStream_t st, Level<T>& V) {
+  const int N = V.n + 1;
+  std::vector<T> C((size_t)N * N);
+  std::vector<double> sv(N);
+  const double pi = std::acos(-1.0);
+  for (int k = 0; k < N; ++k) {
+    const double a = std::sqrt((k ? 2.0 : 1.0) / N);
+    for (int j = 0; j < N; ++j) C[(size_t)k * N + j] = (T)(a * std::cos(pi * k * (2.0 * j + 1.0) / (2.0 * N)));
+    const double sn = std::sin(pi * k / (2.0 * N));
+    sv[k] = sn * sn;
+  }
+  CHK(hipMemcpyAsync(V.C, C.data(), C.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(V.s, sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  CHK(hipStreamSynchronize(st));   // the host vectors end with this scope
+  return W1_OK;
+}
+
+// u = (A A*)^{-1} x in place of x (R3), t scratch: three forward passes (the
+// last divides by the eigenvalues), three inverse passes
+template <typename T>
+int poisson3(hipStream_t s, const Level<T>& V, T* x, T* t, const int* gate) {
+  const int nb = blocks_for(V.N);
+  k3_dct<T, 2, 0><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.s, gate);
+  k3_dct<T, 1, 0><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.s, gate);
+  k3_dct<T, 0, 1><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.s, gate);
+  k3_dct<T, 0, 2><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.s, gate);
+  k3_dct<T, 1, 2><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.s, gate);
+  k3_dct<T, 2, 2><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.s, gate);
+  CHK(hipGetLastError());
+  return W1_OK;
+}
 
 template <typename T>
 int launch_steps(hipStream_t s, const Level<T>& L, int metric, T mu, T tau, int steps, bool check_last,
@@ -502,6 +711,39 @@ int launch_steps(hipStream_t s, const Level<T>& L, int metric, T mu, T tau, int 
   return W1_OK;
 }
 
+template <typename T, int METRIC>
+void prox_post_(hipStream_t s, const Level<T>& L, int nb, T ih, T tau, bool chk, double* part, const int* gate) {
+  if (chk)
+    k3_prox_post<T, METRIC, true><<<nb, NT, 0, s>>>(L.n, L.b[0], L.b[1], L.b[2], L.r, L.m[0], L.m[1], L.m[2],
+                                                    L.w[0], L.w[1], L.w[2], L.wb[0], L.wb[1], L.wb[2], ih, tau,
+                                                    part, gate);
+  else
+    k3_prox_post<T, METRIC, false><<<nb, NT, 0, s>>>(L.n, L.b[0], L.b[1], L.b[2], L.r, L.m[0], L.m[1], L.m[2],
+                                                     L.w[0], L.w[1], L.w[2], L.wb[0], L.wb[1], L.wb[2], ih, tau,
+                                                     part, gate);
+}
+
+template <typename T>
+int launch_prox_steps(hipStream_t s, const Level<T>& L, int metric, T mu, T tau, int steps, bool check_last,
+                      double* part, const int* gate) {
+  const int nb = blocks_for(L.N);
+  const T ih = (T)L.n;
+  for (int k = 0; k < steps; ++k) {
+    k3_prox_pre<T><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.wb[0], L.wb[1], L.wb[2], L.rho, L.b[0],
+                                     L.b[1], L.b[2], L.r, ih, mu, gate);
+    int st = poisson3<T>(s, L, L.r, L.t, gate);
+    if (st) return st;
+    const bool chk = check_last && k == steps - 1;
+    switch (metric) {
+      case 1: prox_post_<T, 1>(s, L, nb, ih, tau, chk, part, gate); break;
+      case 2: prox_post_<T, 2>(s, L, nb, ih, tau, chk, part, gate); break;
+      default: prox_post_<T, 3>(s, L, nb, ih, tau, chk, part, gate);
+    }
+  }
+  CHK(hipGetLastError());
+  return W1_OK;
+}
+
 // final sums of `nb` partials, copied to host `out`
 inline int finish_sums(hipStream_t s, const double* part, int nb, double* dout, double* out) {
   k3_final<<<1, NT, 0, s>>>(part, nb, dout);
@@ -512,39 +754,34 @@ inline int finish_sums(hipStream_t s, const double* part, int nb, double* dout, 
 }
 
 template <typename T>
-int eval_sums(hipStream_t s, const Level<T>& L, int metric, double* part, const int* gate) {
+int eval_sums(hipStream_t s, const Level<T>& L, int metric, const T* pot, double sgn, const T* corr, double* part,
+              const int* gate) {
   const int nb = blocks_for(L.N);
   switch (metric) {
-    case 1: k3_eval<T, 1><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part, gate); break;
-    case 2: k3_eval<T, 2><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part, gate); break;
-    default: k3_eval<T, 3><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], L.phi, L.rho, part, gate);
+    case 1: k3_eval<T, 1><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], pot, sgn, L.rho, corr, part, gate); break;
+    case 2: k3_eval<T, 2><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], pot, sgn, L.rho, corr, part, gate); break;
+    default: k3_eval<T, 3><<<nb, NT, 0, s>>>(L.n, L.m[0], L.m[1], L.m[2], pot, sgn, L.rho, corr, part, gate);
   }
   CHK(hipGetLastError());
   return W1_OK;
 }
 
-template <typename T>
-int eval_level(hipStream_t s, const Level<T>& L, int metric, double* part, double* dout, double* out) {
-  int st = eval_sums<T>(s, L, metric, part, nullptr);
-  if (st) return st;
-  return finish_sums(s, part, blocks_for(L.N), dout, out);
-}
-
-// P, D, lo, kkt from the evaluation sums of a level of side n
+// P, D, lo, hi, kkt from the evaluation sums of a level of side n
 struct Eval {
-  double P, D, lo, kkt, mean;
+  double P, D, lo, hi, kkt, mean;
 };
-inline Eval eval_of(const double* q, int n) {
+inline Eval eval_of(const double* q, int n, bool cert) {
   const double h3 = 1.0 / ((double)n * n * n);
   const double N = (double)(n + 1) * (n + 1) * (n + 1);
   Eval e;
   e.P = q[0] * h3;
-  e.D = -q[1] * h3;
+  e.D = q[1] * h3;
   const double rp = std::sqrt(q[2] * h3) / std::fmax(std::sqrt(q[3] * h3), 1e-300);
   const double rd = std::sqrt(q[4] * h3);
   const double gap = std::fabs(e.P - e.D) / std::fmax(std::fmax(std::fabs(e.P), std::fabs(e.D)), 1e-300);
   e.kkt = std::fmax(rp, std::fmax(rd, gap));
   e.lo = e.D / (q[5] > 1.0 ? q[5] : 1.0);
+  e.hi = cert ? q[7] * h3 : std::numeric_limits<double>::quiet_NaN();
   e.mean = q[6] / N;
   return e;
 }
@@ -553,17 +790,36 @@ inline double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// the potential of a finished level: phi (Algorithm 1, psi = -phi) or
+// psi = (A A*)^{-1} A vphi in plane r (Algorithm 2, Appendix B)
+template <typename T>
+int level_potential(hipStream_t s, const Level<T>& V, bool prox, const T** pot, double* sgn) {
+  if (!prox) {
+    *pot = V.phi;
+    *sgn = -1.0;
+    return W1_OK;
+  }
+  k3_div<T><<<blocks_for(V.N), NT, 0, s>>>(V.n, V.w[0], V.w[1], V.w[2], nullptr, V.r, nullptr);
+  CHK(hipGetLastError());
+  int st = poisson3<T>(s, V, V.r, V.t, nullptr);
+  if (st) return st;
+  *pot = V.r;
+  *sgn = 1.0;
+  return W1_OK;
+}
+
 template <typename T>
 int solve(const w1_params& prm, const double* p0, const double* p1, int on_device, w1_result* out, double* m_out,
           double* psi_out, hipStream_t s) {
   const double t0 = now_s();
   const int L = prm.levels;
+  const bool prox = prm.algo == W1_ALGO_PROX;
   std::vector<Level<T>> lv(L);
   size_t bytes = 0;
   for (int l = 0; l < L; ++l) {
     lv[l].n = prm.n >> (L - 1 - l);
     lv[l].N = (long long)(lv[l].n + 1) * (lv[l].n + 1) * (lv[l].n + 1);
-    bytes += (size_t)lv[l].N * (8 * sizeof(T) + 2 * sizeof(double)) + 16 * 256;
+    bytes += level_bytes<T>(lv[l].n);
   }
   bytes += (size_t)MAXB * NQ3 * sizeof(double) + 256 + NQ3 * sizeof(double) + 256 + sizeof(Gate) + 256;
   DevBuf mem;
@@ -575,17 +831,29 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
     return r;
   };
   for (int l = 0; l < L; ++l) {
-    const size_t pe = (size_t)lv[l].N;
-    for (int a = 0; a < 3; ++a) lv[l].m[a] = (T*)take(pe * sizeof(T));
-    for (int a = 0; a < 3; ++a) lv[l].b[a] = (T*)take(pe * sizeof(T));
-    lv[l].phi = (T*)take(pe * sizeof(T));
-    lv[l].rho = (T*)take(pe * sizeof(T));
-    lv[l].r0 = (double*)take(pe * 8);
-    lv[l].r1 = (double*)take(pe * 8);
+    Level<T>& V = lv[l];
+    const size_t pe = (size_t)V.N * sizeof(T);
+    for (int a = 0; a < 3; ++a) V.m[a] = (T*)take(pe);
+    for (int a = 0; a < 3; ++a) V.b[a] = (T*)take(pe);
+    for (int a = 0; a < 3; ++a) V.w[a] = (T*)take(pe);
+    for (int a = 0; a < 3; ++a) V.wb[a] = (T*)take(pe);
+    V.phi = (T*)take(pe);
+    V.rho = (T*)take(pe);
+    V.r = (T*)take(pe);
+    V.r0 = (double*)take((size_t)V.N * 8);
+    V.r1 = (double*)take((size_t)V.N * 8);
+    V.C = (T*)take((size_t)(V.n + 1) * (V.n + 1) * sizeof(T));
+    V.s = (double*)take((size_t)(V.n + 1) * sizeof(double));
+    V.t = (T*)take(pe);
   }
   double* part = (double*)take((size_t)MAXB * NQ3 * sizeof(double));
   double* dout = (double*)take(NQ3 * sizeof(double));
   Gate* gate = (Gate*)take(sizeof(Gate));
+  if ((size_t)(p - (char*)mem.p) > bytes) return W1_EINVAL;   // layout and size disagree (not expected)
+  for (int l = 0; l < L; ++l) {
+    int st = upload_dct<T>(s, lv[l]);
+    if (st) return st;
+  }
   double q[NQ3];
 
   // input masses -> finest r0, r1; checks (Sec. 2.2 samples the densities on
@@ -635,18 +903,28 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
   for (int l = 0; l < L; ++l) {
     Level<T>& V = lv[l];
     const int nb = blocks_for(V.N);
+    const size_t pe = (size_t)V.N * sizeof(T);
     if (l == 0) {
-      for (int a = 0; a < 3; ++a) CHK(hipMemsetAsync(V.m[a], 0, (size_t)V.N * sizeof(T), s));
-      CHK(hipMemsetAsync(V.phi, 0, (size_t)V.N * sizeof(T), s));
+      for (int a = 0; a < 3; ++a) {
+        CHK(hipMemsetAsync(V.m[a], 0, pe, s));
+        if (prox) CHK(hipMemsetAsync(V.w[a], 0, pe, s));
+      }
+      if (!prox) CHK(hipMemsetAsync(V.phi, 0, pe, s));
     } else {
       const Level<T>& C = lv[l - 1];
-      const int fb = blocks_for(V.N);
-      for (int a = 0; a < 3; ++a) k3_prolong<T><<<fb, NT, 0, s>>>(C.n, a, C.m[a], V.m[a]);
-      k3_prolong<T><<<fb, NT, 0, s>>>(C.n, -1, C.phi, V.phi);
+      for (int a = 0; a < 3; ++a) {
+        k3_prolong<T><<<nb, NT, 0, s>>>(C.n, a, C.m[a], V.m[a]);
+        if (prox) k3_prolong<T><<<nb, NT, 0, s>>>(C.n, a, C.w[a], V.w[a]);
+      }
+      if (!prox) k3_prolong<T><<<nb, NT, 0, s>>>(C.n, -1, C.phi, V.phi);
       CHK(hipGetLastError());
     }
-    // R4 with d = 3: mu = tau = scale / ||A||, ||A|| <= 2 sqrt(3) / h
-    const double mu = sc / (2.0 * std::sqrt(3.0) * V.n);
+    // vphibar = vphi at every level start (R5)
+    if (prox)
+      for (int a = 0; a < 3; ++a) CHK(hipMemcpyAsync(V.wb[a], V.w[a], pe, hipMemcpyDeviceToDevice, s));
+    // R4 with d = 3: Algorithm 1 mu = tau = scale / ||A||, ||A|| <= 2 sqrt(3) / h;
+    // Algorithm 2 mu = tau = scale
+    const double mu = prox ? sc : sc / (2.0 * std::sqrt(3.0) * V.n);
     const double tol = prm.tol * std::pow(2.0, (double)(L - 1 - l) * prm.alpha);
     // blocks of check_every iterations, each ending in the stop test on the
     // device; the host reads the gate after 4, 8, ... 64 queued blocks (the
@@ -659,13 +937,24 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
     while (g.status == G_RUN && queued < total) {
       const int B = std::min(burst, total - queued);
       for (int b = 0; b < B; ++b) {
-        int st = launch_steps<T>(s, V, prm.metric, (T)mu, (T)mu, ce, fpr, part, &gate->status);
+        int st = prox ? launch_prox_steps<T>(s, V, prm.metric, (T)mu, (T)mu, ce, fpr, part, &gate->status)
+                      : launch_steps<T>(s, V, prm.metric, (T)mu, (T)mu, ce, fpr, part, &gate->status);
         if (st) return st;
         if (!fpr) {
-          st = eval_sums<T>(s, V, prm.metric, part, &gate->status);
+          const T* pot = V.phi;
+          double sgn = -1.0;
+          if (prox) {
+            k3_div<T><<<nb, NT, 0, s>>>(V.n, V.w[0], V.w[1], V.w[2], nullptr, V.r, &gate->status);
+            st = poisson3<T>(s, V, V.r, V.t, &gate->status);
+            if (st) return st;
+            pot = V.r;
+            sgn = 1.0;
+          }
+          st = eval_sums<T>(s, V, prm.metric, pot, sgn, nullptr, part, &gate->status);
           if (st) return st;
         }
-        k3_check<<<1, NT, 0, s>>>(part, nb, dout, gate, prm.stop_rule, mu, mu, V.n, tol, ce, prm.max_iters);
+        k3_check<<<1, NT, 0, s>>>(part, nb, dout, gate, prm.algo, prm.stop_rule, mu, mu, V.n, tol, ce,
+                                  prm.max_iters);
         CHK(hipGetLastError());
       }
       queued += B;
@@ -678,20 +967,34 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
     out->iters[l] = g.iters;
     out->measure[l] = g.measure;
     out->levels_run = l + 1;
-    int st = eval_level<T>(s, V, prm.metric, part, dout, q);
+    int st = eval_sums<T>(s, V, prm.metric, prox ? V.w[0] : V.phi, -1.0, nullptr, part, nullptr);
     if (st) return st;
-    out->level_w1[l] = eval_of(q, V.n).P;
+    st = finish_sums(s, part, nb, dout, q);
+    if (st) return st;
+    out->level_w1[l] = eval_of(q, V.n, false).P;
     out->level_seconds[l] = now_s() - t0;
     if (out->status == W1_SOLVE_DIVERGED) break;
   }
+  // certificate of the last level run: its potential, and the minimum-norm
+  // correction c = (A A*)^{-1}(A m - rho) (planes b, free now) for hi
   const Level<T>& V = lv[out->levels_run - 1];
-  int st = eval_level<T>(s, V, prm.metric, part, dout, q);
+  const T* pot = nullptr;
+  double sgn = 0;
+  int st = level_potential<T>(s, V, prox, &pot, &sgn);
   if (st) return st;
-  const Eval ev = eval_of(q, V.n);
+  k3_div<T><<<blocks_for(V.N), NT, 0, s>>>(V.n, V.m[0], V.m[1], V.m[2], V.rho, V.b[0], nullptr);
+  CHK(hipGetLastError());
+  st = poisson3<T>(s, V, V.b[0], V.b[1], nullptr);
+  if (st) return st;
+  st = eval_sums<T>(s, V, prm.metric, pot, sgn, V.b[0], part, nullptr);
+  if (st) return st;
+  st = finish_sums(s, part, blocks_for(V.N), dout, q);
+  if (st) return st;
+  const Eval ev = eval_of(q, V.n, true);
   out->w1 = ev.P;
   out->dual = ev.D;
   out->lo = ev.lo;
-  out->hi = std::numeric_limits<double>::quiet_NaN();
+  out->hi = ev.hi;
   out->kkt = ev.kkt;
   if ((m_out || psi_out) && out->levels_run == L) {
     DevBuf ex;
@@ -699,7 +1002,9 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
     CHK(hipMalloc(&ex.p, need));
     double* om = m_out ? (double*)ex.p : nullptr;
     double* op = psi_out ? (double*)ex.p + (m_out ? 3 * V.N : 0) : nullptr;
-    k3_export<T><<<blocks_for(V.N), NT, 0, s>>>(V.N, V.m[0], V.m[1], V.m[2], V.phi, ev.mean, om, op);
+    // psi: -(phi - mean) for Algorithm 1, Appendix B's psi as is for Algorithm 2
+    k3_export<T><<<blocks_for(V.N), NT, 0, s>>>(V.N, V.m[0], V.m[1], V.m[2], pot, prox ? 0.0 : ev.mean, sgn, om,
+                                                op);
     CHK(hipGetLastError());
     if (m_out) CHK(hipMemcpyAsync(m_out, om, 3 * (size_t)V.N * 8, hipMemcpyDeviceToHost, s));
     if (psi_out) CHK(hipMemcpyAsync(psi_out, op, (size_t)V.N * 8, hipMemcpyDeviceToHost, s));
@@ -709,32 +1014,51 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
   return W1_OK;
 }
 
+// single-step entry points: steps iterations in place on caller arrays
 template <typename T>
-int plain_steps(int n, int metric, double scale, int steps, void* m1, void* m2, void* m3, void* phi,
-                const void* rho, double* fpr_out, hipStream_t s) {
+int steps3(int n, int metric, bool prox, double scale, int steps, void* const* f, const void* rho, double* fpr_out,
+           hipStream_t s) {
   Level<T> V;
   V.n = n;
   V.N = (long long)(n + 1) * (n + 1) * (n + 1);
-  V.m[0] = (T*)m1;
-  V.m[1] = (T*)m2;
-  V.m[2] = (T*)m3;
-  V.phi = (T*)phi;
+  for (int a = 0; a < 3; ++a) V.m[a] = (T*)f[a];
+  if (prox) {
+    for (int a = 0; a < 3; ++a) {
+      V.w[a] = (T*)f[3 + a];
+      V.wb[a] = (T*)f[6 + a];
+    }
+  } else {
+    V.phi = (T*)f[3];
+  }
   V.rho = (T*)rho;
   DevBuf mem;
   const size_t pe = ((size_t)V.N * sizeof(T) + 255) / 256 * 256;
-  CHK(hipMalloc(&mem.p, 3 * pe + (size_t)MAXB * NQ3 * 8 + 256 + NQ3 * 8));
+  const size_t tab = ((size_t)(n + 1) * (n + 1) * sizeof(T) + 255) / 256 * 256 + ((size_t)(n + 1) * 8 + 255) / 256 * 256;
+  CHK(hipMalloc(&mem.p, 5 * pe + tab + (size_t)MAXB * NQ3 * 8 + 256 + NQ3 * 8));
   char* p = (char*)mem.p;
   for (int a = 0; a < 3; ++a) V.b[a] = (T*)(p + a * pe);
-  double* part = (double*)(p + 3 * pe);
+  V.r = (T*)(p + 3 * pe);
+  V.t = (T*)(p + 4 * pe);
+  V.C = (T*)(p + 5 * pe);
+  V.s = (double*)(p + 5 * pe + ((size_t)(n + 1) * (n + 1) * sizeof(T) + 255) / 256 * 256);
+  double* part = (double*)(p + 5 * pe + tab);
   double* dout = part + (size_t)MAXB * NQ3 + 32;
-  const double mu = (scale > 0 ? scale : 0.5) / (2.0 * std::sqrt(3.0) * n);
-  int st = launch_steps<T>(s, V, metric, (T)mu, (T)mu, steps, fpr_out != nullptr, part, nullptr);
+  int st = W1_OK;
+  if (prox) {
+    st = upload_dct<T>(s, V);
+    if (st) return st;
+  }
+  const double sc = scale > 0 ? scale : 0.5;
+  const double mu = prox ? sc : sc / (2.0 * std::sqrt(3.0) * n);
+  st = prox ? launch_prox_steps<T>(s, V, metric, (T)mu, (T)mu, steps, fpr_out != nullptr, part, nullptr)
+            : launch_steps<T>(s, V, metric, (T)mu, (T)mu, steps, fpr_out != nullptr, part, nullptr);
   if (st) return st;
   if (fpr_out) {
     double q[NQ3];
     st = finish_sums(s, part, blocks_for(V.N), dout, q);
     if (st) return st;
-    *fpr_out = (q[0] / mu + q[1] / mu - 2.0 * q[2]) / ((double)n * n * n);
+    const double h3 = 1.0 / ((double)n * n * n);
+    *fpr_out = prox ? (q[0] / mu + q[1] / mu + 2.0 * q[2]) * h3 : (q[0] / mu + q[1] / mu - 2.0 * q[2]) * h3;
   } else {
     CHK(hipStreamSynchronize(s));
   }
@@ -751,7 +1075,8 @@ extern "C" int w1_solve3d(const w1_params* p, const double* p0, const double* p1
   if (!p || !p0 || !p1 || !out) return W1_EINVAL;
   if (p->n < 2 || p->n > 1024 || p->levels < 1 || p->levels > W1_MAX_LEVELS) return W1_EINVAL;
   if (p->n % (1 << (p->levels - 1)) != 0 || (p->n >> (p->levels - 1)) < 2) return W1_EINVAL;
-  if (p->metric < W1_METRIC_L1 || p->metric > W1_METRIC_LINF || p->algo != W1_ALGO_PLAIN) return W1_EINVAL;
+  if (p->metric < W1_METRIC_L1 || p->metric > W1_METRIC_LINF) return W1_EINVAL;
+  if (p->algo != W1_ALGO_PLAIN && p->algo != W1_ALGO_PROX) return W1_EINVAL;
   if (p->precision != W1_FP32 && p->precision != W1_FP64) return W1_EINVAL;
   if (p->stop_rule != W1_STOP_KKT && p->stop_rule != W1_STOP_FPR) return W1_EINVAL;
   if (!(p->tol > 0) || !std::isfinite(p->tol) || !std::isfinite(p->alpha)) return W1_EINVAL;
@@ -767,8 +1092,22 @@ extern "C" int w1_op_plain_steps3d(int32_t n, int32_t metric, int32_t precision,
                                    void* hip_stream) {
   if (n < 1 || n > 1024 || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF) return W1_EINVAL;
   if (!m1 || !m2 || !m3 || !phi || !rho || !(step_scale <= 1.0)) return W1_EINVAL;
+  void* f[4] = {m1, m2, m3, phi};
   hipStream_t s = (hipStream_t)hip_stream;
-  if (precision == W1_FP32) return cube::plain_steps<float>(n, metric, step_scale, steps, m1, m2, m3, phi, rho, fpr_out, s);
-  if (precision == W1_FP64) return cube::plain_steps<double>(n, metric, step_scale, steps, m1, m2, m3, phi, rho, fpr_out, s);
+  if (precision == W1_FP32) return cube::steps3<float>(n, metric, false, step_scale, steps, f, rho, fpr_out, s);
+  if (precision == W1_FP64) return cube::steps3<double>(n, metric, false, step_scale, steps, f, rho, fpr_out, s);
+  return W1_EINVAL;
+}
+
+extern "C" int w1_op_prox_steps3d(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,
+                                  void* m1, void* m2, void* m3, void* w1, void* w2, void* w3, void* wb1, void* wb2,
+                                  void* wb3, const void* rho, double* fpr_out, void* hip_stream) {
+  if (n < 1 || n > 1024 || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF) return W1_EINVAL;
+  if (!m1 || !m2 || !m3 || !w1 || !w2 || !w3 || !wb1 || !wb2 || !wb3 || !rho || !(step_scale <= 1.0))
+    return W1_EINVAL;
+  void* f[9] = {m1, m2, m3, w1, w2, w3, wb1, wb2, wb3};
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (precision == W1_FP32) return cube::steps3<float>(n, metric, true, step_scale, steps, f, rho, fpr_out, s);
+  if (precision == W1_FP64) return cube::steps3<double>(n, metric, true, step_scale, steps, f, rho, fpr_out, s);
   return W1_EINVAL;
 }
