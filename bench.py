@@ -439,28 +439,33 @@ def run_tolerance(args, w1):
 def run_cube(args, w1):
     """d = 3 (the method for general d, Sec. 2.2 / 3.3): one pair of
     isotropic Gaussian mixtures on the unit cube at n = 128 (129^3 nodes),
-    3 levels (33^3, 65^3, 129^3), l_2 metric, Algorithm 3, FPR rule with
-    eps_L = 1e-7 and alpha = -1, FP32 iterates; against the same solve in
-    FP64 on the GPU, and the FP64 oracle's node-update rate on this host."""
+    3 levels (33^3, 65^3, 129^3), l_2 metric, Algorithm 3 (FPR eps_L 1e-7)
+    and Algorithm 4 (FPR eps_L 1e-5), alpha = -1, FP32 iterates; against the
+    same solves in FP64 on the GPU, and the FP64 oracle's Algorithm 1
+    node-update rate on this host.  `value` is Algorithm 3's."""
     import torch
     import w1data
     n, L = 128, 3
     p0, p1 = w1data.pair_gauss_3d(0, n=n)
     d0, d1 = torch.from_numpy(p0).cuda(), torch.from_numpy(p1).cuda()
     out = {}
-    for prec, name in ((w1.FP32, "f32"), (w1.FP64, "f64")):
-        prm = w1.params(n=n, levels=L, metric=w1.METRIC_L2, algo=w1.ALGO_PLAIN, precision=prec,
-                        stop_rule=w1.STOP_FPR, tol=1e-7, alpha=-1.0, max_iters=20000, check_every=10)
-        w1.solve3d(prm, d0, d1)
-        torch.cuda.synchronize()
-        reps = max(1, args.steps) if prec == w1.FP32 else 1
-        t = time.perf_counter()
-        for _ in range(reps):
-            r = w1.solve3d(prm, d0, d1)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / reps
-        out[name] = {"seconds": dt, "w1": r["w1"], "iters": r["iters"], "lo": r["lo"], "kkt": r["kkt"]}
-        log(f"[bench] cube {name}: {dt*1e3:.1f} ms W1 {r['w1']:.7f} iters {r['iters']}")
+    for algo, an, tol in ((w1.ALGO_PLAIN, "plain", 1e-7), (w1.ALGO_PROX, "prox", 1e-5)):
+        for prec, name in ((w1.FP32, "f32"), (w1.FP64, "f64")):
+            prm = w1.params(n=n, levels=L, metric=w1.METRIC_L2, algo=algo, precision=prec,
+                            stop_rule=w1.STOP_FPR, tol=tol, alpha=-1.0, max_iters=20000, check_every=10)
+            w1.solve3d(prm, d0, d1)
+            torch.cuda.synchronize()
+            reps = max(1, args.steps) if prec == w1.FP32 else 1
+            t = time.perf_counter()
+            for _ in range(reps):
+                r = w1.solve3d(prm, d0, d1)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / reps
+            key = name if algo == w1.ALGO_PLAIN else f"prox_{name}"
+            out[key] = {"seconds": dt, "w1": r["w1"], "iters": r["iters"], "lo": r["lo"], "hi": r["hi"],
+                        "kkt": r["kkt"]}
+            log(f"[bench] cube {an} {name}: {dt*1e3:.1f} ms W1 {r['w1']:.7f} [{r['lo']:.6f}, {r['hi']:.6f}] "
+                f"iters {r['iters']}")
     sides = [n >> (L - 1 - l) for l in range(L)]
     nodes = [(s_ + 1) ** 3 for s_ in sides]
     upd = sum(k * nd for k, nd in zip(out["f32"]["iters"], nodes))
@@ -498,7 +503,10 @@ def run_cube(args, w1):
                                    "3 levels, L2 metric, Algorithm 3, FPR eps_L 1e-7 alpha -1, FP32"},
             "cell_updates_per_s": cups, "fp64_single": {"solves_per_s": 1.0 / out["f64"]["seconds"],
                                                         "speedup_fp32": out["f64"]["seconds"] / sec},
-            "accuracy": {"rel_w1_fp32_vs_fp64": rel}, "solves": out, "roofline": roof, "cpu_baseline": cpu}
+            "accuracy": {"rel_w1_fp32_vs_fp64": rel,
+                         "prox_rel_w1_fp32_vs_fp64": abs(out["prox_f32"]["w1"] - out["prox_f64"]["w1"])
+                         / out["prox_f64"]["w1"]},
+            "solves": out, "roofline": roof, "cpu_baseline": cpu}
 
 
 def main():

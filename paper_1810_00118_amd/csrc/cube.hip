@@ -456,11 +456,14 @@ __global__ __launch_bounds__(NT) void k3_div(int n, const T* __restrict__ f0, co
 // AXIS (0: i1, 1: i2, 2: i3): MODE 0 forward (C), MODE 1 forward and then
 // the spectral division by the FP64 eigenvalues of A A*
 // (4/h^2) sum_a sin^2(pi k_a / 2N), the constant mode set to 0, MODE 2
-// inverse (C^T).  C is N x N row-major, s[k] = sin^2(pi k / 2N).
+// inverse (C^T).  Both read the matrix by columns of the output index k
+// (forward from Ct = C^T, inverse from C), so the lanes of a wavefront that
+// hold consecutive k along i3 read consecutive entries; N x N row-major,
+// s[k] = sin^2(pi k / 2N).
 template <typename T, int AXIS, int MODE>
 __global__ __launch_bounds__(NT) void k3_dct(int n, const T* __restrict__ in, T* __restrict__ out,
-                                             const T* __restrict__ C, const double* __restrict__ s,
-                                             const int* __restrict__ gate) {
+                                             const T* __restrict__ C, const T* __restrict__ Ct,
+                                             const double* __restrict__ s, const int* __restrict__ gate) {
   if (gate && *gate != G_RUN) return;
   const int N1 = n + 1;
   const long long S1 = (long long)N1 * N1, N = S1 * N1;
@@ -469,13 +472,9 @@ __global__ __launch_bounds__(NT) void k3_dct(int n, const T* __restrict__ in, T*
     const Idx x = split_(e, N1);
     const int k = AXIS == 0 ? x.i1 : (AXIS == 1 ? x.i2 : x.i3);
     const long long base = e - (long long)k * stride;
+    const T* M = (MODE == 2 ? C : Ct) + k;
     T acc = T(0);
-    if constexpr (MODE == 2) {
-      for (int j = 0; j < N1; ++j) acc = fma3_(C[(size_t)j * N1 + k], in[base + j * stride], acc);
-    } else {
-      const T* row = C + (size_t)k * N1;
-      for (int j = 0; j < N1; ++j) acc = fma3_(row[j], in[base + j * stride], acc);
-    }
+    for (int j = 0; j < N1; ++j) acc = fma3_(M[(size_t)j * N1], in[base + j * stride], acc);
     if constexpr (MODE == 1) {
       const double lam = 4.0 * (double)n * (double)n * (s[x.i1] + s[x.i2] + s[x.i3]);
       acc = (x.i1 | x.i2 | x.i3) == 0 ? T(0) : (T)((double)acc / lam);
@@ -641,29 +640,35 @@ struct Level {
   T *m[3] = {}, *b[3] = {}, *w[3] = {}, *wb[3] = {}, *phi = nullptr, *rho = nullptr, *r = nullptr, *t = nullptr;
   double *r0 = nullptr, *r1 = nullptr;
   T* C = nullptr;        // orthonormal DCT-II matrix, N x N
+  T* Ct = nullptr;       // its transpose
   double* s = nullptr;   // sin^2(pi k / 2N)
 };
 
 template <typename T>
 size_t level_bytes(int n) {
   const size_t N = (size_t)(n + 1) * (n + 1) * (n + 1), L = (size_t)(n + 1);
-  return N * (NPL3 * sizeof(T) + 2 * sizeof(double)) + L * L * sizeof(T) + L * sizeof(double) + 20 * 256;
+  return N * (NPL3 * sizeof(T) + 2 * sizeof(double)) + 2 * L * L * sizeof(T) + L * sizeof(double) + 21 * 256;
 }
 
 // orthonormal DCT-II of length N: C[k][j] = sqrt((k ? 2 : 1)/N) cos(pi k (2j+1) / 2N)
 template <typename T>
 int upload_dct(hipStream_t st, Level<T>& V) {
   const int N = V.n + 1;
-  std::vector<T> C((size_t)N * N);
+  std::vector<T> C((size_t)N * N), Ct((size_t)N * N);
   std::vector<double> sv(N);
   const double pi = std::acos(-1.0);
   for (int k = 0; k < N; ++k) {
     const double a = std::sqrt((k ? 2.0 : 1.0) / N);
-    for (int j = 0; j < N; ++j) C[(size_t)k * N + j] = (T)(a * std::cos(pi * k * (2.0 * j + 1.0) / (2.0 * N)));
+    for (int j = 0; j < N; ++j) {
+      const T c = (T)(a * std::cos(pi * k * (2.0 * j + 1.0) / (2.0 * N)));
+      C[(size_t)k * N + j] = c;
+      Ct[(size_t)j * N + k] = c;
+    }
     const double sn = std::sin(pi * k / (2.0 * N));
     sv[k] = sn * sn;
   }
   CHK(hipMemcpyAsync(V.C, C.data(), C.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  CHK(hipMemcpyAsync(V.Ct, Ct.data(), Ct.size() * sizeof(T), hipMemcpyHostToDevice, st));
   CHK(hipMemcpyAsync(V.s, sv.data(), sv.size() * sizeof(double), hipMemcpyHostToDevice, st));
   CHK(hipStreamSynchronize(st));   // the host vectors end with this scope
   return W1_OK;
@@ -674,12 +679,12 @@ int upload_dct(hipStream_t st, Level<T>& V) {
 template <typename T>
 int poisson3(hipStream_t s, const Level<T>& V, T* x, T* t, const int* gate) {
   const int nb = blocks_for(V.N);
-  k3_dct<T, 2, 0><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.s, gate);
-  k3_dct<T, 1, 0><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.s, gate);
-  k3_dct<T, 0, 1><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.s, gate);
-  k3_dct<T, 0, 2><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.s, gate);
-  k3_dct<T, 1, 2><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.s, gate);
-  k3_dct<T, 2, 2><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.s, gate);
+  k3_dct<T, 2, 0><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.Ct, V.s, gate);
+  k3_dct<T, 1, 0><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.Ct, V.s, gate);
+  k3_dct<T, 0, 1><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.Ct, V.s, gate);
+  k3_dct<T, 0, 2><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.Ct, V.s, gate);
+  k3_dct<T, 1, 2><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.Ct, V.s, gate);
+  k3_dct<T, 2, 2><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.Ct, V.s, gate);
   CHK(hipGetLastError());
   return W1_OK;
 }
@@ -843,6 +848,7 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
     V.r0 = (double*)take((size_t)V.N * 8);
     V.r1 = (double*)take((size_t)V.N * 8);
     V.C = (T*)take((size_t)(V.n + 1) * (V.n + 1) * sizeof(T));
+    V.Ct = (T*)take((size_t)(V.n + 1) * (V.n + 1) * sizeof(T));
     V.s = (double*)take((size_t)(V.n + 1) * sizeof(double));
     V.t = (T*)take(pe);
   }
@@ -1033,14 +1039,16 @@ int steps3(int n, int metric, bool prox, double scale, int steps, void* const* f
   V.rho = (T*)rho;
   DevBuf mem;
   const size_t pe = ((size_t)V.N * sizeof(T) + 255) / 256 * 256;
-  const size_t tab = ((size_t)(n + 1) * (n + 1) * sizeof(T) + 255) / 256 * 256 + ((size_t)(n + 1) * 8 + 255) / 256 * 256;
+  const size_t mat = ((size_t)(n + 1) * (n + 1) * sizeof(T) + 255) / 256 * 256;
+  const size_t tab = 2 * mat + ((size_t)(n + 1) * 8 + 255) / 256 * 256;
   CHK(hipMalloc(&mem.p, 5 * pe + tab + (size_t)MAXB * NQ3 * 8 + 256 + NQ3 * 8));
   char* p = (char*)mem.p;
   for (int a = 0; a < 3; ++a) V.b[a] = (T*)(p + a * pe);
   V.r = (T*)(p + 3 * pe);
   V.t = (T*)(p + 4 * pe);
   V.C = (T*)(p + 5 * pe);
-  V.s = (double*)(p + 5 * pe + ((size_t)(n + 1) * (n + 1) * sizeof(T) + 255) / 256 * 256);
+  V.Ct = (T*)(p + 5 * pe + mat);
+  V.s = (double*)(p + 5 * pe + 2 * mat);
   double* part = (double*)(p + 5 * pe + tab);
   double* dout = part + (size_t)MAXB * NQ3 + 32;
   int st = W1_OK;
