@@ -27,9 +27,11 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <type_traits>
 #include <vector>
 
 #include "engine.hpp"
+#include "mfma_tile.hpp"
 #include "w1.h"
 
 namespace w1 {
@@ -483,6 +485,62 @@ __global__ __launch_bounds__(NT) void k3_dct(int n, const T* __restrict__ in, T*
   }
 }
 
+// The same one-axis DCT pass in FP32 on the matrix cores: a product with the
+// DCT matrix in 64 x 64 output tiles (K = N).  Along i1 and i2 the tile is
+// (frequency k) x (the contiguous index), Out = M In, batched over i1 for
+// the i2 pass; along the contiguous axis i3 it is (line) x (frequency k),
+// Out = In M^T, so every operand load runs along contiguous memory.
+template <int AXIS, int MODE>
+__global__ __launch_bounds__(NT) void k3_dct_mfma(int n, const float* __restrict__ in, float* __restrict__ out,
+                                                  const float* __restrict__ C, const double* __restrict__ s,
+                                                  int tiles_r, int tiles_c, const int* __restrict__ gate) {
+  __shared__ float As[2][64][33];
+  __shared__ float Bs[2][32][68];
+  if (gate && *gate != G_RUN) return;
+  const int N1 = n + 1;
+  const long long S1 = (long long)N1 * N1;
+  const int tr = blockIdx.x % tiles_r, tc = (blockIdx.x / tiles_r) % tiles_c, bt = blockIdx.x / (tiles_r * tiles_c);
+  const int r0 = tr * 64, c0 = tc * 64;
+  // M(k, j): C[k][j] forward, C[j][k] inverse
+  auto Mkj = [&](int k, int j) { return MODE == 2 ? C[(size_t)j * N1 + k] : C[(size_t)k * N1 + j]; };
+  const long long rows = AXIS == 2 ? S1 : N1, cols = AXIS == 0 ? S1 : N1;
+  float acc[16];
+  if constexpr (AXIS == 0) {
+    auto la = [&](int i, int kk) { return Mkj(min(r0 + i, N1 - 1), kk); };
+    auto lb = [&](int kk, int j) {
+      const long long c = c0 + j < S1 ? c0 + j : S1 - 1;
+      return in[(long long)kk * S1 + c];
+    };
+    mfma_tile64_(la, lb, N1, As, Bs, acc);
+  } else if constexpr (AXIS == 1) {
+    const long long base = (long long)bt * S1;
+    auto la = [&](int i, int kk) { return Mkj(min(r0 + i, N1 - 1), kk); };
+    auto lb = [&](int kk, int j) { return in[base + (long long)kk * N1 + min(c0 + j, N1 - 1)]; };
+    mfma_tile64_(la, lb, N1, As, Bs, acc);
+  } else {
+    auto la = [&](int i, int kk) {
+      const long long r = r0 + i < S1 ? r0 + i : S1 - 1;
+      return in[r * N1 + kk];
+    };
+    auto lb = [&](int kk, int j) { return Mkj(min(c0 + j, N1 - 1), kk); };
+    mfma_tile64_(la, lb, N1, As, Bs, acc);
+  }
+  const int col = c0 + mfma_col_();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const long long row = r0 + mfma_row_(r);
+    if (row >= rows || col >= cols) continue;
+    const long long e = AXIS == 0 ? row * S1 + col : (AXIS == 1 ? (long long)bt * S1 + row * N1 + col : row * N1 + col);
+    float v = acc[r];
+    if constexpr (MODE == 1) {
+      const Idx x = split_(e, N1);
+      const double lam = 4.0 * (double)n * (double)n * (s[x.i1] + s[x.i2] + s[x.i3]);
+      v = (x.i1 | x.i2 | x.i3) == 0 ? 0.f : (float)((double)v / lam);
+    }
+    out[e] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // density pyramid (FP64): input checks, scaling, restriction, rho
 // ---------------------------------------------------------------------------
@@ -678,6 +736,19 @@ int upload_dct(hipStream_t st, Level<T>& V) {
 // last divides by the eigenvalues), three inverse passes
 template <typename T>
 int poisson3(hipStream_t s, const Level<T>& V, T* x, T* t, const int* gate) {
+  if constexpr (std::is_same<T, float>::value) {
+    const int N1 = V.n + 1, tn = (N1 + 63) / 64;
+    const long long S1 = (long long)N1 * N1;
+    const int ts = (int)((S1 + 63) / 64);
+    k3_dct_mfma<2, 0><<<ts * tn, NT, 0, s>>>(V.n, x, t, V.C, V.s, ts, tn, gate);
+    k3_dct_mfma<1, 0><<<tn * tn * N1, NT, 0, s>>>(V.n, t, x, V.C, V.s, tn, tn, gate);
+    k3_dct_mfma<0, 1><<<tn * ts, NT, 0, s>>>(V.n, x, t, V.C, V.s, tn, ts, gate);
+    k3_dct_mfma<0, 2><<<tn * ts, NT, 0, s>>>(V.n, t, x, V.C, V.s, tn, ts, gate);
+    k3_dct_mfma<1, 2><<<tn * tn * N1, NT, 0, s>>>(V.n, x, t, V.C, V.s, tn, tn, gate);
+    k3_dct_mfma<2, 2><<<ts * tn, NT, 0, s>>>(V.n, t, x, V.C, V.s, ts, tn, gate);
+    CHK(hipGetLastError());
+    return W1_OK;
+  }
   const int nb = blocks_for(V.N);
   k3_dct<T, 2, 0><<<nb, NT, 0, s>>>(V.n, x, t, V.C, V.Ct, V.s, gate);
   k3_dct<T, 1, 0><<<nb, NT, 0, s>>>(V.n, t, x, V.C, V.Ct, V.s, gate);
