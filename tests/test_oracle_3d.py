@@ -234,8 +234,9 @@ def test_axis_translation_3d(p, shift):
     mass = bump.sum() / a.sum()
     a, b = a / a.sum(), b / b.sum()
     closed = np.abs(s).sum() / n * mass
-    r = o3.solve_plain(a, b, n, p=p, **TIGHT)
+    r = o3.solve_plain(a, b, n, p=p, **dict(TIGHT, tol=1e-6))
     assert r["w1"] == pytest.approx(closed, rel=2e-6)
+    assert r["lo"] <= closed * (1 + 1e-9) and r["hi"] >= closed * (1 - 1e-9)
 
 
 def test_sandwich_3d():
