@@ -57,7 +57,7 @@ struct SlotDesc {
   T ih, mu, tau;
   double h, mud, taud;  // FP64 copies of h, mu, tau for the measures
   double tol;          // stop tolerance of this level
-  int metric;          // 1 or 2
+  int metric;          // 1, 2 or 3 (l_1, l_2, l_inf)
   int pad1;
   int rule;            // RULE_KKT or RULE_FPR
   int cap;             // iteration cap of this level
