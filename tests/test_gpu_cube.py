@@ -184,6 +184,27 @@ def test_prox_cascade_fp32_at_equal_iteration_counts(metric):
     assert res["hi"] == pytest.approx(ref["hi"], rel=1e-4)
 
 
+@pytest.mark.parametrize("n,L", [(2, 1), (3, 1), (6, 2)])
+@pytest.mark.parametrize("algo", [1, 2])
+def test_small_and_odd_grids_3d(n, L, algo):
+    """Edge sizes: the smallest grid, an odd side, a 4^3 coarse level; FP64
+    takes the oracle's decisions; FP32 repeats itself bit for bit."""
+    w1 = require_gpu()
+    p0, p1 = w1data.random_pair_nd(n, 3, seed=50 + n)
+    tol = 1e-6 if algo == 1 else 1e-5
+    prm = w1.params(n=n, levels=L, metric=2, algo=algo, precision=FP64, stop_rule=w1.STOP_FPR, tol=tol,
+                    alpha=-1.0, max_iters=20000, check_every=10)
+    res = w1.solve3d(prm, p0, p1)
+    solve = o3.solve_plain if algo == 1 else o3.solve_prox
+    ref = solve(p0, p1, n, L=L, p=2, stop="fpr", tol=tol, alpha=-1.0, max_iters=20000, check_every=10)
+    assert res["iters"] == ref["iters"]
+    assert res["w1"] == pytest.approx(ref["w1"], rel=1e-9)
+    assert res["lo"] == pytest.approx(ref["lo"], rel=1e-8) and res["hi"] == pytest.approx(ref["hi"], rel=1e-8)
+    prm.precision = FP32
+    a, b = w1.solve3d(prm, p0, p1), w1.solve3d(prm, p0, p1)
+    assert a["iters"] == b["iters"] and a["w1"] == b["w1"] and a["lo"] == b["lo"]
+
+
 def test_cube65_fp32_against_fp64():
     """65^3 nodes, 3 levels (17^3, 33^3, 65^3), paper-style FPR rule: the
     FP32 result within 1e-4 of the FP64 GPU result, the lower bound below
