@@ -466,6 +466,22 @@ def run_cube(args, w1):
                         "kkt": r["kkt"]}
             log(f"[bench] cube {an} {name}: {dt*1e3:.1f} ms W1 {r['w1']:.7f} [{r['lo']:.6f}, {r['hi']:.6f}] "
                 f"iters {r['iters']}")
+    # many pairs at once: w1_solve3d_batch on 8 concurrent streams
+    B = 16
+    bpairs = [tuple(torch.from_numpy(x).cuda() for x in w1data.pair_gauss_3d(i, n=n)) for i in range(B)]
+    batch = {}
+    for algo, an, tol in ((w1.ALGO_PLAIN, "plain", 1e-7), (w1.ALGO_PROX, "prox", 1e-5)):
+        prm = w1.params(n=n, levels=L, metric=w1.METRIC_L2, algo=algo, precision=w1.FP32,
+                        stop_rule=w1.STOP_FPR, tol=tol, alpha=-1.0, max_iters=20000, check_every=10)
+        w1.solve3d_batch(prm, bpairs[:8], workers=8)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rs = w1.solve3d_batch(prm, bpairs, workers=8)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        batch[an] = {"pairs": B, "workers": 8, "seconds": dt, "solves_per_s": B / dt,
+                     "iters_median": [float(np.median([r["iters"][l] for r in rs])) for l in range(L)]}
+        log(f"[bench] cube batch {an}: {B} pairs in {dt:.3f} s, {B / dt:.1f} solves/s")
     sides = [n >> (L - 1 - l) for l in range(L)]
     nodes = [(s_ + 1) ** 3 for s_ in sides]
     upd = sum(k * nd for k, nd in zip(out["f32"]["iters"], nodes))
@@ -506,7 +522,7 @@ def run_cube(args, w1):
             "accuracy": {"rel_w1_fp32_vs_fp64": rel,
                          "prox_rel_w1_fp32_vs_fp64": abs(out["prox_f32"]["w1"] - out["prox_f64"]["w1"])
                          / out["prox_f64"]["w1"]},
-            "solves": out, "roofline": roof, "cpu_baseline": cpu}
+            "solves": out, "batch": batch, "roofline": roof, "cpu_baseline": cpu}
 
 
 def main():

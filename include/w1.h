@@ -296,6 +296,16 @@ int w1_solve3d(const w1_params* params, const double* p0, const double* p1,
                int32_t on_device, w1_result* out, double* m_out,
                double* psi_out, void* hip_stream);
 
+/* w1_solve3d over `count` pairs (p0[i], p1[i], all host or all device by
+ * on_device; out[i] their results, no fields) by `workers` host threads
+ * (1..16, 0 = 4), each with its own stream and device block, taking the
+ * pairs in turn, so the small levels of different pairs overlap on the
+ * device.  Results equal those of w1_solve3d pair by pair.  Returns the
+ * first error any pair met (the pairs after it are not started).         */
+int w1_solve3d_batch(const w1_params* params, int32_t count,
+                     const double* const* p0, const double* const* p1,
+                     int32_t on_device, w1_result* out, int32_t workers);
+
 /* `steps` iterations of eq. (primaldual) in d = 3 in place on device arrays
  * (m1, m2, m3, phi), rho read only, element type by precision, mu = tau =
  * step_scale / (2 sqrt 3 / h) (step_scale <= 0: 1/2; at most 1).  fpr_out

@@ -100,6 +100,8 @@ def lib():
         "w1_op_potential": (C.c_int, [i32, i32, vp, vp, vp, vp]),
         "w1_op_evaluate": (C.c_int, [i32, i32, i32, vp, vp, vp, vp, dp, vp]),
         "w1_solve3d": (C.c_int, [C.POINTER(Params), vp, vp, i32, C.POINTER(Result), vp, vp, vp]),
+        "w1_solve3d_batch": (C.c_int, [C.POINTER(Params), i32, C.POINTER(vp), C.POINTER(vp), i32,
+                                       C.POINTER(Result), i32]),
         "w1_op_plain_steps3d": (C.c_int, [i32, i32, i32, C.c_double, i32, vp, vp, vp, vp, vp, dp, vp]),
         "w1_op_prox_steps3d": (C.c_int, [i32, i32, i32, C.c_double, i32] + [vp] * 10 + [dp, vp]),
     }
@@ -397,3 +399,23 @@ def op_prox_steps3d(n, metric, precision, steps, m1, m2, m3, w1, w2, w3, wb1, wb
                                     *[_ptr(x, d)[0] for x in (m1, m2, m3, w1, w2, w3, wb1, wb2, wb3, rho)],
                                     C.byref(out) if fpr else None, _stream(stream)), "w1_op_prox_steps3d")
     return out.value if fpr else None
+
+
+def solve3d_batch(p: Params, pairs, workers=0):
+    """w1_solve3d over a list of (p0, p1) pairs (all numpy or all cuda
+    tensors) on `workers` concurrent streams; returns the result dicts."""
+    k = len(pairs)
+    A = (C.c_void_p * k)()
+    B = (C.c_void_p * k)()
+    dev = None
+    for i, (a, b) in enumerate(pairs):
+        pa, da = _ptr(a, "float64")
+        pb, db = _ptr(b, "float64")
+        if dev is None:
+            dev = da
+        if da != dev or db != dev:
+            raise ValueError("all masses must be on the same side (host or device)")
+        A[i], B[i] = pa, pb
+    out = (Result * k)()
+    _check(lib().w1_solve3d_batch(C.byref(p), k, A, B, 1 if dev else 0, out, workers), "w1_solve3d_batch")
+    return [r.as_dict() for r in out]

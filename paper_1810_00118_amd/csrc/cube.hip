@@ -22,11 +22,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -885,22 +887,26 @@ int level_potential(hipStream_t s, const Level<T>& V, bool prox, const T** pot, 
 }
 
 template <typename T>
-int solve(const w1_params& prm, const double* p0, const double* p1, int on_device, w1_result* out, double* m_out,
-          double* psi_out, hipStream_t s) {
+size_t solve_bytes(const w1_params& prm) {
+  size_t bytes = 0;
+  for (int l = 0; l < prm.levels; ++l) bytes += level_bytes<T>(prm.n >> (prm.levels - 1 - l));
+  return bytes + (size_t)MAXB * NQ3 * sizeof(double) + 256 + NQ3 * sizeof(double) + 256 + sizeof(Gate) + 256;
+}
+
+// one solve in the caller's device block `mem` of solve_bytes<T>(prm) bytes
+template <typename T>
+int solve_in(const w1_params& prm, const double* p0, const double* p1, int on_device, w1_result* out, double* m_out,
+             double* psi_out, hipStream_t s, void* mem) {
   const double t0 = now_s();
   const int L = prm.levels;
   const bool prox = prm.algo == W1_ALGO_PROX;
   std::vector<Level<T>> lv(L);
-  size_t bytes = 0;
   for (int l = 0; l < L; ++l) {
     lv[l].n = prm.n >> (L - 1 - l);
     lv[l].N = (long long)(lv[l].n + 1) * (lv[l].n + 1) * (lv[l].n + 1);
-    bytes += level_bytes<T>(lv[l].n);
   }
-  bytes += (size_t)MAXB * NQ3 * sizeof(double) + 256 + NQ3 * sizeof(double) + 256 + sizeof(Gate) + 256;
-  DevBuf mem;
-  CHK(hipMalloc(&mem.p, bytes));
-  char* p = (char*)mem.p;
+  const size_t bytes = solve_bytes<T>(prm);
+  char* p = (char*)mem;
   auto take = [&](size_t b) {
     char* r = p;
     p += (b + 255) / 256 * 256;
@@ -926,7 +932,7 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
   double* part = (double*)take((size_t)MAXB * NQ3 * sizeof(double));
   double* dout = (double*)take(NQ3 * sizeof(double));
   Gate* gate = (Gate*)take(sizeof(Gate));
-  if ((size_t)(p - (char*)mem.p) > bytes) return W1_EINVAL;   // layout and size disagree (not expected)
+  if ((size_t)(p - (char*)mem) > bytes) return W1_EINVAL;   // layout and size disagree (not expected)
   for (int l = 0; l < L; ++l) {
     int st = upload_dct<T>(s, lv[l]);
     if (st) return st;
@@ -1091,6 +1097,49 @@ int solve(const w1_params& prm, const double* p0, const double* p1, int on_devic
   return W1_OK;
 }
 
+template <typename T>
+int solve(const w1_params& prm, const double* p0, const double* p1, int on_device, w1_result* out, double* m_out,
+          double* psi_out, hipStream_t s) {
+  DevBuf mem;
+  CHK(hipMalloc(&mem.p, solve_bytes<T>(prm)));
+  return solve_in<T>(prm, p0, p1, on_device, out, m_out, psi_out, s, mem.p);
+}
+
+// `count` pairs over `workers` host threads, each with its own stream and
+// device block, taking pairs in turn: the launch-bound small levels of
+// different pairs overlap on the device
+template <typename T>
+int solve_batch(const w1_params& prm, int count, const double* const* p0, const double* const* p1, int on_device,
+                w1_result* out, int workers) {
+  int dev = 0;
+  CHK(hipGetDevice(&dev));
+  std::atomic<int> next{0}, err{W1_OK};
+  auto run = [&]() {
+    int st = hip_status(hipSetDevice(dev), "hipSetDevice");
+    hipStream_t s = nullptr;
+    if (!st) st = hip_status(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    DevBuf mem;
+    if (!st) st = hip_status(hipMalloc(&mem.p, solve_bytes<T>(prm)), "hipMalloc");
+    while (!st && err.load() == W1_OK) {
+      const int i = next.fetch_add(1);
+      if (i >= count) break;
+      st = solve_in<T>(prm, p0[i], p1[i], on_device, &out[i], nullptr, nullptr, s, mem.p);
+    }
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+    if (st) {
+      int expected = W1_OK;
+      err.compare_exchange_strong(expected, st);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int k = 0; k < workers; ++k) th.emplace_back(run);
+  for (auto& t : th) t.join();
+  return err.load();
+}
+
 // single-step entry points: steps iterations in place on caller arrays
 template <typename T>
 int steps3(int n, int metric, bool prox, double scale, int steps, void* const* f, const void* rho, double* fpr_out,
@@ -1164,6 +1213,27 @@ extern "C" int w1_solve3d(const w1_params* p, const double* p0, const double* p1
   hipStream_t s = (hipStream_t)hip_stream;
   return p->precision == W1_FP32 ? cube::solve<float>(*p, p0, p1, on_device, out, m_out, psi_out, s)
                                  : cube::solve<double>(*p, p0, p1, on_device, out, m_out, psi_out, s);
+}
+
+extern "C" int w1_solve3d_batch(const w1_params* p, int32_t count, const double* const* p0,
+                                const double* const* p1, int32_t on_device, w1_result* out, int32_t workers) {
+  if (!p || count < 0 || (count > 0 && (!p0 || !p1 || !out)) || workers < 0 || workers > 16) return W1_EINVAL;
+  if (count == 0) return W1_OK;
+  for (int i = 0; i < count; ++i)
+    if (!p0[i] || !p1[i]) return W1_EINVAL;
+  // the same parameter checks as w1_solve3d (no masses needed for them)
+  if (p->n < 2 || p->n > 1024 || p->levels < 1 || p->levels > W1_MAX_LEVELS) return W1_EINVAL;
+  if (p->n % (1 << (p->levels - 1)) != 0 || (p->n >> (p->levels - 1)) < 2) return W1_EINVAL;
+  if (p->metric < W1_METRIC_L1 || p->metric > W1_METRIC_LINF) return W1_EINVAL;
+  if (p->algo != W1_ALGO_PLAIN && p->algo != W1_ALGO_PROX) return W1_EINVAL;
+  if (p->precision != W1_FP32 && p->precision != W1_FP64) return W1_EINVAL;
+  if (p->stop_rule != W1_STOP_KKT && p->stop_rule != W1_STOP_FPR) return W1_EINVAL;
+  if (!(p->tol > 0) || !std::isfinite(p->tol) || !std::isfinite(p->alpha)) return W1_EINVAL;
+  if (!std::isfinite(p->step_scale) || p->step_scale > 1.0) return W1_EINVAL;
+  if (p->max_iters < 1 || p->check_every < 1 || p->max_iters % p->check_every != 0) return W1_EINVAL;
+  const int w = std::min(workers > 0 ? workers : 4, count);
+  return p->precision == W1_FP32 ? cube::solve_batch<float>(*p, count, p0, p1, on_device, out, w)
+                                 : cube::solve_batch<double>(*p, count, p0, p1, on_device, out, w);
 }
 
 extern "C" int w1_op_plain_steps3d(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,

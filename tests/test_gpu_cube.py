@@ -205,6 +205,29 @@ def test_small_and_odd_grids_3d(n, L, algo):
     assert a["iters"] == b["iters"] and a["w1"] == b["w1"] and a["lo"] == b["lo"]
 
 
+@pytest.mark.parametrize("algo", [1, 2])
+def test_batch_equals_single_3d(algo):
+    """w1_solve3d_batch on concurrent streams returns each pair's w1_solve3d
+    result bit for bit (host and device masses); a bad pair fails the call."""
+    w1 = require_gpu()
+    import torch
+    n, L = 16, 2
+    pairs = [w1data.pair_gauss_3d(i, n=n) for i in range(6)]
+    prm = w1.params(n=n, levels=L, metric=2, algo=algo, precision=FP32, stop_rule=w1.STOP_FPR,
+                    tol=2e-6 if algo == 1 else 1e-5, alpha=-1.0, max_iters=20000, check_every=10)
+    batch = w1.solve3d_batch(prm, pairs, workers=3)
+    dev_pairs = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b in pairs]
+    batch_dev = w1.solve3d_batch(prm, dev_pairs, workers=4)
+    for (a, b), r, rd in zip(pairs, batch, batch_dev):
+        one = w1.solve3d(prm, a, b)
+        for k in ("iters", "w1", "lo", "hi", "dual"):
+            assert r[k] == one[k] and rd[k] == one[k], k
+    bad = list(pairs)
+    bad[3] = (pairs[3][0], pairs[3][1] * 1.01)
+    with pytest.raises(w1.W1Error):
+        w1.solve3d_batch(prm, bad, workers=2)
+
+
 def test_cube65_fp32_against_fp64():
     """65^3 nodes, 3 levels (17^3, 33^3, 65^3), paper-style FPR rule: the
     FP32 result within 1e-4 of the FP64 GPU result, the lower bound below
