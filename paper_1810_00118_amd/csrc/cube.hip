@@ -1,24 +1,29 @@
 // Algorithms 1 / 3 and 2 / 4 in d = 3 (the paper states the method for any d: the
 // divergence of Sec. 2.2 summed over three axes, the interpolations of
-// Sec. 3.3 as products of 1-D factors).  One pair per call, levels run one
-// after the other from the host.
+// Sec. 3.3 as products of 1-D factors).  One pair per call (or a list of
+// pairs over concurrent streams), levels run one after the other.
 //
 // Layout: a level of side n holds (n+1)^3 nodes, index
 // e = (i1 (n+1) + i2) (n+1) + i3 with i3 contiguous; flux components m1, m2,
 // m3 (m_a on the last node of axis a is not a variable and stays 0), the
-// extrapolated flux b = 2 m+ - m, the potential phi and rho, all in the
-// iterate precision T, plus two FP64 planes for the density pyramid.
+// extrapolated flux b = 2 m+ - m (Algorithm 1) or v (Algorithm 2), vphi and
+// vphibar, the potential phi, rho and the Poisson residual and scratch, all
+// in the iterate precision T, plus two FP64 planes for the density pyramid
+// and the DCT tables.
 //
 // An Algorithm 1 iteration is two node-parallel kernels: the flux half (reads
 // phi at the node and its three forward neighbours, writes m+ and b) and the
 // potential half (reads b at the node and its three backward neighbours,
 // updates phi in place).  An Algorithm 2 iteration is a pre kernel
 // (v = m - mu vphibar and r = A v - rho), the Neumann Poisson solve as six
-// one-axis DCT passes (products with the orthonormal DCT matrix, the
-// eigenvalue division fused into the third), and a post kernel (m+, vphi+,
-// vphibar+).  The stop test's sums (R^k of eq. (pd_stop), or the normalised KKT
-// residual) are block partials in FP64, summed by a one-block kernel and
-// read by the host every `check_every` iterations.
+// one-axis DCT passes (products with the orthonormal DCT matrix, on the
+// matrix cores in FP32, the eigenvalue division fused into the third), and
+// a post kernel (m+, vphi+, vphibar+).  The stop test's sums (R^k of eq.
+// (pd_stop), G^k of eq. (pdhg_stop), or the normalised KKT residual) are
+// block partials in FP64, finished by a one-block kernel that decides the
+// stop on the device every `check_every` iterations; the iteration kernels
+// skip their work once the level has stopped, so the host queues many
+// blocks between its reads of the stop state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
