@@ -272,9 +272,11 @@ int w1_op_evaluate(int32_t n, int32_t metric, int32_t precision,
 /* ---- d = 3 ---------------------------------------------------------------
  * The method is stated for any d (Sec. 2.2: the divergence sums D_{h,i} over
  * the d axes; Sec. 3.3: the interpolations are products of 1-D factors).
- * These run Algorithms 1 / 3 and 2 / 4 on the (n+1)^3 vertex grid of [0,1]^3, one pair
- * per call, synchronously on `hip_stream` (NULL = default stream).  Arrays
- * are dense, index (i1 (n+1) + i2) (n+1) + i3, i3 contiguous.
+ * These run Algorithms 1 / 3 and 2 / 4 on the (n+1)^3 vertex grid of
+ * [0,1]^3, one pair per call synchronously on `hip_stream` (NULL = default
+ * stream), or a list of pairs over streams of their own
+ * (w1_solve3d_batch).  Arrays are dense, index (i1 (n+1) + i2) (n+1) + i3,
+ * i3 contiguous.
  */
 
 /* Algorithm 3 (algo W1_ALGO_PLAIN) or 4 (W1_ALGO_PROX) in d = 3.  p0, p1:
