@@ -59,3 +59,32 @@ def test_tuner_table_is_host_only():
     import paper_1810_00118_amd as w1
     w1.tuner_reset()
     assert w1.tuner_table() == []
+
+
+def test_d3_entry_points_check_arguments_without_a_device():
+    # the d = 3 entry points validate every argument before touching a device
+    if not os.path.exists(LIB):
+        pytest.skip("libw1.so not built")
+    import ctypes as C
+
+    import numpy as np
+
+    import paper_1810_00118_amd as w1
+    L = w1.lib()
+    n = 4
+    a = np.full((n + 1,) * 3, 1.0 / (n + 1) ** 3)
+    out = w1.Result()
+    ok = dict(n=n, levels=2, metric=2, algo=w1.ALGO_PLAIN, precision=w1.FP32, stop_rule=w1.STOP_FPR, tol=1e-6,
+              max_iters=100, check_every=10)
+    for bad in (dict(n=3), dict(levels=3), dict(tol=0.0), dict(metric=0), dict(algo=3), dict(step_scale=2.0),
+                dict(max_iters=15), dict(precision=3)):
+        prm = w1.params(**dict(ok, **bad))
+        st = L.w1_solve3d(C.byref(prm), a.ctypes.data, a.ctypes.data, 0, C.byref(out), None, None, None)
+        assert st == w1.W1_EINVAL, bad
+    prm = w1.params(**ok)
+    assert L.w1_solve3d_batch(C.byref(prm), 0, None, None, 0, None, 4) == w1.W1_OK
+    ptrs = (C.c_void_p * 1)(a.ctypes.data)
+    res = (w1.Result * 1)()
+    assert L.w1_solve3d_batch(C.byref(prm), 1, ptrs, ptrs, 0, res, 17) == w1.W1_EINVAL
+    bad = w1.params(**dict(ok, tol=-1.0))
+    assert L.w1_solve3d_batch(C.byref(bad), 1, ptrs, ptrs, 0, res, 2) == w1.W1_EINVAL
