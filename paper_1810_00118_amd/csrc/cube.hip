@@ -694,6 +694,19 @@ struct DevBuf {
   }
 };
 
+// a solve's device block from the library's exact-size cache; returned
+// after the stream has drained (also on an error path)
+struct Staged {
+  char* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  ~Staged() {
+    if (!p) return;
+    (void)hipStreamSynchronize(s);
+    stage_free(bytes, p);
+  }
+};
+
 // planes of one level: Algorithm 1 uses m, b (= 2 m+ - m), phi; Algorithm 2
 // uses m, w (vphi), wb (vphibar), b (= v), r (residual, then u) and t (DCT
 // scratch); rho, the FP64 density pair and the DCT tables always
@@ -1105,8 +1118,11 @@ int solve_in(const w1_params& prm, const double* p0, const double* p1, int on_de
 template <typename T>
 int solve(const w1_params& prm, const double* p0, const double* p1, int on_device, w1_result* out, double* m_out,
           double* psi_out, hipStream_t s) {
-  DevBuf mem;
-  CHK(hipMalloc(&mem.p, solve_bytes<T>(prm)));
+  Staged mem;
+  mem.bytes = solve_bytes<T>(prm);
+  mem.s = s;
+  int st = stage_alloc(mem.bytes, &mem.p);
+  if (st) return st;
   return solve_in<T>(prm, p0, p1, on_device, out, m_out, psi_out, s, mem.p);
 }
 
@@ -1123,17 +1139,18 @@ int solve_batch(const w1_params& prm, int count, const double* const* p0, const 
     int st = hip_status(hipSetDevice(dev), "hipSetDevice");
     hipStream_t s = nullptr;
     if (!st) st = hip_status(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreateWithFlags");
-    DevBuf mem;
-    if (!st) st = hip_status(hipMalloc(&mem.p, solve_bytes<T>(prm)), "hipMalloc");
-    while (!st && err.load() == W1_OK) {
-      const int i = next.fetch_add(1);
-      if (i >= count) break;
-      st = solve_in<T>(prm, p0[i], p1[i], on_device, &out[i], nullptr, nullptr, s, mem.p);
-    }
-    if (s) {
-      (void)hipStreamSynchronize(s);
-      (void)hipStreamDestroy(s);
-    }
+    {
+      Staged mem;
+      mem.bytes = solve_bytes<T>(prm);
+      mem.s = s;
+      if (!st) st = stage_alloc(mem.bytes, &mem.p);
+      while (!st && err.load() == W1_OK) {
+        const int i = next.fetch_add(1);
+        if (i >= count) break;
+        st = solve_in<T>(prm, p0[i], p1[i], on_device, &out[i], nullptr, nullptr, s, mem.p);
+      }
+    }   // the block goes back to the cache once the stream has drained
+    if (s) (void)hipStreamDestroy(s);
     if (st) {
       int expected = W1_OK;
       err.compare_exchange_strong(expected, st);
