@@ -29,6 +29,10 @@ Readings of the paper taken here (each one is listed in the design notes):
   R8 the potential is reported zero-mean;
   R9 stopping: the paper's fixed-point residual (R^k or G^k) against
      eps_l, or a normalised KKT residual against tol_l; both on a cadence.
+     The KKT residual (the paper defines none) is the largest of the
+     relative distance of m to {A m = rho} (the norm of the minimum-norm
+     correction over f(m)), the RMS Lipschitz excess of the potential and
+     the relative primal-dual gap.
 """
 from __future__ import annotations
 
@@ -45,7 +49,7 @@ __all__ = [
     "pd_step", "prox_step", "potential_from_dual",
     "prolong_potential", "prolong_flux", "restrict_density",
     "level_sides", "level_tolerances", "paper_stop_tolerance",
-    "prepare_levels", "kkt_plain", "kkt_prox", "evaluate", "solve",
+    "prepare_levels", "min_norm_correction", "primal_residual", "kkt_plain", "kkt_prox", "evaluate", "solve",
 ]
 
 
@@ -417,15 +421,28 @@ def _dual_excess(psi, h, p):
     return math.sqrt(float(np.sum(ex * ex)) * h * h), float(gn.max())
 
 
+def min_norm_correction(m1, m2, rho, h):
+    """A*(A A*)^{-1}(A m - rho): the flux change of least L^2_h norm that
+    makes m feasible (m minus it satisfies A m = rho).  Its norm is the
+    primal part of the normalised KKT residual; m minus it is the feasible
+    flux of the certificate's upper bound."""
+    return div_adj(poisson_neumann(div(m1, m2, h) - rho, h), h)
+
+
+def primal_residual(m1, m2, rho, h):
+    """||A*(A A*)^{-1}(A m - rho)||_{L^2_h}, the distance of m to the
+    feasible set {A m = rho} in the L^2_h norm."""
+    c1, c2 = min_norm_correction(m1, m2, rho, h)
+    return math.sqrt(inner_h((c1, c2), (c1, c2), h))
+
+
 def kkt_plain(m1, m2, phi, rho, h, p):
     """Normalised KKT residual of an Algorithm 1 iterate:
-    max(||A m - rho||/||rho||, RMS Lipschitz excess of -phi, relative gap)
-    with P = f(m), D = -<phi, rho>_h."""
-    res = div(m1, m2, h) - rho
-    nr = math.sqrt(inner_h(rho, rho, h))
-    r_pri = math.sqrt(inner_h(res, res, h)) / max(nr, 1e-300)
-    r_dual, _ = _dual_excess(-phi, h, p)
+    max(||A*(A A*)^{-1}(A m - rho)||_{L^2_h} / P, RMS Lipschitz excess of
+    -phi, relative gap) with P = f(m), D = -<phi, rho>_h."""
     P = flux_cost(m1, m2, h, p)
+    r_pri = primal_residual(m1, m2, rho, h) / max(P, 1e-300)
+    r_dual, _ = _dual_excess(-phi, h, p)
     D = -inner_h(phi, rho, h)
     r_gap = abs(P - D) / max(abs(P), abs(D), 1e-300)
     return max(r_pri, r_dual, r_gap), P, D
@@ -435,11 +452,9 @@ def kkt_prox(m1, m2, w1, w2, rho, h, p):
     """Same measure for an Algorithm 2 iterate, the potential psi taken from
     Appendix B: D = <psi, rho>_h."""
     psi = potential_from_dual(w1, w2, h)
-    res = div(m1, m2, h) - rho
-    nr = math.sqrt(inner_h(rho, rho, h))
-    r_pri = math.sqrt(inner_h(res, res, h)) / max(nr, 1e-300)
-    r_dual, _ = _dual_excess(psi, h, p)
     P = flux_cost(m1, m2, h, p)
+    r_pri = primal_residual(m1, m2, rho, h) / max(P, 1e-300)
+    r_dual, _ = _dual_excess(psi, h, p)
     D = inner_h(psi, rho, h)
     r_gap = abs(P - D) / max(abs(P), abs(D), 1e-300)
     return max(r_pri, r_dual, r_gap), P, D

@@ -20,7 +20,7 @@ import numpy as np
 import scipy.fft
 
 __all__ = [
-    "div", "div_adj", "grad_fwd", "pointwise_norm", "flux_cost", "inner_h", "shrink",
+    "div", "div_adj", "grad_fwd", "pointwise_norm", "flux_cost", "inner_h", "shrink", "primal_residual",
     "project_dual_ball", "poisson_neumann", "norm_A_bound", "plain_step_sizes", "pd_step",
     "prolong_potential", "prolong_flux", "restrict_density", "prepare_levels", "kkt_plain",
     "evaluate_plain", "solve_plain", "prox_step", "potential_from_dual", "kkt_prox", "evaluate", "solve_prox",
@@ -240,10 +240,9 @@ def kkt_prox(m, w, rho, h, p):
     """The normalised KKT residual of an Algorithm 2 iterate with the
     potential of Appendix B: D = <psi, rho>_h."""
     psi = potential_from_dual(w, h)
-    res = div(m, h) - rho
-    r_pri = math.sqrt(inner_h(res, res, h)) / max(math.sqrt(inner_h(rho, rho, h)), 1e-300)
-    r_dual, _ = _dual_excess(psi, h, p)
     P = flux_cost(m, h, p)
+    r_pri = primal_residual(m, rho, h) / max(P, 1e-300)
+    r_dual, _ = _dual_excess(psi, h, p)
     D = inner_h(psi, rho, h)
     return max(r_pri, r_dual, abs(P - D) / max(abs(P), abs(D), 1e-300)), P, D
 
@@ -423,13 +422,19 @@ def _dual_excess(psi, h, p):
     return math.sqrt(float(np.sum(ex * ex)) * h ** psi.ndim), float(gn.max())
 
 
+def primal_residual(m, rho, h):
+    """||A*(A A*)^{-1}(A m - rho)||_{L^2_h}: the norm of the minimum-norm
+    flux correction that makes m feasible."""
+    corr = div_adj(poisson_neumann(div(m, h) - rho, h), h)
+    return math.sqrt(inner_h(corr, corr, h))
+
+
 def kkt_plain(m, phi, rho, h, p):
-    """max(||A m - rho|| / ||rho||, RMS Lipschitz excess of -phi, relative
-    gap) with P = f(m), D = -<phi, rho>_h."""
-    res = div(m, h) - rho
-    r_pri = math.sqrt(inner_h(res, res, h)) / max(math.sqrt(inner_h(rho, rho, h)), 1e-300)
-    r_dual, _ = _dual_excess(-phi, h, p)
+    """max(||A*(A A*)^{-1}(A m - rho)|| / P, RMS Lipschitz excess of -phi,
+    relative gap) with P = f(m), D = -<phi, rho>_h."""
     P = flux_cost(m, h, p)
+    r_pri = primal_residual(m, rho, h) / max(P, 1e-300)
+    r_dual, _ = _dual_excess(-phi, h, p)
     D = -inner_h(phi, rho, h)
     return max(r_pri, r_dual, abs(P - D) / max(abs(P), abs(D), 1e-300)), P, D
 
