@@ -83,16 +83,35 @@ typedef struct {
                              (tol_formula_propose); paper's choice -1        */
     double  step_scale;   /* plain: mu = tau = step_scale / (2 sqrt 2 / h);
                              prox: mu = tau = step_scale;  <= 0 selects the
-                             paper's 1/2 for both; at most 1 (1 is the
-                             practical choice of the footnotes to Sec. 3.1:
-                             mu = tau = 1/||A|| with the bound 2 sqrt 2 / h
-                             for ||A||, and 1 for Algorithm 2)              */
+                             paper's 1/2 for both; 1 is the practical choice
+                             of the footnotes to Sec. 3.1 (mu = tau = 1/||A||
+                             with the bound 2 sqrt 2 / h for ||A||, and 1 for
+                             Algorithm 2); above 1 (at most 2) convergence
+                             is not guaranteed and diverge_window must guard
+                             the FPR rule                                   */
     int32_t max_iters;    /* per-level iteration cap (> 0)                    */
     int32_t check_every;  /* stop-test cadence in iterations (> 0)           */
     int32_t block_steps;  /* plain: PDHG steps fused per launch (temporal
                              block depth), 0..26; 0 = autotuned; otherwise
                              the deepest divisor of check_every not above it */
     int32_t flags;        /* W1_FLAG_* bit set                                */
+    double  h;            /* finest grid spacing; <= 0 selects 1/n (Omega =
+                             [0,1]^2).  The solve runs on the unit square and
+                             the outputs are rescaled to Omega = [0, n h]^2
+                             (Sec. 2.2 with the domain scaled by c = n h, unit
+                             masses): W1, dual, lo, hi and level_w1 by c, the
+                             flux by 1/c (1/c^2 in d = 3), the potential by c;
+                             tolerances and stop measures refer to the unit
+                             square                                          */
+    int32_t level_caps[W1_MAX_LEVELS]; /* per-level iteration caps, coarsest
+                             first; 0 takes max_iters; each a multiple of
+                             check_every                                     */
+    int32_t diverge_window; /* FPR rule: a level whose stop measure rises at
+                             this many consecutive stop tests ends as
+                             W1_SOLVE_DIVERGED (R^k of eq. (pd_stop) does not
+                             increase while mu tau ||A||^2 < 1, Sec. 3.1);
+                             0 = off; at least 1 when step_scale > 1        */
+    int32_t reserved;     /* 0                                                */
 } w1_params;
 
 /* W1_FLAG_NO_RESIDENT: never keep a whole level in one workgroup's LDS     */
@@ -136,7 +155,10 @@ int w1_params_check(const w1_params* p);
 size_t w1_bytes_per_solve(const w1_params* p);
 
 /*
- * w1_plan: create a solver handle.
+ * w1_plan: create a solver handle for the multilevel method of Sec. 3.2
+ * (Algorithm 3 or 4 on the level hierarchy h_l = 2^(L-l) h): per-level
+ * state for every slot, the DCT tables of the Poisson solves of eq. (pdhg)
+ * and Appendix B, and the launch plans.
  *   params          : used by w1_solve (copied).
  *   batch_capacity  : most pairs one w1_solve call may take (>= 1).
  *   hbm_budget_bytes: device bytes the handle may hold for solve state; 0

@@ -498,9 +498,14 @@ def solve(p0, p1, n, L=1, p=1, algo=1, stop="kkt", tol=1e-6, alpha=-1.0,
     stop = "fpr": stop when R^k (or G^k) <= eps_l (eq. (pd_stop)/(pdhg_stop)).
     tol_l (or eps_l) = tol (or eps_L) * (h_l/h)^alpha.  Checks run every
     `check_every` iterations and at the cap.  Level 1 starts from zero.
-    `init` optionally supplies the level-1 start (tests of single steps).
+    `max_iters` is one cap for every level or a list of per-level caps,
+    coarsest first.  `init` optionally supplies the level-1 start (tests of
+    single steps).
     """
     sides = level_sides(n, L)
+    caps = [int(max_iters)] * L if np.isscalar(max_iters) else [int(c) for c in max_iters]
+    if len(caps) != L or min(caps) < 1:
+        raise ValueError("max_iters: one positive cap, or one per level")
     rhos = prepare_levels(p0, p1, n, L)
     base = eps_L if (stop == "fpr" and eps_L is not None) else tol
     tols = level_tolerances(base, alpha, n, L)
@@ -525,11 +530,11 @@ def solve(p0, p1, n, L=1, p=1, algo=1, stop="kkt", tol=1e-6, alpha=-1.0,
             while True:
                 m1, m2, phi, R = pd_step(m1, m2, phi, rho, h, mu, tau, p)
                 k += 1
-                if k % check_every == 0 or k >= max_iters:
+                if k % check_every == 0 or k >= caps[l]:
                     meas = R if stop == "fpr" else kkt_plain(m1, m2, phi, rho, h, p)[0]
                     if meas <= tols[l]:
                         break
-                    if k >= max_iters:
+                    if k >= caps[l]:
                         out["status"] = "maxiter"
                         break
             state = (m1, m2, phi)
@@ -549,11 +554,11 @@ def solve(p0, p1, n, L=1, p=1, algo=1, stop="kkt", tol=1e-6, alpha=-1.0,
             while True:
                 m1, m2, w1, w2, wb1, wb2, G = prox_step(m1, m2, w1, w2, wb1, wb2, rho, h, mu, tau, p)
                 k += 1
-                if k % check_every == 0 or k >= max_iters:
+                if k % check_every == 0 or k >= caps[l]:
                     meas = G if stop == "fpr" else kkt_prox(m1, m2, w1, w2, rho, h, p)[0]
                     if meas <= tols[l]:
                         break
-                    if k >= max_iters:
+                    if k >= caps[l]:
                         out["status"] = "maxiter"
                         break
             state = (m1, m2, w1, w2)

@@ -39,7 +39,8 @@ class Params(C.Structure):
         ("n", C.c_int32), ("levels", C.c_int32), ("metric", C.c_int32), ("algo", C.c_int32),
         ("precision", C.c_int32), ("stop_rule", C.c_int32), ("tol", C.c_double), ("alpha", C.c_double),
         ("step_scale", C.c_double), ("max_iters", C.c_int32), ("check_every", C.c_int32),
-        ("block_steps", C.c_int32), ("flags", C.c_int32),
+        ("block_steps", C.c_int32), ("flags", C.c_int32), ("h", C.c_double),
+        ("level_caps", C.c_int32 * MAX_LEVELS), ("diverge_window", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -135,6 +136,9 @@ def params(**kw) -> Params:
     for k, v in kw.items():
         if not hasattr(p, k):
             raise TypeError(f"unknown parameter {k}")
+        if k == "level_caps":
+            caps = list(v) + [0] * (MAX_LEVELS - len(v))
+            v = (C.c_int32 * MAX_LEVELS)(*caps)
         setattr(p, k, v)
     return p
 

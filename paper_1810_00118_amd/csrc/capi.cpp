@@ -51,11 +51,19 @@ extern "C" int w1_params_check(const w1_params* p) {
   // checks fall on multiples of check_every; the cap must be one of them
   if (p->max_iters % p->check_every != 0) return W1_EINVAL;
   if (p->block_steps < 0 || p->block_steps > TILED_MAX_STEPS) return W1_EINVAL;
+  if (!std::isfinite(p->h)) return W1_EINVAL;
+  for (int l = 0; l < W1_MAX_LEVELS; ++l) {
+    const int c = p->level_caps[l];
+    if (c < 0 || (c > 0 && (l >= p->levels || c % p->check_every != 0))) return W1_EINVAL;
+  }
+  if (p->diverge_window < 0 || p->reserved != 0) return W1_EINVAL;
   // plain: mu tau ||A||^2 < 1 holds up to step_scale 1 (the bound 2 sqrt 2 / h
   // exceeds ||A||); prox: mu tau <= 1, the practical choice of the paper.
   // Beyond, the fixed-point residual is no longer a norm of the iterate
-  // change and can pass the stop test on a diverging iterate
-  if (p->step_scale > 1.0) return W1_EINVAL;
+  // change and can pass the stop test on a diverging iterate: larger steps
+  // (up to 2) only with the FPR rule and the rise-window guard
+  if (p->step_scale > 2.0) return W1_EINVAL;
+  if (p->step_scale > 1.0 && (p->diverge_window < 1 || p->stop_rule != W1_STOP_FPR)) return W1_EINVAL;
   return W1_OK;
 }
 
@@ -248,13 +256,15 @@ static void worker_loop(w1_ctx* h) {
       if (b) b->retire(in.bytes, in.mem);
       else stage_free(in.bytes, in.mem);
       if (st) {
+        const size_t bytes = request_bytes(r->prm);
         std::lock_guard<std::mutex> lk(h->mu);
         r->res.status = W1_SOLVE_REJECTED;
         r->state = Request::DONE;
         h->worker_error = st;
-        h->in_use -= request_bytes(r->prm);
+        h->in_use -= bytes;
         h->running -= 1;
         h->finished += 1;
+        r->handed = true;   // last access to r by the worker
         h->cv.notify_all();
       }
     }
@@ -274,11 +284,13 @@ static void worker_loop(w1_ctx* h) {
       for (Request* r : done) {
         if (r->want_fields && r->res.status != W1_SOLVE_REJECTED && r->res.status != W1_SOLVE_FAILED)
           bp->fetch_fields(r);
+        const size_t bytes = request_bytes(r->prm);
         bp->release(r);
         std::lock_guard<std::mutex> lk(h->mu);
-        h->in_use -= request_bytes(r->prm);
+        h->in_use -= bytes;
         h->running -= 1;
         h->finished += 1;
+        r->handed = true;   // last access to r by the worker
       }
       if (!done.empty()) h->cv.notify_all();
     }
@@ -348,7 +360,7 @@ extern "C" int w1_poll(w1_handle h, uint64_t ticket, w1_result* out, double* m1,
     std::lock_guard<std::mutex> lk(h->mu);
     auto it = h->all.find(ticket);
     if (it == h->all.end()) return W1_ENOTFOUND;
-    if (it->second->state != Request::DONE || it->second->slot >= 0) return W1_EAGAIN;
+    if (!it->second->handed) return W1_EAGAIN;
     r = std::move(it->second);
     h->all.erase(it);
   }

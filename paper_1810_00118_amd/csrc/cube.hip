@@ -56,6 +56,8 @@ struct Gate {
   int status;
   int iters;
   double measure;
+  int rises;   // stop tests in a row whose measure rose
+  int pad;
 };
 
 #define CHK(x)                                      \
@@ -231,10 +233,11 @@ __global__ __launch_bounds__(NT) void k3_pot(int n, const T* __restrict__ b0, co
 // ---------------------------------------------------------------------------
 // evaluation sums for a flux m and a potential pot taken with sign sgn
 // (psi = sgn pot: -phi for Algorithm 1, the Appendix B potential for
-// Algorithm 2): q0 sum ||m||_p, q1 sum psi rho, q2 sum (A m - rho)^2,
-// q3 sum rho^2, q4 sum (||grad psi||_q - 1)_+^2, q5 max ||grad psi||_q,
-// q6 sum pot, and with a correction potential c (may be NULL) q7 sum of
-// ||m - A* c||_p, the flux made feasible when c = (A A*)^{-1}(A m - rho)
+// Algorithm 2): q0 sum ||m||_p, q1 sum psi rho, q4 sum
+// (||grad psi||_q - 1)_+^2, q5 max ||grad psi||_q, q6 sum pot, and with the
+// correction potential c = (A A*)^{-1}(A m - rho) (may be NULL) q2 sum
+// |grad+ c|^2 (the squared norm of the least-norm flux correction A* c,
+// over h^3) and q7 sum ||m - A* c||_p (the flux made feasible); q3 is 0
 // ---------------------------------------------------------------------------
 template <typename T, int METRIC>
 __global__ __launch_bounds__(NT) void k3_eval(int n, const T* __restrict__ m0, const T* __restrict__ m1,
@@ -253,25 +256,20 @@ __global__ __launch_bounds__(NT) void k3_eval(int n, const T* __restrict__ m0, c
     const double g0 = x.i1 < n ? (sgn * (double)pot[e + S1] - pc) * ih : 0.0;
     const double g1 = x.i2 < n ? (sgn * (double)pot[e + N1] - pc) * ih : 0.0;
     const double g2 = x.i3 < n ? (sgn * (double)pot[e + 1] - pc) * ih : 0.0;
-    double dv = (x.i1 < n ? a : 0.0) - (x.i1 > 0 ? (double)m0[e - S1] : 0.0);
-    dv += (x.i2 < n ? b : 0.0) - (x.i2 > 0 ? (double)m1[e - N1] : 0.0);
-    dv += (x.i3 < n ? c : 0.0) - (x.i3 > 0 ? (double)m2[e - 1] : 0.0);
-    const double r = dv * ih - rr;
     const double gq = norm_q3_<double, METRIC>(g0, g1, g2);
     const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
     v[0] += norm_p3_<double, METRIC>(a, b, c);
     v[1] += pc * rr;
-    v[2] += r * r;
-    v[3] += rr * rr;
     v[4] += ex * ex;
     v[5] = gq > v[5] ? gq : v[5];
     v[6] += pr;
     if (corr) {
       const double cc = (double)corr[e];
-      const double f0 = x.i1 < n ? a - (cc - (double)corr[e + S1]) * ih : a;
-      const double f1 = x.i2 < n ? b - (cc - (double)corr[e + N1]) * ih : b;
-      const double f2 = x.i3 < n ? c - (cc - (double)corr[e + 1]) * ih : c;
-      v[7] += norm_p3_<double, METRIC>(f0, f1, f2);
+      const double c0 = x.i1 < n ? ((double)corr[e + S1] - cc) * ih : 0.0;
+      const double c1 = x.i2 < n ? ((double)corr[e + N1] - cc) * ih : 0.0;
+      const double c2 = x.i3 < n ? ((double)corr[e + 1] - cc) * ih : 0.0;
+      v[2] += c0 * c0 + c1 * c1 + c2 * c2;
+      v[7] += norm_p3_<double, METRIC>(a + c0, b + c1, c + c2);
     }
   }
   block_out_(v, part);
@@ -294,7 +292,7 @@ __global__ __launch_bounds__(NT) void k3_final(const double* __restrict__ part, 
 // measure, or at the cap
 __global__ __launch_bounds__(NT) void k3_check(const double* __restrict__ part, int nb, double* __restrict__ sums,
                                                Gate* __restrict__ gate, int kind, int rule, double mu, double tau,
-                                               int n, double tol, int steps, int cap) {
+                                               int n, double tol, int steps, int cap, int divwin) {
   if (gate->status != G_RUN) return;   // read by every thread before any write below
   double q[NQ3];
   final_sums_(part, nb, sums, q);
@@ -307,15 +305,23 @@ __global__ __launch_bounds__(NT) void k3_check(const double* __restrict__ part, 
                                    : (q[0] / mu + q[1] / tau + 2.0 * q[2]) * h3;
     } else {
       const double P = q[0] * h3, D = q[1] * h3;
-      const double rp = sqrt(q[2] * h3) / fmax(sqrt(q[3] * h3), 1e-300);
+      const double rp = sqrt(q[2] * h3) / fmax(P, 1e-300);
       const double rd = sqrt(q[4] * h3);
       const double gap = fabs(P - D) / fmax(fmax(fabs(P), fabs(D)), 1e-300);
       meas = fmax(rp, fmax(rd, gap));
     }
     const int it = gate->iters + steps;
+    // the FPR rule's guard: a measure that rises at divwin tests in a row
+    const int rises = gate->iters > 0 && meas > gate->measure ? gate->rises + 1 : 0;
     gate->iters = it;
     gate->measure = meas;
-    gate->status = !isfinite(meas) ? G_DIVERGED : (meas <= tol ? G_CONV : (it >= cap ? G_CAP : G_RUN));
+    gate->rises = rises;
+    // (a negative R^k / G^k: the step metric is no longer positive definite)
+    const bool guard = rule == W1_STOP_FPR && divwin > 0;
+    gate->status = !isfinite(meas) || (guard && meas < 0.0) ? G_DIVERGED
+                   : meas <= tol ? G_CONV
+                   : (guard && rises >= divwin) ? G_DIVERGED
+                   : it >= cap ? G_CAP : G_RUN;
   }
 }
 
@@ -872,7 +878,7 @@ inline Eval eval_of(const double* q, int n, bool cert) {
   Eval e;
   e.P = q[0] * h3;
   e.D = q[1] * h3;
-  const double rp = std::sqrt(q[2] * h3) / std::fmax(std::sqrt(q[3] * h3), 1e-300);
+  const double rp = std::sqrt(q[2] * h3) / std::fmax(e.P, 1e-300);
   const double rd = std::sqrt(q[4] * h3);
   const double gap = std::fabs(e.P - e.D) / std::fmax(std::fmax(std::fabs(e.P), std::fabs(e.D)), 1e-300);
   e.kkt = std::fmax(rp, std::fmax(rd, gap));
@@ -1032,9 +1038,10 @@ int solve_in(const w1_params& prm, const double* p0, const double* p1, int on_de
     // blocks queued past the stop skip their work)
     CHK(hipMemsetAsync(gate, 0, sizeof(Gate), s));
     const bool fpr = prm.stop_rule == W1_STOP_FPR;
-    const int total = prm.max_iters / ce;
+    const int cap = prm.level_caps[l] > 0 ? prm.level_caps[l] : prm.max_iters;
+    const int total = cap / ce;
     int queued = 0, burst = 4;
-    Gate g{G_RUN, 0, 0.0};
+    Gate g{G_RUN, 0, 0.0, 0, 0};
     while (g.status == G_RUN && queued < total) {
       const int B = std::min(burst, total - queued);
       for (int b = 0; b < B; ++b) {
@@ -1051,11 +1058,17 @@ int solve_in(const w1_params& prm, const double* p0, const double* p1, int on_de
             pot = V.r;
             sgn = 1.0;
           }
-          st = eval_sums<T>(s, V, prm.metric, pot, sgn, nullptr, part, &gate->status);
+          // the correction potential (A A*)^{-1}(A m - rho) in b[0] (b is
+          // free between iterations), b[1] scratch
+          k3_div<T><<<nb, NT, 0, s>>>(V.n, V.m[0], V.m[1], V.m[2], V.rho, V.b[0], &gate->status);
+          CHK(hipGetLastError());
+          st = poisson3<T>(s, V, V.b[0], V.b[1], &gate->status);
+          if (st) return st;
+          st = eval_sums<T>(s, V, prm.metric, pot, sgn, V.b[0], part, &gate->status);
           if (st) return st;
         }
-        k3_check<<<1, NT, 0, s>>>(part, nb, dout, gate, prm.algo, prm.stop_rule, mu, mu, V.n, tol, ce,
-                                  prm.max_iters);
+        k3_check<<<1, NT, 0, s>>>(part, nb, dout, gate, prm.algo, prm.stop_rule, mu, mu, V.n, tol, ce, cap,
+                                  prm.diverge_window);
         CHK(hipGetLastError());
       }
       queued += B;
@@ -1092,11 +1105,14 @@ int solve_in(const w1_params& prm, const double* p0, const double* p1, int on_de
   st = finish_sums(s, part, blocks_for(V.N), dout, q);
   if (st) return st;
   const Eval ev = eval_of(q, V.n, true);
-  out->w1 = ev.P;
-  out->dual = ev.D;
-  out->lo = ev.lo;
-  out->hi = ev.hi;
+  // outputs on [0, c]^3 (w1_params.h): W1 by c, flux by 1/c^2, potential by c
+  const double c = domain_scale(prm);
+  out->w1 = c * ev.P;
+  out->dual = c * ev.D;
+  out->lo = c * ev.lo;
+  out->hi = c * ev.hi;
   out->kkt = ev.kkt;
+  for (int l = 0; l < out->levels_run; ++l) out->level_w1[l] *= c;
   if ((m_out || psi_out) && out->levels_run == L) {
     DevBuf ex;
     const size_t need = (m_out ? 3 : 0) * (size_t)V.N * 8 + (psi_out ? (size_t)V.N * 8 : 0);
@@ -1110,6 +1126,12 @@ int solve_in(const w1_params& prm, const double* p0, const double* p1, int on_de
     if (m_out) CHK(hipMemcpyAsync(m_out, om, 3 * (size_t)V.N * 8, hipMemcpyDeviceToHost, s));
     if (psi_out) CHK(hipMemcpyAsync(psi_out, op, (size_t)V.N * 8, hipMemcpyDeviceToHost, s));
     CHK(hipStreamSynchronize(s));
+    if (c != 1.0) {
+      if (m_out)
+        for (long long e = 0; e < 3 * V.N; ++e) m_out[e] /= c * c;
+      if (psi_out)
+        for (long long e = 0; e < V.N; ++e) psi_out[e] *= c;
+    }
   }
   out->seconds = now_s() - t0;
   return W1_OK;
@@ -1215,6 +1237,27 @@ int steps3(int n, int metric, bool prox, double scale, int steps, void* const* f
   return W1_OK;
 }
 
+// parameter checks of the d = 3 entry points (no masses needed for them)
+bool params_ok(const w1_params* p) {
+  if (p->n < 2 || p->n > 1024 || p->levels < 1 || p->levels > W1_MAX_LEVELS) return false;
+  if (p->n % (1 << (p->levels - 1)) != 0 || (p->n >> (p->levels - 1)) < 2) return false;
+  if (p->metric < W1_METRIC_L1 || p->metric > W1_METRIC_LINF) return false;
+  if (p->algo != W1_ALGO_PLAIN && p->algo != W1_ALGO_PROX) return false;
+  if (p->precision != W1_FP32 && p->precision != W1_FP64) return false;
+  if (p->stop_rule != W1_STOP_KKT && p->stop_rule != W1_STOP_FPR) return false;
+  if (!(p->tol > 0) || !std::isfinite(p->tol) || !std::isfinite(p->alpha) || !std::isfinite(p->h)) return false;
+  if (p->max_iters < 1 || p->check_every < 1 || p->max_iters % p->check_every != 0) return false;
+  for (int l = 0; l < W1_MAX_LEVELS; ++l) {
+    const int c = p->level_caps[l];
+    if (c < 0 || (c > 0 && (l >= p->levels || c % p->check_every != 0))) return false;
+  }
+  if (p->diverge_window < 0 || p->reserved != 0) return false;
+  // steps above the practical choice only under the FPR rule's rise guard
+  if (!std::isfinite(p->step_scale) || p->step_scale > 2.0) return false;
+  if (p->step_scale > 1.0 && (p->diverge_window < 1 || p->stop_rule != W1_STOP_FPR)) return false;
+  return true;
+}
+
 }  // namespace cube
 }  // namespace w1
 
@@ -1222,16 +1265,7 @@ using namespace w1;
 
 extern "C" int w1_solve3d(const w1_params* p, const double* p0, const double* p1, int32_t on_device,
                           w1_result* out, double* m_out, double* psi_out, void* hip_stream) {
-  if (!p || !p0 || !p1 || !out) return W1_EINVAL;
-  if (p->n < 2 || p->n > 1024 || p->levels < 1 || p->levels > W1_MAX_LEVELS) return W1_EINVAL;
-  if (p->n % (1 << (p->levels - 1)) != 0 || (p->n >> (p->levels - 1)) < 2) return W1_EINVAL;
-  if (p->metric < W1_METRIC_L1 || p->metric > W1_METRIC_LINF) return W1_EINVAL;
-  if (p->algo != W1_ALGO_PLAIN && p->algo != W1_ALGO_PROX) return W1_EINVAL;
-  if (p->precision != W1_FP32 && p->precision != W1_FP64) return W1_EINVAL;
-  if (p->stop_rule != W1_STOP_KKT && p->stop_rule != W1_STOP_FPR) return W1_EINVAL;
-  if (!(p->tol > 0) || !std::isfinite(p->tol) || !std::isfinite(p->alpha)) return W1_EINVAL;
-  if (!std::isfinite(p->step_scale) || p->step_scale > 1.0) return W1_EINVAL;
-  if (p->max_iters < 1 || p->check_every < 1 || p->max_iters % p->check_every != 0) return W1_EINVAL;
+  if (!p || !p0 || !p1 || !out || !cube::params_ok(p)) return W1_EINVAL;
   hipStream_t s = (hipStream_t)hip_stream;
   return p->precision == W1_FP32 ? cube::solve<float>(*p, p0, p1, on_device, out, m_out, psi_out, s)
                                  : cube::solve<double>(*p, p0, p1, on_device, out, m_out, psi_out, s);
@@ -1244,15 +1278,7 @@ extern "C" int w1_solve3d_batch(const w1_params* p, int32_t count, const double*
   for (int i = 0; i < count; ++i)
     if (!p0[i] || !p1[i]) return W1_EINVAL;
   // the same parameter checks as w1_solve3d (no masses needed for them)
-  if (p->n < 2 || p->n > 1024 || p->levels < 1 || p->levels > W1_MAX_LEVELS) return W1_EINVAL;
-  if (p->n % (1 << (p->levels - 1)) != 0 || (p->n >> (p->levels - 1)) < 2) return W1_EINVAL;
-  if (p->metric < W1_METRIC_L1 || p->metric > W1_METRIC_LINF) return W1_EINVAL;
-  if (p->algo != W1_ALGO_PLAIN && p->algo != W1_ALGO_PROX) return W1_EINVAL;
-  if (p->precision != W1_FP32 && p->precision != W1_FP64) return W1_EINVAL;
-  if (p->stop_rule != W1_STOP_KKT && p->stop_rule != W1_STOP_FPR) return W1_EINVAL;
-  if (!(p->tol > 0) || !std::isfinite(p->tol) || !std::isfinite(p->alpha)) return W1_EINVAL;
-  if (!std::isfinite(p->step_scale) || p->step_scale > 1.0) return W1_EINVAL;
-  if (p->max_iters < 1 || p->check_every < 1 || p->max_iters % p->check_every != 0) return W1_EINVAL;
+  if (!cube::params_ok(p)) return W1_EINVAL;
   const int w = std::min(workers > 0 ? workers : 4, count);
   return p->precision == W1_FP32 ? cube::solve_batch<float>(*p, count, p0, p1, on_device, out, w)
                                  : cube::solve_batch<double>(*p, count, p0, p1, on_device, out, w);

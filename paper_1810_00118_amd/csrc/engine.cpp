@@ -582,8 +582,11 @@ class Batch : public BatchBase {
       double tolL = r->prm.tol;
       if (d.rule == RULE_FPR && tolL <= 0) tolL = paper_eps(r->prm.algo, r->prm.n, L > 1);
       d.tol = tolL * std::pow(2.0, (double)(L - 1 - l) * r->prm.alpha);
-      d.cap = r->prm.max_iters;
-      if (r->kind == K_PROX || l == L - 1) {
+      d.cap = r->prm.level_caps[l] > 0 ? r->prm.level_caps[l] : r->prm.max_iters;
+      d.divwin = d.rule == RULE_FPR ? r->prm.diverge_window : 0;
+      // the Poisson solves of Algorithm 2, of the KKT test and of the
+      // finest level's certificate
+      if (r->kind == K_PROX || l == L - 1 || d.rule == RULE_KKT) {
         DctTab t;
         st = dct_tables<T>(nl + 1, &t);
         if (st) return st;
@@ -790,6 +793,13 @@ class Batch : public BatchBase {
     HIPCHK(hipMemcpyAsync(r->f_m2.data(), fin.out_m2, ne * 8, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipMemcpyAsync(r->f_psi.data(), fin.out_psi, ne * 8, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
+    const double c = domain_scale(r->prm);
+    if (c != 1.0)
+      for (size_t e = 0; e < ne; ++e) {
+        r->f_m1[e] /= c;
+        r->f_m2[e] /= c;
+        r->f_psi[e] *= c;
+      }
     r->fields_ready = true;
     return W1_OK;
   }
@@ -1250,7 +1260,10 @@ class Batch : public BatchBase {
       }
       p.add(ids);
       p.add(nt);
-      if (!fpr) p.add(simple_work(lv));
+      if (!fpr) {
+        p.add(simple_work(lv));
+        p.add(gemm_work(lv));
+      }
       return p;
     }, &off, &cnt, &st);
     if (st) return st;
@@ -1271,7 +1284,15 @@ class Batch : public BatchBase {
       HIPCHK(hipEventRecord(t1, st_));
       tune_pending_.push_back(TunePend{t0, t1, entry, arm, nodes * ce});
     }
-    if (!fpr) K<T>::kkt(st_, (Work*)(base + off[3]), (int)cnt[3], ddesc_, dsc_, K_PLAIN, nl & 1, 1);
+    if (!fpr) {
+      // KKT: the minimum-norm correction potential (A A*)^{-1}(A m - rho)
+      // into plane 6, then the partials
+      Work* ksw = (Work*)(base + off[3]);
+      const int nksw = (int)cnt[3];
+      K<T>::div_pre(st_, ksw, nksw, ddesc_, dsc_, 2, K_PLAIN, 1, nl & 1);
+      poisson((Work*)(base + off[4]), (int)cnt[4], 6, 1);
+      K<T>::kkt(st_, ksw, nksw, ddesc_, dsc_, K_PLAIN, nl & 1, 1);
+    }
     K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PLAIN, ce, nl);
     HIPCHK(hipGetLastError());
     return W1_OK;
@@ -1336,8 +1357,11 @@ class Batch : public BatchBase {
       prof_.end(pi, W1_FAM_PROX_ELEM, 0, nodes * 13.0 * sizeof(T), 0);
     }
     if (!fpr) {
+      // KKT: psi (Appendix B) into plane 8, the correction potential into 6
       K<T>::div_pre(st_, dsw, nsw, ddesc_, dsc_, 1, K_PROX, 1);
       poisson(dgw, ngw, 8, 1);
+      K<T>::div_pre(st_, dsw, nsw, ddesc_, dsc_, 2, K_PROX, 1);
+      poisson(dgw, ngw, 6, 1);
       K<T>::kkt(st_, dsw, nsw, ddesc_, dsc_, K_PROX, 0, 1);
     }
     K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PROX, ce, 0);
@@ -1397,7 +1421,8 @@ class Batch : public BatchBase {
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
     HIPCHK(hipStreamSynchronize(st_));
     for (auto* r : up)
-      if (r->prm.flags & W1_FLAG_LEVEL_COST) r->res.level_w1[r->level] = hsc_[r->slot].eval[0];
+      if (r->prm.flags & W1_FLAG_LEVEL_COST)
+        r->res.level_w1[r->level] = domain_scale(r->prm) * hsc_[r->slot].eval[0];
     return W1_OK;
   }
 
@@ -1440,11 +1465,12 @@ class Batch : public BatchBase {
     const double t = now_seconds();
     for (auto* r : fin) {
       const SlotScalars& s = hsc_[r->slot];
-      r->res.w1 = s.eval[0];
-      r->res.level_w1[r->level] = s.eval[0];
-      r->res.dual = s.eval[1];
-      r->res.lo = s.eval[2];
-      r->res.hi = s.eval[3];
+      const double c = domain_scale(r->prm);
+      r->res.w1 = c * s.eval[0];
+      r->res.level_w1[r->level] = c * s.eval[0];
+      r->res.dual = c * s.eval[1];
+      r->res.lo = c * s.eval[2];
+      r->res.hi = c * s.eval[3];
       r->res.kkt = s.eval[4];
       r->res.seconds = t - r->t_submit;
       r->res.queue_seconds = r->t_admit - r->t_submit;

@@ -45,10 +45,18 @@ struct Request {
   std::vector<double> f_m1, f_m2, f_psi;
   bool fields_ready = false;
   int res_iters_seen = 0;           // profiling: iterations already counted
+  // served mode: set under the handle's mutex after the worker's last
+  // access; only then may w1_poll take the request (and free it)
+  bool handed = false;
 };
 
 // Device bytes of one request.
 size_t request_bytes(const w1_params& p);
+
+// Side of the domain [0, c]^d the outputs refer to (w1_params.h): the solve
+// runs on the unit square and W1 scales by c (unit masses), the flux by
+// c^(1-d), the potential by c.
+inline double domain_scale(const w1_params& p) { return p.h > 0 ? (double)p.n * p.h : 1.0; }
 
 // Per-precision batch of in-flight requests.
 class BatchBase {

@@ -822,6 +822,8 @@ __global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __r
   const int kend = chunk > 0 ? k + chunk : cap;
   int status = ST_RUN;
   double measure = sc.measure;
+  int rises = sc.rises;
+  bool tested = k > 0;   // a stop test of this level has run
   const bool fpr = d.rule == RULE_FPR;
   while (k < kend) {
     ++k;
@@ -895,18 +897,14 @@ __global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __r
           v[2] += ep * adm;
           if (!(finite_(m1[s]) && finite_(m2[s]) && finite_(pv[s]))) v[3] += 1.0;
         } else {
-          // KKT: residual A m - rho, Lipschitz excess of grad phi, cost, <phi, rho>
+          // KKT: Lipschitz excess of grad phi, cost, <phi, rho>
           const bool hd = e < last_row, hr = !((last_col >> s) & 1u);
-          const double am = (double)(((m1[s] - u1) + (m2[s] - l2)) * ih);
           const double rr = (double)rh[s];
-          const double res1 = am - rr;
           const T pc = pv[s];
           const T g1 = hd ? (Lp[e + N] - pc) * ih : T(0);
           const T g2 = hr ? (Lp[e + 1] - pc) * ih : T(0);
           const double gq = (double)norm_q_(g1, g2, metric);
           const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
-          v[0] += res1 * res1;
-          v[1] += rr * rr;
           v[2] += ex * ex;
           v[3] += (double)norm_p_(m1[s], m2[s], metric);
           v[4] += (double)pc * rr;
@@ -914,6 +912,48 @@ __global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __r
           v[7] += rr;
         }
       }
+    }
+    if (!fpr) {
+      // primal part of the KKT residual: ||A* c||_h^2 with c = (A A*)^{-1} r,
+      // r = A m - rho, is h^2 sum_x c r = h^4 sum_{(k,l) != 0} rhat_kl^2 /
+      // (s_k + s_l) in the orthonormal DCT-II basis (rhat = C r C^T,
+      // s_k = 4 sin^2(pi k / 2N)): the forward transform alone, C read from
+      // global memory.  r goes to Lp (the potential is restored from the
+      // registers afterwards), the row transform to Lb.
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          const T u1 = e >= N ? Lb[e - N] : T(0);
+          const T l2 = ((first_col >> s) & 1u) ? T(0) : Lc[e - 1];
+          Lp[e] = ((m1[s] - u1) + (m2[s] - l2)) * ih - rh[s];
+        }
+      }
+      __syncthreads();
+      const W1_GLOBAL T* C = gld_(d.dctC);
+#pragma unroll 1
+      for (int e = threadIdx.x; e < NN; e += NT) {
+        const int kr = e / N, j = e - kr * N;
+        T acc = T(0);
+        for (int i = 0; i < N; ++i) acc = fma_(C[kr * N + i], Lp[i * N + j], acc);
+        Lb[e] = acc;
+      }
+      __syncthreads();
+      double sp = 0.0;
+#pragma unroll 1
+      for (int e = threadIdx.x; e < NN; e += NT) {
+        const int kr = e / N, l = e - kr * N;
+        T acc = T(0);
+        for (int j = 0; j < N; ++j) acc = fma_(Lb[kr * N + j], C[l * N + j], acc);
+        if (e != 0) sp += (double)acc * (double)acc / (d.dcts[kr] + d.dcts[l]);
+      }
+#pragma unroll
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) Lp[e] = pv[s];
+      }
+      v[0] = sp * h2;
     }
     block_reduce_<NT>(v, res, red, 0u);
     __syncthreads();
@@ -923,21 +963,24 @@ __global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __r
         m = h2 * (res[0] / d.mud + res[1] / d.taud - 2.0 * res[2]);
         if (res[3] > 0.0) m = NAN;
       } else {
-        const double rp = sqrt(res[0] / (res[1] > 1e-300 ? res[1] : 1e-300));
-        const double rdl = sqrt(res[2] * h2);
         const double P = res[3] * h2;
+        const double rp = sqrt(res[0] * h2) / fmax(P, 1e-300);
+        const double rdl = sqrt(res[2] * h2);
         const double D = -(res[4] - res[6] / (double)NN * res[7]) * h2;
         const double den = fmax(fmax(fabs(P), fabs(D)), 1e-300);
         const double gap = fabs(P - D) / den;
         m = fmax(rp, fmax(rdl, gap));
       }
+      rises = tested && m > measure ? rises + 1 : 0;
       int st = ST_RUN;
-      if (!isfinite(m)) st = ST_DIVERGED;
+      if (!isfinite(m) || (d.divwin > 0 && m < 0.0)) st = ST_DIVERGED;
       else if (m <= d.tol) st = ST_CONV;
+      else if (d.divwin > 0 && rises >= d.divwin) st = ST_DIVERGED;
       else if (k >= cap) st = ST_CAP;
       flag[0] = st;
       res[0] = m;
     }
+    tested = true;
     __syncthreads();
     status = flag[0];
     measure = res[0];
@@ -960,22 +1003,31 @@ __global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __r
     sc.iters = k;
     sc.status = status;
     sc.measure = measure;
+    sc.rises = rises;
     sc.cur = 0;
   }
 }
 
+// The guard of steps beyond the convergence condition (divwin > 0, FPR
+// rule): R^k and G^k are squared norms of the iterate change in a metric
+// that is positive definite only while mu tau ||A||^2 < 1 (Sec. 3.1), so a
+// negative measure, or one that rises at divwin tests in a row, ends the
+// level as diverged.
+//
 // Stop measure from the reduced partials r[0..NQ): R^k (plain) or G^k (prox)
 // of eq. (pd_stop) / eq. (pdhg_stop) for RULE_FPR, else the normalised KKT
-// residual.
+// residual max(||A* c||_h / P, RMS Lipschitz excess, relative gap), where
+// A* c is the least-norm flux correction that makes m feasible (r[0] holds
+// ||A* c||_h^2 / h^2).
 __device__ double measure_from_(const double* r, int kind, int rule, double h2, double mud, double taud, int NN) {
   if (rule == RULE_FPR) {
     if (r[3] > 0.0) return NAN;
     if (kind == K_PLAIN) return h2 * (r[0] / mud + r[1] / taud - 2.0 * r[2]);
     return h2 * (r[0] / mud + r[1] / taud + 2.0 * r[2]);
   }
-  const double rp = sqrt(r[0] / (r[1] > 1e-300 ? r[1] : 1e-300));
-  const double rdl = sqrt(r[2] * h2);
   const double P = r[3] * h2;
+  const double rp = sqrt(r[0] * h2) / fmax(P, 1e-300);
+  const double rdl = sqrt(r[2] * h2);
   const double sgn = kind == K_PLAIN ? -1.0 : 1.0;
   const double D = sgn * (r[4] - r[6] / (double)NN * r[7]) * h2;
   const double den = fmax(fmax(fabs(P), fabs(D)), 1e-300);
@@ -1246,6 +1298,8 @@ __global__ __launch_bounds__(PRES_THREADS) void k_prox_resident(const int* __res
   const int kend = chunk > 0 ? k + chunk : cap;
   int status = ST_RUN;
   double measure = sc.measure;
+  int rises = sc.rises;
+  bool tested = k > 0;   // a stop test of this level has run
   const bool fpr = d.rule == RULE_FPR;
   while (k < kend) {
     ++k;
@@ -1344,23 +1398,43 @@ __global__ __launch_bounds__(PRES_THREADS) void k_prox_resident(const int* __res
       for (int s = 0; s < NPT; ++s) {
         const int e = threadIdx.x + NT * s;
         if (e < NN) {
-          const T a1 = m1[s] - (((not_top >> s) & 1u) ? P0[e - N] : T(0));
-          const T a2 = m2[s] - (((not_left >> s) & 1u) ? P1[e - 1] : T(0));
-          const double am = (double)((a1 + a2) * ih);
           const double rr = (double)rh[s];
-          const double r1 = am - rr;
           const T pc = P2[e];
           const T g1 = ((has_d >> s) & 1u) ? (P2[e + N] - pc) * ih : T(0);
           const T g2 = ((has_r >> s) & 1u) ? (P2[e + 1] - pc) * ih : T(0);
           const double gq = (double)norm_q_(g1, g2, metric);
           const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
-          v[0] += r1 * r1;
-          v[1] += rr * rr;
           v[2] += ex * ex;
           v[3] += (double)norm_p_(m1[s], m2[s], metric);
           v[4] += (double)pc * rr;
           v[6] += (double)pc;
           v[7] += rr;
+        }
+      }
+      // primal part: the correction potential c = (A A*)^{-1}(A m - rho)
+      // (psi in P2 is no longer read after this barrier), then
+      // sum |grad+ c|^2
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          const T a1 = m1[s] - (((not_top >> s) & 1u) ? P0[e - N] : T(0));
+          const T a2 = m2[s] - (((not_left >> s) & 1u) ? P1[e - 1] : T(0));
+          P2[e] = (a1 + a2) * ih - rh[s];
+        }
+      }
+      __syncthreads();
+      res_poisson_(CE, CO, P2, F0, F1, lam, L);
+      const double ihd = 1.0 / d.h;
+#pragma unroll
+      for (int s = 0; s < NPT; ++s) {
+        const int e = threadIdx.x + NT * s;
+        if (e < NN) {
+          const double cc = (double)P2[e];
+          const double c1 = ((has_d >> s) & 1u) ? ((double)P2[e + N] - cc) * ihd : 0.0;
+          const double c2 = ((has_r >> s) & 1u) ? ((double)P2[e + 1] - cc) * ihd : 0.0;
+          v[0] += c1 * c1 + c2 * c2;
         }
       }
     }
@@ -1370,13 +1444,16 @@ __global__ __launch_bounds__(PRES_THREADS) void k_prox_resident(const int* __res
     __syncthreads();
     if (threadIdx.x == 0) {
       const double m = measure_from_(res, K_PROX, d.rule, h2, d.mud, d.taud, NN);
+      rises = tested && m > measure ? rises + 1 : 0;
       int st = ST_RUN;
-      if (!isfinite(m)) st = ST_DIVERGED;
+      if (!isfinite(m) || (d.divwin > 0 && m < 0.0)) st = ST_DIVERGED;
       else if (m <= d.tol) st = ST_CONV;
+      else if (d.divwin > 0 && rises >= d.divwin) st = ST_DIVERGED;
       else if (k >= cap) st = ST_CAP;
       flag[0] = st;
       res[0] = m;
     }
+    tested = true;
     __syncthreads();
     status = flag[0];
     measure = res[0];
@@ -1402,14 +1479,17 @@ __global__ __launch_bounds__(PRES_THREADS) void k_prox_resident(const int* __res
     sc.iters = k;
     sc.status = status;
     sc.measure = measure;
+    sc.rises = rises;
   }
 }
 
 // ---------------------------------------------------------------------------
 // KKT partials of an Algorithm 1 iterate (current set) or of an Algorithm 2
-// iterate with its potential psi in plane 8:
-// q0 sum (A m - rho)^2, q1 sum rho^2, q2 sum excess^2, q3 sum ||m||_p,
-// q4 sum pot*rho, q6 sum pot, q7 sum rho.
+// iterate with its potential psi in plane 8, given the minimum-norm
+// correction potential c = (A A*)^{-1}(A m - rho) in plane 6:
+// q0 sum |grad+ c|^2 (the squared norm of the flux correction A* c, over
+// h^2), q2 sum excess^2, q3 sum ||m||_p, q4 sum pot*rho, q6 sum pot,
+// q7 sum rho.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_kkt(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
@@ -1435,20 +1515,20 @@ __global__ __launch_bounds__(256) void k_kkt(const Work* __restrict__ work, cons
     pot = d.p[8];
   }
   const T ih = d.ih;
+  const T* corr = d.p[6];
+  const double ihd = 1.0 / d.h;
   double v[NQ] = {0, 0, 0, 0, 0, 0, 0, 0};
   SIMPLE_TILE_LOOP(d, w, {
-    const T a1 = m1[off] - (i > 0 ? m1[off - pitch] : T(0));
-    const T a2 = m2[off] - (j > 0 ? m2[off - 1] : T(0));
-    const double am = (double)((a1 + a2) * ih);
     const double rr = (double)d.rho[off];
-    const double r1 = am - rr;
+    const double cc = (double)corr[off];
+    const double c1 = i < n ? ((double)corr[off + pitch] - cc) * ihd : 0.0;
+    const double c2 = j < n ? ((double)corr[off + 1] - cc) * ihd : 0.0;
     const T pc = pot[off];
     const T g1 = i < n ? (pot[off + pitch] - pc) * ih : T(0);
     const T g2 = j < n ? (pot[off + 1] - pc) * ih : T(0);
     const double gq = (double)norm_q_(g1, g2, d.metric);
     const double ex = gq > 1.0 ? gq - 1.0 : 0.0;
-    v[0] += r1 * r1;
-    v[1] += rr * rr;
+    v[0] += c1 * c1 + c2 * c2;
     v[2] += ex * ex;
     v[3] += (double)norm_p_(m1[off], m2[off], d.metric);
     v[4] += (double)pc * rr;
@@ -1462,13 +1542,14 @@ __global__ __launch_bounds__(256) void k_kkt(const Work* __restrict__ work, cons
 // node-field inputs of a Poisson solve, written to plane 6:
 //   mode 0: A(m - mu vphibar) - rho   (projection step of eq. (pdhg))
 //   mode 1: A vphi                    (Appendix B potential)
-//   mode 2: A m - rho                 (certificate correction), m from the
-//           current plain set (kind plain) or planes 0, 1 (prox)
+//   mode 2: A m - rho                 (certificate and KKT correction), m
+//           from the plain set cur ^ set_xor (kind plain) or planes 0, 1
+//           (prox)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_div_pre(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
                                                  const SlotScalars* __restrict__ scal, int mode, int kind,
-                                                 int gate) {
+                                                 int gate, int set_xor) {
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
   const SlotScalars& sc = scal[w.x / MAXL];
@@ -1481,7 +1562,7 @@ __global__ __launch_bounds__(256) void k_div_pre(const Work* __restrict__ work, 
     a1p = d.p[2];
     a2p = d.p[3];
   } else if (kind == K_PLAIN) {
-    const int cs = sc.cur & 1;
+    const int cs = (sc.cur ^ set_xor) & 1;
     a1p = d.p[3 * cs];
     a2p = d.p[3 * cs + 1];
   } else {
@@ -1814,12 +1895,15 @@ __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, cons
     const int N = d.n + 1;
     const double m = measure_from_(res, kind, d.rule, d.h * d.h, d.mud, d.taud, N * N);
     const int k = sc.iters + block_len;
+    const int rises = sc.iters > 0 && m > sc.measure ? sc.rises + 1 : 0;
     int st = ST_RUN;
-    if (!isfinite(m)) st = ST_DIVERGED;
+    if (!isfinite(m) || (d.divwin > 0 && m < 0.0)) st = ST_DIVERGED;
     else if (m <= d.tol) st = ST_CONV;
+    else if (d.divwin > 0 && rises >= d.divwin) st = ST_DIVERGED;
     else if (k >= d.cap) st = ST_CAP;
     sc.iters = k;
     sc.measure = m;
+    sc.rises = rises;
     sc.status = st;
     sc.cur ^= launches & 1;
   }
@@ -2074,8 +2158,8 @@ template <typename T> void K<T>::kkt(hipStream_t s, const Work* w, int nw, const
   if (nw) LAUNCH(k_kkt<T>, nw, 256, 0, s, w, d, sc, kind, set_xor, gate);
 }
 template <typename T> void K<T>::div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                         const SlotScalars* sc, int mode, int kind, int gate) {
-  if (nw) LAUNCH(k_div_pre<T>, nw, 256, 0, s, w, d, sc, mode, kind, gate);
+                                         const SlotScalars* sc, int mode, int kind, int gate, int set_xor) {
+  if (nw) LAUNCH(k_div_pre<T>, nw, 256, 0, s, w, d, sc, mode, kind, gate, set_xor);
 }
 template <typename T> void K<T>::gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                       const SlotScalars* sc, int mode, int src, int dst, int mat, bool scale,

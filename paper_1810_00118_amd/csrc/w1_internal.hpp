@@ -58,7 +58,8 @@ struct SlotDesc {
   double h, mud, taud;  // FP64 copies of h, mu, tau for the measures
   double tol;          // stop tolerance of this level
   int metric;          // 1, 2 or 3 (l_1, l_2, l_inf)
-  int pad1;
+  int divwin;          // FPR rule: rises of the measure in a row that end
+                       // the level as diverged (0 = no such test)
   int rule;            // RULE_KKT or RULE_FPR
   int cap;             // iteration cap of this level
 };
@@ -73,7 +74,7 @@ struct SlotScalars {
                        // whose status is not ST_RUN
   int iters;           // iterations run at the current level
   int cur;             // plain: plane set (0 = A, 1 = B) holding the iterate
-  int pad;
+  int rises;           // stop tests in a row whose measure rose
 };
 
 // Work item: x = descriptor index (or -1 for padding), y = tile row,
@@ -118,8 +119,9 @@ struct K {
                             int max_side, int check_every, int chunk, int metric);
   static void kkt(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int kind,
                   int set_xor, int gate);
+  // mode 2 of a plain slot reads plane set cur ^ set_xor (as kkt)
   static void div_pre(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int mode,
-                      int kind, int gate);
+                      int kind, int gate, int set_xor = 0);
   static void gemm(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc, int mode,
                    int src, int dst, int mat, bool scale, int gate);
   // (A A*)^{-1} of plane 6 into plane dst with the folded FP32 passes

@@ -42,13 +42,20 @@ def test_library_loads_and_checks_params_without_a_device():
     assert w1.bytes_per_solve(p) > 0
     for m in (1, 2, 3):
         assert w1.check_params(w1.params(n=512, levels=4, metric=m)) == 0
-    # the paper's practical step sizes (scale 1) are accepted, larger ones not
+    # the paper's practical step sizes (scale 1) are accepted; larger ones
+    # (up to 2) only under the FPR rule with the rise-window guard
     assert w1.check_params(w1.params(n=512, levels=4, step_scale=1.0)) == 0
-    for bad in (dict(n=100, levels=4), dict(levels=0), dict(metric=4), dict(metric=0),
-                dict(max_iters=15, check_every=10), dict(step_scale=1.5), dict(algo=7)):
-        q = w1.params(n=512, levels=4)
-        for k, v in bad.items():
-            setattr(q, k, v)
+    assert w1.check_params(w1.params(n=512, levels=4, step_scale=1.5, diverge_window=3)) == 0
+    # per-level caps (multiples of check_every, only on existing levels), a domain scale
+    assert w1.check_params(w1.params(n=512, levels=4, level_caps=[100, 0, 50, 10])) == 0
+    assert w1.check_params(w1.params(n=512, levels=4, h=0.5 / 512)) == 0
+    for bad in (dict(n=100), dict(levels=0), dict(metric=4), dict(metric=0),
+                dict(max_iters=15, check_every=10), dict(step_scale=1.5), dict(algo=7),
+                dict(step_scale=1.5, diverge_window=3, stop_rule=w1.STOP_KKT, tol=1e-6),
+                dict(step_scale=2.5, diverge_window=3), dict(diverge_window=-1),
+                dict(level_caps=[15]), dict(level_caps=[10, 10, 10, 10, 10]), dict(level_caps=[-10]),
+                dict(h=float("inf")), dict(reserved=1)):
+        q = w1.params(**dict(dict(n=512, levels=4), **bad))
         assert w1.check_params(q) == w1.W1_EINVAL, bad
     assert w1.strerror(w1.W1_EINVAL) == "invalid argument"
 
@@ -77,7 +84,8 @@ def test_d3_entry_points_check_arguments_without_a_device():
     ok = dict(n=n, levels=2, metric=2, algo=w1.ALGO_PLAIN, precision=w1.FP32, stop_rule=w1.STOP_FPR, tol=1e-6,
               max_iters=100, check_every=10)
     for bad in (dict(n=3), dict(levels=3), dict(tol=0.0), dict(metric=0), dict(algo=3), dict(step_scale=2.0),
-                dict(max_iters=15), dict(precision=3)):
+                dict(max_iters=15), dict(precision=3), dict(level_caps=[15]), dict(level_caps=[10, 10, 10]),
+                dict(step_scale=1.5, diverge_window=2, stop_rule=w1.STOP_KKT), dict(diverge_window=-2)):
         prm = w1.params(**dict(ok, **bad))
         st = L.w1_solve3d(C.byref(prm), a.ctypes.data, a.ctypes.data, 0, C.byref(out), None, None, None)
         assert st == w1.W1_EINVAL, bad

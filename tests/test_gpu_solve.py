@@ -79,19 +79,13 @@ def test_prox_kkt_rule_resident_levels(precision):
         assert res["iters"] == ref["iters"]
         _check_parity(w1, res, fields, ref, n, metric, rho, precision)
         return
-    # FP32: the rounding noise of the FP32 Poisson solves (~1e-7 relative,
-    # white) enters m+ through grad u, so A m+ - rho is the discrete
-    # Laplacian of that noise: the primal part of the in-loop KKT residual
-    # has a floor (~1.7e-4 at 65^2, ~7e-4 at 129^2 here) above this
-    # schedule's level tolerances, and the levels run to the cap; W1 and
-    # the FP64 evaluation of the returned (feasibility-corrected) fields
-    # still meet the tolerance
-    assert res["iters"] == [20000, 20000, 20000]
-    assert res["w1"] == pytest.approx(ref["w1"], rel=1e-4)
-    m1, m2, psi = fields
-    ev_gpu = o.evaluate(m1, m2, psi, rho, 1.0 / n, P_OF[metric])
-    assert ev_gpu["kkt"] <= 1e-4
-    assert max(res["lo"], ref["lo"]) <= min(res["hi"], ref["hi"]) * (1 + 1e-6)
+    # FP32: the primal term is the norm of the minimum-norm flux correction,
+    # so the rounding noise of the FP32 Poisson solves enters it once
+    # through a gradient (not through the Laplacian of A m - rho): every
+    # level stops below the cap, and the FP64 evaluation of the returned
+    # fields meets the oracle's to 1e-5
+    assert all(k < 20000 for k in res["iters"]), res["iters"]
+    _check_parity(w1, res, fields, ref, n, metric, rho, precision)
 
 
 @pytest.mark.parametrize("algo", [1, 2])
@@ -363,3 +357,131 @@ def test_served_batch_failure_ends_requests():
     assert res["running"] == 0 and res["finished"] == 4
     assert all(s == w1lib.SOLVE_FAILED for s in res["status"]), res
 
+
+
+def test_served_poll_while_running():
+    """Requests are polled from a second thread while the worker runs them
+    (a request is handed to w1_poll only after the worker's last access):
+    every result arrives, equal to the request solved alone, and the
+    budget's bytes in use return to 0 after w1_drain."""
+    import threading
+    w1 = require_gpu()
+    reqs = []
+    for i in range(12):
+        n = (32, 64, 128)[i % 3]
+        p0, p1 = w1data.pair_gauss3(400 + i, n=n)
+        L = {32: 1, 64: 2, 128: 3}[n]
+        prm = w1.params(n=n, levels=L, metric=2, algo=1 + i % 2, precision=FP32, stop_rule=w1.STOP_FPR,
+                        tol=0.0, max_iters=2000, check_every=10)
+        reqs.append((prm, p0, p1))
+    got = {}
+    with w1.Solver(reqs[0][0], capacity=3) as srv:
+        tickets = [srv.submit(p0, p1, prm) for prm, p0, p1 in reqs]
+
+        def poller():
+            pending = list(tickets)
+            while pending:
+                for t in list(pending):
+                    r = srv.poll(t)
+                    if r is not None:
+                        got[t] = r[0]
+                        pending.remove(t)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        srv.drain()
+        th.join(timeout=60)
+        assert not th.is_alive()
+        st = srv.stats()
+        assert st["bytes"] == 0 and st["running"] == 0 and st["finished"] == len(reqs)
+    for t, (prm, p0, p1) in zip(tickets, reqs):
+        with w1.Solver(prm) as s:
+            alone = s.solve([(p0, p1)])[0]
+        assert got[t]["iters"] == alone["iters"]
+        assert got[t]["w1"] == pytest.approx(alone["w1"], rel=1e-6)
+
+
+@pytest.mark.parametrize("algo", [1, 2])
+def test_level_caps_match_oracle(algo):
+    """Per-level iteration caps (coarsest first): in FP64 the GPU runs every
+    level to its own cap exactly as the oracle does (tolerance 0), and a cap
+    above a level's natural stop leaves that level's stop unchanged."""
+    w1 = require_gpu()
+    n, L, metric = 128, 3, 2
+    p0, p1 = w1data.pair_gauss3(21, n=n)
+    caps = [300, 40, 20] if algo == 1 else [30, 10, 5]
+    prm = w1.params(n=n, levels=L, metric=metric, algo=algo, precision=FP64, stop_rule=w1.STOP_FPR,
+                    tol=1e-300, max_iters=20000, check_every=5, level_caps=caps)
+    with w1.Solver(prm) as s:
+        res = s.solve([(p0, p1)])[0]
+        fields = s.fields(0)
+    ref = o.solve(p0, p1, n, L=L, p=2, algo=algo, stop="fpr", eps_L=1e-300, alpha=-1.0, max_iters=caps,
+                  check_every=5)
+    assert res["iters"] == caps == ref["iters"]
+    assert res["status"] == w1.SOLVE_MAXITER
+    assert res["w1"] == pytest.approx(ref["w1"], rel=1e-10)
+    np.testing.assert_allclose(fields[0], ref["m1"], rtol=0, atol=1e-9 * np.abs(ref["m1"]).max())
+    # caps above the paper rule's stops: the same iterations as without caps
+    eps = o.paper_stop_tolerance(algo, n, True)
+    free = w1.params(n=n, levels=L, metric=metric, algo=algo, precision=FP64, stop_rule=w1.STOP_FPR, tol=eps,
+                     max_iters=20000, check_every=5)
+    with w1.Solver(free) as s:
+        a = s.solve([(p0, p1)])[0]
+    capped = w1.params(n=n, levels=L, metric=metric, algo=algo, precision=FP64, stop_rule=w1.STOP_FPR, tol=eps,
+                       max_iters=20000, check_every=5, level_caps=[k + 5 for k in a["iters"]])
+    with w1.Solver(capped) as s:
+        b = s.solve([(p0, p1)])[0]
+    assert a["iters"] == b["iters"] and a["w1"] == b["w1"]
+
+
+@pytest.mark.parametrize("algo", [1, 2])
+def test_step_guard(algo):
+    """Steps beyond the convergence condition run only under the FPR rule's
+    guard: at the practical steps (scale 1) the guard never fires and the
+    FP64 run takes the oracle's stops; at scale 2 (Algorithm 1: the
+    metric of R^k turns indefinite, R^k goes negative; Algorithm 2:
+    mu tau = 4, G^k climbs to a plateau) the first level ends as diverged
+    within a few tests instead of passing the stop test or running to the
+    cap."""
+    w1 = require_gpu()
+    n, L = 64, 2
+    p0, p1 = w1data.pair_gauss3(0, n=n)
+    eps = o.paper_stop_tolerance(algo, n, True)
+    for precision in (FP64, FP32):
+        prm = w1.params(n=n, levels=L, metric=2, algo=algo, precision=precision, stop_rule=w1.STOP_FPR, tol=eps,
+                        step_scale=1.0, max_iters=20000, check_every=10, diverge_window=3)
+        with w1.Solver(prm) as s:
+            res = s.solve([(p0, p1)])[0]
+        ref = o.solve(p0, p1, n, L=L, p=2, algo=algo, stop="fpr", eps_L=eps, alpha=-1.0, max_iters=20000,
+                      check_every=10, step_scale=1.0, return_fields=False)
+        assert res["status"] == w1.SOLVE_OK
+        if precision == FP64:
+            assert res["iters"] == ref["iters"]
+        assert res["w1"] == pytest.approx(ref["w1"], rel=1e-4)
+        bad = w1.params(n=n, levels=L, metric=2, algo=algo, precision=precision, stop_rule=w1.STOP_FPR, tol=eps,
+                        step_scale=2.0, max_iters=20000, check_every=10, diverge_window=3)
+        with w1.Solver(bad) as s:
+            r2 = s.solve([(p0, p1)])[0]
+        assert r2["status"] == w1.SOLVE_DIVERGED
+        assert r2["levels_run"] == 1 and r2["iters"][0] <= 200
+
+
+def test_domain_scale():
+    """w1_params.h: the same masses on [0, c]^2 (c = n h) give c times W1,
+    dual and bracket, the flux over c and the potential times c."""
+    w1 = require_gpu()
+    n, L = 64, 2
+    p0, p1 = w1data.pair_gauss3(2, n=n)
+    base = dict(n=n, levels=L, metric=2, algo=w1.ALGO_PROX, precision=FP64, stop_rule=w1.STOP_FPR, tol=0.0,
+                max_iters=20000, check_every=10)
+    out = []
+    for h in (0.0, 3.0 / n):
+        with w1.Solver(w1.params(h=h, **base)) as s:
+            out.append((s.solve([(p0, p1)])[0], s.fields(0)))
+    (a, fa), (b, fb) = out
+    assert a["iters"] == b["iters"]
+    for k in ("w1", "dual", "lo", "hi"):
+        assert b[k] == pytest.approx(3.0 * a[k], rel=1e-14)
+    assert b["kkt"] == a["kkt"]
+    np.testing.assert_allclose(fb[0], fa[0] / 3.0, rtol=1e-14)
+    np.testing.assert_allclose(fb[2], fa[2] * 3.0, rtol=1e-14)

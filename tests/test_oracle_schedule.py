@@ -43,3 +43,30 @@ def test_level_sides():
     assert o.level_sides(512, 4) == [64, 128, 256, 512]
     assert o.level_sides(64, 1) == [64]
     assert o.level_sides(256, 6) == [8, 16, 32, 64, 128, 256]
+
+
+@pytest.mark.parametrize("algo", [1, 2])
+def test_per_level_caps(algo):
+    """Per-level iteration caps: with a zero tolerance every level runs to
+    its own cap; one cap repeated per level is the scalar cap; a cap above
+    a level's stop leaves that level unchanged."""
+    import oracle.w1_oracle as o
+    import w1data
+    n, L = 16, 3
+    p0, p1 = w1data.random_pair(n, 5)
+    caps = [7, 3, 5]
+    r = o.solve(p0, p1, n, L=L, p=2, algo=algo, stop="fpr", tol=0.0, eps_L=0.0, max_iters=caps,
+                return_fields=False)
+    assert r["iters"] == caps and r["status"] == "maxiter"
+    a = o.solve(p0, p1, n, L=L, p=2, algo=algo, stop="fpr", tol=0.0, eps_L=0.0, max_iters=[4, 4, 4],
+                return_fields=False)
+    b = o.solve(p0, p1, n, L=L, p=2, algo=algo, stop="fpr", tol=0.0, eps_L=0.0, max_iters=4,
+                return_fields=False)
+    assert a["iters"] == b["iters"] == [4, 4, 4] and a["w1"] == b["w1"]
+    eps = 1e-3 if algo == 2 else 1e-5
+    free = o.solve(p0, p1, n, L=L, p=2, algo=algo, stop="fpr", eps_L=eps, max_iters=5000, return_fields=False)
+    capped = o.solve(p0, p1, n, L=L, p=2, algo=algo, stop="fpr", eps_L=eps,
+                     max_iters=[k + 1 for k in free["iters"]], return_fields=False)
+    assert capped["iters"] == free["iters"] and capped["w1"] == free["w1"]
+    with pytest.raises(ValueError):
+        o.solve(p0, p1, n, L=L, p=2, algo=algo, max_iters=[5, 5], return_fields=False)
