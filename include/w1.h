@@ -276,6 +276,21 @@ int w1_op_prox_steps(int32_t n, int32_t metric, int32_t precision,
 int w1_op_poisson(int32_t n, int32_t precision, const void* r, void* u,
                   void* hip_stream);
 
+/* w1_op_poisson without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and kernels as w1_op_poisson
+ * (r, u: device, dense (n+1)^2, may alias); 1 <= n <= 512, else W1_EINVAL
+ * before any device call.  Its working memory (DCT tables, two planes, the
+ * descriptor and work list) is a static device array of w1_noalloc_bytes()
+ * bytes per GPU, held until the process ends and rewritten by every call;
+ * calls that overlap on one GPU (other streams or threads) race and must
+ * be serialised by the caller.  Queued on hip_stream (NULL: the default
+ * stream) without a host synchronisation: u is ready when the stream
+ * reaches the end of the call's work.                                     */
+int w1_op_poisson_noalloc(int32_t n, int32_t precision, const void* r,
+                          void* u, void* hip_stream);
+size_t w1_noalloc_bytes(void);
+
 /* Appendix B: psi = (A A*)^{-1} A vphi, zero mean.                        */
 int w1_op_potential(int32_t n, int32_t precision, const void* w1,
                     const void* w2, void* psi, void* hip_stream);

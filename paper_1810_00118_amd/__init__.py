@@ -98,6 +98,8 @@ def lib():
         "w1_op_plain_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, i32, vp, vp, vp, vp, dp, vp]),
         "w1_op_prox_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, vp, vp, vp, dp, vp]),
         "w1_op_poisson": (C.c_int, [i32, i32, vp, vp, vp]),
+        "w1_op_poisson_noalloc": (C.c_int, [i32, i32, vp, vp, vp]),
+        "w1_noalloc_bytes": (C.c_size_t, []),
         "w1_op_potential": (C.c_int, [i32, i32, vp, vp, vp, vp]),
         "w1_op_evaluate": (C.c_int, [i32, i32, i32, vp, vp, vp, vp, dp, vp]),
         "w1_solve3d": (C.c_int, [C.POINTER(Params), vp, vp, i32, C.POINTER(Result), vp, vp, vp]),
@@ -349,6 +351,18 @@ def op_prox_steps(n, metric, precision, steps, m1, m2, w1, w2, wb1, wb2, rho, st
 def op_poisson(n, precision, r, u, stream=None):
     d = _dt(precision)
     _check(lib().w1_op_poisson(n, precision, _ptr(r, d)[0], _ptr(u, d)[0], _stream(stream)), "w1_op_poisson")
+
+
+def op_poisson_noalloc(n, precision, r, u, stream=None):
+    """w1_op_poisson without device allocation (static per-GPU working
+    memory; asynchronous on `stream`)."""
+    d = _dt(precision)
+    _check(lib().w1_op_poisson_noalloc(n, precision, _ptr(r, d)[0], _ptr(u, d)[0], _stream(stream)),
+           "w1_op_poisson_noalloc")
+
+
+def noalloc_bytes():
+    return int(lib().w1_noalloc_bytes())
 
 
 def op_potential(n, precision, w1, w2, psi, stream=None):
