@@ -372,7 +372,9 @@ int w1_op_prox_steps3d(int32_t n, int32_t metric, int32_t precision,
  *   out[2] node updates (one node of one PDHG iteration), out[3] algorithmic
  *   HBM bytes (per family: plain tiled 7 words per node update; prox
  *   elementwise 13 words per node per iteration; DCT pass 2 words per node
- *   per pass; resident 0), out[4] floating-point operations (DCT passes).
+ *   per pass; resident 0), out[4] floating-point operations (DCT passes)
+ *   or, for the plain tiled family, the node updates its launches compute
+ *   (the overlapping halo of the temporal blocks included).
  * Families: W1_FAM_PLAIN_TILED, W1_FAM_PLAIN_RESIDENT, W1_FAM_DCT,
  * W1_FAM_PROX_ELEM, W1_FAM_OTHER, W1_FAM_PROX_RESIDENT (whole small prox
  * levels in one workgroup; resident families count node updates only).    */

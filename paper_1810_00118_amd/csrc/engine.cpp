@@ -61,6 +61,21 @@ template <typename T>
 static inline int dct_t(int n) { return sizeof(T) == 4 ? fold_tiles(n + 1) : gemm_t(n); }
 static inline int tiled_ti(int n, int rh, int S) { return cdiv(n + 1, rh - 2 * S); }
 static inline int tiled_tj(int n, int S) { return cdiv(n + 1, TILED_RW - 2 * S); }
+// nodes of a side-n grid that the tiled kernel's regions (rh x TILED_RW,
+// origins at multiples of the interior size minus the S-node halo) cover,
+// counted with multiplicity: the node updates one of its S-step launches
+// computes per step, halo recomputation included, outside the grid not
+static double tiled_computed(int n, int rh, int S) {
+  auto covered = [n](int tiles, int inner, int width, int S_) {
+    double tot = 0;
+    for (int t = 0; t < tiles; ++t) {
+      const int lo = std::max(t * inner - S_, 0), hi = std::min(t * inner - S_ + width - 1, n);
+      tot += hi >= lo ? hi - lo + 1 : 0;
+    }
+    return tot;
+  };
+  return covered(tiled_ti(n, rh, S), rh - 2 * S, rh, S) * covered(tiled_tj(n, S), TILED_RW - 2 * S, TILED_RW, S);
+}
 static inline int max_tiles(int n) {
   // the tiled kernel has the most tiles at its deepest temporal block
   const int tiled = tiled_ti(n, TILED_RH, TILED_MAX_STEPS) * tiled_tj(n, TILED_MAX_STEPS);
@@ -1273,12 +1288,16 @@ class Batch : public BatchBase {
     int* dn = (int*)(base + off[2]);
     const int ns = (int)cnt[1];
     const double wb = 7.0 * sizeof(T);  // read m1 m2 phi rho, write m1 m2 phi
+    // node updates the launch computes, the overlapping halo included
+    // (reported in the profile's fifth field for this family)
+    double computed = 0;
+    for (auto* r : P) computed += tiled_computed(r->sides[r->level], tc.rh, tc.steps);
     if (t0 && t1) HIPCHK(hipEventRecord(t0, st_));
     for (int li = 0; li < nl; ++li) {
       const bool chk = fpr && li == nl - 1;
       const int pi = prof_.begin();
       K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, li, tc.steps, tc.rh, chk, P[0]->prm.metric, tc.nwv);
-      prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * tc.steps, nodes * tc.steps * wb, 0);
+      prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * tc.steps, nodes * tc.steps * wb, computed * tc.steps);
     }
     if (t0 && t1) {
       HIPCHK(hipEventRecord(t1, st_));
@@ -1448,16 +1467,25 @@ class Batch : public BatchBase {
         K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 1, kind, 0);
         poisson(dgw, (int)gw.size(), 8, 0);
       }
+      // Algorithm 2 with the certificate: the returned flux is the FP64
+      // re-projection of m^K onto {A m = rho} (m^K is feasible by
+      // construction; the FP32 rounding of its last Poisson solve is
+      // removed), and the certificate's correction is that flux's own
+      const int polish = kind == K_PROX && cert ? 1 : 0;
       if (cert) {
         K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 2, kind, 0);
+        poisson(dgw, (int)gw.size(), polish ? POLISH_PLANE : 6, 0);
+      }
+      if (polish) {
+        K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 3, kind, 0);
         poisson(dgw, (int)gw.size(), 6, 0);
       }
-      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, cert);
+      K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, cert, polish);
       int *di, *dn;
       st = reduce_lists(lv, simple_tiles_f, &di, &dn);
       if (st) return st;
       K<T>::eval_final(st_, di, dn, (int)grp.size(), ddesc_, dsc_, kind, cert);
-      K<T>::export_fields(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind);
+      K<T>::export_fields(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, polish);
       HIPCHK(hipGetLastError());
     }
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));

@@ -1545,6 +1545,9 @@ __global__ __launch_bounds__(256) void k_kkt(const Work* __restrict__ work, cons
 //   mode 2: A m - rho                 (certificate and KKT correction), m
 //           from the plain set cur ^ set_xor (kind plain) or planes 0, 1
 //           (prox)
+//   mode 3: A (m + grad+ c) - rho     (prox: the re-projected flux, c in
+//           POLISH_PLANE)
+// Modes 2 and 3 form the residual in FP64 against the slot's FP64 densities.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_div_pre(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
@@ -1583,8 +1586,29 @@ __global__ __launch_bounds__(256) void k_div_pre(const Work* __restrict__ work, 
       v2c = j < n ? a2p[off] : T(0);
       v2l = j > 0 ? a2p[off - 1] : T(0);
     }
-    const T dv = ((v1c - v1u) + (v2c - v2l)) * ih;
-    out[off] = mode == 1 ? dv : dv - d.rho[off];
+    if (mode == 3) {
+      // A (m + grad+ c) - rho of the re-projected flux (c in POLISH_PLANE),
+      // in FP64 from the FP32 planes
+      const T* c = d.p[POLISH_PLANE];
+      const double ihd = (double)n, cc = (double)c[off];
+      const double f1c = i < n ? (double)a1p[off] + ((double)c[off + pitch] - cc) * ihd : 0.0;
+      const double f1u = i > 0 ? (double)a1p[off - pitch] + (cc - (double)c[off - pitch]) * ihd : 0.0;
+      const double f2c = j < n ? (double)a2p[off] + ((double)c[off + 1] - cc) * ihd : 0.0;
+      const double f2l = j > 0 ? (double)a2p[off - 1] + (cc - (double)c[off - 1]) * ihd : 0.0;
+      const double rr = d.r0 ? d.r0[off] - d.r1[off] : (double)d.rho[off];
+      out[off] = (T)(((f1c - f1u) + (f2c - f2l)) * ihd - rr);
+    } else if (mode == 2) {
+      // the residual of the correction in FP64 arithmetic against the FP64
+      // densities where the slot keeps them (its constant part is ignored by
+      // the Poisson solve): near feasibility A m - rho is far smaller than
+      // A m, so an FP32 residual would be mostly its own rounding
+      const double dv2 = (((double)v1c - (double)v1u) + ((double)v2c - (double)v2l)) * (double)n;
+      const double rr = d.r0 ? d.r0[off] - d.r1[off] : (double)d.rho[off];
+      out[off] = (T)(dv2 - rr);
+    } else {
+      const T dv = ((v1c - v1u) + (v2c - v2l)) * ih;
+      out[off] = mode == 1 ? dv : dv - d.rho[off];
+    }
   })
 }
 
@@ -1912,14 +1936,20 @@ __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, cons
 // ---------------------------------------------------------------------------
 // FP64 certificate (finest level): needs the Poisson correction
 // corr = (A A*)^{-1}(A m - rho) in plane 6 (read only with cert) and, for
-// prox, psi in plane 8.
+// prox, psi in plane 8.  With `polish` (prox) the flux m is first replaced
+// by its FP64 re-projection m + grad+ c onto {A m = rho} (c in
+// POLISH_PLANE, plane 6 then holds the re-projected flux's own
+// correction): an Algorithm 2 iterate is feasible by construction, and in
+// FP32 the rounding of its Poisson solve leaves A m - rho at the level of
+// the noise's gradient, which this removes.
 // q0 sum ||m||_p, q1 sum pot*rho, q2 sum ||m + grad+ corr||_p,
 // q3 sum |grad+ corr|^2, q4 sum excess^2, q5 max ||grad pot||_q (max),
 // q6 sum pot, q7 sum rho.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc,
-                                                   const SlotScalars* __restrict__ scal, int kind, int cert) {
+                                                   const SlotScalars* __restrict__ scal, int kind, int cert,
+                                                   int polish) {
   __shared__ double lds[4 * NQ];
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
@@ -1937,10 +1967,16 @@ __global__ __launch_bounds__(256) void k_eval_sums(const Work* __restrict__ work
     pot = d.p[8];
   }
   const T* corr = d.p[6];
+  const T* pol = polish ? d.p[POLISH_PLANE] : nullptr;
   const double ih = 1.0 / d.h;
   double v[NQ] = {0, 0, 0, 0, 0, -INFINITY, 0, 0};
   SIMPLE_TILE_LOOP(d, w, {
-    const double a = (double)m1[off], b = (double)m2[off];
+    double a = (double)m1[off], b = (double)m2[off];
+    if (pol) {
+      const double pc0 = (double)pol[off];
+      if (i < n) a += ((double)pol[off + pitch] - pc0) * ih;
+      if (j < n) b += ((double)pol[off + 1] - pc0) * ih;
+    }
     const double cc = cert ? (double)corr[off] : 0.0;
     const double c1 = cert && i < n ? ((double)corr[off + pitch] - cc) * ih : 0.0;
     const double c2 = cert && j < n ? ((double)corr[off + 1] - cc) * ih : 0.0;
@@ -2016,7 +2052,7 @@ __global__ __launch_bounds__(256) void k_eval_final(const int* __restrict__ idx,
 template <typename T>
 __global__ __launch_bounds__(256) void k_export_fields(const Work* __restrict__ work,
                                                        const SlotDesc<T>* __restrict__ desc,
-                                                       const SlotScalars* __restrict__ scal, int kind) {
+                                                       const SlotScalars* __restrict__ scal, int kind, int polish) {
   const Work w = work[blockIdx.x];
   if (w.x < 0) return;
   const SlotDesc<T>& d = desc[w.x];
@@ -2035,10 +2071,19 @@ __global__ __launch_bounds__(256) void k_export_fields(const Work* __restrict__ 
     m2 = d.p[1];
     pot = d.p[8];
   }
+  const T* pol = polish ? d.p[POLISH_PLANE] : nullptr;
+  const int n = d.n, pitch = d.pitch;
+  const double ih = 1.0 / d.h;
   SIMPLE_TILE_LOOP(d, w, {
     const size_t o = (size_t)i * (d.n + 1) + j;
-    if (om1) om1[o] = (double)m1[off];
-    if (om2) om2[o] = (double)m2[off];
+    double a = (double)m1[off], b = (double)m2[off];
+    if (pol) {
+      const double pc0 = (double)pol[off];
+      if (i < n) a += ((double)pol[off + pitch] - pc0) * ih;
+      if (j < n) b += ((double)pol[off + 1] - pc0) * ih;
+    }
+    if (om1) om1[o] = a;
+    if (om2) om2[o] = b;
     if (opsi) opsi[o] = kind == K_PLAIN ? -((double)pot[off] - mean) : (double)pot[off];
   })
 }
@@ -2197,16 +2242,16 @@ template <typename T> void K<T>::check(hipStream_t s, const int* idx, const int*
   if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len, launches);
 }
 template <typename T> void K<T>::eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                           const SlotScalars* sc, int kind, int cert) {
-  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, sc, kind, cert);
+                                           const SlotScalars* sc, int kind, int cert, int polish) {
+  if (nw) LAUNCH(k_eval_sums<T>, nw, 256, 0, s, w, d, sc, kind, cert, polish);
 }
 template <typename T> void K<T>::eval_final(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
                                             SlotScalars* sc, int kind, int cert) {
   if (ns) LAUNCH(k_eval_final<T>, ns, 256, 0, s, idx, nt, d, sc, kind, cert);
 }
 template <typename T> void K<T>::export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                               const SlotScalars* sc, int kind) {
-  if (nw) LAUNCH(k_export_fields<T>, nw, 256, 0, s, w, d, sc, kind);
+                                               const SlotScalars* sc, int kind, int polish) {
+  if (nw) LAUNCH(k_export_fields<T>, nw, 256, 0, s, w, d, sc, kind, polish);
 }
 
 // FP32 only: the FP64 iterate does not fit the register budget

@@ -30,6 +30,9 @@ constexpr int TILED_RW = 128;        // plain tiled kernel region width
 constexpr int TILED_RH = 64;         // plain tiled kernel region height
 constexpr int TILED_MAX_STEPS = 26;  // most PDHG steps per tiled launch
 constexpr int PRES_THREADS = 1024;   // resident kernel workgroup size (Algorithm 2)
+constexpr int POLISH_PLANE = 4;      // prox, after the last iteration: the
+                                     // re-projection potential (vphibar1 is
+                                     // no longer read)
 
 enum Status : int { ST_RUN = 0, ST_CONV = 1, ST_CAP = 2, ST_DIVERGED = 3, ST_REJECT = 4 };
 enum Rule : int { RULE_KKT = 1, RULE_FPR = 2 };
@@ -132,13 +135,15 @@ struct K {
                         bool check);
   static void check(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
                     SlotScalars* sc, int kind, int block_len, int launches);
-  // cert = 0: no Poisson correction in plane 6; lo, hi and kkt are NaN
+  // cert = 0: no Poisson correction in plane 6; lo, hi and kkt are NaN.
+  // polish = 1 (prox): the flux evaluated (and exported) is m + grad+ c with
+  // c = (A A*)^{-1}(A m - rho) in POLISH_PLANE, its own correction in plane 6
   static void eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                        int kind, int cert);
+                        int kind, int cert, int polish = 0);
   static void eval_final(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
                          SlotScalars* sc, int kind, int cert);
   static void export_fields(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                            int kind);
+                            int kind, int polish = 0);
 };
 
 int resident_lds_bytes(int side, int elem);

@@ -98,8 +98,9 @@ def test_served_request_2048():
     an integer that FP32 arithmetic decides (the last levels can stop one
     iteration later, and one prox iteration at 2049^2 moves the normalised
     KKT by ~5e-5), so the oracle is also run to the FP32 path's own
-    per-level iteration counts and the FP32 result meets W1 1e-4 and KKT
-    1e-5 against that run; against the oracle's own stops W1 keeps 1e-4."""
+    per-level iteration counts and the FP32 result (its flux re-projected
+    onto {A m = rho} in FP64) meets W1 1e-4 and KKT 1e-5 against that run;
+    against the oracle's own stops W1 keeps 1e-4 and KKT 1e-4."""
     w1 = require_gpu()
     req = [q for q in w1data.served_requests(400) if q.n == 2048][0]
     p0, p1 = w1data.served_pair(req)
@@ -132,4 +133,4 @@ def test_served_request_2048():
             assert same["iters"] == res["iters"]
             ev_same = o.evaluate(same["m1"], same["m2"], same["psi"], rho, 1.0 / n, 2)
             assert res["w1"] == pytest.approx(same["w1"], rel=1e-4)
-            assert abs(ev_gpu["kkt"] - ev_same["kkt"]) <= kkt_tol
+            assert abs(ev_gpu["kkt"] - ev_same["kkt"]) <= 1e-5

@@ -276,7 +276,10 @@ def test_served_resident_beside_batched():
 
 def test_no_certificate_flag():
     """Without the certificate the solve runs the same iterations and gives
-    the same W1 and dual; only lo, hi and kkt are left as NaN."""
+    the same dual (and, for Algorithm 1, the same W1); only lo, hi and kkt
+    are left as NaN.  With it, Algorithm 2's W1 is the cost of the FP64
+    re-projection of m^K onto {A m = rho}, within the FP32 projection noise
+    of the unprojected cost."""
     w1 = require_gpu()
     pairs = [w1data.pair_gauss3(60 + i, n=64) for i in range(2)]
     out = []
@@ -286,8 +289,12 @@ def test_no_certificate_flag():
                             tol=0.0, max_iters=2000, check_every=10, flags=flags)
             with w1.Solver(prm, capacity=2) as s:
                 out.append(s.solve(pairs))
-    for a, b in zip(out[0] + out[1], out[2] + out[3]):
-        assert a["iters"] == b["iters"] and a["w1"] == b["w1"] and a["dual"] == b["dual"]
+    for k, (a, b) in enumerate(zip(out[0] + out[1], out[2] + out[3])):
+        assert a["iters"] == b["iters"] and a["dual"] == b["dual"]
+        if k < 2:   # Algorithm 1
+            assert a["w1"] == b["w1"]
+        else:
+            assert a["w1"] == pytest.approx(b["w1"], rel=1e-5)
         assert np.isfinite(a["lo"]) and np.isfinite(a["hi"]) and np.isfinite(a["kkt"])
         assert np.isnan(b["lo"]) and np.isnan(b["hi"]) and np.isnan(b["kkt"])
 
