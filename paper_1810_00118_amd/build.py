@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libw1.so")
 
-SOURCES = ["kernels.hip", "engine.cpp", "capi.cpp", "cube.hip", "noalloc.hip"]
+SOURCES = ["kernels.hip", "fftdct.hip", "engine.cpp", "capi.cpp", "cube.hip", "noalloc.hip"]
 ARCH = os.environ.get("W1_OFFLOAD_ARCH", "gfx950")
 
 

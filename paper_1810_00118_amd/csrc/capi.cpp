@@ -536,6 +536,22 @@ struct Op {
       d.dctCp = (const T*)a;
       d.dctCtp = (const T*)b;
     }
+    if (uses_fft(M, (int)sizeof(T))) {
+      std::vector<float> ch, fb, tw, mk;
+      fft_tables(M, &ch, &fb, &tw, &mk);
+      float2* tabs[4];
+      int k = 0;
+      for (auto* v : {&ch, &fb, &tw, &mk}) {
+        void* q;
+        if (alloc(v->size() * sizeof(float), &q)) return W1_EDEVICE;
+        HIPCHK(hipMemcpy(q, v->data(), v->size() * sizeof(float), hipMemcpyHostToDevice));
+        tabs[k++] = (float2*)q;
+      }
+      d.fft_chirp = tabs[0];
+      d.fft_fb = tabs[1];
+      d.fft_tw = tabs[2];
+      d.fft_mk = tabs[3];
+    }
     return W1_OK;
   }
   int commit(int count) {
@@ -566,7 +582,7 @@ struct Op {
   }
   std::vector<Work> gemmw(int x, int side) {
     std::vector<Work> w;
-    const int t = sizeof(T) == 4 ? fold_tiles(side + 1) : cdiv(side + 1, GEMM_T);
+    const int t = sizeof(T) == 4 && !uses_fft(side + 1, 4) ? fold_tiles(side + 1) : cdiv(side + 1, GEMM_T);
     for (int a = 0; a < t; ++a)
       for (int b = 0; b < t; ++b) w.push_back(make_int4(x, a, b, a * t + b));
     return w;
@@ -580,7 +596,10 @@ struct Op {
   }
   void poisson(Work* gw, int ng, int dst) {
     if constexpr (sizeof(T) == 4) {
-      K<T>::poisson_fold(st, gw, ng, dd, dsc, dst, 0);
+      if (uses_fft(N, 4))
+        poisson_fft(st, gw, ng, (const SlotDesc<float>*)dd, dsc, dst, 0, 1u << __builtin_ctz((unsigned)(2 * (N - 1))));
+      else
+        K<T>::poisson_fold(st, gw, ng, dd, dsc, dst, 0);
       return;
     }
     K<T>::gemm(st, gw, ng, dd, dsc, 0, 6, 7, 1, false, 0);

@@ -58,7 +58,10 @@ static inline int simple_tiles(int n) { return simple_ti(n) * simple_tj(n); }
 static inline int gemm_t(int n) { return cdiv(n + 1, GEMM_T); }
 // tiles per side of the DCT work list: the folded FP32 passes may need more
 template <typename T>
-static inline int dct_t(int n) { return sizeof(T) == 4 ? fold_tiles(n + 1) : gemm_t(n); }
+static inline int dct_t(int n) {
+  if (uses_fft(n + 1, (int)sizeof(T))) return gemm_t(n);   // 64 x 64 transpose tiles
+  return sizeof(T) == 4 ? fold_tiles(n + 1) : gemm_t(n);
+}
 static inline int tiled_ti(int n, int rh, int S) { return cdiv(n + 1, rh - 2 * S); }
 static inline int tiled_tj(int n, int S) { return cdiv(n + 1, TILED_RW - 2 * S); }
 // nodes of a side-n grid that the tiled kernel's regions (rh x TILED_RW,
@@ -301,6 +304,10 @@ struct DctTab {
   void* Cp = nullptr;    // FP32 only: rows of C in even / odd order
   void* Ctp = nullptr;   // FP32 only: transpose of Cp
   double* s = nullptr;
+  float2* chirp = nullptr;   // FP32, uses_fft(N): the FFT path's tables
+  float2* fb = nullptr;
+  float2* tw = nullptr;
+  float2* mk = nullptr;
 };
 static std::mutex g_dct_mu;
 static std::map<std::pair<int, int>, DctTab> g_dct;
@@ -334,6 +341,15 @@ static int dct_tables(int N, DctTab* out) {
   HIPCHK(hipMemcpy(t.C, C.data(), C.size() * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(t.Ct, Ct.data(), Ct.size() * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(t.s, s.data(), N * sizeof(double), hipMemcpyHostToDevice));
+  if (uses_fft(N, (int)sizeof(T))) {
+    std::vector<float> ch, fb, tw, mk;
+    fft_tables(N, &ch, &fb, &tw, &mk);
+    for (auto pr : {std::make_pair(&ch, &t.chirp), std::make_pair(&fb, &t.fb), std::make_pair(&tw, &t.tw),
+                    std::make_pair(&mk, &t.mk)}) {
+      HIPCHK(hipMalloc((void**)pr.second, pr.first->size() * sizeof(float)));
+      HIPCHK(hipMemcpy(*pr.second, pr.first->data(), pr.first->size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+  }
   if (sizeof(T) == 4) {
     std::vector<T> Cp, Ctp;
     fold_order(N, C, &Cp, &Ctp);
@@ -460,8 +476,14 @@ class Prof {
     pend_[i].bytes = bytes;
   }
   // after the stream has been synchronised
+  // (launches whose end event has not completed yet stay pending)
   void harvest() {
+    std::vector<Pend> keep;
     for (auto& p : pend_) {
+      if (hipEventQuery(p.b) == hipErrorNotReady) {
+        keep.push_back(p);
+        continue;
+      }
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         tot_[p.fam][0] += 1;
@@ -473,7 +495,7 @@ class Prof {
       pool_.push_back(p.a);
       pool_.push_back(p.b);
     }
-    pend_.clear();
+    pend_.swap(keep);
   }
   void stats(int f, double* o) const {
     for (int k = 0; k < 5; ++k) o[k] = tot_[f][k];
@@ -519,7 +541,11 @@ class Batch : public BatchBase {
     // few busy compute units overlap the batched launches of other levels
     if (ok_) ok_ = hipStreamCreateWithFlags(&rs_, hipStreamNonBlocking) == hipSuccess;
     if (ok_) ok_ = hipEventCreateWithFlags(&ev_up_, hipEventDisableTiming) == hipSuccess &&
-                   hipEventCreateWithFlags(&ev_res_, hipEventDisableTiming) == hipSuccess;
+                   hipEventCreateWithFlags(&ev_res_, hipEventDisableTiming) == hipSuccess &&
+                   hipEventCreateWithFlags(&ev_sc_, hipEventDisableTiming) == hipSuccess &&
+                   hipEventCreateWithFlags(&ev_arena_, hipEventDisableTiming) == hipSuccess;
+    // W1_SPECULATE=0 turns the speculative iteration blocks off
+    if (const char* e = std::getenv("W1_SPECULATE")) speculate_ = std::atoi(e) != 0;
     // failure injection for tests of the error paths: W1_FAIL_AT_STEP=k
     // makes the k-th step of every batch of the process fail from the host
     // (no device work is affected)
@@ -546,6 +572,8 @@ class Batch : public BatchBase {
     (void)hipHostFree(hsc_);
     if (ev_up_) (void)hipEventDestroy(ev_up_);
     if (ev_res_) (void)hipEventDestroy(ev_res_);
+    if (ev_sc_) (void)hipEventDestroy(ev_sc_);
+    if (ev_arena_) (void)hipEventDestroy(ev_arena_);
     if (rs_) (void)hipStreamDestroy(rs_);
   }
 
@@ -610,6 +638,10 @@ class Batch : public BatchBase {
         d.dctCp = (const T*)t.Cp;
         d.dctCtp = (const T*)t.Ctp;
         d.dcts = t.s;
+        d.fft_chirp = t.chirp;
+        d.fft_fb = t.fb;
+        d.fft_tw = t.tw;
+        d.fft_mk = t.mk;
       }
     }
     double* part = (double*)p;
@@ -658,6 +690,12 @@ class Batch : public BatchBase {
     if (fail_at_ > 0 && n_steps_ == fail_at_) {
       g_err = "step failure injected by W1_FAIL_AT_STEP";
       return fail(W1_EDEVICE);
+    }
+    // the previous step's uploads may still be queued behind its
+    // speculative blocks: their staging bytes are rewritten only after
+    if (arena_pending_) {
+      HIPCHK(hipEventSynchronize(ev_arena_));
+      arena_pending_ = false;
     }
     arena_.reset();
     int st = W1_OK;
@@ -736,16 +774,34 @@ class Batch : public BatchBase {
       if (st) return fail(st);
     }
     n_blocks_ += maxnb;
-    for (int b = 0; b < maxnb; ++b) {
-      int gp = 0, gx = 0;
-      for (auto& g : groups) {
-        const int gi = g.prox ? gx++ : gp++;
-        if (b >= g.nb) continue;
-        st = g.prox ? launch_prox_block(*g.v, gi) : launch_tiled_block(*g.v, gi);
-        if (st) return fail(st);
+    auto blocks = [&](int from, int to, bool spec) {
+      for (int b = from; b < to; ++b) {
+        int gp = 0, gx = 0;
+        for (auto& g : groups) {
+          const int gi = g.prox ? gx++ : gp++;
+          if (b >= g.nb) continue;
+          const int e = g.prox ? launch_prox_block(*g.v, gi) : launch_tiled_block(*g.v, gi, spec);
+          if (e) return e;
+        }
       }
+      return (int)W1_OK;
+    };
+    st = blocks(0, maxnb, false);
+    if (st) return fail(st);
+    // The stop state after these blocks is copied back while a quarter as
+    // many blocks more are queued behind the copy: slots still running keep
+    // the device busy while the host handles the ones that stopped (the
+    // gated kernels skip a slot once it has stopped, and level transitions
+    // queued below run after these blocks)
+    st = queue_scalars();
+    if (st) return fail(st);
+    if (speculate_ && !groups.empty()) {
+      const int spec = std::max(1, maxnb / 4);
+      n_blocks_ += spec;
+      st = blocks(0, spec, true);
+      if (st) return fail(st);
     }
-    st = read_scalars();
+    st = wait_scalars();
     if (st) return fail(st);
     std::vector<Request*> up, fin;
     auto consider = [&](Request* r) {
@@ -778,6 +834,8 @@ class Batch : public BatchBase {
       st = finalize(fin);
       if (st) return fail(st);
     }
+    HIPCHK(hipEventRecord(ev_arena_, st_));
+    arena_pending_ = true;
     return W1_OK;
   }
 
@@ -870,7 +928,11 @@ class Batch : public BatchBase {
     o[2] = n_uploads_;
     o[3] = n_blocks_;
   }
-  void kernel_stats(int f, double* o) const override { prof_.stats(f, o); }
+  void kernel_stats(int f, double* o) const override {
+    (void)hipStreamSynchronize(st_);   // the last step's speculative blocks
+    prof_.harvest();
+    prof_.stats(f, o);
+  }
 
  private:
   int fail(int st) {
@@ -903,14 +965,26 @@ class Batch : public BatchBase {
     retire_.clear();
   }
 
-  int read_scalars() {
+  // the slot scalars after the work queued so far: copy queued, event
+  // recorded; wait_scalars() waits for that event only, so work queued in
+  // between (speculative iteration blocks) overlaps the host's processing
+  int queue_scalars() {
     if (res_side_) {
       // resident levels launched on the side stream finish before the copy
       HIPCHK(hipStreamWaitEvent(st_, ev_res_, 0));
       res_side_ = false;
     }
     HIPCHK(hipMemcpyAsync(hsc_, dsc_, sizeof(SlotScalars) * cap_, hipMemcpyDeviceToHost, st_));
-    HIPCHK(hipStreamSynchronize(st_));
+    HIPCHK(hipEventRecord(ev_sc_, st_));
+    return W1_OK;
+  }
+  int read_scalars() {
+    int st = queue_scalars();
+    if (st) return st;
+    return wait_scalars();
+  }
+  int wait_scalars() {
+    HIPCHK(hipEventSynchronize(ev_sc_));
     free_retired();
     for (auto& t : tune_pending_) {
       float ms = 0.f;
@@ -1243,7 +1317,8 @@ class Batch : public BatchBase {
   }
 
   // -- plain: one block of check_every iterations, tiled -------------------
-  int launch_tiled_block(std::vector<Request*>& P, int group) {
+  // spec: a speculative block (never timed by the autotuner)
+  int launch_tiled_block(std::vector<Request*>& P, int group, bool spec = false) {
     int st = W1_OK;
     const int ce = P[0]->prm.check_every;
     const bool fpr = P[0]->prm.stop_rule == W1_STOP_FPR;
@@ -1253,6 +1328,7 @@ class Batch : public BatchBase {
     int arm = -1;
     long entry = -1;
     const TileChoice tc = g_tuner().pick(prec, nodes, ce, P[0]->prm.block_steps, &arm, &entry);
+    if (spec) arm = -1;
     const int nl = ce / tc.steps;   // the tuner only offers divisors of ce
     auto lv = at_level(P);
     const std::string key = "P" + std::to_string(group) + "_" + std::to_string(tc.rh) + "_" + std::to_string(tc.steps);
@@ -1309,7 +1385,7 @@ class Batch : public BatchBase {
       Work* ksw = (Work*)(base + off[3]);
       const int nksw = (int)cnt[3];
       K<T>::div_pre(st_, ksw, nksw, ddesc_, dsc_, 2, K_PLAIN, 1, nl & 1);
-      poisson((Work*)(base + off[4]), (int)cnt[4], 6, 1);
+      poisson((Work*)(base + off[4]), (int)cnt[4], 6, 1, lv);
       K<T>::kkt(st_, ksw, nksw, ddesc_, dsc_, K_PLAIN, nl & 1, 1);
     }
     K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PLAIN, ce, nl);
@@ -1318,9 +1394,19 @@ class Batch : public BatchBase {
   }
 
   // -- Poisson solve through four DCT passes ------------------------------
-  void poisson(Work* gw, int ng, int dst, int gate) {
+  void poisson(Work* gw, int ng, int dst, int gate, const std::vector<std::pair<Request*, int>>& lv) {
     if constexpr (sizeof(T) == 4) {
-      K<T>::poisson_fold(st_, gw, ng, ddesc_, dsc_, dst, gate);
+      // each slot takes the FFT path or the folded matrix passes by its
+      // transform length; the kernels of the other path return at once
+      unsigned sizes = 0;
+      bool fold = false;
+      for (auto& e : lv) {
+        const int N = e.first->sides[e.second] + 1;
+        if (uses_fft(N, 4)) sizes |= 1u << __builtin_ctz((unsigned)(2 * (N - 1)));
+        else fold = true;
+      }
+      if (fold) K<T>::poisson_fold(st_, gw, ng, ddesc_, dsc_, dst, gate);
+      if (sizes) poisson_fft(st_, gw, ng, (const SlotDesc<float>*)ddesc_, dsc_, dst, gate, sizes);
       return;
     }
     K<T>::gemm(st_, gw, ng, ddesc_, dsc_, 0, 6, 7, 1, false, gate);   // rows:    X C^T
@@ -1356,21 +1442,30 @@ class Batch : public BatchBase {
     int* di = (int*)(base + off[2]);
     int* dn = (int*)(base + off[3]);
     const int nsw = (int)cnt[0], ngw = (int)cnt[1], ns = (int)cnt[2];
-    double nodes = 0, flops = 0;
+    double nodes = 0, flops = 0, dbytes = 0;
     for (auto* r : X) {
-      const double N = r->sides[r->level] + 1;
+      const int n1 = r->sides[r->level] + 1;
+      const double N = n1;
       nodes += N * N;
-      // flops the passes execute: the FP32 passes fold each length-N
-      // product into two of about half the length
-      flops += (sizeof(T) == 4 ? 4.0 : 8.0) * N * N * N;
+      if (uses_fft(n1, (int)sizeof(T))) {
+        // five passes over the plane (three transforms of line pairs, two
+        // transposes); flops of the line transforms, conventionally counted
+        flops += fft_poisson_flops(n1);
+        dbytes += N * N * 10.0 * sizeof(T);
+      } else {
+        // the FP32 passes fold each length-N product into two of about
+        // half the length
+        flops += (sizeof(T) == 4 ? 4.0 : 8.0) * N * N * N;
+        dbytes += N * N * 8.0 * sizeof(T);
+      }
     }
     for (int it = 0; it < ce; ++it) {
       int pi = prof_.begin();
       K<T>::div_pre(st_, dsw, nsw, ddesc_, dsc_, 0, K_PROX, 1);
       prof_.end(pi, W1_FAM_PROX_ELEM, nodes, nodes * 6.0 * sizeof(T), 0);
       pi = prof_.begin();
-      poisson(dgw, ngw, 6, 1);
-      prof_.end(pi, W1_FAM_DCT, nodes, nodes * 8.0 * sizeof(T), flops);
+      poisson(dgw, ngw, 6, 1, lv);
+      prof_.end(pi, W1_FAM_DCT, nodes, dbytes, flops);
       pi = prof_.begin();
       K<T>::prox_post(st_, dsw, nsw, ddesc_, dsc_, fpr && it == ce - 1);
       prof_.end(pi, W1_FAM_PROX_ELEM, 0, nodes * 13.0 * sizeof(T), 0);
@@ -1378,9 +1473,9 @@ class Batch : public BatchBase {
     if (!fpr) {
       // KKT: psi (Appendix B) into plane 8, the correction potential into 6
       K<T>::div_pre(st_, dsw, nsw, ddesc_, dsc_, 1, K_PROX, 1);
-      poisson(dgw, ngw, 8, 1);
+      poisson(dgw, ngw, 8, 1, lv);
       K<T>::div_pre(st_, dsw, nsw, ddesc_, dsc_, 2, K_PROX, 1);
-      poisson(dgw, ngw, 6, 1);
+      poisson(dgw, ngw, 6, 1, lv);
       K<T>::kkt(st_, dsw, nsw, ddesc_, dsc_, K_PROX, 0, 1);
     }
     K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PROX, ce, 0);
@@ -1465,7 +1560,7 @@ class Batch : public BatchBase {
       if (st) return st;
       if (kind == K_PROX) {
         K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 1, kind, 0);
-        poisson(dgw, (int)gw.size(), 8, 0);
+        poisson(dgw, (int)gw.size(), 8, 0, lv);
       }
       // Algorithm 2 with the certificate: the returned flux is the FP64
       // re-projection of m^K onto {A m = rho} (m^K is feasible by
@@ -1474,11 +1569,11 @@ class Batch : public BatchBase {
       const int polish = kind == K_PROX && cert ? 1 : 0;
       if (cert) {
         K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 2, kind, 0);
-        poisson(dgw, (int)gw.size(), polish ? POLISH_PLANE : 6, 0);
+        poisson(dgw, (int)gw.size(), polish ? POLISH_PLANE : 6, 0, lv);
       }
       if (polish) {
         K<T>::div_pre(st_, dsw, (int)sw.size(), ddesc_, dsc_, 3, kind, 0);
-        poisson(dgw, (int)gw.size(), 6, 0);
+        poisson(dgw, (int)gw.size(), 6, 0, lv);
       }
       K<T>::eval_sums(st_, dsw, (int)sw.size(), ddesc_, dsc_, kind, cert, polish);
       int *di, *dn;
@@ -1536,6 +1631,10 @@ class Batch : public BatchBase {
   hipStream_t rs_ = nullptr;        // side stream of the resident levels
   hipEvent_t ev_up_ = nullptr;      // this step's uploads, for the side stream
   hipEvent_t ev_res_ = nullptr;     // the side stream's launches of this step
+  hipEvent_t ev_sc_ = nullptr;      // the slot scalars' copy of this step
+  hipEvent_t ev_arena_ = nullptr;   // after the last upload of the previous step
+  bool arena_pending_ = false;
+  bool speculate_ = true;
   bool res_side_ = false;
   int64_t fail_at_ = 0;              // W1_FAIL_AT_STEP (tests only)
   Arena arena_;
@@ -1548,7 +1647,7 @@ class Batch : public BatchBase {
   std::vector<int> dirty_;
   uint64_t gen_ = 0;
   std::map<std::string, DevList> lists_;
-  Prof prof_;
+  mutable Prof prof_;
   std::vector<std::pair<int, std::vector<Request*>>> resident_pending_;
 };
 

@@ -513,6 +513,23 @@ __device__ __forceinline__ int lane_prev_i(int v) { return __builtin_amdgcn_upda
 // lane i receives lane i+1 (lane 63 receives 0)
 __device__ __forceinline__ int lane_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
 
+// rotations: lane i receives lane i+1 (lane 63 receives lane 0) / lane i-1
+// (lane 0 receives lane 63)
+__device__ __forceinline__ int lane_rot_next_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x134, 0xf, 0xf, true); }
+__device__ __forceinline__ int lane_rot_prev_i(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x13c, 0xf, 0xf, true); }
+__device__ __forceinline__ float lane_rot_next(float v) { return __int_as_float(lane_rot_next_i(__float_as_int(v))); }
+__device__ __forceinline__ float lane_rot_prev(float v) { return __int_as_float(lane_rot_prev_i(__float_as_int(v))); }
+__device__ __forceinline__ double lane_rot_next(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_rot_next_i((int)(b & 0xffffffffll)), hi = lane_rot_next_i((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_rot_prev(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_rot_prev_i((int)(b & 0xffffffffll)), hi = lane_rot_prev_i((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ float lane_prev(float v) { return __int_as_float(lane_prev_i(__float_as_int(v))); }
 __device__ __forceinline__ float lane_next(float v) { return __int_as_float(lane_next_i(__float_as_int(v))); }
 __device__ __forceinline__ float lane_read(float v, int l) {
@@ -606,7 +623,10 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
   for (int b = 0; b < NC; ++b) {
     const int c = lane + 64 * b, gj = gj0 + c;
     cin[b] = (unsigned)gj <= (unsigned)n;
-    chr[b] = gj < n && c + 1 < RW;
+    // no neighbour to the right outside the grid either (gj < 0): every
+    // node outside the grid then keeps zero iterates without masking (its
+    // gradient, flux, extrapolated flux and divergence are all zero)
+    chr[b] = gj >= 0 && gj < n && c + 1 < RW;
   }
 
   // a row of the strip, or a column half, that lies wholly outside the grid
@@ -651,19 +671,18 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
 #pragma unroll
     for (int a = 0; a < NR; ++a) {
       // potential at the next column: lane + 1, crossing into the second
-      // column half at lane 63; the region's last column has no neighbour
-      const T x0 = lane_next(ph[a][0]);
+      // column half at lane 63 (lane 0 offers that half's first column to
+      // the rotation); the region's last column has no neighbour
+      const T x0 = lane_rot_next(lane == 0 ? ph[a][1] : ph[a][0]);
       const T x1 = lane_next(ph[a][1]);
-      const T h0 = lane_read(ph[a][1], 0);
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
         if (!(rin[a] && hact[b])) continue;
         const T pc = ph[a][b];
         const T pd = a + 1 < NR ? ph[a + 1 < NR ? a + 1 : a][b] : (wv + 1 < NWV ? Bp[wv + 1 < NWV ? wv + 1 : wv][lane + 64 * b] : pc);
-        const T pr = b == 0 ? (lane == 63 ? h0 : x0) : x1;
+        const T pr = b == 0 ? x0 : x1;
         T n1, n2;
         plain_flux_(m1[a][b], m2[a][b], pc, pd, pr, rhd[a], chr[b], ih, mu, metric, n1, n2);
-        if (!(rin[a] && cin[b])) { n1 = T(0); n2 = T(0); }
         b1[a][b] = fma_(T(2), n1, -m1[a][b]);   // 2 n1 is exact: the same rounding as (n1 + n1) - m1
         b2[a][b] = fma_(T(2), n2, -m2[a][b]);
         if constexpr (KEEP) {
@@ -685,32 +704,30 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
 #pragma unroll
     for (int a = 0; a < NR; ++a) {
       // extrapolated flux (axis 2) at the previous column: lane - 1,
-      // crossing back from the second column half at lane 0
+      // crossing back from the second column half at lane 0 (lane 63
+      // offers the first half's last column to the rotation)
       const T y0 = lane_prev(b2[a][0]);
-      const T y1 = lane_prev(b2[a][1]);
-      const T g63 = lane_read(b2[a][0], 63);
+      const T y1 = lane_rot_prev(lane == 63 ? b2[a][0] : b2[a][1]);
       // the same shifts of the new flux (axis 2) for the checked step; the
       // cross-lane reads run with every lane active, outside any per-lane
       // condition, so no lane reads a masked-off neighbour
-      T z0 = T(0), z1 = T(0), z63 = T(0);
+      T z0 = T(0), z1 = T(0);
       if constexpr (KEEP) {
         z0 = lane_prev(m2[a][0]);
-        z1 = lane_prev(m2[a][1]);
-        z63 = lane_read(m2[a][0], 63);
+        z1 = lane_rot_prev(lane == 63 ? m2[a][0] : m2[a][1]);
       }
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
         if (!(rin[a] && hact[b])) continue;
         const T b1u = a > 0 ? b1[a > 0 ? a - 1 : 0][b] : (wv > 0 ? Bb[wv > 0 ? wv - 1 : 0][lane + 64 * b] : T(0));
-        const T b2l = b == 0 ? y0 : (lane == 0 ? g63 : y1);
-        T pn = plain_potential_(ph[a][b], b1[a][b], b1u, b2[a][b], b2l, rh[a][b], ih, tau);
-        if (!(rin[a] && cin[b])) pn = T(0);
+        const T b2l = b == 0 ? y0 : y1;
+        const T pn = plain_potential_(ph[a][b], b1[a][b], b1u, b2[a][b], b2l, rh[a][b], ih, tau);
         if constexpr (KEEP) {
           const int r = r0 + a, c = lane + 64 * b;
           // flux change at the node, at (i-1, j) and at (i, j-1); interior
           // nodes have r, c >= S >= 1, so both neighbours are in the region
           const T m1u = a > 0 ? m1[a > 0 ? a - 1 : 0][b] : (wv > 0 ? Bm[wv > 0 ? wv - 1 : 0][lane + 64 * b] : T(0));
-          const T m2l = b == 0 ? z0 : (lane == 0 ? z63 : z1);
+          const T m2l = b == 0 ? z0 : z1;
           if (rin[a] && cin[b] && r >= S && r < RH - S && c >= S && c < RW - S) {
             const T e1c = b1[a][b] - m1[a][b], e1u = b1u - m1u;
             const T e2c = b2[a][b] - m2[a][b], e2l = b2l - m2l;
@@ -725,7 +742,14 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
     }
   };
 
-  for (int s = 0; s < S - 1; ++s) step(std::false_type{});
+  // two steps per trip: the new flux lands in the registers the old one
+  // frees, with no copies between steps
+  int s = 0;
+  for (; s + 2 <= S - 1; s += 2) {
+    step(std::false_type{});
+    step(std::false_type{});
+  }
+  if (s < S - 1) step(std::false_type{});
   if constexpr (CHECK) {
     step(std::true_type{});
     double v[NQ] = {(double)q0, (double)q1, (double)q2, 0, 0, 0, 0, 0};
@@ -1726,6 +1750,7 @@ __global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
   if (gate && scal[w.x / MAXL].status != ST_RUN) return;
   const SlotDesc<float>& d = desc[w.x];
   const int N = d.n + 1, ld = d.pitch, h = N / 2, ne = N - h, no = h;
+  if (uses_fft(N, 4)) return;   // solved by the FFT path
   const W1_GLOBAL float* __restrict__ X = gld_(d.p[src]);
   W1_GLOBAL float* __restrict__ Y = gst_(d.p[dst]);
   const W1_GLOBAL float* __restrict__ Cp = gld_(d.dctCp);

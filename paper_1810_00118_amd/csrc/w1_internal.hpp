@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <cmath>
 #include <vector>
 
 namespace w1 {
@@ -30,6 +31,10 @@ constexpr int TILED_RW = 128;        // plain tiled kernel region width
 constexpr int TILED_RH = 64;         // plain tiled kernel region height
 constexpr int TILED_MAX_STEPS = 26;  // most PDHG steps per tiled launch
 constexpr int PRES_THREADS = 1024;   // resident kernel workgroup size (Algorithm 2)
+constexpr int FFT_MIN_N = 1025;      // FP32 Poisson solves by FFT from this
+                                     // transform length on (N = n + 1 with
+                                     // 2 (N - 1) a power of two up to 8192)
+constexpr int FFT_MAX_N = 4097;
 constexpr int POLISH_PLANE = 4;      // prox, after the last iteration: the
                                      // re-projection potential (vphibar1 is
                                      // no longer read)
@@ -51,6 +56,11 @@ struct SlotDesc {
   const double* dcts;  // 4 sin^2(pi k / 2N), k < N
   const T* dctCp;      // C with its rows in even-then-odd frequency order
   const T* dctCtp;     // and its transpose (folded FP32 passes)
+  // FP32, N >= FFT_MIN_N: tables of the FFT-based transforms (M = 2N - 2):
+  const float2* fft_chirp;   // c_m = e^{-i pi m^2 / N}, m < N
+  const float2* fft_fb;      // FFT_M of the chirp filter conj(c), over M
+  const float2* fft_tw;      // e^{-2 pi i t / M}, t < M
+  const float2* fft_mk;      // e^{-i pi k / 2N}, k < N
   const double* in0;   // finest level only: input masses, dense pitch n+1
   const double* in1;
   double* out_m1;      // finest level only: exported fields, dense FP64
@@ -147,6 +157,28 @@ struct K {
 };
 
 int resident_lds_bytes(int side, int elem);
+// the FP32 Poisson solve by FFT (fftdct.hip) of every listed slot with
+// FFT_MIN_N <= N <= FFT_MAX_N (others return at once): plane 6 in (and
+// overwritten), plane 7 scratch, result in plane dst; the list holds
+// T x T tiles per slot with T >= cdiv(N, 64).  `sizes`: bit m set when a
+// listed slot has 2 (N - 1) = 2^m
+void poisson_fft(hipStream_t s, const Work* w, int nw, const SlotDesc<float>* d, const SlotScalars* sc, int dst,
+                 int gate, unsigned sizes);
+__host__ __device__ inline bool uses_fft(int N, int elem) {
+  return elem == 4 && N >= FFT_MIN_N && N <= FFT_MAX_N && ((N - 1) & (N - 2)) == 0;
+}
+// flops of one Poisson solve by the FFT path, counted conventionally: four
+// line transforms (rows, columns both ways, rows) of ceil(N/2) line pairs,
+// each pair a Bluestein DFT of two length-M FFTs (5 M log2 M) plus the
+// pointwise filter (6 M) and the chirp, twiddle and unpacking work (~30 N)
+inline double fft_poisson_flops(int N) {
+  const double M = 2.0 * (N - 1), lg = std::log2(M);
+  return 4.0 * ((N + 1) / 2) * (2.0 * 5.0 * M * lg + 6.0 * M + 30.0 * N);
+}
+// host tables of the FFT path for transform length N (FP64 computed,
+// rounded to FP32): chirp (N), fb (M), tw (M), mk (N) complex pairs
+void fft_tables(int N, std::vector<float>* chirp, std::vector<float>* fb, std::vector<float>* tw,
+                std::vector<float>* mk);
 // frequency order of the folded DCT: ne = N - N/2 even frequencies first,
 // then the N/2 odd ones
 inline int fold_perm(int x, int N) {

@@ -140,6 +140,29 @@ def test_prox_steps_trajectory(precision, n, metric):
     assert G == pytest.approx(Gw, rel=1e-8 if precision == FP64 else 1e-2, abs=1e-12)
 
 
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_prox_steps_trajectory_fft(n):
+    """Algorithm 2 steps on grids whose FP32 Poisson solves take the FFT
+    path follow the oracle's iterates and G^k."""
+    w1 = require_gpu()
+    h = 1.0 / n
+    rho = _rho(n, 3 + n)
+    m1, m2, _ = _rand_state(n, 4)
+    rng = np.random.default_rng(5)
+    v1 = rng.uniform(-1, 1, (n + 1, n + 1)); v1[n, :] = 0
+    v2 = rng.uniform(-1, 1, (n + 1, n + 1)); v2[:, n] = 0
+    g = [dev(x, tdtype(FP32)) for x in (m1, m2, v1, v2, v1, v2, rho)]
+    k = 4
+    G = w1.op_prox_steps(n, 2, FP32, k, *g, fpr=True)
+    st = (m1, m2, v1, v2, v1.copy(), v2.copy())
+    for _ in range(k):
+        out = o.prox_step(*st, rho, h, 0.5, 0.5, 2)
+        st, Gw = out[:6], out[6]
+    for got, want in zip(g[:6], st):
+        assert rel_err(host(got), want) <= 1e-4
+    assert G == pytest.approx(Gw, rel=1e-2, abs=1e-12)
+
+
 @pytest.mark.parametrize("n", [4, 7, 16, 32, 40, 63, 64])
 @pytest.mark.parametrize("metric", [1, 2, 3])
 @pytest.mark.parametrize("k", [1, 10, 60])
@@ -183,8 +206,10 @@ def test_prox_resident_rejects_unsupported():
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
-@pytest.mark.parametrize("n", [4, 16, 63, 64, 99, 128, 129, 200, 512, 1000])
+@pytest.mark.parametrize("n", [4, 16, 63, 64, 99, 128, 129, 200, 512, 1000, 1024, 2048])
 def test_poisson(precision, n):
+    # FP32 from n = 1024 on: the FFT path (Bluestein DFTs of the DCT lines);
+    # below, and in FP64, products with the DCT matrix
     w1 = require_gpu()
     rng = np.random.default_rng(n)
     r = rng.standard_normal((n + 1, n + 1)); r -= r.mean()
