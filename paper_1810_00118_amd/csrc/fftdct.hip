@@ -17,7 +17,9 @@
 //    the offsets k - j span -(N-1)..N-1, and the only two that coincide
 //    modulo M (+-(N-1)) carry the same chirp value, so no wrap-around term
 //    is wrong.  Two power-of-two FFTs of length M per line pair, in LDS
-//    (Stockham radix-4 passes, one radix-2 pass for odd powers of two).
+//    (Stockham passes of radix 16, 8 or 4; the loads of the input are the
+//    first pass's reads, and the product with the chirp's transform is
+//    folded into the last pass's writes).
 //
 // A 2-D solve is five passes over the grid: rows forward, a transpose, the
 // columns forward, divided by the eigenvalue lambda_kl = (s_k + s_l) / h^2
@@ -34,12 +36,57 @@
 
 namespace w1 {
 
+// The Stockham plan per transform length M: radix of pass q (0 past the
+// last), 1024 = 4^5, 2048 = 8^3 4, 4096 = 8^4, 8192 = 16^3 2, so every pass
+// has at least one butterfly per thread of the workgroup.
+__host__ __device__ constexpr int fft_radix(int M, int q) {
+  return M == 1024   ? (q < 5 ? 4 : 0)
+         : M == 2048 ? (q < 3 ? 8 : q == 3 ? 4 : 0)
+         : M == 4096 ? (q < 4 ? 8 : 0)
+         : M == 8192 ? (q < 3 ? 16 : q == 3 ? 2 : 0)
+                     : 0;
+}
+// threads per workgroup of a line transform of length M (every pass has
+// a whole number of butterflies per thread)
+__host__ __device__ constexpr int fft_threads(int M) { return M >= 4096 ? 512 : 256; }
+__host__ __device__ constexpr int fft_passes(int M) {
+  int q = 0;
+  while (fft_radix(M, q)) ++q;
+  return q;
+}
+// span Ns of the sub-transforms pass q combines (the product of the
+// earlier radices)
+__host__ __device__ constexpr int fft_ns(int M, int q) {
+  int ns = 1;
+  for (int p = 0; p < q; ++p) ns *= fft_radix(M, p);
+  return ns;
+}
+// offset of pass q's twiddles in the table: (R - 1) Ns entries per pass
+// with Ns > 1 (the first pass's are all 1); the total stays below M
+__host__ __device__ constexpr int fft_twoff(int M, int q) {
+  int off = 0;
+  for (int p = 0; p < q; ++p)
+    if (fft_ns(M, p) > 1) off += (fft_radix(M, p) - 1) * fft_ns(M, p);
+  return off;
+}
+
 namespace {
 
-constexpr int FT = 256;   // threads per workgroup
+constexpr int FT = 256;   // threads per workgroup of the transpose
+
+// Tables and planes are device global memory.  Through generic pointers
+// the compiler emits flat loads, which also count against the LDS wait
+// counter (every wait for an LDS read would wait for the table loads in
+// flight too); through these address-space-1 pointers they are global loads.
+#define FG __attribute__((address_space(1)))
+// a complex table entry through a global pointer
+__device__ __forceinline__ float2 ld2_(const FG float2* p) {
+  const FG float* q = (const FG float*)p;
+  return make_float2(q[0], q[1]);
+}
 
 __device__ __forceinline__ float2 cmul_(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cadd_(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub_(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -127,154 +174,166 @@ __device__ __forceinline__ void dftR_(float2 (&v)[R]) {
   else dft16_(v);
 }
 
-// One Stockham pass of radix R over length M in LDS: for every butterfly
-// j < M / R (k = j mod Ns), X'[(j / Ns) Ns R + k + r Ns] = DFT_R over r of
-// X[j + r M / R] e^{-2 pi i r k / (Ns R)}.  Every thread reads its
-// butterflies' inputs and twiddles (the twiddle loads do not depend on the
-// data and overlap the LDS reads and the barrier), the workgroup
-// synchronises, then writes their outputs.  tw[t] = e^{-2 pi i t / M}.
-template <int M, int R>
-__device__ __forceinline__ void fft_pass_(float2* __restrict__ buf, const float2* __restrict__ tw, int Ns) {
-  constexpr int NB = M / R, PB = (NB + FT - 1) / FT;
-  const int step = M / (Ns * R);
+// LDS index swizzle: bits 0..4 of a buffer index are XORed with bits 4..8
+// (a bijection on every length here).  The Stockham passes write at
+// strides R and Ns R; without it the 64 lanes of a wavefront would write
+// the first radix-16 pass into a single LDS bank.
+__device__ __forceinline__ int sw_(int i) { return i ^ ((i >> 4) & 31); }
+
+// Stockham pass q of the transform of length M: butterfly j < M / R (with
+// k = j mod Ns) takes X[j + r M / R] e^{-2 pi i r k / (Ns R)}, r < R, and
+// writes its length-R DFT to X'[(j / Ns) Ns R + k + r Ns].
+//   SRC: the inputs come from load(p), the sequence at position p (first
+//        pass only: nothing is read from LDS, so no barrier is needed
+//        before the writes)
+//   FB:  the outputs are written as conj(X'_p fb_p) (last pass only)
+// The twiddles of pass q (Ns > 1) sit at tw + fft_twoff(M, q), at
+// [(r - 1) Ns + k], so consecutive butterflies read consecutive entries.
+// Reads, twiddle and fb loads are issued before the barrier; the pass ends
+// synchronised.
+template <int M, int q, bool SRC, bool FB, class L>
+__device__ __forceinline__ void fft_pass_(float2* __restrict__ buf, const FG float2* __restrict__ tw,
+                                          const FG float2* __restrict__ fb, const L& load) {
+  constexpr int FL = fft_threads(M), R = fft_radix(M, q), Ns = fft_ns(M, q), NB = M / R, PB = NB / FL;
+  static_assert(NB % FL == 0, "whole butterflies per thread");
+  // the table pointers are made opaque here, so the compiler keeps each
+  // pass's twiddle and fb loads in that pass instead of hoisting all of
+  // them (loop invariants of the pair loop) into registers at the start
+  const FG float2* t = tw + fft_twoff(M, q);
+  asm volatile("" : "+s"(t));
+  if constexpr (FB) asm volatile("" : "+s"(fb));
   float2 v[PB][R];
+  float2 f[FB ? PB : 1][FB ? R : 1];
 #pragma unroll
   for (int b = 0; b < PB; ++b) {
-    const int j = threadIdx.x + FT * b;
-    if (j < NB) {
-      const int k = j & (Ns - 1);
-      v[b][0] = buf[j];
+    const int j = threadIdx.x + FL * b, k = j & (Ns - 1), o = (j - k) * R + k;
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[b][r] = cmul_(buf[j + r * NB], tw[r * k * step]);
+    for (int r = 0; r < R; ++r) {
+      float2 x;
+      if constexpr (SRC) {
+        // a Bluestein input is 0 from position N = M/2 + 1 on: of the
+        // upper half only position M/2 (butterfly 0) is loaded
+        if (r < R / 2) x = load(j + r * NB);
+        else if (r == R / 2) x = j == 0 ? load(M / 2) : make_float2(0.f, 0.f);
+        else x = make_float2(0.f, 0.f);
+      } else {
+        x = buf[sw_(j + r * NB)];
+      }
+      if constexpr (Ns > 1) {
+        if (r > 0) x = cmul_(x, ld2_(t + (r - 1) * Ns + k));
+      }
+      v[b][r] = x;
+      if constexpr (FB) f[b][r] = ld2_(fb + o + r * Ns);
     }
   }
-  __syncthreads();
+  if constexpr (!SRC) __syncthreads();
 #pragma unroll
   for (int b = 0; b < PB; ++b) {
-    const int j = threadIdx.x + FT * b;
-    if (j < NB) {
-      const int k = j & (Ns - 1);
-      dftR_<R>(v[b]);
-      const int o = (j - k) * R + k;   // (j / Ns) Ns R + k
+    const int j = threadIdx.x + FL * b, k = j & (Ns - 1), o = (j - k) * R + k;
+    dftR_<R>(v[b]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[o + r * Ns] = v[b][r];
+    for (int r = 0; r < R; ++r) {
+      float2 y = v[b][r];
+      if constexpr (FB) y = conj_(cmul_(y, f[b][r]));
+      buf[sw_(o + r * Ns)] = y;
     }
   }
   __syncthreads();
 }
 
-// In-place forward FFT of length M in LDS (natural order in and out),
-// Stockham passes chosen so every pass has at least FT butterflies:
-// 1024 = 4^5, 2048 = 8^3 4, 4096 = 16^3, 8192 = 16^3 2.  Ends synchronised.
-template <int M>
-__device__ void fft_(float2* __restrict__ buf, const float2* __restrict__ tw) {
-  if constexpr (M == 4096) {
-    fft_pass_<M, 16>(buf, tw, 1);
-    fft_pass_<M, 16>(buf, tw, 16);
-    fft_pass_<M, 16>(buf, tw, 256);
-  } else if constexpr (M == 8192) {
-    fft_pass_<M, 16>(buf, tw, 1);
-    fft_pass_<M, 16>(buf, tw, 16);
-    fft_pass_<M, 16>(buf, tw, 256);
-    fft_pass_<M, 2>(buf, tw, 4096);
-  } else if constexpr (M == 2048) {
-    fft_pass_<M, 8>(buf, tw, 1);
-    fft_pass_<M, 8>(buf, tw, 8);
-    fft_pass_<M, 8>(buf, tw, 64);
-    fft_pass_<M, 4>(buf, tw, 512);
-  } else {
-    static_assert(M == 1024, "transform lengths 1024..8192");
-#pragma unroll 1
-    for (int Ns = 1; Ns < M; Ns *= 4) fft_pass_<M, 4>(buf, tw, Ns);
-  }
+// Forward FFT of length M into LDS (natural order, swizzled), from load()
+// when SRC, else in place from LDS; with FB the result is stored as
+// conj(X fb).  Ends synchronised.
+template <int M, bool SRC, bool FB, class L>
+__device__ __forceinline__ void fft_(float2* __restrict__ buf, const FG float2* __restrict__ tw,
+                                     const FG float2* __restrict__ fb, const L& load) {
+  constexpr int Q = fft_passes(M);
+  fft_pass_<M, 0, SRC, FB && Q == 1>(buf, tw, fb, load);
+  if constexpr (Q > 1) fft_pass_<M, 1, false, FB && Q == 2>(buf, tw, fb, load);
+  if constexpr (Q > 2) fft_pass_<M, 2, false, FB && Q == 3>(buf, tw, fb, load);
+  if constexpr (Q > 3) fft_pass_<M, 3, false, FB && Q == 4>(buf, tw, fb, load);
+  if constexpr (Q > 4) fft_pass_<M, 4, false, FB && Q == 5>(buf, tw, fb, load);
 }
 
-// Bluestein: on entry buf[j] = a_j = z_j c_j (j < N) and 0 up to M; on exit
-// buf[k] holds conj(y_k) with y = a (*) b (circular, length M), so the DFT of
-// z is Z_k = c_k conj(buf[k]) for k < N.  fb = FFT(b) / M.
-template <int M>
-__device__ void bluestein_(float2* __restrict__ buf, const float2* __restrict__ tw, const float2* __restrict__ fb) {
-  fft_<M>(buf, tw);
-  for (int p = threadIdx.x; p < M; p += FT) buf[p] = conj_(cmul_(buf[p], fb[p]));
-  __syncthreads();
-  fft_<M>(buf, tw);   // FFT(conj(A)) = M conj(IFFT(A)): fb carries the 1 / M
+// Bluestein: load(j) = a_j = z_j c_j (j < N), 0 up to M.  On exit buf[k]
+// (swizzled) holds conj(y_k) with y = a (*) b (circular, length M), so the
+// DFT of z is Z_k = c_k conj(buf[k]) for k < N.  fb = FFT(b) / M.
+template <int M, class L>
+__device__ void bluestein_(float2* __restrict__ buf, const FG float2* __restrict__ tw, const FG float2* __restrict__ fb,
+                           const L& load) {
+  fft_<M, true, true>(buf, tw, fb, load);   // conj(FFT(a) fb)
+  fft_<M, false, false>(buf, tw, fb, load);   // FFT(conj(A)) = M conj(IFFT(A)): fb carries the 1 / M
 }
 
 // orthonormal DCT scale s_k
 __device__ __forceinline__ float dct_s_(int k, int N) {
   return k == 0 ? sqrtf(1.f / (float)N) : sqrtf(2.f / (float)N);
 }
+// 1 / s_k
+__device__ __forceinline__ float dct_is_(int k, int N) {
+  return k == 0 ? sqrtf((float)N) : sqrtf(0.5f * (float)N);
+}
 
 // Makhoul's order: position j of v holds x_{src(j)}
 __device__ __forceinline__ int mk_src_(int j, int N) { return j <= (N - 1) / 2 ? 2 * j : 2 * (N - 1 - j) + 1; }
 
 // forward: lines x0 (real part) and x1 (imaginary part), read through
-// `get(line, i)`, into buf as a_j = z_j c_j (zero padded); synchronised
-template <int M, class G>
-__device__ void load_forward_(float2* buf, const float2* chirp, int N, const G& get) {
-  for (int j = threadIdx.x; j < M; j += FT) {
-    float2 a = make_float2(0.f, 0.f);
-    if (j < N) {
-      const int s = mk_src_(j, N);
-      a = cmul_(make_float2(get(0, s), get(1, s)), chirp[j]);
-    }
-    buf[j] = a;
-  }
-  __syncthreads();
+// `get(line, i)`: position j of the Bluestein input, a_j = z_j c_j (0 past N)
+template <class G>
+__device__ __forceinline__ float2 at_forward_(int j, const FG float2* chirp, int N, const G& get) {
+  if (j >= N) return make_float2(0.f, 0.f);
+  const int s = mk_src_(j, N);
+  return cmul_(make_float2(get(0, s), get(1, s)), ld2_(chirp + j));
 }
 
 // after bluestein_ of a forward load: the two lines' orthonormal DCT-II
 // coefficients X0_k, X1_k, k < N, handed to put(k, X0_k, X1_k)
-template <class P>
-__device__ void unpack_forward_(const float2* buf, const float2* chirp, const float2* mk, int N, const P& put) {
-  for (int k = threadIdx.x; k < N; k += FT) {
+template <int M, class P>
+__device__ void unpack_forward_(const float2* buf, const FG float2* chirp, const FG float2* mk, int N, const P& put) {
+  for (int k = threadIdx.x; k < N; k += fft_threads(M)) {
     const int kr = k == 0 ? 0 : N - k;
-    const float2 Z = cmul_(chirp[k], conj_(buf[k]));
-    const float2 Zr = conj_(cmul_(chirp[kr], conj_(buf[kr])));   // conj(Z_{N-k})
+    const float2 Z = cmul_(ld2_(chirp + k), conj_(buf[sw_(k)]));
+    const float2 Zr = conj_(cmul_(ld2_(chirp + kr), conj_(buf[sw_(kr)])));   // conj(Z_{N-k})
     // V0 = (Z + conj Zr) / 2, V1 = (Z - conj Zr) / 2i; X = s Re(mk V)
     const float2 V0 = make_float2(0.5f * (Z.x + Zr.x), 0.5f * (Z.y + Zr.y));
     const float2 V1 = make_float2(0.5f * (Z.y - Zr.y), -0.5f * (Z.x - Zr.x));
     const float s = dct_s_(k, N);
-    put(k, s * (mk[k].x * V0.x - mk[k].y * V0.y), s * (mk[k].x * V1.x - mk[k].y * V1.y));
+    const float2 e = ld2_(mk + k);
+    put(k, s * (e.x * V0.x - e.y * V0.y), s * (e.x * V1.x - e.y * V1.y));
   }
 }
 
 // inverse: from two lines of orthonormal DCT coefficients (got through
-// `get(line, k)`), buf as a_j = conj(W_j) c_j with
-// W = spec(U0) + i spec(U1), spec(U)_k = e^{i pi k / 2N} (U_k / s_k - i U_{N-k} / s_{N-k})
-template <int M, class G>
-__device__ void load_inverse_(float2* buf, const float2* chirp, const float2* mk, int N, const G& get) {
-  for (int j = threadIdx.x; j < M; j += FT) {
-    float2 a = make_float2(0.f, 0.f);
-    if (j < N) {
-      const float sj = dct_s_(j, N);
-      const float u0 = get(0, j) / sj, u1 = get(1, j) / sj;
-      float r0 = 0.f, r1 = 0.f;
-      if (j > 0) {
-        const float sr = dct_s_(N - j, N);
-        r0 = get(0, N - j) / sr;
-        r1 = get(1, N - j) / sr;
-      }
-      // e^{i t} = conj(mk_j); spec = e^{i t} (u - i r)
-      const float2 e = conj_(mk[j]);
-      const float2 s0 = cmul_(e, make_float2(u0, -r0)), s1 = cmul_(e, make_float2(u1, -r1));
-      const float2 W = make_float2(s0.x - s1.y, s0.y + s1.x);   // s0 + i s1
-      a = cmul_(conj_(W), chirp[j]);
-    }
-    buf[j] = a;
+// `get(line, k)`), position j of the Bluestein input, a_j = conj(W_j) c_j
+// with W = spec(U0) + i spec(U1),
+// spec(U)_k = e^{i pi k / 2N} (U_k / s_k - i U_{N-k} / s_{N-k})
+template <class G>
+__device__ __forceinline__ float2 at_inverse_(int j, const FG float2* chirp, const FG float2* mk, int N, const G& get) {
+  if (j >= N) return make_float2(0.f, 0.f);
+  const float isj = dct_is_(j, N);
+  const float u0 = get(0, j) * isj, u1 = get(1, j) * isj;
+  float r0 = 0.f, r1 = 0.f;
+  if (j > 0) {
+    const float isr = dct_is_(N - j, N);
+    r0 = get(0, N - j) * isr;
+    r1 = get(1, N - j) * isr;
   }
-  __syncthreads();
+  // e^{i t} = conj(mk_j); spec = e^{i t} (u - i r)
+  const float2 e = conj_(ld2_(mk + j));
+  const float2 s0 = cmul_(e, make_float2(u0, -r0)), s1 = cmul_(e, make_float2(u1, -r1));
+  const float2 W = make_float2(s0.x - s1.y, s0.y + s1.x);   // s0 + i s1
+  return cmul_(conj_(W), ld2_(chirp + j));
 }
 
 // after bluestein_ of an inverse load: D = DFT(conj W) = c_k conj(buf[k]),
 // v = conj(D) / N = (c_k conj(buf[k]))^* / N; the line values at position
 // i come from v at the Makhoul index of i; handed to put(i, x0_i, x1_i)
-template <class P>
-__device__ void unpack_inverse_(const float2* buf, const float2* chirp, int N, const P& put) {
+template <int M, class P>
+__device__ void unpack_inverse_(const float2* buf, const FG float2* chirp, int N, const P& put) {
   const float iN = 1.f / (float)N;
-  for (int i = threadIdx.x; i < N; i += FT) {
+  for (int i = threadIdx.x; i < N; i += fft_threads(M)) {
     const int j = (i & 1) ? N - 1 - (i >> 1) : (i >> 1);
-    const float2 v = conj_(cmul_(chirp[j], conj_(buf[j])));
+    const float2 v = conj_(cmul_(ld2_(chirp + j), conj_(buf[sw_(j)])));
     put(i, v.x * iN, v.y * iN);
   }
 }
@@ -286,7 +345,7 @@ __device__ void unpack_inverse_(const float2* buf, const float2* chirp, int N, c
 //   MODE 2: lines of src (the transposed row transform: line l is the
 //           axis-2 frequency l) -> DCT-II, divided by lambda, DCT-III, to dst
 template <int M, int MODE>
-__global__ __launch_bounds__(FT) void k_fft_lines(const Work* __restrict__ work, const SlotDesc<float>* __restrict__ desc,
+__global__ __launch_bounds__(fft_threads(M)) void k_fft_lines(const Work* __restrict__ work, const SlotDesc<float>* __restrict__ desc,
                                                   const SlotScalars* __restrict__ scal, int src, int dst, int gate) {
   __shared__ float2 buf[M];
   __shared__ float2 S[MODE == 2 ? M / 2 + 1 : 1];   // MODE 2: scaled spectra
@@ -298,33 +357,33 @@ __global__ __launch_bounds__(FT) void k_fft_lines(const Work* __restrict__ work,
   if (2 * (N - 1) != M) return;   // another transform length's launch
   const int ld = d.pitch, T = (N + 63) / 64, np = (N + 1) / 2;
   if (w.y >= T || w.z >= T) return;   // the list may be wider than T x T
-  const float* __restrict__ X = d.p[src];
-  float* __restrict__ Y = d.p[dst];
-  const float2* __restrict__ chirp = d.fft_chirp;
-  const float2* __restrict__ fb = d.fft_fb;
-  const float2* __restrict__ tw = d.fft_tw;
-  const float2* __restrict__ mk = d.fft_mk;
+  const FG float* __restrict__ X = (const FG float*)d.p[src];
+  FG float* __restrict__ Y = (FG float*)d.p[dst];
+  const FG float2* __restrict__ chirp = (const FG float2*)d.fft_chirp;
+  const FG float2* __restrict__ fb = (const FG float2*)d.fft_fb;
+  const FG float2* __restrict__ tw = (const FG float2*)d.fft_tw;
+  const FG float2* __restrict__ mk = (const FG float2*)d.fft_mk;
   for (int p = w.y * T + w.z; p < np; p += T * T) {
     const int l0 = 2 * p, l1 = 2 * p + 1;
     const bool has1 = l1 < N;
+    const FG float* __restrict__ x0 = X + (size_t)l0 * ld;
+    const FG float* __restrict__ x1 = X + (size_t)(has1 ? l1 : l0) * ld;
     auto get = [&](int line, int i) -> float {
-      if (line == 1 && !has1) return 0.f;
-      return X[(size_t)(line ? l1 : l0) * ld + i];
+      if (line == 0) return x0[i];
+      return has1 ? x1[i] : 0.f;
     };
     if (MODE == 1) {
-      load_inverse_<M>(buf, chirp, mk, N, get);
-      bluestein_<M>(buf, tw, fb);
-      unpack_inverse_(buf, chirp, N, [&](int i, float a, float b) {
+      bluestein_<M>(buf, tw, fb, [&](int j) { return at_inverse_(j, chirp, mk, N, get); });
+      unpack_inverse_<M>(buf, chirp, N, [&](int i, float a, float b) {
         Y[(size_t)l0 * ld + i] = a;
         if (has1) Y[(size_t)l1 * ld + i] = b;
       });
       __syncthreads();
       continue;
     }
-    load_forward_<M>(buf, chirp, N, get);
-    bluestein_<M>(buf, tw, fb);
+    bluestein_<M>(buf, tw, fb, [&](int j) { return at_forward_(j, chirp, N, get); });
     if (MODE == 0) {
-      unpack_forward_(buf, chirp, mk, N, [&](int k, float a, float b) {
+      unpack_forward_<M>(buf, chirp, mk, N, [&](int k, float a, float b) {
         Y[(size_t)l0 * ld + k] = a;
         if (has1) Y[(size_t)l1 * ld + k] = b;
       });
@@ -334,16 +393,16 @@ __global__ __launch_bounds__(FT) void k_fft_lines(const Work* __restrict__ work,
     // MODE 2: spectra of lines l0, l1 along the axis-1 frequency k, divided
     // by lambda_{k l} (FP64 table of s), staged in S, then inverted
     const double h2 = d.h * d.h;
-    const double* __restrict__ s = d.dcts;
-    unpack_forward_(buf, chirp, mk, N, [&](int k, float a, float b) {
+    const FG double* __restrict__ s = (const FG double*)d.dcts;
+    unpack_forward_<M>(buf, chirp, mk, N, [&](int k, float a, float b) {
       const double f0 = (k == 0 && l0 == 0) ? 0.0 : h2 / (s[k] + s[l0]);
       const double f1 = has1 ? h2 / (s[k] + s[l1]) : 0.0;
       S[k] = make_float2((float)((double)a * f0), (float)((double)b * f1));
     });
     __syncthreads();
-    load_inverse_<M>(buf, chirp, mk, N, [&](int line, int k) -> float { return line ? S[k].y : S[k].x; });
-    bluestein_<M>(buf, tw, fb);
-    unpack_inverse_(buf, chirp, N, [&](int i, float a, float b) {
+    auto getS = [&](int line, int k) -> float { return line ? S[k].y : S[k].x; };
+    bluestein_<M>(buf, tw, fb, [&](int j) { return at_inverse_(j, chirp, mk, N, getS); });
+    unpack_inverse_<M>(buf, chirp, N, [&](int i, float a, float b) {
       Y[(size_t)l0 * ld + i] = a;
       if (has1) Y[(size_t)l1 * ld + i] = b;
     });
@@ -361,8 +420,8 @@ __global__ __launch_bounds__(FT) void k_transpose(const Work* __restrict__ work,
   const SlotDesc<float>& d = desc[w.x];
   const int N = d.n + 1, ld = d.pitch;
   if (!uses_fft(N, 4)) return;
-  const float* __restrict__ X = d.p[src];
-  float* __restrict__ Y = d.p[dst];
+  const FG float* __restrict__ X = (const FG float*)d.p[src];
+  FG float* __restrict__ Y = (FG float*)d.p[dst];
   const int i0 = w.y * 64, j0 = w.z * 64;
   if (i0 >= N || j0 >= N) return;
   const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
@@ -428,9 +487,20 @@ void fft_tables(int N, std::vector<float>* chirp, std::vector<float>* fb, std::v
   for (int p = 0; p < M; ++p) {
     (*fb)[2 * p] = (float)(B[p].real() / M);
     (*fb)[2 * p + 1] = (float)(B[p].imag() / M);
-    const double t = -2.0 * pi * (double)p / (double)M;
-    (*tw)[2 * p] = (float)std::cos(t);
-    (*tw)[2 * p + 1] = (float)std::sin(t);
+  }
+  // pass q's twiddles e^{-2 pi i r k / (Ns R)}, 1 <= r < R, k < Ns, at
+  // fft_twoff(M, q) + (r - 1) Ns + k
+  for (int q = 0; q < fft_passes(M); ++q) {
+    const int R = fft_radix(M, q), Ns = fft_ns(M, q);
+    if (Ns == 1) continue;
+    for (int r = 1; r < R; ++r)
+      for (int k = 0; k < Ns; ++k) {
+        const long long e = ((long long)r * k) % ((long long)Ns * R);
+        const double t = -2.0 * pi * (double)e / (double)(Ns * R);
+        const size_t at = (size_t)fft_twoff(M, q) + (size_t)(r - 1) * Ns + k;
+        (*tw)[2 * at] = (float)std::cos(t);
+        (*tw)[2 * at + 1] = (float)std::sin(t);
+      }
   }
 }
 
@@ -443,9 +513,9 @@ void poisson_fft(hipStream_t s, const Work* w, int nw, const SlotDesc<float>* d,
   auto rows = [&](auto Mc, int mode, int a, int b) {
     constexpr int M = decltype(Mc)::value;
     if (!(sizes & (1u << __builtin_ctz(M)))) return;
-    if (mode == 0) hipLaunchKernelGGL((k_fft_lines<M, 0>), dim3(nw), dim3(FT), 0, s, w, d, sc, a, b, gate);
-    if (mode == 1) hipLaunchKernelGGL((k_fft_lines<M, 1>), dim3(nw), dim3(FT), 0, s, w, d, sc, a, b, gate);
-    if (mode == 2) hipLaunchKernelGGL((k_fft_lines<M, 2>), dim3(nw), dim3(FT), 0, s, w, d, sc, a, b, gate);
+    if (mode == 0) hipLaunchKernelGGL((k_fft_lines<M, 0>), dim3(nw), dim3(fft_threads(M)), 0, s, w, d, sc, a, b, gate);
+    if (mode == 1) hipLaunchKernelGGL((k_fft_lines<M, 1>), dim3(nw), dim3(fft_threads(M)), 0, s, w, d, sc, a, b, gate);
+    if (mode == 2) hipLaunchKernelGGL((k_fft_lines<M, 2>), dim3(nw), dim3(fft_threads(M)), 0, s, w, d, sc, a, b, gate);
   };
   auto all = [&](int mode, int a, int b) {
     rows(std::integral_constant<int, 1024>{}, mode, a, b);
