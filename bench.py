@@ -156,8 +156,10 @@ def run_uneven(args, w1):
     dev = [(n, m, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for n, m, a, b in items]
 
     def prm_for(n, m, precision=w1.FP32):
+        # W1 only: the served requests keep no output fields
         return w1.params(n=n, levels=_levels(n), metric=m, algo=w1.ALGO_PROX, precision=precision,
-                         stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=10)
+                         stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=10,
+                         flags=w1.FLAG_NO_FIELDS)
 
     srv = w1.Solver(prm_for(512, 2), capacity=P)
     for k in range(args.warmup):
@@ -254,7 +256,8 @@ def run_served(args, w1):
 
     def prm_for(n, precision=w1.FP32):
         return w1.params(n=n, levels=_levels(n), metric=w1.METRIC_L2, algo=w1.ALGO_PROX, precision=precision,
-                         stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=1)
+                         stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=1,
+                         flags=w1.FLAG_NO_FIELDS)
 
     srv = w1.Solver(prm_for(max(sizes)), capacity=256)
     srv.serve_config(1 << 30)
@@ -337,6 +340,34 @@ def run_served(args, w1):
             "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in ks.items()
                         if v["launches"]},
             "cpu_baseline": None}
+
+
+def run_poisson(args, w1):
+    """The FP32 Neumann Poisson solve of eq. (pdhg) alone (w1_op_poisson,
+    one pair of sides per size in --sizes): FFT path for sides 1024..4096,
+    folded matrix passes below.  Each call also sets up its tables and
+    planes, so the per-call wall time is an upper bound; the kernels' own
+    times come from a kernel trace of this run."""
+    import torch
+    sizes = [int(x) for x in args.sizes.split(",")]
+    out = {}
+    for n in sizes:
+        rng = np.random.default_rng(n)
+        r = rng.standard_normal((n + 1, n + 1))
+        r -= r.mean()
+        gr = torch.from_numpy(r).float().cuda()
+        gu = torch.zeros_like(gr)
+        for _ in range(max(1, args.warmup)):
+            w1.op_poisson(n, w1.FP32, gr, gu)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            w1.op_poisson(n, w1.FP32, gr, gu)
+        torch.cuda.synchronize()
+        out[str(n)] = {"ms_per_call_wall": (time.perf_counter() - t) * 1e3 / args.steps,
+                       "path": "fft" if n + 1 >= 1025 else "matrix passes"}
+        log(f"[bench] poisson n={n}: {out[str(n)]['ms_per_call_wall']:.2f} ms per call")
+    return {"workload": "Neumann Poisson solve, FP32, one grid per call", "steps": args.steps, "sizes": out}
 
 
 def run_single(args, w1):
@@ -598,7 +629,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
     ap.add_argument("--workload", default="uniform",
-                    choices=["uniform", "uneven", "served", "single", "tolerance", "cube"])
+                    choices=["uniform", "uneven", "served", "single", "tolerance", "cube", "poisson"])
     ap.add_argument("--ground", default="l2", choices=["l1", "l2", "linf"],
                     help="uniform: ground metric of the flux cost (the headline figure is l2)")
     ap.add_argument("--step-scale", type=float, default=0.0,
@@ -628,7 +659,7 @@ def main():
 
     if args.workload != "uniform":
         assert torch.cuda.is_available(), "bench.py needs a HIP device"
-        run = {"uneven": run_uneven, "served": run_served, "single": run_single,
+        run = {"uneven": run_uneven, "served": run_served, "single": run_single, "poisson": run_poisson,
                "tolerance": run_tolerance, "cube": run_cube}[args.workload]
         print(json.dumps(run(args, w1)), flush=True)
         return

@@ -124,6 +124,12 @@ typedef struct {
 /* transition; the quantity the tolerance study of Sec. 5.2 compares with   */
 /* the level optimum); without it level_w1 holds NaN below the finest level */
 #define W1_FLAG_LEVEL_COST 4
+/* W1_FLAG_NO_FIELDS: served requests (w1_submit) keep no output fields:    */
+/* the worker skips the three device-to-host copies of m1, m2 and psi and   */
+/* its wait on them when the request ends; w1_poll then returns W1_EINVAL   */
+/* (leaving the result pollable) if it is given field buffers.  Other bits  */
+/* of flags are rejected by w1_params_check.                                */
+#define W1_FLAG_NO_FIELDS 8
 
 typedef struct {
     double  w1;           /* f(m^K) = sum ||m||_p h^2 on the finest level     */

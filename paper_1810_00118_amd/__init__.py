@@ -22,7 +22,7 @@ METRIC_L1, METRIC_L2, METRIC_LINF = 1, 2, 3
 ALGO_PLAIN, ALGO_PROX = 1, 2
 FP32, FP64 = 1, 2
 STOP_KKT, STOP_FPR = 1, 2
-FLAG_NO_RESIDENT, FLAG_NO_CERT, FLAG_LEVEL_COST = 1, 2, 4
+FLAG_NO_RESIDENT, FLAG_NO_CERT, FLAG_LEVEL_COST, FLAG_NO_FIELDS = 1, 2, 4, 8
 MAX_LEVELS = 12
 FAM_PLAIN_TILED, FAM_PLAIN_RESIDENT, FAM_DCT, FAM_PROX_ELEM, FAM_OTHER = 0, 1, 2, 3, 4
 FAMILIES = {0: "plain_tiled", 1: "plain_resident", 2: "dct", 3: "prox_elem", 4: "other", 5: "prox_resident"}

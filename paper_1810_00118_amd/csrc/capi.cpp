@@ -57,6 +57,7 @@ extern "C" int w1_params_check(const w1_params* p) {
     if (c < 0 || (c > 0 && (l >= p->levels || c % p->check_every != 0))) return W1_EINVAL;
   }
   if (p->diverge_window < 0 || p->reserved != 0) return W1_EINVAL;
+  if (p->flags & ~(W1_FLAG_NO_RESIDENT | W1_FLAG_NO_CERT | W1_FLAG_LEVEL_COST | W1_FLAG_NO_FIELDS)) return W1_EINVAL;
   // plain: mu tau ||A||^2 < 1 holds up to step_scale 1 (the bound 2 sqrt 2 / h
   // exceeds ||A||); prox: mu tau <= 1, the practical choice of the paper.
   // Beyond, the fixed-point residual is no longer a norm of the iterate
@@ -93,6 +94,7 @@ static void fill_request(Request* r, const w1_params& p) {
   r->sides.clear();
   for (int l = 0; l < p.levels; ++l) r->sides.push_back(p.n >> (p.levels - 1 - l));
   r->kind = p.algo == W1_ALGO_PLAIN ? K_PLAIN : K_PROX;
+  r->want_fields = (p.flags & W1_FLAG_NO_FIELDS) == 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -360,6 +362,9 @@ extern "C" int w1_poll(w1_handle h, uint64_t ticket, w1_result* out, double* m1,
     std::lock_guard<std::mutex> lk(h->mu);
     auto it = h->all.find(ticket);
     if (it == h->all.end()) return W1_ENOTFOUND;
+    // fields asked of a request submitted without them: refused before the
+    // ticket is consumed, so the result can still be polled
+    if ((m1 || m2 || psi) && !it->second->want_fields) return W1_EINVAL;
     if (!it->second->handed) return W1_EAGAIN;
     r = std::move(it->second);
     h->all.erase(it);
@@ -504,30 +509,40 @@ struct Op {
   }
   int dct(SlotDesc<T>& d) {
     // tables owned here: built from the same closed form as the engine's
+    // (the FFT path needs no N x N matrices)
     const int M = d.n + 1;
-    std::vector<T> C((size_t)M * M), Ct((size_t)M * M);
+    const bool fft = uses_fft(M, (int)sizeof(T));
     std::vector<double> s(M);
     const double pi = 3.14159265358979323846;
     for (int k = 0; k < M; ++k) {
-      const double sk = k == 0 ? std::sqrt(1.0 / M) : std::sqrt(2.0 / M);
-      for (int j = 0; j < M; ++j) {
-        const double v = sk * std::cos(pi * k * (2.0 * j + 1.0) / (2.0 * M));
-        C[(size_t)k * M + j] = (T)v;
-        Ct[(size_t)j * M + k] = (T)v;
-      }
       const double sn = std::sin(pi * k / (2.0 * M));
       s[k] = 4.0 * sn * sn;
     }
-    void *a, *b, *c;
-    int e = alloc(C.size() * sizeof(T), &a) | alloc(Ct.size() * sizeof(T), &b) | alloc(M * 8, &c);
-    if (e) return W1_EDEVICE;
-    HIPCHK(hipMemcpy(a, C.data(), C.size() * sizeof(T), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(b, Ct.data(), Ct.size() * sizeof(T), hipMemcpyHostToDevice));
+    void* c;
+    if (alloc(M * 8, &c)) return W1_EDEVICE;
     HIPCHK(hipMemcpy(c, s.data(), M * 8, hipMemcpyHostToDevice));
-    d.dctC = (const T*)a;
-    d.dctCt = (const T*)b;
     d.dcts = (const double*)c;
-    if (sizeof(T) == 4) {
+    std::vector<T> C, Ct;
+    if (!fft) {
+      C.resize((size_t)M * M);
+      Ct.resize((size_t)M * M);
+      for (int k = 0; k < M; ++k) {
+        const double sk = k == 0 ? std::sqrt(1.0 / M) : std::sqrt(2.0 / M);
+        for (int j = 0; j < M; ++j) {
+          const double v = sk * std::cos(pi * k * (2.0 * j + 1.0) / (2.0 * M));
+          C[(size_t)k * M + j] = (T)v;
+          Ct[(size_t)j * M + k] = (T)v;
+        }
+      }
+      void *a, *b;
+      if (alloc(C.size() * sizeof(T), &a) | alloc(Ct.size() * sizeof(T), &b)) return W1_EDEVICE;
+      HIPCHK(hipMemcpy(a, C.data(), C.size() * sizeof(T), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(b, Ct.data(), Ct.size() * sizeof(T), hipMemcpyHostToDevice));
+      d.dctC = (const T*)a;
+      d.dctCt = (const T*)b;
+    }
+    if (sizeof(T) == 4 && !fft) {
+      void *a, *b;
       std::vector<T> Cp, Ctp;
       fold_order(M, C, &Cp, &Ctp);
       if (alloc(Cp.size() * sizeof(T), &a) | alloc(Ctp.size() * sizeof(T), &b)) return W1_EDEVICE;
@@ -536,7 +551,7 @@ struct Op {
       d.dctCp = (const T*)a;
       d.dctCtp = (const T*)b;
     }
-    if (uses_fft(M, (int)sizeof(T))) {
+    if (fft) {
       std::vector<float> ch, fb, tw, mk;
       fft_tables(M, &ch, &fb, &tw, &mk);
       float2* tabs[4];

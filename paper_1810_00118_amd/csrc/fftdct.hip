@@ -354,7 +354,7 @@ __global__ __launch_bounds__(fft_threads(M)) void k_fft_lines(const Work* __rest
   if (gate && scal[w.x / MAXL].status != ST_RUN) return;
   const SlotDesc<float>& d = desc[w.x];
   const int N = d.n + 1;
-  if (2 * (N - 1) != M) return;   // another transform length's launch
+  if (!d.fft_tw || 2 * (N - 1) != M) return;   // no FFT tables, or another length's launch
   const int ld = d.pitch, T = (N + 63) / 64, np = (N + 1) / 2;
   if (w.y >= T || w.z >= T) return;   // the list may be wider than T x T
   const FG float* __restrict__ X = (const FG float*)d.p[src];
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(FT) void k_transpose(const Work* __restrict__ work,
   if (gate && scal[w.x / MAXL].status != ST_RUN) return;
   const SlotDesc<float>& d = desc[w.x];
   const int N = d.n + 1, ld = d.pitch;
-  if (!uses_fft(N, 4)) return;
+  if (!d.fft_tw) return;   // solved by the matrix passes
   const FG float* __restrict__ X = (const FG float*)d.p[src];
   FG float* __restrict__ Y = (FG float*)d.p[dst];
   const int i0 = w.y * 64, j0 = w.z * 64;

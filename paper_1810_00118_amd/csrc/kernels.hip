@@ -1750,7 +1750,7 @@ __global__ __launch_bounds__(256) void k_dct_fold(const Work* __restrict__ work,
   if (gate && scal[w.x / MAXL].status != ST_RUN) return;
   const SlotDesc<float>& d = desc[w.x];
   const int N = d.n + 1, ld = d.pitch, h = N / 2, ne = N - h, no = h;
-  if (uses_fft(N, 4)) return;   // solved by the FFT path
+  if (d.fft_tw) return;   // a slot with FFT tables is solved by the FFT path
   const W1_GLOBAL float* __restrict__ X = gld_(d.p[src]);
   W1_GLOBAL float* __restrict__ Y = gst_(d.p[dst]);
   const W1_GLOBAL float* __restrict__ Cp = gld_(d.dctCp);

@@ -49,12 +49,14 @@ def test_library_loads_and_checks_params_without_a_device():
     # per-level caps (multiples of check_every, only on existing levels), a domain scale
     assert w1.check_params(w1.params(n=512, levels=4, level_caps=[100, 0, 50, 10])) == 0
     assert w1.check_params(w1.params(n=512, levels=4, h=0.5 / 512)) == 0
+    for f in (w1.FLAG_NO_RESIDENT, w1.FLAG_NO_CERT, w1.FLAG_LEVEL_COST, w1.FLAG_NO_FIELDS, 15):
+        assert w1.check_params(w1.params(n=512, levels=4, flags=f)) == 0
     for bad in (dict(n=100), dict(levels=0), dict(metric=4), dict(metric=0),
                 dict(max_iters=15, check_every=10), dict(step_scale=1.5), dict(algo=7),
                 dict(step_scale=1.5, diverge_window=3, stop_rule=w1.STOP_KKT, tol=1e-6),
                 dict(step_scale=2.5, diverge_window=3), dict(diverge_window=-1),
                 dict(level_caps=[15]), dict(level_caps=[10, 10, 10, 10, 10]), dict(level_caps=[-10]),
-                dict(h=float("inf")), dict(reserved=1)):
+                dict(h=float("inf")), dict(reserved=1), dict(flags=16), dict(flags=-1)):
         q = w1.params(**dict(dict(n=512, levels=4), **bad))
         assert w1.check_params(q) == w1.W1_EINVAL, bad
     assert w1.strerror(w1.W1_EINVAL) == "invalid argument"

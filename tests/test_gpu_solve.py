@@ -408,6 +408,40 @@ def test_served_poll_while_running():
         assert got[t]["w1"] == pytest.approx(alone["w1"], rel=1e-6)
 
 
+def test_served_without_fields():
+    """W1_FLAG_NO_FIELDS: served requests end with the same results as with
+    fields kept; asking w1_poll for their fields is refused with W1_EINVAL
+    and leaves the result pollable."""
+    w1 = require_gpu()
+    reqs = []
+    for i in range(6):
+        n = (64, 128)[i % 2]
+        p0, p1 = w1data.pair_gauss3(500 + i, n=n)
+        reqs.append((n, p0, p1))
+
+    def prm(n, flags):
+        return w1.params(n=n, levels={64: 2, 128: 3}[n], metric=2, algo=1 + (n == 128), precision=FP32,
+                         stop_rule=w1.STOP_FPR, tol=0.0, max_iters=2000, check_every=10, flags=flags)
+
+    out = {}
+    for flags in (0, w1.FLAG_NO_FIELDS):
+        with w1.Solver(prm(128, flags), capacity=4) as srv:
+            tickets = [srv.submit(p0, p1, prm(n, flags)) for n, p0, p1 in reqs]
+            srv.drain()
+            res = []
+            for t, (n, _, _) in zip(tickets, reqs):
+                if flags:
+                    with pytest.raises(w1.W1Error) as e:
+                        srv.poll(t, n=n, fields=True)
+                    assert e.value.status == w1.W1_EINVAL
+                r = srv.poll(t)
+                assert r is not None and r[1] is None
+                res.append(r[0])
+            out[flags] = res
+    for a, b in zip(out[0], out[w1.FLAG_NO_FIELDS]):
+        assert a["iters"] == b["iters"] and a["w1"] == b["w1"] and a["hi"] == b["hi"]
+
+
 @pytest.mark.parametrize("algo", [1, 2])
 def test_level_caps_match_oracle(algo):
     """Per-level iteration caps (coarsest first): in FP64 the GPU runs every
