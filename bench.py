@@ -56,6 +56,25 @@ TILED_VALU_CYCLES = {"l1": 482 / 16, "l2": (514 + 3 * 16) / 16, "linf": 626 / 16
 ALG_VALU_SLOTS = {"l1": 6 + 6 + 2 + 6, "l2": 6 + 11 + 2 + 6, "linf": 6 + 14 + 2 + 6}
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per useful node update of `kernel` from the committed
+    counter summary (profiles/<kernel minus k_>_traffic.md, its JSON block),
+    or None when that summary is missing or was taken on another version of
+    the kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", kernel.replace("k_", "", 1) + "_traffic.md")
+    src = os.path.join(ROOT, "paper_1810_00118_amd", "csrc", "kernels.hip")
+    try:
+        txt = open(path).read()
+        block = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, IndexError, ValueError):
+        return None
+    if block.get("kernels_hip_sha256_16") != sha or block.get("workload") != workload:
+        return None
+    return block
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -370,6 +389,29 @@ def run_poisson(args, w1):
     return {"workload": "Neumann Poisson solve, FP32, one grid per call", "steps": args.steps, "sizes": out}
 
 
+def run_tiled(args, w1):
+    """The plain tiled kernel alone on one stream (w1_op_plain_steps): one
+    grid of side --n, FP32, l_2, 16 wavefronts, 10 steps per launch,
+    --steps launches per call.  For counter collection (HBM bytes per
+    launch) and kernel traces of a single, fixed launch shape."""
+    import torch
+    n = args.n
+    rng = np.random.default_rng(n)
+    r = rng.random((n + 1, n + 1))
+    r -= r.mean()
+    rho = torch.from_numpy(r).float().cuda()
+    m1, m2, phi = (torch.zeros_like(rho) for _ in range(3))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    w1.op_plain_steps(n, w1.METRIC_L2, w1.FP32, 10 * args.steps, m1, m2, phi, rho, block_steps=10, waves=16)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    ups = float(n + 1) ** 2 * 10 * args.steps
+    log(f"[bench] tiled n={n}: {args.steps} launches, {el * 1e3:.2f} ms")
+    return {"workload": f"plain tiled kernel, one {n + 1}^2 grid, FP32, l_2, 16 wavefronts, 10 steps per launch",
+            "launches": args.steps, "useful_updates_per_launch": ups / args.steps, "wall_ms": el * 1e3}
+
+
 def run_single(args, w1):
     """Single pair at n = 512: eight anisotropic Gaussians and the same
     mixture shifted by up to 0.1 (W1 close to the shift length), L2, 4-level
@@ -629,7 +671,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
     ap.add_argument("--workload", default="uniform",
-                    choices=["uniform", "uneven", "served", "single", "tolerance", "cube", "poisson"])
+                    choices=["uniform", "uneven", "served", "single", "tolerance", "cube", "poisson", "tiled"])
     ap.add_argument("--ground", default="l2", choices=["l1", "l2", "linf"],
                     help="uniform: ground metric of the flux cost (the headline figure is l2)")
     ap.add_argument("--step-scale", type=float, default=0.0,
@@ -659,7 +701,7 @@ def main():
 
     if args.workload != "uniform":
         assert torch.cuda.is_available(), "bench.py needs a HIP device"
-        run = {"uneven": run_uneven, "served": run_served, "single": run_single, "poisson": run_poisson,
+        run = {"uneven": run_uneven, "served": run_served, "single": run_single, "poisson": run_poisson, "tiled": run_tiled,
                "tolerance": run_tolerance, "cube": run_cube}[args.workload]
         print(json.dumps(run(args, w1)), flush=True)
         return
@@ -784,9 +826,15 @@ def main():
             Tm = float(np.median(T_))
             covered = computed / Tm          # region nodes read per launch step block
             dram = (16.0 * covered + 12.0 * useful / Tm) / useful   # read m1 m2 phi rho, write m1 m2 phi
+            # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
+            # counts (per useful update, scaled to this run's launches)
+            tr = measured_traffic("k_plain_tiled", "uniform256") if (n, P, args.ground) == (256, 256, "l2") else None
+            traffic = tr["bytes_per_useful_update"] * useful / st["launches"] if tr else None
             roof = {"kernel": dom, "bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
                     "unit": "TOP/s (VALU lane-ops, non-packed FP32)", "frac": achieved / VALU_LANE_OPS_PEAK,
-                    "traffic": None, "avg_launch_ms": avg_ms, "launches": st["launches"],
+                    "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                    "traffic_gbs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
+                    "avg_launch_ms": avg_ms, "launches": st["launches"],
                     "alg_valu_slots_per_update": alg,
                     "valu_cycles_per_update": cyc,
                     "issue_frac_computed": computed * cyc / sec / VALU_LANE_OPS_PEAK,

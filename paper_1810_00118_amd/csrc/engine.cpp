@@ -546,6 +546,10 @@ class Batch : public BatchBase {
                    hipEventCreateWithFlags(&ev_arena_, hipEventDisableTiming) == hipSuccess;
     // W1_SPECULATE=0 turns the speculative iteration blocks off
     if (const char* e = std::getenv("W1_SPECULATE")) speculate_ = std::atoi(e) != 0;
+    // W1_SIDE_STREAM=0 keeps every launch on the batch's stream (no
+    // cross-stream event waits): the mode for counter collection, whose
+    // per-dispatch serialisation must not meet a wait on another queue
+    if (const char* e = std::getenv("W1_SIDE_STREAM")) side_stream_ = std::atoi(e) != 0;
     // failure injection for tests of the error paths: W1_FAIL_AT_STEP=k
     // makes the k-th step of every batch of the process fail from the host
     // (no device work is affected)
@@ -769,7 +773,7 @@ class Batch : public BatchBase {
       const bool alone = groups.empty();
       // beside other levels, a few resident slots (each holds one compute
       // unit) run on the side stream; a large set fills the device anyway
-      const bool side = !alone && (int)R.size() <= 64;
+      const bool side = side_stream_ && !alone && (int)R.size() <= 64;
       st = launch_resident(R, alone ? 0 : step_us, side);
       if (st) return fail(st);
     }
@@ -1635,6 +1639,7 @@ class Batch : public BatchBase {
   hipEvent_t ev_arena_ = nullptr;   // after the last upload of the previous step
   bool arena_pending_ = false;
   bool speculate_ = true;
+  bool side_stream_ = true;
   bool res_side_ = false;
   int64_t fail_at_ = 0;              // W1_FAIL_AT_STEP (tests only)
   Arena arena_;
