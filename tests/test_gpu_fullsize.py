@@ -134,3 +134,101 @@ def test_served_request_2048():
             ev_same = o.evaluate(same["m1"], same["m2"], same["psi"], rho, 1.0 / n, 2)
             assert res["w1"] == pytest.approx(same["w1"], rel=1e-4)
             assert abs(ev_gpu["kkt"] - ev_same["kkt"]) <= 1e-5
+
+
+def test_config1_all_seeds():
+    """Config 1 on all 16 seeds (64x64, three isotropic Gaussians + floor,
+    l_1, plain PDHG, 2 levels, KKT 1e-6 or 20k per level), FP64 through one
+    batch: each pair takes the oracle's stop decisions (identical per-level
+    iteration counts), W1 to 1e-10, the normalised KKT of its fields to 1e-5.
+    The oracle solves run in a pool of spawned processes (no GPU state)."""
+    import multiprocessing as mp
+    import os
+    from tests import oracle_jobs
+    w1 = require_gpu()
+    n, L, seeds = 64, 2, list(range(16))
+    pairs = [w1data.pair_gauss3(k) for k in seeds]
+    with mp.get_context("spawn").Pool(min(16, os.cpu_count() or 1)) as pool:
+        refs = pool.map(oracle_jobs.config1, seeds)
+    prm = w1.params(n=n, levels=L, metric=1, algo=w1.ALGO_PLAIN, precision=2, stop_rule=w1.STOP_KKT,
+                    tol=1e-6, max_iters=20000, check_every=10)
+    with w1.Solver(prm, capacity=len(seeds)) as s:
+        res = s.solve(pairs)
+        fields = [s.fields(i) for i in range(len(seeds))]
+    for (p0, p1), r, f, ref in zip(pairs, res, fields, refs):
+        assert r["iters"] == ref["iters"]
+        assert r["w1"] == pytest.approx(ref["w1"], rel=1e-10)
+        rho = o.prepare_levels(p0, p1, n, L)[-1]
+        kg = o.evaluate(*f, rho, 1.0 / n, 1)["kkt"]
+        kr = o.evaluate(ref["m1"], ref["m2"], ref["psi"], rho, 1.0 / n, 1)["kkt"]
+        assert abs(kg - kr) <= 1e-5
+
+
+def test_served_request_1024():
+    """A 1024-grid served request (6 levels, prox, the paper's rule tested
+    every iteration, FFT Poisson solves at the finest level) against the
+    oracle: FP64 takes the oracle's stop decisions (identical iteration
+    counts, W1 to 1e-8, KKT to 1e-5); FP32 meets W1 1e-4 and, at the
+    oracle run to its own per-level counts, KKT 1e-5."""
+    w1 = require_gpu()
+    req = [q for q in w1data.served_requests(400) if q.n == 1024][0]
+    p0, p1 = w1data.served_pair(req)
+    n, L = 1024, 6
+    ref = o.solve(p0, p1, n, L=L, p=2, algo=2, stop="fpr", eps_L=o.paper_stop_tolerance(2, n, True),
+                  alpha=-1.0, max_iters=20000, check_every=1)
+    rho = o.prepare_levels(p0, p1, n, L)[-1]
+    ev_ref = o.evaluate(ref["m1"], ref["m2"], ref["psi"], rho, 1.0 / n, 2)
+    for precision in (2, FP32):
+        prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PROX, precision=precision, stop_rule=w1.STOP_FPR,
+                        tol=0.0, alpha=-1.0, max_iters=20000, check_every=1)
+        with w1.Solver(prm, capacity=1) as s:
+            t = s.submit(p0, p1, prm)
+            s.drain()
+            r = None
+            while r is None:
+                r = s.poll(t, n=n, fields=True)
+        res, fields = r
+        assert res["status"] in (0, 1)
+        assert res["w1"] == pytest.approx(ref["w1"], rel=1e-8 if precision == 2 else 1e-4)
+        ev_gpu = o.evaluate(*fields, rho, 1.0 / n, 2)
+        assert max(res["lo"], ref["lo"]) <= min(res["hi"], ref["hi"]) * (1 + 1e-6)
+        if precision == 2:
+            assert res["iters"] == ref["iters"]
+            assert abs(ev_gpu["kkt"] - ev_ref["kkt"]) <= 1e-5
+        else:
+            same = ref if res["iters"] == ref["iters"] else o.solve(
+                p0, p1, n, L=L, p=2, algo=2, stop="fpr", eps_L=1e-300, alpha=-1.0, max_iters=res["iters"],
+                check_every=1)
+            ev_same = o.evaluate(same["m1"], same["m2"], same["psi"], rho, 1.0 / n, 2)
+            assert res["w1"] == pytest.approx(same["w1"], rel=1e-4)
+            assert abs(ev_gpu["kkt"] - ev_same["kkt"]) <= 1e-5
+
+
+def test_served_mix_equals_alone_large():
+    """Continuous batching at the served sizes: 256^2 .. 1024^2 requests of
+    both algorithms and both metrics arrive together on a handle with three
+    slots; each result equals the same request solved alone (identical
+    per-level iteration counts, W1 to 1e-6)."""
+    w1 = require_gpu()
+    reqs = []
+    for i, (n, algo) in enumerate([(1024, 2), (256, 1), (512, 2), (256, 2), (512, 1), (1024, 2)]):
+        p0, p1 = w1data.pair_gauss3(700 + i, n=n, K=5)
+        L = int(round(np.log2(n // 32))) + 1
+        prm = w1.params(n=n, levels=L, metric=1 + i % 2, algo=algo, precision=FP32, stop_rule=w1.STOP_FPR,
+                        tol=0.0, alpha=-1.0, max_iters=3000 if algo == 1 else 20000,
+                        check_every=10 if algo == 1 else 1)
+        reqs.append((prm, p0, p1))
+    with w1.Solver(reqs[0][0], capacity=3) as srv:
+        tickets = [srv.submit(p0, p1, prm) for prm, p0, p1 in reqs]
+        srv.drain()
+        served = []
+        for t in tickets:
+            r = None
+            while r is None:
+                r = srv.poll(t)
+            served.append(r[0])
+    for (prm, p0, p1), res in zip(reqs, served):
+        with w1.Solver(prm) as s:
+            alone = s.solve([(p0, p1)])[0]
+        assert res["iters"] == alone["iters"]
+        assert res["w1"] == pytest.approx(alone["w1"], rel=1e-6)
