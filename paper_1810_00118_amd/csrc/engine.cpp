@@ -260,22 +260,29 @@ void tuner_reset() { g_tuner().reset(); }
 // ---------------------------------------------------------------------------
 // caching device allocator for solve state (exact-size reuse)
 // ---------------------------------------------------------------------------
+// Idle blocks are kept up to a cap (W1_BLOCK_CACHE_BYTES in the
+// environment, default 4 GiB); a block that would exceed it goes back to
+// the device at once.  A failed hipMalloc releases every idle block and
+// retries once.
 class BlockCache {
  public:
+  BlockCache() {
+    if (const char* e = std::getenv("W1_BLOCK_CACHE_BYTES")) cap_ = (size_t)std::strtoull(e, nullptr, 10);
+  }
   int get(size_t bytes, char** out) {
     std::lock_guard<std::mutex> g(mu_);
     auto it = free_.find(bytes);
     if (it != free_.end()) {
       *out = it->second;
       free_.erase(it);
+      cached_ -= bytes;
       return W1_OK;
     }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
-      // release cached blocks and retry once
-      for (auto& kv : free_) (void)hipFree(kv.second);
-      free_.clear();
+      (void)hipGetLastError();
+      trim_locked();
       e = hipMalloc(&p, bytes);
       if (e != hipSuccess) return hip_status(e, "hipMalloc(solve state)");
     }
@@ -284,15 +291,25 @@ class BlockCache {
   }
   void put(size_t bytes, char* p) {
     std::lock_guard<std::mutex> g(mu_);
+    if (cached_ + bytes > cap_) {
+      (void)hipFree(p);
+      return;
+    }
     free_.emplace(bytes, p);
+    cached_ += bytes;
   }
-  ~BlockCache() {
-    for (auto& kv : free_) (void)hipFree(kv.second);
-  }
+  ~BlockCache() { trim_locked(); }
 
  private:
+  void trim_locked() {
+    for (auto& kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+    cached_ = 0;
+  }
   std::mutex mu_;
   std::multimap<size_t, char*> free_;
+  size_t cached_ = 0;
+  size_t cap_ = (size_t)4 << 30;
 };
 
 // ---------------------------------------------------------------------------
@@ -1014,9 +1031,11 @@ class Batch : public BatchBase {
   }
 
   // -- work lists --------------------------------------------------------
-  // XCD-aware order: the launch's workgroup i runs on XCD i mod 8, so each
-  // XCD receives spatially contiguous tiles (a slot's row band, or whole
-  // slots when there are many) and halo re-reads hit its own L2.
+  // XCD-aware order: a launch's workgroup i normally runs on XCD i mod 8
+  // (the dispatcher's round robin; not guaranteed when launches follow
+  // each other closely), so each XCD mostly receives spatially contiguous
+  // tiles (a slot's row band, or whole slots when there are many) and halo
+  // re-reads hit its own L2.  Only locality depends on it, not results.
   static std::vector<Work> order_xcd(std::vector<std::vector<Work>>& q) {
     size_t mx = 0;
     for (auto& v : q) mx = std::max(mx, v.size());
