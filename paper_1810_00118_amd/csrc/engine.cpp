@@ -567,6 +567,9 @@ class Batch : public BatchBase {
     // cross-stream event waits): the mode for counter collection, whose
     // per-dispatch serialisation must not meet a wait on another queue
     if (const char* e = std::getenv("W1_SIDE_STREAM")) side_stream_ = std::atoi(e) != 0;
+    // W1_PAIRED_CHECK=0: the plain path's stop test after every block (the
+    // paired form gives the same bits)
+    if (const char* e = std::getenv("W1_PAIRED_CHECK")) pairs_ = std::atoi(e) != 0;
     // failure injection for tests of the error paths: W1_FAIL_AT_STEP=k
     // makes the k-th step of every batch of the process fail from the host
     // (no device work is affected)
@@ -801,7 +804,15 @@ class Batch : public BatchBase {
         for (auto& g : groups) {
           const int gi = g.prox ? gx++ : gp++;
           if (b >= g.nb) continue;
-          const int e = g.prox ? launch_prox_block(*g.v, gi) : launch_tiled_block(*g.v, gi, spec);
+          // plain groups take their blocks in pairs (from, from + 1), ...:
+          // the pair's first block runs without a stop test of its own
+          int pair = -1;
+          if (!g.prox) {
+            const int r = b - from, last = std::min(to, g.nb);
+            if (r % 2 == 0 && b + 1 < last) pair = 0;
+            else if (r % 2 == 1) pair = 1;
+          }
+          const int e = g.prox ? launch_prox_block(*g.v, gi) : launch_tiled_block(*g.v, gi, spec, pair);
           if (e) return e;
         }
       }
@@ -1341,7 +1352,13 @@ class Batch : public BatchBase {
 
   // -- plain: one block of check_every iterations, tiled -------------------
   // spec: a speculative block (never timed by the autotuner)
-  int launch_tiled_block(std::vector<Request*>& P, int group, bool spec = false) {
+  // pair: -1 a block with its stop test; 0 the first of two blocks whose
+  // stop tests run together after the second (1).  A pair needs one launch
+  // per block: the second launch then reads the first's output set and
+  // leaves it intact, so a slot that stops after the first block stops on
+  // that block's iterate, as with a test per block; the partials of the
+  // two blocks sit side by side in the slot's partial buffer.
+  int launch_tiled_block(std::vector<Request*>& P, int group, bool spec = false, int pair = -1) {
     int st = W1_OK;
     const int ce = P[0]->prm.check_every;
     const bool fpr = P[0]->prm.stop_rule == W1_STOP_FPR;
@@ -1350,9 +1367,32 @@ class Batch : public BatchBase {
     const int prec = sizeof(T) == 8 ? W1_FP64 : W1_FP32;
     int arm = -1;
     long entry = -1;
-    const TileChoice tc = g_tuner().pick(prec, nodes, ce, P[0]->prm.block_steps, &arm, &entry);
-    if (spec) arm = -1;
+    if ((int)pair_open_.size() <= group) {
+      pair_open_.resize(group + 1, 0);
+      pair_tc_.resize(group + 1);
+    }
+    const bool second = pair == 1 && pair_open_[group];
+    pair_open_[group] = 0;
+    TileChoice tc;
+    if (second) {
+      tc = pair_tc_[group];   // the first block's shape (never a tuner trial)
+    } else {
+      tc = g_tuner().pick(prec, nodes, ce, P[0]->prm.block_steps, &arm, &entry);
+      if (spec) arm = -1;
+    }
     const int nl = ce / tc.steps;   // the tuner only offers divisors of ce
+    bool first = false;
+    if (pair == 0 && pairs_ && fpr && nl == 1) {
+      first = true;
+      for (auto* r : P) {
+        const int n = r->sides[r->level];
+        if (2 * tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.steps) > max_tiles(r->prm.n)) first = false;
+      }
+      if (first) {
+        pair_open_[group] = 1;
+        pair_tc_[group] = tc;
+      }
+    }
     auto lv = at_level(P);
     const std::string key = "P" + std::to_string(group) + "_" + std::to_string(tc.rh) + "_" + std::to_string(tc.steps);
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -1395,7 +1435,10 @@ class Batch : public BatchBase {
     for (int li = 0; li < nl; ++li) {
       const bool chk = fpr && li == nl - 1;
       const int pi = prof_.begin();
-      K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, li, tc.steps, tc.rh, chk, P[0]->prm.metric, tc.nwv);
+      // the second of a pair reads the set the first wrote (the stop test
+      // that would flip the slot's current set has not run in between)
+      K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, second ? 1 : li, tc.steps, tc.rh, chk, P[0]->prm.metric, tc.nwv,
+                        second ? 1 : 0);
       prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * tc.steps, nodes * tc.steps * wb, computed * tc.steps);
     }
     if (t0 && t1) {
@@ -1411,7 +1454,7 @@ class Batch : public BatchBase {
       poisson((Work*)(base + off[4]), (int)cnt[4], 6, 1, lv);
       K<T>::kkt(st_, ksw, nksw, ddesc_, dsc_, K_PLAIN, nl & 1, 1);
     }
-    K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PLAIN, ce, nl);
+    if (!first) K<T>::check(st_, di, dn, ns, ddesc_, dsc_, K_PLAIN, ce, nl, second ? 2 : 1);
     HIPCHK(hipGetLastError());
     return W1_OK;
   }
@@ -1659,6 +1702,9 @@ class Batch : public BatchBase {
   bool arena_pending_ = false;
   bool speculate_ = true;
   bool side_stream_ = true;
+  bool pairs_ = true;                  // W1_PAIRED_CHECK=0: a stop test after every block
+  std::vector<char> pair_open_;        // per plain group: a pair's first block is queued
+  std::vector<TileChoice> pair_tc_;    // its launch shape
   bool res_side_ = false;
   int64_t fail_at_ = 0;              // W1_FAIL_AT_STEP (tests only)
   Arena arena_;

@@ -583,7 +583,7 @@ template <typename T, bool CHECK, int METRIC, int NWV = 8,
                                         : (sizeof(T) == 4 ? (CHECK ? W1_TILED_WPE_CHECK : W1_TILED_WPE) : 2))>
 __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU, 8))) void k_plain_tiled(
     const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc, const SlotScalars* __restrict__ scal,
-    int li, int steps) {
+    int li, int steps, int second) {
   constexpr int RH = TILED_RH, RW = TILED_RW, NR = RH / NWV, NC = 2;
   static_assert(NR * NWV == RH, "wavefronts split the region's rows evenly");
   __shared__ T Bp[NWV][RW];   // first potential row of each strip
@@ -753,7 +753,10 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
   if constexpr (CHECK) {
     step(std::true_type{});
     double v[NQ] = {(double)q0, (double)q1, (double)q2, 0, 0, 0, 0, 0};
-    block_reduce_<NWV * 64, 4>(v, d.part + (size_t)w.w * NQ, lds, 0u);
+    // the second block of a pair writes after the first block's partials
+    const size_t off =
+        second ? (size_t)((n + RH - 2 * S) / (RH - 2 * S)) * ((n + RW - 2 * S) / (RW - 2 * S)) : 0;
+    block_reduce_<NWV * 64, 4>(v, d.part + (off + (size_t)w.w) * NQ, lds, 0u);
   } else {
     step(std::false_type{});
   }
@@ -1922,39 +1925,51 @@ __global__ __launch_bounds__(256) void k_prox_post(const Work* __restrict__ work
 // ---------------------------------------------------------------------------
 
 template <typename T>
+// blocks = 2: two one-launch blocks ran back to back (the second reading
+// the first's output set) with their partials at tiles [0, nt) and
+// [nt, 2 nt); the first block's test runs first, and the second's only if
+// the slot still runs after it, so the decisions and the iterate a slot
+// stops on are those of one test per block.
 __global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, const int* __restrict__ ntiles,
                                                const SlotDesc<T>* __restrict__ desc, SlotScalars* __restrict__ scal,
-                                               int kind, int block_len, int launches) {
+                                               int kind, int block_len, int launches, int blocks) {
   __shared__ double lds[4 * NQ];
   __shared__ double res[NQ];
+  __shared__ int running;
   const int x = idx[blockIdx.x];
   const int nt = ntiles[blockIdx.x];
   if (scal[x / MAXL].status != ST_RUN) return;
   const SlotDesc<T>& d = desc[x];
-  double v[NQ];
-  for (int q = 0; q < NQ; ++q) {
-    Acc a{0.0, 0.0};
-    for (int t = threadIdx.x; t < nt; t += 256) a.add(d.part[(size_t)t * NQ + q]);
-    v[q] = a.get();
-  }
-  block_reduce_<256>(v, res, lds, 0u);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    SlotScalars& sc = scal[x / MAXL];
-    const int N = d.n + 1;
-    const double m = measure_from_(res, kind, d.rule, d.h * d.h, d.mud, d.taud, N * N);
-    const int k = sc.iters + block_len;
-    const int rises = sc.iters > 0 && m > sc.measure ? sc.rises + 1 : 0;
-    int st = ST_RUN;
-    if (!isfinite(m) || (d.divwin > 0 && m < 0.0)) st = ST_DIVERGED;
-    else if (m <= d.tol) st = ST_CONV;
-    else if (d.divwin > 0 && rises >= d.divwin) st = ST_DIVERGED;
-    else if (k >= d.cap) st = ST_CAP;
-    sc.iters = k;
-    sc.measure = m;
-    sc.rises = rises;
-    sc.status = st;
-    sc.cur ^= launches & 1;
+  for (int b = 0; b < blocks; ++b) {
+    const double* part = d.part + (size_t)b * nt * NQ;
+    double v[NQ];
+    for (int q = 0; q < NQ; ++q) {
+      Acc a{0.0, 0.0};
+      for (int t = threadIdx.x; t < nt; t += 256) a.add(part[(size_t)t * NQ + q]);
+      v[q] = a.get();
+    }
+    block_reduce_<256>(v, res, lds, 0u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      SlotScalars& sc = scal[x / MAXL];
+      const int N = d.n + 1;
+      const double m = measure_from_(res, kind, d.rule, d.h * d.h, d.mud, d.taud, N * N);
+      const int k = sc.iters + block_len;
+      const int rises = sc.iters > 0 && m > sc.measure ? sc.rises + 1 : 0;
+      int st = ST_RUN;
+      if (!isfinite(m) || (d.divwin > 0 && m < 0.0)) st = ST_DIVERGED;
+      else if (m <= d.tol) st = ST_CONV;
+      else if (d.divwin > 0 && rises >= d.divwin) st = ST_DIVERGED;
+      else if (k >= d.cap) st = ST_CAP;
+      sc.iters = k;
+      sc.measure = m;
+      sc.rises = rises;
+      sc.status = st;
+      sc.cur ^= launches & 1;
+      running = st == ST_RUN;
+    }
+    __syncthreads();
+    if (!running) return;
   }
 }
 
@@ -2158,7 +2173,7 @@ template <typename T> void K<T>::prolong(hipStream_t s, const Work* w, int nw, c
 }
 template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                              const SlotScalars* sc, int li, int steps, int rh, bool check,
-                                             int metric, int nwv) {
+                                             int metric, int nwv, int second) {
   if (!nw) return;
   if (rh != TILED_RH || steps < 1 || steps > TILED_MAX_STEPS || (metric < 1 || metric > 3) ||
       (nwv != 8 && nwv != 16)) {
@@ -2166,7 +2181,8 @@ template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int n
             nwv);
     return;
   }
-#define W1_TILED_LAUNCH(C, M, NWV) LAUNCH((k_plain_tiled<T, C, M, NWV>), nw, NWV * 64, 0, s, w, d, sc, li, steps)
+#define W1_TILED_LAUNCH(C, M, NWV) \
+  LAUNCH((k_plain_tiled<T, C, M, NWV>), nw, NWV * 64, 0, s, w, d, sc, li, steps, second)
 #define W1_TILED_METRIC(NWV)                   \
   switch (metric) {                            \
     case 1:                                    \
@@ -2263,8 +2279,8 @@ template <typename T> void K<T>::prox_post(hipStream_t s, const Work* w, int nw,
   else LAUNCH((k_prox_post<T, false>), nw, 256, 0, s, w, d, sc);
 }
 template <typename T> void K<T>::check(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
-                                       SlotScalars* sc, int kind, int block_len, int launches) {
-  if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len, launches);
+                                       SlotScalars* sc, int kind, int block_len, int launches, int blocks) {
+  if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len, launches, blocks);
 }
 template <typename T> void K<T>::eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                            const SlotScalars* sc, int kind, int cert, int polish) {

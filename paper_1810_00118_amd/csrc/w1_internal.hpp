@@ -120,8 +120,10 @@ struct K {
   // the plain kernels are compiled per ground metric: every slot of one
   // launch has `metric` (others in the list are skipped); the tiled
   // kernel's 64 x 128 region is split over nwv = 8 or 16 wavefronts
+  // second = 1: the second of two one-launch blocks checked together (its
+  // stop-test partials go after the first block's)
   static void plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                          int launch_index, int steps, int rh, bool check, int metric, int nwv);
+                          int launch_index, int steps, int rh, bool check, int metric, int nwv, int second = 0);
   static int plain_resident_max_side();
   static void plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
                              int max_side, int check_every, int chunk, int metric);
@@ -144,7 +146,7 @@ struct K {
   static void prox_post(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
                         bool check);
   static void check(hipStream_t s, const int* idx, const int* ntiles, int ns, const SlotDesc<T>* d,
-                    SlotScalars* sc, int kind, int block_len, int launches);
+                    SlotScalars* sc, int kind, int block_len, int launches, int blocks = 1);
   // cert = 0: no Poisson correction in plane 6; lo, hi and kkt are NaN.
   // polish = 1 (prox): the flux evaluated (and exported) is m + grad+ c with
   // c = (A A*)^{-1}(A m - rho) in POLISH_PLANE, its own correction in plane 6

@@ -526,3 +526,36 @@ def test_domain_scale():
     assert b["kkt"] == a["kkt"]
     np.testing.assert_allclose(fb[0], fa[0] / 3.0, rtol=1e-14)
     np.testing.assert_allclose(fb[2], fa[2] * 3.0, rtol=1e-14)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_paired_stop_tests_same_bits(precision):
+    """Plain levels run their iteration blocks in pairs whose two stop
+    tests are taken together after the second block (the second block reads
+    the first's output set, which it leaves intact).  The results are
+    bit-identical to a stop test after every block (W1_PAIRED_CHECK=0):
+    per-level iterations, W1, the bracket, for pairs that stop on either
+    block of a pair."""
+    import os
+    w1 = require_gpu()
+    n, L = 128, 3
+    pairs = [w1data.pair_gauss3(900 + i, n=n) for i in range(12)]
+    prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PLAIN, precision=precision, stop_rule=w1.STOP_FPR,
+                    tol=0.0, alpha=-1.0, max_iters=20000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+    out = {}
+    old = os.environ.get("W1_PAIRED_CHECK")
+    try:
+        for paired in ("1", "0"):
+            os.environ["W1_PAIRED_CHECK"] = paired
+            with w1.Solver(prm, capacity=len(pairs)) as s:
+                out[paired] = s.solve(pairs)
+    finally:
+        if old is None:
+            os.environ.pop("W1_PAIRED_CHECK", None)
+        else:
+            os.environ["W1_PAIRED_CHECK"] = old
+    # both parities of the stop block occur (20 iterations per pair)
+    assert {r["iters"][-1] // 10 % 2 for r in out["1"]} == {0, 1}
+    for a, b in zip(out["1"], out["0"]):
+        assert a["status"] == b["status"] and a["iters"] == b["iters"]
+        assert a["w1"] == b["w1"] and a["lo"] == b["lo"] and a["hi"] == b["hi"]
