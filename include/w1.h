@@ -372,9 +372,14 @@ int w1_op_prox_steps3d(int32_t n, int32_t metric, int32_t precision,
 
 /* ---- kernel timing ------------------------------------------------------
  * w1_profile(h, 1) resets and enables per-launch HIP-event timing on the
- * handle's stream (0 disables it).  w1_kernel_stats(h, family, out) then
- * returns for one kernel family, summed over both precisions:
- *   out[0] launches, out[1] total milliseconds,
+ * handle's stream (0 disables it; negative values are W1_EINVAL).  Plain
+ * tiled launches take the events into the dispatch itself (their start and
+ * end times); a timed dispatch ends with a cache flush, so w1_profile(h, k)
+ * with k > 1 times only about one tiled launch in k (a fixed pseudo-random
+ * sample), every other family still every launch.
+ * w1_kernel_stats(h, family, out) then returns for one kernel family, summed
+ * over both precisions and over the timed launches:
+ *   out[0] launches timed, out[1] total milliseconds,
  *   out[2] node updates (one node of one PDHG iteration), out[3] algorithmic
  *   HBM bytes (per family: plain tiled 7 words per node update; prox
  *   elementwise 13 words per node per iteration; DCT pass 2 words per node

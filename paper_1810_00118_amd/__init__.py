@@ -269,8 +269,9 @@ class Solver:
         _check(st, "w1_poll")
         return r.as_dict(), (tuple(bufs) if fields else None)
 
-    def profile(self, enable=True):
-        _check(lib().w1_profile(self.h, 1 if enable else 0), "w1_profile")
+    def profile(self, enable=True, every=1):
+        """Per-launch kernel timing on (every >= 1: about one tiled launch in `every`) or off."""
+        _check(lib().w1_profile(self.h, int(every) if enable else 0), "w1_profile")
 
     def kernel_stats(self):
         out = {}

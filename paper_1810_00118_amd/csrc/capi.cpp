@@ -434,12 +434,12 @@ extern "C" int w1_destroy(w1_handle h) {
 }
 
 extern "C" int w1_profile(w1_handle h, int32_t enable) {
-  if (!h) return W1_EINVAL;
+  if (!h || enable < 0) return W1_EINVAL;
   std::lock_guard<std::mutex> g(h->run_mu);
   for (int prec = W1_FP32; prec <= W1_FP64; ++prec) {
     BatchBase* b = h->batch(prec);
     if (!b) return W1_EDEVICE;
-    b->profile(enable != 0);
+    b->profile(enable);
   }
   return W1_OK;
 }

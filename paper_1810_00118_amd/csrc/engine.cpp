@@ -464,8 +464,10 @@ class Prof {
     for (auto e : pool_) (void)hipEventDestroy(e);
   }
   bool on = false;
+  int every = 1;
   void reset() {
     for (int f = 0; f < W1_NFAM; ++f) tot_[f][0] = tot_[f][1] = tot_[f][2] = tot_[f][3] = tot_[f][4] = 0;
+    drawn_ = 0;
   }
   // returns the pending index (or -1 when off); `s`: the launch's stream
   // when it is not the batch's own
@@ -478,10 +480,30 @@ class Prof {
     pend_.push_back(p);
     return (int)pend_.size() - 1;
   }
+  // the same pair of events, not recorded here: the launch itself takes
+  // them (hipExtLaunchKernel), so they carry the dispatch's own start and
+  // end times and add no marker packets between dependent launches
+  // With `every` = k > 1 only a sample of about one launch in k is timed
+  // (a fixed pseudo-random sequence, so no period of the launch pattern
+  // aliases with it): timed dispatches end with a cache flush that the
+  // untimed ones skip.
+  int begin_ext(hipEvent_t* a, hipEvent_t* b) {
+    *a = *b = nullptr;
+    if (!on) return -1;
+    if (every > 1 && mix64(++drawn_) % (uint64_t)every != 0) return -1;
+    Pend p;
+    p.a = ev();
+    p.b = ev();
+    p.ext = true;
+    *a = p.a;
+    *b = p.b;
+    pend_.push_back(p);
+    return (int)pend_.size() - 1;
+  }
   void end(int i, int fam, double units, double bytes, double flops, hipStream_t s = nullptr) {
     if (i < 0) return;
     Pend& p = pend_[i];
-    (void)hipEventRecord(p.b, s ? s : st_);
+    if (!p.ext) (void)hipEventRecord(p.b, s ? s : st_);
     p.fam = fam;
     p.units = units;
     p.bytes = bytes;
@@ -521,6 +543,7 @@ class Prof {
  private:
   struct Pend {
     hipEvent_t a, b;
+    bool ext = false;
     int fam = W1_FAM_OTHER;
     double units = 0, bytes = 0, flops = 0;
   };
@@ -534,9 +557,17 @@ class Prof {
     (void)hipEventCreate(&e);
     return e;
   }
+  // SplitMix64's output function (Steele, Lea and Flood, 2014)
+  static uint64_t mix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+  }
   hipStream_t st_;
   std::vector<Pend> pend_;
   std::vector<hipEvent_t> pool_;
+  uint64_t drawn_ = 0;
   double tot_[W1_NFAM][5] = {};
 };
 
@@ -949,8 +980,9 @@ class Batch : public BatchBase {
     return W1_OK;
   }
 
-  void profile(bool on) override {
-    prof_.on = on;
+  void profile(int every) override {
+    prof_.on = every > 0;
+    prof_.every = every > 1 ? every : 1;
     prof_.reset();
   }
   void retire(size_t bytes, char* mem) override { retire_.emplace_back(bytes, mem); }
@@ -1434,11 +1466,12 @@ class Batch : public BatchBase {
     if (t0 && t1) HIPCHK(hipEventRecord(t0, st_));
     for (int li = 0; li < nl; ++li) {
       const bool chk = fpr && li == nl - 1;
-      const int pi = prof_.begin();
+      hipEvent_t e0, e1;
+      const int pi = prof_.begin_ext(&e0, &e1);
       // the second of a pair reads the set the first wrote (the stop test
       // that would flip the slot's current set has not run in between)
       K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, second ? 1 : li, tc.steps, tc.rh, chk, P[0]->prm.metric, tc.nwv,
-                        second ? 1 : 0);
+                        second ? 1 : 0, e0, e1);
       prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * tc.steps, nodes * tc.steps * wb, computed * tc.steps);
     }
     if (t0 && t1) {

@@ -21,6 +21,7 @@
 //   vphi+ = Proj_{||.||_q <= 1}(vphi + tau m+);  vphibar+ = 2 vphi+ - vphi.
 #include "w1_internal.hpp"
 #include "mfma_tile.hpp"
+#include <hip/hip_ext.h>
 #include <cmath>
 #include <cstdio>
 #include <type_traits>
@@ -2132,6 +2133,9 @@ __global__ __launch_bounds__(256) void k_export_fields(const Work* __restrict__ 
 // launchers
 // ---------------------------------------------------------------------------
 #define LAUNCH(kern, grid, block, lds, s, ...) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__)
+// the same, with events that take the dispatch's own start and end times
+#define LAUNCH_EV(kern, grid, block, lds, s, e0, e1, ...) \
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, e0, e1, 0, __VA_ARGS__)
 
 template <typename T> void K<T>::zero(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, unsigned mask) {
   if (nw) LAUNCH(k_zero<T>, nw, 256, 0, s, w, d, mask);
@@ -2173,7 +2177,7 @@ template <typename T> void K<T>::prolong(hipStream_t s, const Work* w, int nw, c
 }
 template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                              const SlotScalars* sc, int li, int steps, int rh, bool check,
-                                             int metric, int nwv, int second) {
+                                             int metric, int nwv, int second, hipEvent_t ev0, hipEvent_t ev1) {
   if (!nw) return;
   if (rh != TILED_RH || steps < 1 || steps > TILED_MAX_STEPS || (metric < 1 || metric > 3) ||
       (nwv != 8 && nwv != 16)) {
@@ -2182,7 +2186,7 @@ template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int n
     return;
   }
 #define W1_TILED_LAUNCH(C, M, NWV) \
-  LAUNCH((k_plain_tiled<T, C, M, NWV>), nw, NWV * 64, 0, s, w, d, sc, li, steps, second)
+  LAUNCH_EV((k_plain_tiled<T, C, M, NWV>), nw, NWV * 64, 0, s, ev0, ev1, w, d, sc, li, steps, second)
 #define W1_TILED_METRIC(NWV)                   \
   switch (metric) {                            \
     case 1:                                    \

@@ -121,9 +121,11 @@ struct K {
   // launch has `metric` (others in the list are skipped); the tiled
   // kernel's 64 x 128 region is split over nwv = 8 or 16 wavefronts
   // second = 1: the second of two one-launch blocks checked together (its
-  // stop-test partials go after the first block's)
+  // stop-test partials go after the first block's); ev0 / ev1, when given,
+  // receive the dispatch's start and end times
   static void plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                          int launch_index, int steps, int rh, bool check, int metric, int nwv, int second = 0);
+                          int launch_index, int steps, int rh, bool check, int metric, int nwv, int second = 0,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
   static int plain_resident_max_side();
   static void plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
                              int max_side, int check_every, int chunk, int metric);

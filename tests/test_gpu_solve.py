@@ -559,3 +559,31 @@ def test_paired_stop_tests_same_bits(precision):
     for a, b in zip(out["1"], out["0"]):
         assert a["status"] == b["status"] and a["iters"] == b["iters"]
         assert a["w1"] == b["w1"] and a["lo"] == b["lo"] and a["hi"] == b["hi"]
+
+
+def test_kernel_timing_sample():
+    """Per-launch timing (w1_profile) changes no result: the same bits with
+    every tiled launch timed, with about one in 8 timed and untimed.  The
+    sample times fewer launches than the full count, its average launch
+    duration is positive, and a negative setting is rejected."""
+    w1 = require_gpu()
+    n, L = 128, 2
+    pairs = [w1data.pair_gauss3(950 + i, n=n) for i in range(8)]
+    prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_FPR,
+                    tol=0.0, alpha=-1.0, max_iters=4000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+    out, stats = {}, {}
+    with w1.Solver(prm, capacity=len(pairs)) as s:
+        s.solve(pairs)                      # launch shapes settled by the autotuner
+        for every in (0, 1, 8):
+            s.profile(every > 0, every=max(every, 1))
+            out[every] = s.solve(pairs)
+            stats[every] = s.kernel_stats()["plain_tiled"]
+        s.profile(False)
+        with pytest.raises(RuntimeError):
+            s.profile(True, every=-1)
+    for k in (1, 8):
+        for a, b in zip(out[0], out[k]):
+            assert a["iters"] == b["iters"] and a["w1"] == b["w1"] and a["hi"] == b["hi"]
+    full, part = stats[1], stats[8]
+    assert full["launches"] > 50 and 0 < part["launches"] < full["launches"] / 3
+    assert part["ms"] > 0 and part["node_updates"] > 0
