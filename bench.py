@@ -835,7 +835,7 @@ def main():
         if e["best"] >= 0:
             a = e["arms"][e["best"]]
             tuned.append({"precision": e["precision"], "class": e["class"], "waves": a["waves"], "T": a["T"],
-                          "ns_per_update": a["ns_per_update"]})
+                          "width": a.get("width", 128), "ns_per_update": a["ns_per_update"]})
 
     # ---- dominant kernel roofline (HIP events in the timed region) ----
     # (tiled launches are timed on a sample of about one in

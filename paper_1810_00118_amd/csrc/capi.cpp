@@ -602,9 +602,9 @@ struct Op {
       for (int b = 0; b < t; ++b) w.push_back(make_int4(x, a, b, a * t + b));
     return w;
   }
-  std::vector<Work> tiled(int x, int side, int rh, int S) {
+  std::vector<Work> tiled(int x, int side, int rh, int rw, int S) {
     std::vector<Work> w;
-    const int ti = cdiv(side + 1, rh - 2 * S), tj = cdiv(side + 1, TILED_RW - 2 * S);
+    const int ti = cdiv(side + 1, rh - 2 * S), tj = cdiv(side + 1, rw - 2 * S);
     for (int a = 0; a < ti; ++a)
       for (int b = 0; b < tj; ++b) w.push_back(make_int4(x, a, b, a * tj + b));
     return w;
@@ -632,8 +632,8 @@ struct Op {
 int check_side(int n) { return (n >= 1 && n <= 8192) ? W1_OK : W1_EINVAL; }
 
 template <typename T>
-int op_plain_steps(int n, int metric, double scale, int steps, int block, int nwv, void* m1, void* m2, void* phi,
-                   const void* rho, double* fpr, hipStream_t s) {
+int op_plain_steps(int n, int metric, double scale, int steps, int block, int nwv, int rw, void* m1, void* m2,
+                   void* phi, const void* rho, double* fpr, hipStream_t s) {
   Op<T> op(n, s);
   const double sc = scale > 0 ? scale : 0.5;
   const double mu = sc / (2.0 * std::sqrt(2.0) * n);
@@ -647,7 +647,8 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, int nw
   d.rho = (T*)rho;
   void* pp;
   // one partial per tile at the deepest temporal block (the most tiles)
-  const size_t ntile = (size_t)cdiv(n + 1, TILED_RH - 2 * TILED_MAX_STEPS) * cdiv(n + 1, TILED_RW - 2 * TILED_MAX_STEPS);
+  const int maxS = rw == TILED_RW ? TILED_MAX_STEPS : TILED_NARROW_MAX_STEPS;
+  const size_t ntile = (size_t)cdiv(n + 1, TILED_RH - 2 * maxS) * cdiv(n + 1, rw - 2 * maxS);
   if (op.alloc(sizeof(double) * NQ * ntile + 4096, &pp)) return W1_ENOMEM;
   d.part = (double*)pp;
   if (block < 0) {
@@ -670,21 +671,21 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, int nw
   int st = op.commit(1);
   if (st) return st;
   const int rh = TILED_RH;
-  const int T_ = std::max(1, std::min(block > 0 ? block : 1, TILED_MAX_STEPS));
+  const int T_ = std::max(1, std::min(block > 0 ? block : 1, maxS));
   int done = 0, li = 0, lastS = 1;
   while (done < steps) {
     const int S = std::min(T_, steps - done);
     const bool chk = fpr && done + S == steps;
-    auto w = op.tiled(0, n, rh, S);
+    auto w = op.tiled(0, n, rh, rw, S);
     Work* dw = op.upload(w);
     if (!dw) return W1_EDEVICE;
-    K<T>::plain_tiled(s, dw, (int)w.size(), op.dd, op.dsc, li, S, rh, chk, metric, nwv);
+    K<T>::plain_tiled(s, dw, (int)w.size(), op.dd, op.dsc, li, S, rh, rw, chk, metric, nwv);
     ++li;
     done += S;
     lastS = S;
   }
   if (fpr) {
-    std::vector<int> idx{0}, nt{(int)op.tiled(0, n, rh, lastS).size()};
+    std::vector<int> idx{0}, nt{(int)op.tiled(0, n, rh, rw, lastS).size()};
     int* di = op.upload(idx);
     int* dn = op.upload(nt);
     if (!di || !dn) return W1_EDEVICE;
@@ -918,18 +919,21 @@ extern "C" int w1_op_prolong(int32_t nc, int32_t precision, const void* c_m1, co
 }
 
 extern "C" int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,
-                                 int32_t block_steps, int32_t waves, void* m1, void* m2, void* phi, const void* rho,
-                                 double* fpr_out, void* hip_stream) {
+                                 int32_t block_steps, int32_t waves, int32_t region_width, void* m1, void* m2,
+                                 void* phi, const void* rho, double* fpr_out, void* hip_stream) {
   if (check_side(n) || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF || !m1 || !m2 || !phi || !rho)
     return W1_EINVAL;
   if (step_scale > 1.0 || block_steps > TILED_MAX_STEPS || (waves != 0 && waves != 8 && waves != 16))
     return W1_EINVAL;
+  const int rw = region_width ? region_width : TILED_RW;
+  if ((rw != TILED_RW && rw != TILED_RW_NARROW) || (rw == TILED_RW_NARROW && block_steps > TILED_NARROW_MAX_STEPS))
+    return W1_EINVAL;
   const int nwv = waves ? waves : 8;
   hipStream_t s = (hipStream_t)hip_stream;
-  return DISPATCH(precision,
-                  op_plain_steps<float>(n, metric, step_scale, steps, block_steps, nwv, m1, m2, phi, rho, fpr_out, s),
-                  op_plain_steps<double>(n, metric, step_scale, steps, block_steps, nwv, m1, m2, phi, rho, fpr_out,
-                                         s));
+  return DISPATCH(
+      precision,
+      op_plain_steps<float>(n, metric, step_scale, steps, block_steps, nwv, rw, m1, m2, phi, rho, fpr_out, s),
+      op_plain_steps<double>(n, metric, step_scale, steps, block_steps, nwv, rw, m1, m2, phi, rho, fpr_out, s));
 }
 
 extern "C" int w1_tuner_table(char* buf, size_t len) {

@@ -63,12 +63,12 @@ static inline int dct_t(int n) {
   return sizeof(T) == 4 ? fold_tiles(n + 1) : gemm_t(n);
 }
 static inline int tiled_ti(int n, int rh, int S) { return cdiv(n + 1, rh - 2 * S); }
-static inline int tiled_tj(int n, int S) { return cdiv(n + 1, TILED_RW - 2 * S); }
-// nodes of a side-n grid that the tiled kernel's regions (rh x TILED_RW,
-// origins at multiples of the interior size minus the S-node halo) cover,
-// counted with multiplicity: the node updates one of its S-step launches
-// computes per step, halo recomputation included, outside the grid not
-static double tiled_computed(int n, int rh, int S) {
+static inline int tiled_tj(int n, int rw, int S) { return cdiv(n + 1, rw - 2 * S); }
+// nodes of a side-n grid that the tiled kernel's regions (rh x rw, origins
+// at multiples of the interior size minus the S-node halo) cover, counted
+// with multiplicity: the node updates one of its S-step launches computes
+// per step, halo recomputation included, outside the grid not
+static double tiled_computed(int n, int rh, int rw, int S) {
   auto covered = [n](int tiles, int inner, int width, int S_) {
     double tot = 0;
     for (int t = 0; t < tiles; ++t) {
@@ -77,11 +77,13 @@ static double tiled_computed(int n, int rh, int S) {
     }
     return tot;
   };
-  return covered(tiled_ti(n, rh, S), rh - 2 * S, rh, S) * covered(tiled_tj(n, S), TILED_RW - 2 * S, TILED_RW, S);
+  return covered(tiled_ti(n, rh, S), rh - 2 * S, rh, S) * covered(tiled_tj(n, rw, S), rw - 2 * S, rw, S);
 }
 static inline int max_tiles(int n) {
   // the tiled kernel has the most tiles at its deepest temporal block
-  const int tiled = tiled_ti(n, TILED_RH, TILED_MAX_STEPS) * tiled_tj(n, TILED_MAX_STEPS);
+  const int tiled = std::max(tiled_ti(n, TILED_RH, TILED_MAX_STEPS) * tiled_tj(n, TILED_RW, TILED_MAX_STEPS),
+                             tiled_ti(n, TILED_RH, TILED_NARROW_MAX_STEPS) *
+                                 tiled_tj(n, TILED_RW_NARROW, TILED_NARROW_MAX_STEPS));
   const int g = std::max(gemm_t(n), fold_tiles(n + 1));
   return std::max(simple_tiles(n), std::max(g * g, tiled));
 }
@@ -131,14 +133,20 @@ class Tuner {
       e.key = key;
       for (int nwv : {8, 16}) {
         if (requested > 0) {
-          e.arms.push_back(Arm{nwv, depth_for(requested, check_every)});
+          e.arms.push_back(Arm{nwv, depth_for(requested, check_every), TILED_RW});
           continue;
         }
         // depth 1 only when nothing deeper divides the cadence
         for (int t = 2; t <= std::min(check_every, TILED_MAX_STEPS); ++t)
-          if (check_every % t == 0) e.arms.push_back(Arm{nwv, t});
-        if (e.arms.empty() || e.arms.back().nwv != nwv) e.arms.push_back(Arm{nwv, depth_for(1, check_every)});
+          if (check_every % t == 0) e.arms.push_back(Arm{nwv, t, TILED_RW});
+        if (e.arms.empty() || e.arms.back().nwv != nwv) e.arms.push_back(Arm{nwv, depth_for(1, check_every), TILED_RW});
       }
+      // the narrow region at its deepest offered block: for active sets that
+      // leave compute units idle, twice the workgroups at a larger halo
+      // share (the size class decides, as for the other shapes)
+      const int tn = depth_for(requested > 0 ? std::min(requested, TILED_NARROW_MAX_STEPS) : TILED_NARROW_MAX_STEPS,
+                               check_every);
+      for (int nwv : {8, 16}) e.arms.push_back(Arm{nwv, tn, TILED_RW_NARROW});
       it = tab_.emplace(key, e).first;
       order_.push_back(key);
     }
@@ -171,6 +179,7 @@ class Tuner {
     c.rh = TILED_RH;
     c.steps = e.arms[a].T;
     c.nwv = e.arms[a].nwv;
+    c.rw = e.arms[a].rw;
     *arm_out = e.best < 0 ? a : -1;   // only exploration blocks are timed
     *entry_out = (long)(std::find(order_.begin(), order_.end(), key) - order_.begin());
     return c;
@@ -202,8 +211,9 @@ class Tuner {
       out += "\"arms\":[";
       for (size_t a = 0; a < e.arms.size(); ++a) {
         const Arm& A = e.arms[a];
-        std::snprintf(buf, sizeof buf, "%s{\"waves\":%d,\"T\":%d,\"blocks\":%d,\"ns_per_update\":%.6g}",
-                      a ? "," : "", A.nwv, A.T, A.done, A.units > 0 ? A.ms * 1e6 / A.units : -1.0);
+        std::snprintf(buf, sizeof buf,
+                      "%s{\"waves\":%d,\"T\":%d,\"width\":%d,\"blocks\":%d,\"ns_per_update\":%.6g}", a ? "," : "",
+                      A.nwv, A.T, A.rw, A.done, A.units > 0 ? A.ms * 1e6 / A.units : -1.0);
         out += buf;
       }
       std::snprintf(buf, sizeof buf, "],\"best\":%d}", e.best);
@@ -220,7 +230,7 @@ class Tuner {
 
  private:
   struct Arm {
-    int nwv, T;
+    int nwv, T, rw;
     int seen = 0, done = 0;
     double ms = 0, units = 0;
     double cost() const { return units > 0 ? ms / units : 1e300; }
@@ -1115,10 +1125,10 @@ class Batch : public BatchBase {
   std::vector<Work> gemm_work(const std::vector<std::pair<Request*, int>>& lv) {
     return make_work(lv, [](int n, int* ti, int* tj) { *ti = *tj = dct_t<T>(n); });
   }
-  std::vector<Work> tiled_work(const std::vector<std::pair<Request*, int>>& lv, int rh, int S) {
-    return make_work(lv, [rh, S](int n, int* ti, int* tj) {
+  std::vector<Work> tiled_work(const std::vector<std::pair<Request*, int>>& lv, int rh, int rw, int S) {
+    return make_work(lv, [rh, rw, S](int n, int* ti, int* tj) {
       *ti = tiled_ti(n, rh, S);
-      *tj = tiled_tj(n, S);
+      *tj = tiled_tj(n, rw, S);
     });
   }
   static std::vector<std::pair<Request*, int>> at_level(const std::vector<Request*>& rs) {
@@ -1418,7 +1428,7 @@ class Batch : public BatchBase {
       first = true;
       for (auto* r : P) {
         const int n = r->sides[r->level];
-        if (2 * tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.steps) > max_tiles(r->prm.n)) first = false;
+        if (2 * tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.rw, tc.steps) > max_tiles(r->prm.n)) first = false;
       }
       if (first) {
         pair_open_[group] = 1;
@@ -1426,7 +1436,8 @@ class Batch : public BatchBase {
       }
     }
     auto lv = at_level(P);
-    const std::string key = "P" + std::to_string(group) + "_" + std::to_string(tc.rh) + "_" + std::to_string(tc.steps);
+    const std::string key = "P" + std::to_string(group) + "_" + std::to_string(tc.rh) + "x" + std::to_string(tc.rw) +
+                            "_" + std::to_string(tc.steps);
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (arm >= 0) {
       t0 = tune_event();
@@ -1437,12 +1448,12 @@ class Batch : public BatchBase {
     std::vector<size_t> off, cnt;
     char* base = cached_packed(key, [&] {
       Packed p;
-      p.add(tiled_work(lv, tc.rh, tc.steps));
+      p.add(tiled_work(lv, tc.rh, tc.rw, tc.steps));
       std::vector<int> ids, nt;
       for (auto* r : P) {
         const int n = r->sides[r->level];
         ids.push_back(dx(r, r->level));
-        nt.push_back(fpr ? tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.steps) : simple_tiles(n));
+        nt.push_back(fpr ? tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.rw, tc.steps) : simple_tiles(n));
       }
       p.add(ids);
       p.add(nt);
@@ -1462,7 +1473,7 @@ class Batch : public BatchBase {
     // node updates the launch computes, the overlapping halo included
     // (reported in the profile's fifth field for this family)
     double computed = 0;
-    for (auto* r : P) computed += tiled_computed(r->sides[r->level], tc.rh, tc.steps);
+    for (auto* r : P) computed += tiled_computed(r->sides[r->level], tc.rh, tc.rw, tc.steps);
     if (t0 && t1) HIPCHK(hipEventRecord(t0, st_));
     for (int li = 0; li < nl; ++li) {
       const bool chk = fpr && li == nl - 1;
@@ -1470,8 +1481,8 @@ class Batch : public BatchBase {
       const int pi = prof_.begin_ext(&e0, &e1);
       // the second of a pair reads the set the first wrote (the stop test
       // that would flip the slot's current set has not run in between)
-      K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, second ? 1 : li, tc.steps, tc.rh, chk, P[0]->prm.metric, tc.nwv,
-                        second ? 1 : 0, e0, e1);
+      K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, second ? 1 : li, tc.steps, tc.rh, tc.rw, chk, P[0]->prm.metric,
+                        tc.nwv, second ? 1 : 0, e0, e1);
       prof_.end(pi, W1_FAM_PLAIN_TILED, nodes * tc.steps, nodes * tc.steps * wb, computed * tc.steps);
     }
     if (t0 && t1) {

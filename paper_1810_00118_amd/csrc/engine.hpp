@@ -94,6 +94,7 @@ struct TileChoice {
   int rh;      // region rows
   int steps;   // temporal block depth
   int nwv;     // wavefronts per workgroup (8 or 16)
+  int rw;      // region columns (128, or 64 for launches that leave the device idle)
 };
 // launch-shape autotuner of the plain tiled kernel (process-wide)
 std::string tuner_table();   // JSON array of the tuner's entries

@@ -556,7 +556,10 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 // ---------------------------------------------------------------------------
 // Algorithm 1, tiled with temporal blocking, iterate held in registers.
 // A workgroup of 8 wavefronts covers a 64 x 128 region: wavefront w owns
-// rows [8w, 8w+8), lane l owns columns l and l+64.  The region is the
+// rows [8w, 8w+8), lane l owns columns l and l+64 (16 wavefronts: rows
+// [4w, 4w+4)).  The 64 x 64 region (RWID = 64, lane l owns column l) spreads
+// a grid over twice as many workgroups at a larger halo share, for launches
+// that leave most of the device idle.  The region is the
 // output tile plus a halo of `steps` nodes on every side; after s steps the
 // flux is valid on rows [s-1, 63-s] and the potential on [s, 63-s] (same for
 // columns), so `steps` iterations run without leaving the workgroup and the
@@ -579,13 +582,14 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 #ifndef W1_TILED_WPE_CHECK
 #define W1_TILED_WPE_CHECK 4
 #endif
-template <typename T, bool CHECK, int METRIC, int NWV = 8,
+template <typename T, bool CHECK, int METRIC, int NWV = 8, int RWID = TILED_RW,
           int WAVES_PER_EU = (NWV == 16 ? (sizeof(T) == 4 ? 8 : 4)
                                         : (sizeof(T) == 4 ? (CHECK ? W1_TILED_WPE_CHECK : W1_TILED_WPE) : 2))>
 __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU, 8))) void k_plain_tiled(
     const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc, const SlotScalars* __restrict__ scal,
     int li, int steps, int second) {
-  constexpr int RH = TILED_RH, RW = TILED_RW, NR = RH / NWV, NC = 2;
+  constexpr int RH = TILED_RH, RW = RWID, NR = RH / NWV, NC = RW / 64;
+  static_assert(NC == 1 || NC == 2, "regions are 64 or 128 columns wide");
   static_assert(NR * NWV == RH, "wavefronts split the region's rows evenly");
   __shared__ T Bp[NWV][RW];   // first potential row of each strip
   __shared__ T Bb[NWV][RW];   // last extrapolated-flux row (axis 1) of each strip
@@ -674,8 +678,13 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
       // potential at the next column: lane + 1, crossing into the second
       // column half at lane 63 (lane 0 offers that half's first column to
       // the rotation); the region's last column has no neighbour
-      const T x0 = lane_rot_next(lane == 0 ? ph[a][1] : ph[a][0]);
-      const T x1 = lane_next(ph[a][1]);
+      T x0, x1 = T(0);
+      if constexpr (NC == 2) {
+        x0 = lane_rot_next(lane == 0 ? ph[a][NC - 1] : ph[a][0]);
+        x1 = lane_next(ph[a][NC - 1]);
+      } else {
+        x0 = lane_next(ph[a][0]);
+      }
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
         if (!(rin[a] && hact[b])) continue;
@@ -708,14 +717,15 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
       // crossing back from the second column half at lane 0 (lane 63
       // offers the first half's last column to the rotation)
       const T y0 = lane_prev(b2[a][0]);
-      const T y1 = lane_rot_prev(lane == 63 ? b2[a][0] : b2[a][1]);
+      T y1 = T(0);
+      if constexpr (NC == 2) y1 = lane_rot_prev(lane == 63 ? b2[a][0] : b2[a][NC - 1]);
       // the same shifts of the new flux (axis 2) for the checked step; the
       // cross-lane reads run with every lane active, outside any per-lane
       // condition, so no lane reads a masked-off neighbour
       T z0 = T(0), z1 = T(0);
       if constexpr (KEEP) {
         z0 = lane_prev(m2[a][0]);
-        z1 = lane_rot_prev(lane == 63 ? m2[a][0] : m2[a][1]);
+        if constexpr (NC == 2) z1 = lane_rot_prev(lane == 63 ? m2[a][0] : m2[a][NC - 1]);
       }
 #pragma unroll
       for (int b = 0; b < NC; ++b) {
@@ -2176,35 +2186,43 @@ template <typename T> void K<T>::prolong(hipStream_t s, const Work* w, int nw, c
   if (nw) LAUNCH(k_prolong<T>, nw, 256, 0, s, w, d, sc, kind);
 }
 template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
-                                             const SlotScalars* sc, int li, int steps, int rh, bool check,
+                                             const SlotScalars* sc, int li, int steps, int rh, int rw, bool check,
                                              int metric, int nwv, int second, hipEvent_t ev0, hipEvent_t ev1) {
   if (!nw) return;
-  if (rh != TILED_RH || steps < 1 || steps > TILED_MAX_STEPS || (metric < 1 || metric > 3) ||
-      (nwv != 8 && nwv != 16)) {
-    fprintf(stderr, "w1: internal error: %d steps in a %d-row region, metric %d, %d waves\n", steps, rh, metric,
-            nwv);
+  if (rh != TILED_RH || (rw != 64 && rw != 128) || steps < 1 || steps > TILED_MAX_STEPS || 2 * steps >= rw ||
+      (metric < 1 || metric > 3) || (nwv != 8 && nwv != 16)) {
+    fprintf(stderr, "w1: internal error: %d steps in a %d x %d region, metric %d, %d waves\n", steps, rh, rw,
+            metric, nwv);
     return;
   }
-#define W1_TILED_LAUNCH(C, M, NWV) \
-  LAUNCH_EV((k_plain_tiled<T, C, M, NWV>), nw, NWV * 64, 0, s, ev0, ev1, w, d, sc, li, steps, second)
-#define W1_TILED_METRIC(NWV)                   \
-  switch (metric) {                            \
-    case 1:                                    \
-      if (check) W1_TILED_LAUNCH(true, 1, NWV); \
-      else W1_TILED_LAUNCH(false, 1, NWV);      \
-      break;                                   \
-    case 2:                                    \
-      if (check) W1_TILED_LAUNCH(true, 2, NWV); \
-      else W1_TILED_LAUNCH(false, 2, NWV);      \
-      break;                                   \
-    default:                                   \
-      if (check) W1_TILED_LAUNCH(true, 3, NWV); \
-      else W1_TILED_LAUNCH(false, 3, NWV);      \
+#define W1_TILED_LAUNCH(C, M, NWV, RWD) \
+  LAUNCH_EV((k_plain_tiled<T, C, M, NWV, RWD>), nw, NWV * 64, 0, s, ev0, ev1, w, d, sc, li, steps, second)
+#define W1_TILED_METRIC(NWV, RWD)                   \
+  switch (metric) {                                 \
+    case 1:                                         \
+      if (check) W1_TILED_LAUNCH(true, 1, NWV, RWD); \
+      else W1_TILED_LAUNCH(false, 1, NWV, RWD);      \
+      break;                                        \
+    case 2:                                         \
+      if (check) W1_TILED_LAUNCH(true, 2, NWV, RWD); \
+      else W1_TILED_LAUNCH(false, 2, NWV, RWD);      \
+      break;                                        \
+    default:                                        \
+      if (check) W1_TILED_LAUNCH(true, 3, NWV, RWD); \
+      else W1_TILED_LAUNCH(false, 3, NWV, RWD);      \
   }
-  if (nwv == 16) {
-    W1_TILED_METRIC(16)
+  if (rw == 128) {
+    if (nwv == 16) {
+      W1_TILED_METRIC(16, 128)
+    } else {
+      W1_TILED_METRIC(8, 128)
+    }
   } else {
-    W1_TILED_METRIC(8)
+    if (nwv == 16) {
+      W1_TILED_METRIC(16, 64)
+    } else {
+      W1_TILED_METRIC(8, 64)
+    }
   }
 #undef W1_TILED_METRIC
 #undef W1_TILED_LAUNCH

@@ -28,8 +28,10 @@ constexpr int ST_H = 16;             // simple per-node tile: 16 rows x 64 cols
 constexpr int ST_W = 64;
 constexpr int GEMM_T = 64;           // DCT GEMM output tile
 constexpr int TILED_RW = 128;        // plain tiled kernel region width
+constexpr int TILED_RW_NARROW = 64;  // its narrow region (twice the workgroups)
 constexpr int TILED_RH = 64;         // plain tiled kernel region height
 constexpr int TILED_MAX_STEPS = 26;  // most PDHG steps per tiled launch
+constexpr int TILED_NARROW_MAX_STEPS = 16;   // ... in the narrow region
 constexpr int PRES_THREADS = 1024;   // resident kernel workgroup size (Algorithm 2)
 constexpr int FFT_MIN_N = 1025;      // FP32 Poisson solves by FFT from this
                                      // transform length on (N = n + 1 with
@@ -119,13 +121,14 @@ struct K {
                       int kind);
   // the plain kernels are compiled per ground metric: every slot of one
   // launch has `metric` (others in the list are skipped); the tiled
-  // kernel's 64 x 128 region is split over nwv = 8 or 16 wavefronts
+  // kernel's rh x rw region (64 x 128 or 64 x 64) is split over nwv = 8 or
+  // 16 wavefronts
   // second = 1: the second of two one-launch blocks checked together (its
   // stop-test partials go after the first block's); ev0 / ev1, when given,
   // receive the dispatch's start and end times
   static void plain_tiled(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, const SlotScalars* sc,
-                          int launch_index, int steps, int rh, bool check, int metric, int nwv, int second = 0,
-                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                          int launch_index, int steps, int rh, int rw, bool check, int metric, int nwv,
+                          int second = 0, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
   static int plain_resident_max_side();
   static void plain_resident(hipStream_t s, const int* idx, int ns, const SlotDesc<T>* d, SlotScalars* sc,
                              int max_side, int check_every, int chunk, int metric);

@@ -31,8 +31,8 @@ def _rand_state(n, seed, scale=1.0):
 @pytest.mark.parametrize("precision", [FP64, FP32])
 @pytest.mark.parametrize("n", [33, 100, 200])
 @pytest.mark.parametrize("metric", [1, 2, 3])
-@pytest.mark.parametrize("block", [1, 4, -1])
-def test_plain_steps_trajectory(precision, n, metric, block):
+@pytest.mark.parametrize("block,width", [(1, 0), (4, 0), (-1, 0), (4, 64), (10, 64)])
+def test_plain_steps_trajectory(precision, n, metric, block, width):
     w1 = require_gpu()
     if block < 0 and n + 1 > 65:
         pytest.skip("resident kernel holds sides up to 65")
@@ -43,7 +43,8 @@ def test_plain_steps_trajectory(precision, n, metric, block):
     dt = tdtype(precision)
     g = [dev(x, dt) for x in (m1, m2, phi, rho)]
     for k in (1, 10, 40):
-        R = w1.op_plain_steps(n, metric, precision, k, g[0], g[1], g[2], g[3], block_steps=block, fpr=True)
+        R = w1.op_plain_steps(n, metric, precision, k, g[0], g[1], g[2], g[3], block_steps=block, fpr=True,
+                              width=width)
         a1, a2, ap = m1.copy(), m2.copy(), phi.copy()
         for _ in range(k):
             a1, a2, ap, Rw = o.pd_step(a1, a2, ap, rho, h, mu, tau, P_OF[metric])
@@ -106,13 +107,52 @@ def test_resident_and_tiled_agree_bitwise(precision, n, metric):
     m1, m2, phi = _rand_state(n, 4)
     dt = tdtype(precision)
     outs = []
-    for block, waves in ((-1, 0), (1, 8), (3, 8), (6, 16), (5, 16), (1, 16)):
+    for block, waves, width in ((-1, 0, 0), (1, 8, 0), (3, 8, 0), (6, 16, 0), (5, 16, 0), (1, 16, 0),
+                                (5, 16, 64), (3, 8, 64), (1, 16, 64)):
         g = [dev(x, dt) for x in (m1, m2, phi, rho)]
-        w1.op_plain_steps(n, metric, precision, 25, g[0], g[1], g[2], g[3], block_steps=block, waves=waves)
+        w1.op_plain_steps(n, metric, precision, 25, g[0], g[1], g[2], g[3], block_steps=block, waves=waves,
+                          width=width)
         outs.append([host(x) for x in g[:3]])
     for other in outs[1:]:
         for a, b in zip(outs[0], other):
             np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("n", [100, 200, 300])
+@pytest.mark.parametrize("metric", [1, 2, 3])
+def test_region_shapes_agree_bitwise(precision, n, metric):
+    """The 64 x 128 and 64 x 64 regions, over 8 or 16 wavefronts and at
+    every block depth, give the same iterates bit for bit (grids of several
+    tiles in both directions with ragged last tiles).  R^k is a sum of
+    per-tile partials, whose grouping follows the tiling: equal up to
+    rounding."""
+    w1 = require_gpu()
+    rho = _rho(n, 11)
+    m1, m2, phi = _rand_state(n, 12)
+    dt = tdtype(precision)
+    outs = []
+    for block, waves, width in ((10, 16, 0), (1, 8, 0), (7, 8, 0), (10, 16, 64), (10, 8, 64), (16, 16, 64),
+                                (4, 8, 64)):
+        g = [dev(x, dt) for x in (m1, m2, phi, rho)]
+        R = w1.op_plain_steps(n, metric, precision, 40, g[0], g[1], g[2], g[3], block_steps=block, waves=waves,
+                              width=width, fpr=True)
+        outs.append(([host(x) for x in g[:3]], R))
+    for other, R in outs[1:]:
+        assert R == pytest.approx(outs[0][1], rel=1e-12 if precision == FP64 else 1e-6)
+        for a, b in zip(outs[0][0], other):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_region_width_rejected():
+    """Region widths other than 0, 64 and 128, and narrow blocks deeper than
+    16 steps, are W1_EINVAL."""
+    w1 = require_gpu()
+    n = 40
+    g = [dev(x, tdtype(FP32)) for x in (*_rand_state(n, 1), _rho(n, 1))]
+    for width, block in ((32, 4), (96, 4), (64, 17)):
+        with pytest.raises(w1.W1Error):
+            w1.op_plain_steps(n, 2, FP32, 4, *g, block_steps=block, width=width)
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
