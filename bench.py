@@ -47,11 +47,15 @@ FP32_VALU_TFLOPS = 157.3
 # VALU issue rate without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 # VALU issue cycles per node update of the plain tiled kernel's step loop
-# (16 wavefronts, FP32), counted in its compiled code: instructions of the
-# loop body (two steps) over the 16 node updates a thread makes in it,
-# v_rsq_f32 (the l_2 shrink's reciprocal square root, quarter rate) at 4
-# cycles
-TILED_VALU_CYCLES = {"l1": 482 / 16, "l2": (514 + 3 * 16) / 16, "linf": 626 / 16}
+# (FP32), counted in its compiled code per region shape (width, wavefronts):
+# instructions of the loop body (two steps) over the node updates a thread
+# makes in it (16; 8 for the 64 x 64 region over 16 wavefronts), v_rsq_f32
+# (the l_2 shrink's reciprocal square root, quarter rate) at 4 cycles
+TILED_VALU_CYCLES = {
+    (128, 16): {"l1": 482 / 16, "l2": (514 + 3 * 16) / 16, "linf": 626 / 16},
+    (64, 8): {"l1": 470 / 16, "l2": (502 + 3 * 16) / 16, "linf": 615 / 16},
+    (64, 16): {"l1": 230 / 8, "l2": (250 + 3 * 8) / 8, "linf": 308 / 8},
+}
 # VALU issue slots the node update itself needs (the algorithmic figure):
 # flux half per component 3 (difference, times 1/h, m + mu g), dual-norm
 # prox (l_1: 3 per component; l_2: |v|^2 2, test 1, rsq 4 slots, factor 1,
@@ -408,9 +412,10 @@ def run_poisson(args, w1):
 
 def run_tiled(args, w1):
     """The plain tiled kernel alone on one stream (w1_op_plain_steps): one
-    grid of side --n, FP32, l_2, 16 wavefronts, 10 steps per launch,
-    --steps launches per call.  For counter collection (HBM bytes per
-    launch) and kernel traces of a single, fixed launch shape."""
+    grid of side --n, FP32, l_2, 64 x --tiled-width regions over
+    --tiled-waves wavefronts, 10 steps per launch, --steps launches per call.
+    For counter collection (HBM bytes per launch) and kernel traces of a
+    single, fixed launch shape."""
     import torch
     n = args.n
     rng = np.random.default_rng(n)
@@ -420,12 +425,14 @@ def run_tiled(args, w1):
     m1, m2, phi = (torch.zeros_like(rho) for _ in range(3))
     torch.cuda.synchronize()
     t = time.perf_counter()
-    w1.op_plain_steps(n, w1.METRIC_L2, w1.FP32, 10 * args.steps, m1, m2, phi, rho, block_steps=10, waves=16)
+    w1.op_plain_steps(n, w1.METRIC_L2, w1.FP32, 10 * args.steps, m1, m2, phi, rho, block_steps=10,
+                      waves=args.tiled_waves, width=args.tiled_width)
     torch.cuda.synchronize()
     el = time.perf_counter() - t
     ups = float(n + 1) ** 2 * 10 * args.steps
     log(f"[bench] tiled n={n}: {args.steps} launches, {el * 1e3:.2f} ms")
-    return {"workload": f"plain tiled kernel, one {n + 1}^2 grid, FP32, l_2, 16 wavefronts, 10 steps per launch",
+    return {"workload": f"plain tiled kernel, one {n + 1}^2 grid, FP32, l_2, 64 x {args.tiled_width} regions, "
+                        f"{args.tiled_waves} wavefronts, 10 steps per launch",
             "launches": args.steps, "useful_updates_per_launch": ups / args.steps, "wall_ms": el * 1e3}
 
 
@@ -701,6 +708,8 @@ def main():
                     help="uniform: skip the FP64 reference of every pair (traced runs); the value then counts "
                          "every solve and says so")
     ap.add_argument("--block-steps", type=int, default=0)
+    ap.add_argument("--tiled-width", type=int, default=128, choices=[64, 128], help="tiled: region columns")
+    ap.add_argument("--tiled-waves", type=int, default=16, choices=[8, 16], help="tiled: wavefronts per region")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many bytes device-to-device (HBM counter calibration)")
     ap.add_argument("--workload", default="uniform",
@@ -854,7 +863,11 @@ def main():
             # slots over every node it computes, halo included
             sec = st["ms"] * 1e-3
             useful, computed = st["node_updates"], st["flops"]
-            cyc = TILED_VALU_CYCLES[args.ground]
+            # the compiled count of the shape the autotuner chose for the
+            # largest active set (the launches that carry most of the work)
+            big = max((a for a in tuned if a["precision"] == 1), key=lambda a: a["class"], default=None)
+            shape = (big["width"], big["waves"]) if big else (128, 16)
+            cyc = TILED_VALU_CYCLES.get(shape, {}).get(args.ground)
             alg = ALG_VALU_SLOTS[args.ground]
             achieved = useful * alg / sec
             T_ = [a["T"] for a in tuned] or [10]
@@ -874,7 +887,8 @@ def main():
                                       "(events bound to the dispatch: kernel start to end)",
                     "alg_valu_slots_per_update": alg,
                     "valu_cycles_per_update": cyc,
-                    "issue_frac_computed": computed * cyc / sec / VALU_LANE_OPS_PEAK,
+                    "region_shape": f"64 x {shape[0]}, {shape[1]} wavefronts",
+                    "issue_frac_computed": computed * cyc / sec / VALU_LANE_OPS_PEAK if cyc else None,
                     "useful_updates_per_launch": useful / st["launches"],
                     "computed_updates_per_launch": computed / st["launches"],
                     "halo_factor": computed / useful,
