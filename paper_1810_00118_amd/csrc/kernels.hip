@@ -863,15 +863,18 @@ __global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __r
   int rises = sc.rises;
   bool tested = k > 0;   // a stop test of this level has run
   const bool fpr = d.rule == RULE_FPR;
-  while (k < kend) {
-    ++k;
-    const bool chk = (k % check_every == 0) || (k >= cap);
+  // one iteration; CHK keeps the flux change and the potential change of
+  // every node for the stop test that follows it (the other iterations
+  // carry no such state)
+  T e1[NPT], e2[NPT], dp[NPT];
+#pragma unroll
+  for (int s = 0; s < NPT; ++s) e1[s] = e2[s] = dp[s] = T(0);
+  auto iter = [&](auto chk_tag) __attribute__((always_inline)) {
+    constexpr bool CHK = decltype(chk_tag)::value;
     // flux half: potential neighbours from LDS; 2 m+ - m to Lb, Lc
-    T e1[NPT], e2[NPT];
 #pragma unroll
     for (int s = 0; s < NPT; ++s) {
       const int e = threadIdx.x + NT * s;
-      e1[s] = e2[s] = T(0);
       if (e < NN) {
         const bool hd = e < last_row, hr = !((last_col >> s) & 1u);
         const T pc = pv[s];
@@ -883,30 +886,41 @@ __global__ __launch_bounds__(ResCfg<T>::NT) void k_plain_resident(const int* __r
         b2[s] = fma_(T(2), n2, -m2[s]);
         Lb[e] = b1[s];
         Lc[e] = b2[s];
-        e1[s] = n1 - m1[s];
-        e2[s] = n2 - m2[s];
+        if constexpr (CHK) {
+          e1[s] = n1 - m1[s];
+          e2[s] = n2 - m2[s];
+        }
         m1[s] = n1;
         m2[s] = n2;
       }
     }
     __syncthreads();
     // potential half: extrapolated flux at (i-1, j) and (i, j-1)
-    T dp[NPT];
 #pragma unroll
     for (int s = 0; s < NPT; ++s) {
       const int e = threadIdx.x + NT * s;
-      dp[s] = T(0);
       if (e < NN) {
         const T b1u = e >= N ? Lb[e - N] : T(0);
         const T b2l = ((first_col >> s) & 1u) ? T(0) : Lc[e - 1];
         const T pn = plain_potential_(pv[s], b1[s], b1u, b2[s], b2l, rh[s], ih, tau);
-        dp[s] = pn - pv[s];
+        if constexpr (CHK) dp[s] = pn - pv[s];
         pv[s] = pn;
         Lp[e] = pn;
       }
     }
     __syncthreads();
-    if (!chk) continue;
+  };
+  while (k < kend) {
+    // the iterations up to the next stop test (a multiple of check_every,
+    // or the cap) or to the end of this launch's chunk; the tested one last
+    int next = (k / check_every + 1) * check_every;
+    if (next > cap) next = cap;
+    if (next > kend) next = kend;
+    const bool tested_here = next % check_every == 0 || next >= cap;
+    for (int plain = next - k - (tested_here ? 1 : 0); plain > 0; --plain) iter(std::false_type{});
+    k = next;
+    if (!tested_here) continue;   // a chunk that ends between stop tests
+    iter(std::true_type{});
 
     // ---- stop test ----
     // exchange the flux change (FPR) or the new flux (KKT) through Lb, Lc;
