@@ -1955,46 +1955,54 @@ template <typename T>
 // [nt, 2 nt); the first block's test runs first, and the second's only if
 // the slot still runs after it, so the decisions and the iterate a slot
 // stops on are those of one test per block.
-__global__ __launch_bounds__(256) void k_check(const int* __restrict__ idx, const int* __restrict__ ntiles,
-                                               const SlotDesc<T>* __restrict__ desc, SlotScalars* __restrict__ scal,
-                                               int kind, int block_len, int launches, int blocks) {
-  __shared__ double lds[4 * NQ];
-  __shared__ double res[NQ];
-  __shared__ int running;
+__global__ __launch_bounds__(64) void k_check(const int* __restrict__ idx, const int* __restrict__ ntiles,
+                                              const SlotDesc<T>* __restrict__ desc, SlotScalars* __restrict__ scal,
+                                              int kind, int block_len, int launches, int blocks) {
+  // one wavefront per slot: each lane sums every 64th tile (compensated),
+  // a butterfly leaves the totals in every lane, every lane forms the same
+  // decision and lane 0 stores it; the slot's state stays in registers
+  // between the blocks
   const int x = idx[blockIdx.x];
   const int nt = ntiles[blockIdx.x];
-  if (scal[x / MAXL].status != ST_RUN) return;
+  const int lane = threadIdx.x;
+  SlotScalars& sc = scal[x / MAXL];
+  if (sc.status != ST_RUN) return;
   const SlotDesc<T>& d = desc[x];
+  int iters = sc.iters, rises = sc.rises, cur = sc.cur;
+  double measure = sc.measure;
+  const int N = d.n + 1;
   for (int b = 0; b < blocks; ++b) {
     const double* part = d.part + (size_t)b * nt * NQ;
     double v[NQ];
+#pragma unroll
     for (int q = 0; q < NQ; ++q) {
       Acc a{0.0, 0.0};
-      for (int t = threadIdx.x; t < nt; t += 256) a.add(part[(size_t)t * NQ + q]);
+      for (int t = lane; t < nt; t += 64) a.add(part[(size_t)t * NQ + q]);
       v[q] = a.get();
     }
-    block_reduce_<256>(v, res, lds, 0u);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      SlotScalars& sc = scal[x / MAXL];
-      const int N = d.n + 1;
-      const double m = measure_from_(res, kind, d.rule, d.h * d.h, d.mud, d.taud, N * N);
-      const int k = sc.iters + block_len;
-      const int rises = sc.iters > 0 && m > sc.measure ? sc.rises + 1 : 0;
-      int st = ST_RUN;
-      if (!isfinite(m) || (d.divwin > 0 && m < 0.0)) st = ST_DIVERGED;
-      else if (m <= d.tol) st = ST_CONV;
-      else if (d.divwin > 0 && rises >= d.divwin) st = ST_DIVERGED;
-      else if (k >= d.cap) st = ST_CAP;
-      sc.iters = k;
-      sc.measure = m;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+    const double m = measure_from_(v, kind, d.rule, d.h * d.h, d.mud, d.taud, N * N);
+    const int k = iters + block_len;
+    rises = iters > 0 && m > measure ? rises + 1 : 0;
+    int st = ST_RUN;
+    if (!isfinite(m) || (d.divwin > 0 && m < 0.0)) st = ST_DIVERGED;
+    else if (m <= d.tol) st = ST_CONV;
+    else if (d.divwin > 0 && rises >= d.divwin) st = ST_DIVERGED;
+    else if (k >= d.cap) st = ST_CAP;
+    iters = k;
+    measure = m;
+    cur ^= launches & 1;
+    if (lane == 0) {
+      sc.iters = iters;
+      sc.measure = measure;
       sc.rises = rises;
       sc.status = st;
-      sc.cur ^= launches & 1;
-      running = st == ST_RUN;
+      sc.cur = cur;
     }
-    __syncthreads();
-    if (!running) return;
+    if (st != ST_RUN) return;
   }
 }
 
@@ -2316,7 +2324,7 @@ template <typename T> void K<T>::prox_post(hipStream_t s, const Work* w, int nw,
 }
 template <typename T> void K<T>::check(hipStream_t s, const int* idx, const int* nt, int ns, const SlotDesc<T>* d,
                                        SlotScalars* sc, int kind, int block_len, int launches, int blocks) {
-  if (ns) LAUNCH(k_check<T>, ns, 256, 0, s, idx, nt, d, sc, kind, block_len, launches, blocks);
+  if (ns) LAUNCH(k_check<T>, ns, 64, 0, s, idx, nt, d, sc, kind, block_len, launches, blocks);
 }
 template <typename T> void K<T>::eval_sums(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d,
                                            const SlotScalars* sc, int kind, int cert, int polish) {
