@@ -782,9 +782,12 @@ __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_
       const int r = r0 + a, c = lane + 64 * b;
       if (rin[a] && cin[b] && r >= S && r < RH - S && c >= S && c < RW - S) {
         const size_t off = (size_t)(gi0 + r) * pitch + (gj0 + c);
-        om1[off] = m1[a][b];
-        om2[off] = m2[a][b];
-        oph[off] = ph[a][b];
+        // streaming stores: the next launch reads these planes from other
+        // compute units, so they need not stay in this XCD's L2 (fewer dirty
+        // lines to write back when the launch ends; ~1% per launch)
+        __builtin_nontemporal_store(m1[a][b], &om1[off]);
+        __builtin_nontemporal_store(m2[a][b], &om2[off]);
+        __builtin_nontemporal_store(ph[a][b], &oph[off]);
       }
     }
 }
