@@ -188,6 +188,8 @@ int w1_plan(const w1_params* params, int32_t batch_capacity,
  * difference <= 1e-9); a pair that violates this gets status
  * W1_SOLVE_REJECTED while the others are solved.  Non-convergence is not
  * an error: W1_SOLVE_MAXITER with the certificate.  Blocks until done.
+ * Device masses are read in place (no staging copy): they must stay
+ * allocated and unchanged until w1_solve returns; host masses are copied.
  */
 int w1_solve(w1_handle h, int32_t count, const double* const* p0,
              const double* const* p1, int32_t on_device, w1_result* out);

@@ -182,7 +182,7 @@ extern "C" int w1_solve(w1_handle h, int32_t count, const double* const* p0, con
     std::unique_ptr<Request> r(new Request());
     fill_request(r.get(), h->prm);
     r->t_submit = t0;
-    int st = b->admit(r.get(), p0[k], p1[k], on_device);
+    int st = b->admit(r.get(), p0[k], p1[k], on_device, on_device != 0);
     if (st) return st;
     h->last.push_back(std::move(r));
   }

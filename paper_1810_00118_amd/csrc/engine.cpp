@@ -649,7 +649,7 @@ class Batch : public BatchBase {
     return a;
   }
 
-  int admit(Request* r, const double* p0, const double* p1, int on_device) override {
+  int admit(Request* r, const double* p0, const double* p1, int on_device, bool borrow) override {
     if (!ok_) return W1_EDEVICE;
     int slot = -1;
     for (int i = 0; i < cap_; ++i)
@@ -725,11 +725,17 @@ class Batch : public BatchBase {
     fin.out_m1 = in0;
     fin.out_m2 = in1;
     fin.out_psi = psi;
-    // queued on the batch's stream: the sources stay valid until the next
-    // synchronisation (w1_solve's caller buffers, or staging retired then)
-    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    HIPCHK(hipMemcpyAsync(in0, p0, ne * 8, kind, st_));
-    HIPCHK(hipMemcpyAsync(in1, p1, ne * 8, kind, st_));
+    if (borrow && on_device) {
+      // read in place by the preparation (w1_solve's caller buffers)
+      fin.in0 = p0;
+      fin.in1 = p1;
+    } else {
+      // queued on the batch's stream: the sources stay valid until the next
+      // synchronisation (staging retired then)
+      const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+      HIPCHK(hipMemcpyAsync(in0, p0, ne * 8, kind, st_));
+      HIPCHK(hipMemcpyAsync(in1, p1, ne * 8, kind, st_));
+    }
     r->state = Request::PREP;
     r->level = 0;
     r->res = w1_result{};

@@ -62,7 +62,9 @@ inline double domain_scale(const w1_params& p) { return p.h > 0 ? (double)p.n * 
 class BatchBase {
  public:
   virtual ~BatchBase() {}
-  virtual int admit(Request* r, const double* p0, const double* p1, int on_device) = 0;
+  // borrow (device inputs only): p0 / p1 stay valid and unchanged until the
+  // request's preparation has run, so it reads them in place
+  virtual int admit(Request* r, const double* p0, const double* p1, int on_device, bool borrow = false) = 0;
   virtual int step() = 0;                 // advance every slot by one block
   virtual int active() const = 0;
   virtual void collect(std::vector<Request*>& done) = 0;

@@ -587,3 +587,28 @@ def test_kernel_timing_sample():
     full, part = stats[1], stats[8]
     assert full["launches"] > 50 and 0 < part["launches"] < full["launches"] / 3
     assert part["ms"] > 0 and part["node_updates"] > 0
+
+
+def test_device_inputs_read_in_place():
+    """w1_solve reads device masses in place: the results equal those of the
+    same masses passed from host memory (which are copied), and the caller's
+    device buffers are unchanged afterwards, fields fetched included."""
+    import torch
+    w1 = require_gpu()
+    n, L = 96, 2
+    pairs = [w1data.pair_gauss3(960 + i, n=n) for i in range(5)]
+    dev = [(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for a, b in pairs]
+    keep = [(a.clone(), b.clone()) for a, b in dev]
+    prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_FPR,
+                    tol=0.0, alpha=-1.0, max_iters=4000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+    with w1.Solver(prm, capacity=len(pairs)) as s:
+        r_host = s.solve(pairs)
+    with w1.Solver(prm, capacity=len(pairs)) as s:
+        r_dev = s.solve(dev)
+        for k in range(len(pairs)):
+            s.fields(k)
+    torch.cuda.synchronize()
+    for a, b in zip(r_host, r_dev):
+        assert a["iters"] == b["iters"] and a["w1"] == b["w1"] and a["hi"] == b["hi"]
+    for (a, b), (ka, kb) in zip(dev, keep):
+        assert torch.equal(a, ka) and torch.equal(b, kb)
