@@ -708,6 +708,9 @@ def main():
                     help="uniform: skip the FP64 reference of every pair (traced runs); the value then counts "
                          "every solve and says so")
     ap.add_argument("--block-steps", type=int, default=0)
+    ap.add_argument("--graph", action="store_true",
+                    help="uniform: plain-only steps replay captured HIP graphs (W1_GRAPH=1); "
+                         "launches untimed, so no roofline")
     ap.add_argument("--tiled-width", type=int, default=128, choices=[64, 128], help="tiled: region columns")
     ap.add_argument("--tiled-waves", type=int, default=16, choices=[8, 16], help="tiled: wavefronts per region")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -761,12 +764,14 @@ def main():
     prm = w1.params(n=n, levels=L, metric=gm, algo=w1.ALGO_PLAIN, precision=w1.FP32,
                     stop_rule=w1.STOP_FPR, tol=0.0, alpha=-1.0, max_iters=20000, check_every=10,
                     block_steps=args.block_steps, step_scale=args.step_scale)
+    if args.graph:
+        os.environ["W1_GRAPH"] = "1"
     solver = w1.Solver(prm, capacity=P)
     for k in range(args.warmup):
         t = time.perf_counter()
         solver.solve(dev_pairs)
         log(f"[bench] warmup {k} {time.perf_counter() - t:.3f}s")
-    solver.profile(True, every=TILED_TIMING_EVERY)
+    solver.profile(not args.graph, every=TILED_TIMING_EVERY)
     c0 = solver.counters()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -219,8 +219,10 @@ int w1_poll(w1_handle h, uint64_t ticket, w1_result* out, double* m1,
             double* m2, double* psi);
 /* Engine counters since w1_plan, both precisions: [0] host steps (one
  * synchronisation each), [1] level starts, [2] work-list uploads,
- * [3] iteration blocks queued.                                             */
-int w1_engine_counters(w1_handle h, int64_t* out4);
+ * [3] iteration blocks queued, [4] block sequences captured into HIP
+ * graphs (W1_GRAPH=1 in the environment: plain-only steps replay their
+ * block sequence from a graph while the slot set is unchanged).            */
+int w1_engine_counters(w1_handle h, int64_t* out5);
 /* Block until every submitted request is done.                             */
 int w1_drain(w1_handle h);
 /* Served-mode counters: [0] admitted, [1] finished, [2] queued now,

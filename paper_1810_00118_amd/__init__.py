@@ -286,9 +286,10 @@ class Solver:
         _check(lib().w1_drain(self.h), "w1_drain")
 
     def counters(self):
-        o = (C.c_int64 * 4)()
+        o = (C.c_int64 * 5)()
         _check(lib().w1_engine_counters(self.h, o), "w1_engine_counters")
-        return {"host_steps": o[0], "level_starts": o[1], "list_uploads": o[2], "blocks": o[3]}
+        return {"host_steps": o[0], "level_starts": o[1], "list_uploads": o[2], "blocks": o[3],
+                "graphs_captured": o[4]}
 
     def stats(self):
         o = (C.c_int64 * 6)()

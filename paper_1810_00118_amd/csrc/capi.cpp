@@ -401,12 +401,12 @@ extern "C" int w1_serve_stats(w1_handle h, int64_t* o) {
 extern "C" int w1_engine_counters(w1_handle h, int64_t* o) {
   if (!h || !o) return W1_EINVAL;
   std::lock_guard<std::mutex> g(h->run_mu);
-  for (int k = 0; k < 4; ++k) o[k] = 0;
+  for (int k = 0; k < 5; ++k) o[k] = 0;
   for (auto* b : {h->b32.get(), h->b64.get()}) {
     if (!b) continue;
-    int64_t c[4];
+    int64_t c[5];
     b->counters(c);
-    for (int k = 0; k < 4; ++k) o[k] += c[k];
+    for (int k = 0; k < 5; ++k) o[k] += c[k];
   }
   return W1_OK;
 }

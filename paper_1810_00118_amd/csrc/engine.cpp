@@ -185,6 +185,14 @@ class Tuner {
     return c;
   }
 
+  // the entry of this active set has chosen its shape (no block of it is
+  // an exploration block any more)
+  bool settled(int precision, double active_nodes, int check_every, int requested) {
+    std::lock_guard<std::mutex> g(mu_);
+    auto it = tab_.find(std::make_tuple(precision, check_every, requested, size_class(active_nodes)));
+    return it != tab_.end() && it->second.best >= 0;
+  }
+
   void report(long entry, int arm, double ms, double node_updates) {
     if (arm < 0 || node_updates <= 0) return;
     std::lock_guard<std::mutex> g(mu_);
@@ -611,6 +619,9 @@ class Batch : public BatchBase {
     // W1_PAIRED_CHECK=0: the plain path's stop test after every block (the
     // paired form gives the same bits)
     if (const char* e = std::getenv("W1_PAIRED_CHECK")) pairs_ = std::atoi(e) != 0;
+    // W1_GRAPH=1: plain-only steps replay their block sequence from a
+    // captured HIP graph (same launches, same bits)
+    if (const char* e = std::getenv("W1_GRAPH")) graph_ = std::atoi(e) != 0;
     // failure injection for tests of the error paths: W1_FAIL_AT_STEP=k
     // makes the k-th step of every batch of the process fail from the host
     // (no device work is affected)
@@ -619,6 +630,7 @@ class Batch : public BatchBase {
   ~Batch() override {
     (void)hipStreamSynchronize(st_);
     if (rs_) (void)hipStreamSynchronize(rs_);
+    drop_graphs();
     free_retired();
     for (auto& t : tune_pending_) {
       tune_pool_.push_back(t.a);
@@ -865,8 +877,23 @@ class Batch : public BatchBase {
       }
       return (int)W1_OK;
     };
-    st = blocks(0, maxnb, false);
+    // plain-only steps may replay a captured graph of the same launches: the
+    // work lists are those of the last eager step of this generation (the
+    // same device buffers), the autotuner has settled on every group's
+    // shape, and no launch is timed
+    bool graphable = graph_ && R.empty() && X.empty() && !prof_.on && lists_gen_ == gen_;
+    if (graphable)
+      for (auto& kv : P) {
+        double nodes = 0;
+        for (auto* r : kv.second) nodes += node_count(r->sides[r->level]);
+        const auto& r0 = kv.second[0]->prm;
+        if (r0.stop_rule != W1_STOP_FPR ||
+            !g_tuner().settled(sizeof(T) == 8 ? W1_FP64 : W1_FP32, nodes, r0.check_every, r0.block_steps))
+          graphable = false;
+      }
+    st = graphable ? graph_blocks(0, maxnb, false, blocks) : blocks(0, maxnb, false);
     if (st) return fail(st);
+    lists_gen_ = gen_;
     // The stop state after these blocks is copied back while a quarter as
     // many blocks more are queued behind the copy: slots still running keep
     // the device busy while the host handles the ones that stopped (the
@@ -877,7 +904,7 @@ class Batch : public BatchBase {
     if (speculate_ && !groups.empty()) {
       const int spec = std::max(1, maxnb / 4);
       n_blocks_ += spec;
-      st = blocks(0, spec, true);
+      st = graphable ? graph_blocks(0, spec, true, blocks) : blocks(0, spec, true);
       if (st) return fail(st);
     }
     st = wait_scalars();
@@ -1007,6 +1034,7 @@ class Batch : public BatchBase {
     o[1] = n_levels_;
     o[2] = n_uploads_;
     o[3] = n_blocks_;
+    o[4] = n_graphs_;
   }
   void kernel_stats(int f, double* o) const override {
     (void)hipStreamSynchronize(st_);   // the last step's speculative blocks
@@ -1217,6 +1245,12 @@ class Batch : public BatchBase {
                       int* status) {
     DevList& L = lists_[key];
     if (L.gen != gen_) {
+      if (capturing_) {
+        // a list that is not on the device yet cannot be uploaded inside a
+        // capture: the step runs its blocks eagerly instead
+        *status = kNotCaptured;
+        return nullptr;
+      }
       Packed p = build();
       *status = upload_list(L, p.b.data(), p.b.size());
       if (*status) return nullptr;
@@ -1719,6 +1753,62 @@ class Batch : public BatchBase {
     ++gen_;
     return W1_OK;
   }
+
+  // -- captured block sequences (W1_GRAPH=1) -------------------------------
+  // One graph per (first block, end, speculative) of the current
+  // generation: the launches of a block sequence depend only on the work
+  // lists (fixed within a generation), the autotuner's settled shapes and
+  // the pairing of blocks, so a replay issues the same kernels with the
+  // same arguments; the gated kernels read the slots' state on the device.
+  // A new generation drops every graph.
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    uint64_t gen = ~0ull;
+  };
+  template <typename F>
+  int graph_blocks(int from, int to, bool spec, F& blocks) {
+    if (graphs_gen_ != gen_) {
+      drop_graphs();
+      graphs_gen_ = gen_;
+    }
+    GraphEntry& g = graphs_[std::make_tuple(from, to, spec)];
+    if (!g.exec) {
+      HIPCHK(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+      capturing_ = true;
+      const int st = blocks(from, to, spec);
+      capturing_ = false;
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(st_, &graph);
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        graphs_.erase(std::make_tuple(from, to, spec));
+        return st == kNotCaptured ? blocks(from, to, spec) : st;
+      }
+      if (e != hipSuccess) return hip_status(e, "hipStreamEndCapture(blocks)");
+      const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        g.exec = nullptr;
+        return hip_status(ei, "hipGraphInstantiate(blocks)");
+      }
+      g.gen = gen_;
+      ++n_graphs_;
+    }
+    HIPCHK(hipGraphLaunch(g.exec, st_));
+    return W1_OK;
+  }
+  void drop_graphs() {
+    for (auto& kv : graphs_)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    graphs_.clear();
+  }
+  static constexpr int kNotCaptured = -1000;   // internal: capture abandoned
+  bool graph_ = false;
+  bool capturing_ = false;
+  uint64_t graphs_gen_ = ~0ull;
+  uint64_t lists_gen_ = ~0ull;   // generation of the last block sequence issued
+  int64_t n_graphs_ = 0;
+  std::map<std::tuple<int, int, bool>, GraphEntry> graphs_;
 
   // timing events of the autotuner's exploration blocks
   struct TunePend {

@@ -82,7 +82,7 @@ class BatchBase {
   virtual void retire(size_t bytes, char* mem) = 0;
   // [0] host steps (one synchronisation each), [1] level starts,
   // [2] work-list uploads, [3] iteration blocks queued
-  virtual void counters(int64_t* out4) const = 0;
+  virtual void counters(int64_t* out5) const = 0;
 };
 
 std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t stream);

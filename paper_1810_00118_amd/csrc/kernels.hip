@@ -2173,8 +2173,14 @@ __global__ __launch_bounds__(256) void k_export_fields(const Work* __restrict__ 
 // ---------------------------------------------------------------------------
 #define LAUNCH(kern, grid, block, lds, s, ...) hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__)
 // the same, with events that take the dispatch's own start and end times
-#define LAUNCH_EV(kern, grid, block, lds, s, e0, e1, ...) \
-  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, e0, e1, 0, __VA_ARGS__)
+// (without events, an ordinary launch: it can be captured into a graph)
+#define LAUNCH_EV(kern, grid, block, lds, s, e0, e1, ...)                                  \
+  do {                                                                                     \
+    if ((e0) || (e1))                                                                      \
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, e0, e1, 0, __VA_ARGS__); \
+    else                                                                                   \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, __VA_ARGS__);              \
+  } while (0)
 
 template <typename T> void K<T>::zero(hipStream_t s, const Work* w, int nw, const SlotDesc<T>* d, unsigned mask) {
   if (nw) LAUNCH(k_zero<T>, nw, 256, 0, s, w, d, mask);

@@ -612,3 +612,41 @@ def test_device_inputs_read_in_place():
         assert a["iters"] == b["iters"] and a["w1"] == b["w1"] and a["hi"] == b["hi"]
     for (a, b), (ka, kb) in zip(dev, keep):
         assert torch.equal(a, ka) and torch.equal(b, kb)
+
+
+def test_graph_replay_same_bits():
+    """W1_GRAPH=1: plain-only steps replay their block sequences from
+    captured HIP graphs while the slot set is unchanged (each graph is
+    replayed over several steps, with the host's own stop handling,
+    uploads and synchronisations between replays).  Per-level iterations,
+    W1 and the bracket equal those of the eager launches bit for bit, and
+    graphs were in fact captured."""
+    import os
+    w1 = require_gpu()
+    n, L = 128, 3
+    pairs = [w1data.pair_gauss3(970 + i, n=n) for i in range(10)]
+    prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_FPR,
+                    tol=0.0, alpha=-1.0, max_iters=20000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+    old = os.environ.get("W1_GRAPH")
+    out, graphs = {}, {}
+    try:
+        os.environ["W1_GRAPH"] = "0"
+        with w1.Solver(prm, capacity=len(pairs)) as s:
+            s.solve(pairs)                       # launch shapes settled by the autotuner
+            out["0"] = s.solve(pairs)
+        for mode in ("1", "0"):
+            os.environ["W1_GRAPH"] = mode
+            with w1.Solver(prm, capacity=len(pairs)) as s:
+                c0 = s.counters()["graphs_captured"]
+                out[mode + "b"] = s.solve(pairs)
+                graphs[mode] = s.counters()["graphs_captured"] - c0
+    finally:
+        if old is None:
+            os.environ.pop("W1_GRAPH", None)
+        else:
+            os.environ["W1_GRAPH"] = old
+    assert graphs["1"] > 0 and graphs["0"] == 0
+    for a, b, c in zip(out["0"], out["1b"], out["0b"]):
+        for x in (b, c):
+            assert a["status"] == x["status"] and a["iters"] == x["iters"]
+            assert a["w1"] == x["w1"] and a["lo"] == x["lo"] and a["hi"] == x["hi"]
