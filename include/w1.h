@@ -382,8 +382,9 @@ int w1_op_prox_steps3d(int32_t n, int32_t metric, int32_t precision,
  * handle's stream (0 disables it; negative values are W1_EINVAL).  Plain
  * tiled launches take the events into the dispatch itself (their start and
  * end times); a timed dispatch ends with a cache flush, so w1_profile(h, k)
- * with k > 1 times only about one tiled launch in k (a fixed pseudo-random
- * sample), every other family still every launch.
+ * with k > 1 times only about one launch in k (a fixed pseudo-random
+ * sample) of the tiled and the Algorithm 2 families; the whole-level
+ * resident launches are timed every time.
  * w1_kernel_stats(h, family, out) then returns for one kernel family, summed
  * over both precisions and over the timed launches:
  *   out[0] launches timed, out[1] total milliseconds,

@@ -270,7 +270,7 @@ class Solver:
         return r.as_dict(), (tuple(bufs) if fields else None)
 
     def profile(self, enable=True, every=1):
-        """Per-launch kernel timing on (every >= 1: about one tiled launch in `every`) or off."""
+        """Per-launch kernel timing on (every >= 1: about one launch in `every`) or off."""
         _check(lib().w1_profile(self.h, int(every) if enable else 0), "w1_profile")
 
     def kernel_stats(self):

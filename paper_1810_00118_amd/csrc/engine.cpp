@@ -489,8 +489,11 @@ class Prof {
   }
   // returns the pending index (or -1 when off); `s`: the launch's stream
   // when it is not the batch's own
-  int begin(hipStream_t s = nullptr) {
+  // sample: subject to the 1-in-`every` draw (whole-level resident
+  // launches, one per step, are always timed)
+  int begin(hipStream_t s = nullptr, bool sample = true) {
     if (!on) return -1;
+    if (sample && every > 1 && mix64(++drawn_) % (uint64_t)every != 0) return -1;
     Pend p;
     p.a = ev();
     p.b = ev();
@@ -1416,7 +1419,7 @@ class Batch : public BatchBase {
       int chunk = 0;
       if (budget_us > 0) chunk = std::max(1, (int)(budget_us / it_us));
       const int c = chunk > 0 ? ((chunk + ce - 1) / ce) * ce : 0;
-      const int pi = prof_.begin(ls);
+      const int pi = prof_.begin(ls, false);
       if (kind == K_PLAIN)
         K<T>::plain_resident(ls, di, nids, ddesc_, dsc_, maxside, ce, c, metric);
       else

@@ -75,7 +75,7 @@ class BatchBase {
   // input preparation only: rho of every level to dense caller buffers
   virtual int prep_export(Request* r, void* const* rho_out) = 0;
   // per-family kernel timing (HIP events on the batch's stream)
-  virtual void profile(int every) = 0;   // 0: off; k >= 1: time about one tiled launch in k
+  virtual void profile(int every) = 0;   // 0: off; k >= 1: time about one launch in k
   virtual void kernel_stats(int family, double* out5) const = 0;
   // device memory that work already queued on the batch's stream may still
   // read: returned to the cache at the batch's next host synchronisation
