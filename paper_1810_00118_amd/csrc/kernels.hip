@@ -1973,13 +1973,18 @@ __global__ __launch_bounds__(64) void k_check(const int* __restrict__ idx, const
   const int nt = ntiles[blockIdx.x];
   const int lane = threadIdx.x;
   SlotScalars& sc = scal[x / MAXL];
-  if (sc.status != ST_RUN) return;
   const SlotDesc<T>& d = desc[x];
+  // the slot's state and its level's constants in one round of loads
+  // (before the status test, so that no load waits for another)
+  const int status0 = sc.status;
   int iters = sc.iters, rises = sc.rises, cur = sc.cur;
   double measure = sc.measure;
-  const int N = d.n + 1;
+  const double* const part0 = d.part;
+  const int N = d.n + 1, rule = d.rule, divwin = d.divwin, cap = d.cap;
+  const double h2 = d.h * d.h, mud = d.mud, taud = d.taud, tol = d.tol;
+  if (status0 != ST_RUN) return;
   for (int b = 0; b < blocks; ++b) {
-    const double* part = d.part + (size_t)b * nt * NQ;
+    const double* part = part0 + (size_t)b * nt * NQ;
     double v[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -1991,14 +1996,14 @@ __global__ __launch_bounds__(64) void k_check(const int* __restrict__ idx, const
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
-    const double m = measure_from_(v, kind, d.rule, d.h * d.h, d.mud, d.taud, N * N);
+    const double m = measure_from_(v, kind, rule, h2, mud, taud, N * N);
     const int k = iters + block_len;
     rises = iters > 0 && m > measure ? rises + 1 : 0;
     int st = ST_RUN;
-    if (!isfinite(m) || (d.divwin > 0 && m < 0.0)) st = ST_DIVERGED;
-    else if (m <= d.tol) st = ST_CONV;
-    else if (d.divwin > 0 && rises >= d.divwin) st = ST_DIVERGED;
-    else if (k >= d.cap) st = ST_CAP;
+    if (!isfinite(m) || (divwin > 0 && m < 0.0)) st = ST_DIVERGED;
+    else if (m <= tol) st = ST_CONV;
+    else if (divwin > 0 && rises >= divwin) st = ST_DIVERGED;
+    else if (k >= cap) st = ST_CAP;
     iters = k;
     measure = m;
     cur ^= launches & 1;
