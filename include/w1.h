@@ -223,6 +223,13 @@ int w1_poll(w1_handle h, uint64_t ticket, w1_result* out, double* m1,
  * graphs (W1_GRAPH=1 in the environment: plain-only steps replay their
  * block sequence from a graph while the slot set is unchanged).            */
 int w1_engine_counters(w1_handle h, int64_t* out5);
+/* Return to the device the idle solve-state blocks that finished solves
+ * left in the process-wide cache (kept for reuse up to W1_BLOCK_CACHE_BYTES
+ * in the environment, default 4 GiB).  Blocks in use are not touched, so
+ * it may be called while solves run; released_bytes (host, may be NULL)
+ * receives their size.  A failed device allocation anywhere in the library
+ * does this by itself and tries once more.  Returns W1_OK.                 */
+int w1_trim_cache(size_t* released_bytes);
 /* Block until every submitted request is done.                             */
 int w1_drain(w1_handle h);
 /* Served-mode counters: [0] admitted, [1] finished, [2] queued now,

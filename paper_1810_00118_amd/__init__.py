@@ -87,6 +87,7 @@ def lib():
         "w1_serve_stats": (C.c_int, [vp, C.POINTER(C.c_int64)]),
         "w1_engine_counters": (C.c_int, [vp, C.POINTER(C.c_int64)]),
         "w1_destroy": (C.c_int, [vp]),
+        "w1_trim_cache": (C.c_int, [C.POINTER(C.c_size_t)]),
         "w1_strerror": (C.c_char_p, [C.c_int]),
         "w1_version": (C.c_char_p, []),
         "w1_profile": (C.c_int, [vp, i32]),
@@ -325,6 +326,13 @@ def op_plain_steps(n, metric, precision, steps, m1, m2, phi, rho, step_scale=0.0
                                    *[_ptr(x, d)[0] for x in (m1, m2, phi, rho)],
                                    C.byref(out) if fpr else None, _stream(stream)), "w1_op_plain_steps")
     return out.value if fpr else None
+
+
+def trim_cache() -> int:
+    """Idle cached solve-state blocks back to the device; returns the bytes released."""
+    out = C.c_size_t(0)
+    _check(lib().w1_trim_cache(C.byref(out)), "w1_trim_cache")
+    return int(out.value)
 
 
 def tuner_table():

@@ -411,6 +411,12 @@ extern "C" int w1_engine_counters(w1_handle h, int64_t* o) {
   return W1_OK;
 }
 
+extern "C" int w1_trim_cache(size_t* released_bytes) {
+  const size_t b = cache_trim();
+  if (released_bytes) *released_bytes = b;
+  return W1_OK;
+}
+
 extern "C" int w1_destroy(w1_handle h) {
   if (!h) return W1_EINVAL;
   {
@@ -482,7 +488,7 @@ struct Op {
     for (void* p : temps) (void)hipFree(p);
   }
   int alloc(size_t bytes, void** p) {
-    HIPCHK(hipMalloc(p, std::max<size_t>(bytes, 256)));
+    HIPCHK(dev_malloc(p, std::max<size_t>(bytes, 256)));
     temps.push_back(*p);
     return W1_OK;
   }

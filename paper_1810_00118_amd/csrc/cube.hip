@@ -1116,7 +1116,7 @@ int solve_in(const w1_params& prm, const double* p0, const double* p1, int on_de
   if ((m_out || psi_out) && out->levels_run == L) {
     DevBuf ex;
     const size_t need = (m_out ? 3 : 0) * (size_t)V.N * 8 + (psi_out ? (size_t)V.N * 8 : 0);
-    CHK(hipMalloc(&ex.p, need));
+    CHK(dev_malloc(&ex.p, need));
     double* om = m_out ? (double*)ex.p : nullptr;
     double* op = psi_out ? (double*)ex.p + (m_out ? 3 * V.N : 0) : nullptr;
     // psi: -(phi - mean) for Algorithm 1, Appendix B's psi as is for Algorithm 2
@@ -1205,7 +1205,7 @@ int steps3(int n, int metric, bool prox, double scale, int steps, void* const* f
   const size_t pe = ((size_t)V.N * sizeof(T) + 255) / 256 * 256;
   const size_t mat = ((size_t)(n + 1) * (n + 1) * sizeof(T) + 255) / 256 * 256;
   const size_t tab = 2 * mat + ((size_t)(n + 1) * 8 + 255) / 256 * 256;
-  CHK(hipMalloc(&mem.p, 5 * pe + tab + (size_t)MAXB * NQ3 * 8 + 256 + NQ3 * 8));
+  CHK(dev_malloc(&mem.p, 5 * pe + tab + (size_t)MAXB * NQ3 * 8 + 256 + NQ3 * 8));
   char* p = (char*)mem.p;
   for (int a = 0; a < 3; ++a) V.b[a] = (T*)(p + a * pe);
   V.r = (T*)(p + 3 * pe);

@@ -316,13 +316,20 @@ class BlockCache {
     free_.emplace(bytes, p);
     cached_ += bytes;
   }
+  // every idle block back to the device; returns the bytes released
+  size_t trim() {
+    std::lock_guard<std::mutex> g(mu_);
+    return trim_locked();
+  }
   ~BlockCache() { trim_locked(); }
 
  private:
-  void trim_locked() {
+  size_t trim_locked() {
     for (auto& kv : free_) (void)hipFree(kv.second);
     free_.clear();
+    const size_t b = cached_;
     cached_ = 0;
+    return b;
   }
   std::mutex mu_;
   std::multimap<size_t, char*> free_;
@@ -370,9 +377,9 @@ static int dct_tables(int N, DctTab* out) {
     s[k] = 4.0 * sn * sn;
   }
   DctTab t;
-  HIPCHK(hipMalloc(&t.C, C.size() * sizeof(T)));
-  HIPCHK(hipMalloc(&t.Ct, Ct.size() * sizeof(T)));
-  HIPCHK(hipMalloc((void**)&t.s, N * sizeof(double)));
+  HIPCHK(dev_malloc((void**)&t.C, C.size() * sizeof(T)));
+  HIPCHK(dev_malloc((void**)&t.Ct, Ct.size() * sizeof(T)));
+  HIPCHK(dev_malloc((void**)&t.s, N * sizeof(double)));
   HIPCHK(hipMemcpy(t.C, C.data(), C.size() * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(t.Ct, Ct.data(), Ct.size() * sizeof(T), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(t.s, s.data(), N * sizeof(double), hipMemcpyHostToDevice));
@@ -381,15 +388,15 @@ static int dct_tables(int N, DctTab* out) {
     fft_tables(N, &ch, &fb, &tw, &mk);
     for (auto pr : {std::make_pair(&ch, &t.chirp), std::make_pair(&fb, &t.fb), std::make_pair(&tw, &t.tw),
                     std::make_pair(&mk, &t.mk)}) {
-      HIPCHK(hipMalloc((void**)pr.second, pr.first->size() * sizeof(float)));
+      HIPCHK(dev_malloc((void**)pr.second, pr.first->size() * sizeof(float)));
       HIPCHK(hipMemcpy(*pr.second, pr.first->data(), pr.first->size() * sizeof(float), hipMemcpyHostToDevice));
     }
   }
   if (sizeof(T) == 4) {
     std::vector<T> Cp, Ctp;
     fold_order(N, C, &Cp, &Ctp);
-    HIPCHK(hipMalloc(&t.Cp, Cp.size() * sizeof(T)));
-    HIPCHK(hipMalloc(&t.Ctp, Ctp.size() * sizeof(T)));
+    HIPCHK(dev_malloc((void**)&t.Cp, Cp.size() * sizeof(T)));
+    HIPCHK(dev_malloc((void**)&t.Ctp, Ctp.size() * sizeof(T)));
     HIPCHK(hipMemcpy(t.Cp, Cp.data(), Cp.size() * sizeof(T), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(t.Ctp, Ctp.data(), Ctp.size() * sizeof(T), hipMemcpyHostToDevice));
   }
@@ -427,7 +434,7 @@ class Arena {
       Chunk c;
       c.cap = std::max<size_t>(bytes, (size_t)4 << 20);
       if (hipHostMalloc((void**)&c.h, c.cap, hipHostMallocDefault) != hipSuccess ||
-          hipMalloc((void**)&c.d, c.cap) != hipSuccess) {
+          dev_malloc((void**)&c.d, c.cap) != hipSuccess) {
         *status = W1_ENOMEM;
         g_err = "upload arena allocation failed";
         return nullptr;
@@ -467,6 +474,14 @@ static BlockCache& g_blocks_ref() {
 #define g_blocks g_blocks_ref()
 int stage_alloc(size_t bytes, char** out) { return g_blocks.get(bytes, out); }
 void stage_free(size_t bytes, char* mem) { g_blocks.put(bytes, mem); }
+size_t cache_trim() { return g_blocks.trim(); }
+hipError_t dev_malloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) return e;
+  (void)hipGetLastError();
+  g_blocks.trim();
+  return hipMalloc(p, bytes);
+}
 
 // ---------------------------------------------------------------------------
 // per-family launch timing with HIP events on the batch's stream
@@ -601,8 +616,8 @@ class Batch : public BatchBase {
   Batch(int capacity, hipStream_t s) : cap_(capacity), st_(s), arena_(s), prof_(s) {
     slots_.assign(cap_, nullptr);
     hdesc_.assign((size_t)cap_ * MAXL, SlotDesc<T>{});
-    ok_ = hipMalloc((void**)&ddesc_, sizeof(SlotDesc<T>) * cap_ * MAXL) == hipSuccess &&
-          hipMalloc((void**)&dsc_, sizeof(SlotScalars) * cap_) == hipSuccess &&
+    ok_ = dev_malloc((void**)&ddesc_, sizeof(SlotDesc<T>) * cap_ * MAXL) == hipSuccess &&
+          dev_malloc((void**)&dsc_, sizeof(SlotScalars) * cap_) == hipSuccess &&
           hipHostMalloc((void**)&hsc_, sizeof(SlotScalars) * cap_, hipHostMallocDefault) == hipSuccess;
     if (ok_) ok_ = hipMemsetAsync(dsc_, 0, sizeof(SlotScalars) * cap_, st_) == hipSuccess;
     if (ok_) ok_ = hipStreamSynchronize(st_) == hipSuccess;
@@ -1203,7 +1218,7 @@ class Batch : public BatchBase {
       (void)hipHostFree(L.h);
       L.d = L.h = nullptr;
       L.cap = bytes * 2;
-      if (hipMalloc(&L.d, L.cap) != hipSuccess || hipHostMalloc(&L.h, L.cap, hipHostMallocDefault) != hipSuccess) {
+      if (dev_malloc(&L.d, L.cap) != hipSuccess || hipHostMalloc(&L.h, L.cap, hipHostMallocDefault) != hipSuccess) {
         L.cap = 0;
         g_err = "work list allocation failed";
         return W1_ENOMEM;

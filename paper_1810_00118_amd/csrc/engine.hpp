@@ -90,6 +90,11 @@ std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t strea
 // device staging memory for served requests (the solve-state block cache)
 int stage_alloc(size_t bytes, char** out);
 void stage_free(size_t bytes, char* mem);
+// idle cached blocks back to the device (bytes released)
+size_t cache_trim();
+// hipMalloc that, when it fails, returns the cache's idle blocks to the
+// device and tries once more
+hipError_t dev_malloc(void** p, size_t bytes);
 
 // Tuning choice for the plain tiled kernel.
 struct TileChoice {

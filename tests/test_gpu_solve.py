@@ -650,3 +650,23 @@ def test_graph_replay_same_bits():
         for x in (b, c):
             assert a["status"] == x["status"] and a["iters"] == x["iters"]
             assert a["w1"] == x["w1"] and a["lo"] == x["lo"] and a["hi"] == x["hi"]
+
+
+def test_trim_cache_releases_idle_blocks():
+    """Finished solves leave their device blocks in the process-wide cache;
+    w1_trim_cache returns them to the device (bytes released > 0), a second
+    call finds none, and later solves allocate afresh with the same
+    results."""
+    w1 = require_gpu()
+    n, L = 64, 2
+    pairs = [w1data.pair_gauss3(990 + i, n=n) for i in range(3)]
+    prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_FPR,
+                    tol=0.0, alpha=-1.0, max_iters=2000, check_every=10)
+    with w1.Solver(prm, capacity=len(pairs)) as s:
+        a = s.solve(pairs)
+    assert w1.trim_cache() > 0
+    assert w1.trim_cache() == 0
+    with w1.Solver(prm, capacity=len(pairs)) as s:
+        b = s.solve(pairs)
+    for x, y in zip(a, b):
+        assert x["iters"] == y["iters"] and x["w1"] == y["w1"]
