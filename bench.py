@@ -861,7 +861,8 @@ def main():
         if e["best"] >= 0:
             a = e["arms"][e["best"]]
             tuned.append({"precision": e["precision"], "class": e["class"], "waves": a["waves"], "T": a["T"],
-                          "width": a.get("width", 128), "ns_per_update": a["ns_per_update"]})
+                          "width": a.get("width", 128), "height": a.get("height", 64),
+                          "ns_per_update": a["ns_per_update"]})
 
     # ---- dominant kernel roofline (HIP events in the timed region) ----
     # (tiled and Algorithm 2 launches are timed on a sample of about one in

@@ -271,13 +271,14 @@ int w1_op_prolong(int32_t nc, int32_t precision,
  * tiled launch, block_steps < 0 runs the whole-level LDS kernel (n <= 64);
  * waves (0, 8 or 16) splits each tiled region over that many wavefronts,
  * region_width (0 or 128: 64 x 128 regions; 64: 64 x 64 regions, at most 16
- * steps per launch) sets the region's columns.  Every choice gives the
- * same iterates bit for bit.                                               */
+ * steps per launch) sets the region's columns, region_height (0 or 64; 32
+ * with region_width 64 and waves 8: 32 x 64 regions, at most 10 steps per
+ * launch) its rows.  Every choice gives the same iterates bit for bit.     */
 int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision,
                       double step_scale, int32_t steps, int32_t block_steps,
-                      int32_t waves, int32_t region_width, void* m1, void* m2,
-                      void* phi, const void* rho, double* fpr_out,
-                      void* hip_stream);
+                      int32_t waves, int32_t region_width,
+                      int32_t region_height, void* m1, void* m2, void* phi,
+                      const void* rho, double* fpr_out, void* hip_stream);
 
 /* `steps` iterations of eq. (pdhg) in place on (m1, m2, vphi1, vphi2,
  * vphibar1, vphibar2), mu = tau = step_scale (<= 0: 1/2; at most 1).  fpr_out

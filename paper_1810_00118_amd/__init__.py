@@ -96,7 +96,8 @@ def lib():
         "w1_tuner_reset": (C.c_int, []),
         "w1_op_prepare": (C.c_int, [i32, i32, i32, vp, vp, C.POINTER(vp), vp]),
         "w1_op_prolong": (C.c_int, [i32, i32, vp, vp, vp, vp, vp, vp, vp]),
-        "w1_op_plain_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, i32, i32, vp, vp, vp, vp, dp, vp]),
+        "w1_op_plain_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, i32, i32, i32, vp, vp, vp, vp, dp,
+                                        vp]),
         "w1_op_prox_steps": (C.c_int, [i32, i32, i32, C.c_double, i32, i32, vp, vp, vp, vp, vp, vp, vp, dp, vp]),
         "w1_op_poisson": (C.c_int, [i32, i32, vp, vp, vp]),
         "w1_op_poisson_noalloc": (C.c_int, [i32, i32, vp, vp, vp]),
@@ -319,10 +320,10 @@ def op_prolong(nc, precision, c_m1, c_m2, c_phi, f_m1, f_m2, f_phi, stream=None)
 
 
 def op_plain_steps(n, metric, precision, steps, m1, m2, phi, rho, step_scale=0.0, block_steps=0, fpr=False,
-                   stream=None, waves=0, width=0):
+                   stream=None, waves=0, width=0, height=0):
     d = _dt(precision)
     out = C.c_double(np.nan)
-    _check(lib().w1_op_plain_steps(n, metric, precision, step_scale, steps, block_steps, waves, width,
+    _check(lib().w1_op_plain_steps(n, metric, precision, step_scale, steps, block_steps, waves, width, height,
                                    *[_ptr(x, d)[0] for x in (m1, m2, phi, rho)],
                                    C.byref(out) if fpr else None, _stream(stream)), "w1_op_plain_steps")
     return out.value if fpr else None

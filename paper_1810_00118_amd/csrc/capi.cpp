@@ -638,8 +638,8 @@ struct Op {
 int check_side(int n) { return (n >= 1 && n <= 8192) ? W1_OK : W1_EINVAL; }
 
 template <typename T>
-int op_plain_steps(int n, int metric, double scale, int steps, int block, int nwv, int rw, void* m1, void* m2,
-                   void* phi, const void* rho, double* fpr, hipStream_t s) {
+int op_plain_steps(int n, int metric, double scale, int steps, int block, int nwv, int rw, int rh, void* m1,
+                   void* m2, void* phi, const void* rho, double* fpr, hipStream_t s) {
   Op<T> op(n, s);
   const double sc = scale > 0 ? scale : 0.5;
   const double mu = sc / (2.0 * std::sqrt(2.0) * n);
@@ -653,8 +653,9 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, int nw
   d.rho = (T*)rho;
   void* pp;
   // one partial per tile at the deepest temporal block (the most tiles)
-  const int maxS = rw == TILED_RW ? TILED_MAX_STEPS : TILED_NARROW_MAX_STEPS;
-  const size_t ntile = (size_t)cdiv(n + 1, TILED_RH - 2 * maxS) * cdiv(n + 1, rw - 2 * maxS);
+  const int maxS = rh == TILED_RH_SHORT ? TILED_SHORT_MAX_STEPS
+                                        : (rw == TILED_RW ? TILED_MAX_STEPS : TILED_NARROW_MAX_STEPS);
+  const size_t ntile = (size_t)cdiv(n + 1, rh - 2 * maxS) * cdiv(n + 1, rw - 2 * maxS);
   if (op.alloc(sizeof(double) * NQ * ntile + 4096, &pp)) return W1_ENOMEM;
   d.part = (double*)pp;
   if (block < 0) {
@@ -676,7 +677,6 @@ int op_plain_steps(int n, int metric, double scale, int steps, int block, int nw
   }
   int st = op.commit(1);
   if (st) return st;
-  const int rh = TILED_RH;
   const int T_ = std::max(1, std::min(block > 0 ? block : 1, maxS));
   int done = 0, li = 0, lastS = 1;
   while (done < steps) {
@@ -925,21 +925,26 @@ extern "C" int w1_op_prolong(int32_t nc, int32_t precision, const void* c_m1, co
 }
 
 extern "C" int w1_op_plain_steps(int32_t n, int32_t metric, int32_t precision, double step_scale, int32_t steps,
-                                 int32_t block_steps, int32_t waves, int32_t region_width, void* m1, void* m2,
-                                 void* phi, const void* rho, double* fpr_out, void* hip_stream) {
+                                 int32_t block_steps, int32_t waves, int32_t region_width, int32_t region_height,
+                                 void* m1, void* m2, void* phi, const void* rho, double* fpr_out,
+                                 void* hip_stream) {
   if (check_side(n) || steps < 1 || metric < W1_METRIC_L1 || metric > W1_METRIC_LINF || !m1 || !m2 || !phi || !rho)
     return W1_EINVAL;
   if (step_scale > 1.0 || block_steps > TILED_MAX_STEPS || (waves != 0 && waves != 8 && waves != 16))
     return W1_EINVAL;
   const int rw = region_width ? region_width : TILED_RW;
+  const int rh = region_height ? region_height : TILED_RH;
   if ((rw != TILED_RW && rw != TILED_RW_NARROW) || (rw == TILED_RW_NARROW && block_steps > TILED_NARROW_MAX_STEPS))
+    return W1_EINVAL;
+  if (rh != TILED_RH && (rh != TILED_RH_SHORT || rw != TILED_RW_NARROW || (waves != 0 && waves != 8) ||
+                         block_steps > TILED_SHORT_MAX_STEPS))
     return W1_EINVAL;
   const int nwv = waves ? waves : 8;
   hipStream_t s = (hipStream_t)hip_stream;
   return DISPATCH(
       precision,
-      op_plain_steps<float>(n, metric, step_scale, steps, block_steps, nwv, rw, m1, m2, phi, rho, fpr_out, s),
-      op_plain_steps<double>(n, metric, step_scale, steps, block_steps, nwv, rw, m1, m2, phi, rho, fpr_out, s));
+      op_plain_steps<float>(n, metric, step_scale, steps, block_steps, nwv, rw, rh, m1, m2, phi, rho, fpr_out, s),
+      op_plain_steps<double>(n, metric, step_scale, steps, block_steps, nwv, rw, rh, m1, m2, phi, rho, fpr_out, s));
 }
 
 extern "C" int w1_tuner_table(char* buf, size_t len) {

@@ -81,9 +81,11 @@ static double tiled_computed(int n, int rh, int rw, int S) {
 }
 static inline int max_tiles(int n) {
   // the tiled kernel has the most tiles at its deepest temporal block
-  const int tiled = std::max(tiled_ti(n, TILED_RH, TILED_MAX_STEPS) * tiled_tj(n, TILED_RW, TILED_MAX_STEPS),
-                             tiled_ti(n, TILED_RH, TILED_NARROW_MAX_STEPS) *
-                                 tiled_tj(n, TILED_RW_NARROW, TILED_NARROW_MAX_STEPS));
+  const int tiled = std::max({tiled_ti(n, TILED_RH, TILED_MAX_STEPS) * tiled_tj(n, TILED_RW, TILED_MAX_STEPS),
+                              tiled_ti(n, TILED_RH, TILED_NARROW_MAX_STEPS) *
+                                  tiled_tj(n, TILED_RW_NARROW, TILED_NARROW_MAX_STEPS),
+                              tiled_ti(n, TILED_RH_SHORT, TILED_SHORT_MAX_STEPS) *
+                                  tiled_tj(n, TILED_RW_NARROW, TILED_SHORT_MAX_STEPS)});
   const int g = std::max(gemm_t(n), fold_tiles(n + 1));
   return std::max(simple_tiles(n), std::max(g * g, tiled));
 }
@@ -133,20 +135,26 @@ class Tuner {
       e.key = key;
       for (int nwv : {8, 16}) {
         if (requested > 0) {
-          e.arms.push_back(Arm{nwv, depth_for(requested, check_every), TILED_RW});
+          e.arms.push_back(Arm{nwv, depth_for(requested, check_every), TILED_RW, TILED_RH});
           continue;
         }
         // depth 1 only when nothing deeper divides the cadence
         for (int t = 2; t <= std::min(check_every, TILED_MAX_STEPS); ++t)
-          if (check_every % t == 0) e.arms.push_back(Arm{nwv, t, TILED_RW});
-        if (e.arms.empty() || e.arms.back().nwv != nwv) e.arms.push_back(Arm{nwv, depth_for(1, check_every), TILED_RW});
+          if (check_every % t == 0) e.arms.push_back(Arm{nwv, t, TILED_RW, TILED_RH});
+        if (e.arms.empty() || e.arms.back().nwv != nwv)
+          e.arms.push_back(Arm{nwv, depth_for(1, check_every), TILED_RW, TILED_RH});
       }
       // the narrow region at its deepest offered block: for active sets that
       // leave compute units idle, twice the workgroups at a larger halo
       // share (the size class decides, as for the other shapes)
       const int tn = depth_for(requested > 0 ? std::min(requested, TILED_NARROW_MAX_STEPS) : TILED_NARROW_MAX_STEPS,
                                check_every);
-      for (int nwv : {8, 16}) e.arms.push_back(Arm{nwv, tn, TILED_RW_NARROW});
+      for (int nwv : {8, 16}) e.arms.push_back(Arm{nwv, tn, TILED_RW_NARROW, TILED_RH});
+      // the short narrow region (32 x 64, 8 wavefronts): twice the
+      // workgroups again, for the few slots still running late in a batch
+      const int ts = depth_for(requested > 0 ? std::min(requested, TILED_SHORT_MAX_STEPS) : TILED_SHORT_MAX_STEPS,
+                               check_every);
+      e.arms.push_back(Arm{8, ts, TILED_RW_NARROW, TILED_RH_SHORT});
       it = tab_.emplace(key, e).first;
       order_.push_back(key);
     }
@@ -176,7 +184,7 @@ class Tuner {
       }
     }
     TileChoice c;
-    c.rh = TILED_RH;
+    c.rh = e.arms[a].rh;
     c.steps = e.arms[a].T;
     c.nwv = e.arms[a].nwv;
     c.rw = e.arms[a].rw;
@@ -220,8 +228,8 @@ class Tuner {
       for (size_t a = 0; a < e.arms.size(); ++a) {
         const Arm& A = e.arms[a];
         std::snprintf(buf, sizeof buf,
-                      "%s{\"waves\":%d,\"T\":%d,\"width\":%d,\"blocks\":%d,\"ns_per_update\":%.6g}", a ? "," : "",
-                      A.nwv, A.T, A.rw, A.done, A.units > 0 ? A.ms * 1e6 / A.units : -1.0);
+                      "%s{\"waves\":%d,\"T\":%d,\"width\":%d,\"height\":%d,\"blocks\":%d,\"ns_per_update\":%.6g}",
+                      a ? "," : "", A.nwv, A.T, A.rw, A.rh, A.done, A.units > 0 ? A.ms * 1e6 / A.units : -1.0);
         out += buf;
       }
       std::snprintf(buf, sizeof buf, "],\"best\":%d}", e.best);
@@ -238,7 +246,7 @@ class Tuner {
 
  private:
   struct Arm {
-    int nwv, T, rw;
+    int nwv, T, rw, rh;
     int seen = 0, done = 0;
     double ms = 0, units = 0;
     double cost() const { return units > 0 ? ms / units : 1e300; }

@@ -102,6 +102,7 @@ struct TileChoice {
   int steps;   // temporal block depth
   int nwv;     // wavefronts per workgroup (8 or 16)
   int rw;      // region columns (128, or 64 for launches that leave the device idle)
+  // (rh: 64, or 32 with rw 64 and 8 wavefronts)
 };
 // launch-shape autotuner of the plain tiled kernel (process-wide)
 std::string tuner_table();   // JSON array of the tuner's entries

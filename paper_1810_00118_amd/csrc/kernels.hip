@@ -559,7 +559,9 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 // rows [8w, 8w+8), lane l owns columns l and l+64 (16 wavefronts: rows
 // [4w, 4w+4)).  The 64 x 64 region (RWID = 64, lane l owns column l) spreads
 // a grid over twice as many workgroups at a larger halo share, for launches
-// that leave most of the device idle.  The region is the
+// that leave most of the device idle; the 32 x 64 region over 8 wavefronts
+// (4 rows each) halves the work of a workgroup again, for the launches of a
+// few slots late in a batch.  The region is the
 // output tile plus a halo of `steps` nodes on every side; after s steps the
 // flux is valid on rows [s-1, 63-s] and the potential on [s, 63-s] (same for
 // columns), so `steps` iterations run without leaving the workgroup and the
@@ -582,13 +584,13 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 #ifndef W1_TILED_WPE_CHECK
 #define W1_TILED_WPE_CHECK 4
 #endif
-template <typename T, bool CHECK, int METRIC, int NWV = 8, int RWID = TILED_RW,
+template <typename T, bool CHECK, int METRIC, int NWV = 8, int RWID = TILED_RW, int RHT = TILED_RH,
           int WAVES_PER_EU = (NWV == 16 ? (sizeof(T) == 4 ? 8 : 4)
                                         : (sizeof(T) == 4 ? (CHECK ? W1_TILED_WPE_CHECK : W1_TILED_WPE) : 2))>
 __global__ __launch_bounds__(NWV * 64) __attribute__((amdgpu_waves_per_eu(WAVES_PER_EU, 8))) void k_plain_tiled(
     const Work* __restrict__ work, const SlotDesc<T>* __restrict__ desc, const SlotScalars* __restrict__ scal,
     int li, int steps, int second) {
-  constexpr int RH = TILED_RH, RW = RWID, NR = RH / NWV, NC = RW / 64;
+  constexpr int RH = RHT, RW = RWID, NR = RH / NWV, NC = RW / 64;
   static_assert(NC == 1 || NC == 2, "regions are 64 or 128 columns wide");
   static_assert(NR * NWV == RH, "wavefronts split the region's rows evenly");
   __shared__ T Bp[NWV][RW];   // first potential row of each strip
@@ -2229,39 +2231,43 @@ template <typename T> void K<T>::plain_tiled(hipStream_t s, const Work* w, int n
                                              const SlotScalars* sc, int li, int steps, int rh, int rw, bool check,
                                              int metric, int nwv, int second, hipEvent_t ev0, hipEvent_t ev1) {
   if (!nw) return;
-  if (rh != TILED_RH || (rw != 64 && rw != 128) || steps < 1 || steps > TILED_MAX_STEPS || 2 * steps >= rw ||
-      (metric < 1 || metric > 3) || (nwv != 8 && nwv != 16)) {
+  const bool shape = (rh == TILED_RH && (rw == 64 || rw == 128) && (nwv == 8 || nwv == 16)) ||
+                     (rh == TILED_RH_SHORT && rw == 64 && nwv == 8);
+  if (!shape || steps < 1 || steps > TILED_MAX_STEPS || 2 * steps >= rw || 2 * steps >= rh ||
+      (metric < 1 || metric > 3)) {
     fprintf(stderr, "w1: internal error: %d steps in a %d x %d region, metric %d, %d waves\n", steps, rh, rw,
             metric, nwv);
     return;
   }
-#define W1_TILED_LAUNCH(C, M, NWV, RWD) \
-  LAUNCH_EV((k_plain_tiled<T, C, M, NWV, RWD>), nw, NWV * 64, 0, s, ev0, ev1, w, d, sc, li, steps, second)
-#define W1_TILED_METRIC(NWV, RWD)                   \
-  switch (metric) {                                 \
-    case 1:                                         \
-      if (check) W1_TILED_LAUNCH(true, 1, NWV, RWD); \
-      else W1_TILED_LAUNCH(false, 1, NWV, RWD);      \
-      break;                                        \
-    case 2:                                         \
-      if (check) W1_TILED_LAUNCH(true, 2, NWV, RWD); \
-      else W1_TILED_LAUNCH(false, 2, NWV, RWD);      \
-      break;                                        \
-    default:                                        \
-      if (check) W1_TILED_LAUNCH(true, 3, NWV, RWD); \
-      else W1_TILED_LAUNCH(false, 3, NWV, RWD);      \
+#define W1_TILED_LAUNCH(C, M, NWV, RWD, RHD) \
+  LAUNCH_EV((k_plain_tiled<T, C, M, NWV, RWD, RHD>), nw, NWV * 64, 0, s, ev0, ev1, w, d, sc, li, steps, second)
+#define W1_TILED_METRIC(NWV, RWD, RHD)                   \
+  switch (metric) {                                      \
+    case 1:                                              \
+      if (check) W1_TILED_LAUNCH(true, 1, NWV, RWD, RHD); \
+      else W1_TILED_LAUNCH(false, 1, NWV, RWD, RHD);      \
+      break;                                             \
+    case 2:                                              \
+      if (check) W1_TILED_LAUNCH(true, 2, NWV, RWD, RHD); \
+      else W1_TILED_LAUNCH(false, 2, NWV, RWD, RHD);      \
+      break;                                             \
+    default:                                             \
+      if (check) W1_TILED_LAUNCH(true, 3, NWV, RWD, RHD); \
+      else W1_TILED_LAUNCH(false, 3, NWV, RWD, RHD);      \
   }
-  if (rw == 128) {
+  if (rh == TILED_RH_SHORT) {
+    W1_TILED_METRIC(8, 64, TILED_RH_SHORT)
+  } else if (rw == 128) {
     if (nwv == 16) {
-      W1_TILED_METRIC(16, 128)
+      W1_TILED_METRIC(16, 128, TILED_RH)
     } else {
-      W1_TILED_METRIC(8, 128)
+      W1_TILED_METRIC(8, 128, TILED_RH)
     }
   } else {
     if (nwv == 16) {
-      W1_TILED_METRIC(16, 64)
+      W1_TILED_METRIC(16, 64, TILED_RH)
     } else {
-      W1_TILED_METRIC(8, 64)
+      W1_TILED_METRIC(8, 64, TILED_RH)
     }
   }
 #undef W1_TILED_METRIC

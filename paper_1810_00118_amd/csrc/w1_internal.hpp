@@ -32,6 +32,8 @@ constexpr int TILED_RW_NARROW = 64;  // its narrow region (twice the workgroups)
 constexpr int TILED_RH = 64;         // plain tiled kernel region height
 constexpr int TILED_MAX_STEPS = 26;  // most PDHG steps per tiled launch
 constexpr int TILED_NARROW_MAX_STEPS = 16;   // ... in the narrow region
+constexpr int TILED_RH_SHORT = 32;           // the short narrow region's height
+constexpr int TILED_SHORT_MAX_STEPS = 10;    // ... and its deepest block
 constexpr int PRES_THREADS = 1024;   // resident kernel workgroup size (Algorithm 2)
 constexpr int FFT_MIN_N = 1025;      // FP32 Poisson solves by FFT from this
                                      // transform length on (N = n + 1 with
@@ -121,8 +123,8 @@ struct K {
                       int kind);
   // the plain kernels are compiled per ground metric: every slot of one
   // launch has `metric` (others in the list are skipped); the tiled
-  // kernel's rh x rw region (64 x 128 or 64 x 64) is split over nwv = 8 or
-  // 16 wavefronts
+  // kernel's rh x rw region (64 x 128 or 64 x 64 over nwv = 8 or 16
+  // wavefronts, or 32 x 64 over 8)
   // second = 1: the second of two one-launch blocks checked together (its
   // stop-test partials go after the first block's); ev0 / ev1, when given,
   // receive the dispatch's start and end times

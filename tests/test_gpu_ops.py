@@ -122,7 +122,7 @@ def test_resident_and_tiled_agree_bitwise(precision, n, metric):
 @pytest.mark.parametrize("n", [100, 200, 300])
 @pytest.mark.parametrize("metric", [1, 2, 3])
 def test_region_shapes_agree_bitwise(precision, n, metric):
-    """The 64 x 128 and 64 x 64 regions, over 8 or 16 wavefronts and at
+    """The 64 x 128, 64 x 64 and 32 x 64 regions, over 8 or 16 wavefronts and at
     every block depth, give the same iterates bit for bit (grids of several
     tiles in both directions with ragged last tiles).  R^k is a sum of
     per-tile partials, whose grouping follows the tiling: equal up to
@@ -132,11 +132,12 @@ def test_region_shapes_agree_bitwise(precision, n, metric):
     m1, m2, phi = _rand_state(n, 12)
     dt = tdtype(precision)
     outs = []
-    for block, waves, width in ((10, 16, 0), (1, 8, 0), (7, 8, 0), (10, 16, 64), (10, 8, 64), (16, 16, 64),
-                                (4, 8, 64)):
+    for block, waves, width, height in ((10, 16, 0, 0), (1, 8, 0, 0), (7, 8, 0, 0), (10, 16, 64, 0),
+                                        (10, 8, 64, 0), (16, 16, 64, 0), (4, 8, 64, 0), (10, 8, 64, 32),
+                                        (3, 8, 64, 32)):
         g = [dev(x, dt) for x in (m1, m2, phi, rho)]
         R = w1.op_plain_steps(n, metric, precision, 40, g[0], g[1], g[2], g[3], block_steps=block, waves=waves,
-                              width=width, fpr=True)
+                              width=width, height=height, fpr=True)
         outs.append(([host(x) for x in g[:3]], R))
     for other, R in outs[1:]:
         assert R == pytest.approx(outs[0][1], rel=1e-12 if precision == FP64 else 1e-6)
@@ -145,14 +146,18 @@ def test_region_shapes_agree_bitwise(precision, n, metric):
 
 
 def test_region_width_rejected():
-    """Region widths other than 0, 64 and 128, and narrow blocks deeper than
-    16 steps, are W1_EINVAL."""
+    """Region widths other than 0, 64 and 128, narrow blocks deeper than 16
+    steps, and short regions other than 32 x 64 over 8 wavefronts with at
+    most 10 steps, are W1_EINVAL."""
     w1 = require_gpu()
     n = 40
     g = [dev(x, tdtype(FP32)) for x in (*_rand_state(n, 1), _rho(n, 1))]
     for width, block in ((32, 4), (96, 4), (64, 17)):
         with pytest.raises(w1.W1Error):
             w1.op_plain_steps(n, 2, FP32, 4, *g, block_steps=block, width=width)
+    for width, height, waves, block in ((128, 32, 8, 4), (64, 32, 16, 4), (64, 32, 8, 11), (64, 48, 8, 4)):
+        with pytest.raises(w1.W1Error):
+            w1.op_plain_steps(n, 2, FP32, 4, *g, block_steps=block, width=width, height=height, waves=waves)
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
