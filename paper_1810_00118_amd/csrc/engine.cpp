@@ -89,6 +89,9 @@ static inline int max_tiles(int n) {
   const int g = std::max(gemm_t(n), fold_tiles(n + 1));
   return std::max(simple_tiles(n), std::max(g * g, tiled));
 }
+// a slot's stop-test partials: room for two blocks of the most tiles, so
+// that blocks of any launch shape can take their stop tests in pairs
+static inline int part_tiles(int n) { return 2 * max_tiles(n); }
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static double paper_eps(int algo, int n, bool multilevel) {
@@ -105,7 +108,7 @@ size_t request_bytes(const w1_params& p) {
     const size_t pe = plane_elems(nl);
     b += (NPLANES + 1) * align256(pe * es) + 2 * align256(pe * 8);
   }
-  b += align256((size_t)max_tiles(p.n) * NQ * 8);
+  b += align256((size_t)part_tiles(p.n) * NQ * 8);
   b += 3 * align256((size_t)(p.n + 1) * (p.n + 1) * 8);
   return b;
 }
@@ -748,7 +751,7 @@ class Batch : public BatchBase {
       }
     }
     double* part = (double*)p;
-    p += align256((size_t)max_tiles(r->prm.n) * NQ * 8);
+    p += align256((size_t)part_tiles(r->prm.n) * NQ * 8);
     const size_t ne = (size_t)(r->prm.n + 1) * (r->prm.n + 1);
     double* in0 = (double*)p;
     p += align256(ne * 8);
@@ -1494,7 +1497,7 @@ class Batch : public BatchBase {
       first = true;
       for (auto* r : P) {
         const int n = r->sides[r->level];
-        if (2 * tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.rw, tc.steps) > max_tiles(r->prm.n)) first = false;
+        if (2 * tiled_ti(n, tc.rh, tc.steps) * tiled_tj(n, tc.rw, tc.steps) > part_tiles(r->prm.n)) first = false;
       }
       if (first) {
         pair_open_[group] = 1;
