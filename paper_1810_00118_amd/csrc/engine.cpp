@@ -1827,6 +1827,9 @@ class Batch : public BatchBase {
     return W1_OK;
   }
   void drop_graphs() {
+    if (graphs_.empty()) return;
+    // a replay of the previous step (its speculative blocks) may still run
+    (void)hipStreamSynchronize(st_);
     for (auto& kv : graphs_)
       if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     graphs_.clear();
