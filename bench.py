@@ -878,9 +878,19 @@ def main():
             # the algorithm's node updates need (halo recomputation and the
             # kernel's own index and lane-shift work not counted) per second
             # of its launches; issue_frac_computed is the compiled loop's
-            # slots over every node it computes, halo included
-            sec = st["ms"] * 1e-3
-            useful, computed = st["node_updates"], st["flops"]
+            # slots over every node it computes, halo included.
+            # The launches' number is exact (`issued`), their mean duration
+            # the timed sample's; the useful node updates come from the
+            # solves' own iteration counts (all node updates of the timed
+            # solves minus those of the resident levels, which are all
+            # timed), not from the launches' slot lists: a slot that stops
+            # inside a step's queued blocks is skipped on the device but
+            # stays in the list it was issued with.
+            issued = max(st["issued"], st["launches"])
+            sec = avg_ms * 1e-3 * issued
+            useful = cell_updates * args.steps - kstats["plain_resident"]["node_updates"]
+            halo = st["flops"] / st["node_updates"]   # computed per useful update, as issued
+            computed = useful * halo
             # the compiled count of the shape the autotuner chose for the
             # largest active set (the launches that carry most of the work)
             big = max((a for a in tuned if a["precision"] == 1), key=lambda a: a["class"], default=None)
@@ -890,30 +900,29 @@ def main():
             achieved = useful * alg / sec
             T_ = [a["T"] for a in tuned] or [10]
             Tm = float(np.median(T_))
-            covered = computed / Tm          # region nodes read per launch step block
-            dram = (16.0 * covered + 12.0 * useful / Tm) / useful   # read m1 m2 phi rho, write m1 m2 phi
+            dram = (16.0 * halo + 12.0) / Tm   # per useful update: read m1 m2 phi rho per region node, write m1 m2 phi
             # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
             # counts (per useful update, scaled to this run's launches)
             tr = measured_traffic("k_plain_tiled", "uniform256") if (n, P, args.ground) == (256, 256, "l2") else None
-            traffic = tr["bytes_per_useful_update"] * useful / st["launches"] if tr else None
+            traffic = tr["bytes_per_useful_update"] * useful / issued if tr else None
             roof = {"kernel": dom, "bound": "alu", "achieved": achieved / 1e12, "peak": VALU_LANE_OPS_PEAK / 1e12,
                     "unit": "TOP/s (VALU lane-ops, non-packed FP32)", "frac": achieved / VALU_LANE_OPS_PEAK,
                     "traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                     "traffic_gbs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
-                    "avg_launch_ms": avg_ms, "launches": st["launches"],
+                    "avg_launch_ms": avg_ms, "launches": issued, "launches_timed": st["launches"],
                     "timed_launches": f"pseudo-random sample of about 1 in {TILED_TIMING_EVERY} launches "
                                       "(events bound to the dispatch: kernel start to end)",
                     "alg_valu_slots_per_update": alg,
                     "valu_cycles_per_update": cyc,
                     "region_shape": f"64 x {shape[0]}, {shape[1]} wavefronts",
                     "issue_frac_computed": computed * cyc / sec / VALU_LANE_OPS_PEAK if cyc else None,
-                    "useful_updates_per_launch": useful / st["launches"],
-                    "computed_updates_per_launch": computed / st["launches"],
-                    "halo_factor": computed / useful,
+                    "useful_updates_per_launch": useful / issued,
+                    "computed_updates_per_launch": computed / issued,
+                    "halo_factor": halo,
                     "useful_updates_per_s": useful / sec,
                     "modelled_dram_bytes_per_useful_update": dram,
                     "modelled_dram_gbs": dram * useful / sec / 1e9,
-                    "effective_alg_gbs_28B": st["alg_bytes"] / sec / 1e9}
+                    "effective_alg_gbs_28B": 28.0 * useful / sec / 1e9}
         elif dom == "prox_elem":
             achieved = st["alg_bytes"] / (st["ms"] * 1e-3) / 1e9
             roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

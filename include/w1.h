@@ -401,7 +401,10 @@ int w1_op_prox_steps3d(int32_t n, int32_t metric, int32_t precision,
  *   elementwise 13 words per node per iteration; DCT pass 2 words per node
  *   per pass; resident 0), out[4] floating-point operations (DCT passes)
  *   or, for the plain tiled family, the node updates its launches compute
- *   (the overlapping halo of the temporal blocks included).
+ *   (the overlapping halo of the temporal blocks included), out[5] the
+ *   family's launches while timing was on, timed or not.  Node updates and
+ *   bytes are those the launch was issued for: a slot that stops inside a
+ *   step's queued blocks is skipped by the device but still counted.
  * Families: W1_FAM_PLAIN_TILED, W1_FAM_PLAIN_RESIDENT, W1_FAM_DCT,
  * W1_FAM_PROX_ELEM, W1_FAM_OTHER, W1_FAM_PROX_RESIDENT (whole small prox
  * levels in one workgroup; resident families count node updates only).    */
@@ -409,7 +412,7 @@ enum { W1_FAM_PLAIN_TILED = 0, W1_FAM_PLAIN_RESIDENT = 1, W1_FAM_DCT = 2,
        W1_FAM_PROX_ELEM = 3, W1_FAM_OTHER = 4, W1_FAM_PROX_RESIDENT = 5,
        W1_NFAM = 6 };
 int w1_profile(w1_handle h, int32_t enable);
-int w1_kernel_stats(w1_handle h, int32_t family, double* out5);
+int w1_kernel_stats(w1_handle h, int32_t family, double* out6);
 
 /* ---- launch-shape autotuner ---------------------------------------------
  * The plain tiled kernel's temporal depth and wavefronts per workgroup are

@@ -278,10 +278,10 @@ class Solver:
     def kernel_stats(self):
         out = {}
         for f, name in FAMILIES.items():
-            o = (C.c_double * 5)()
+            o = (C.c_double * 6)()
             _check(lib().w1_kernel_stats(self.h, f, o), "w1_kernel_stats")
             out[name] = {"launches": int(o[0]), "ms": o[1], "node_updates": o[2], "alg_bytes": o[3],
-                         "flops": o[4]}
+                         "flops": o[4], "issued": int(o[5])}
         return out
 
     def drain(self):

@@ -186,14 +186,20 @@ extern "C" int w1_solve(w1_handle h, int32_t count, const double* const* p0, con
     if (st) return st;
     h->last.push_back(std::move(r));
   }
+  // a closed batch: long steps (fewer host synchronisations); the served
+  // worker's short steps again afterwards
+  b->set_step_budget(kBatchStepUs, kBatchStepBlocks);
+  int st = W1_OK;
   while (true) {
-    int st = b->step();
-    if (st) return st;
+    st = b->step();
+    if (st) break;
     bool all_done = true;
     for (auto& r : h->last)
       if (r->state != Request::DONE) all_done = false;
     if (all_done) break;
   }
+  b->set_step_budget(kServedStepUs, kServedStepBlocks);
+  if (st) return st;
   for (int k = 0; k < count; ++k) out[k] = h->last[k]->res;
   return W1_OK;
 }
@@ -450,15 +456,15 @@ extern "C" int w1_profile(w1_handle h, int32_t enable) {
   return W1_OK;
 }
 
-extern "C" int w1_kernel_stats(w1_handle h, int32_t family, double* out5) {
-  if (!h || !out5 || family < 0 || family >= W1_NFAM) return W1_EINVAL;
+extern "C" int w1_kernel_stats(w1_handle h, int32_t family, double* out6) {
+  if (!h || !out6 || family < 0 || family >= W1_NFAM) return W1_EINVAL;
   std::lock_guard<std::mutex> g(h->run_mu);
-  for (int k = 0; k < 5; ++k) out5[k] = 0;
+  for (int k = 0; k < 6; ++k) out6[k] = 0;
   for (auto* b : {h->b32.get(), h->b64.get()}) {
     if (!b) continue;
-    double o[5];
+    double o[6];
     b->kernel_stats(family, o);
-    for (int k = 0; k < 5; ++k) out5[k] += o[k];
+    for (int k = 0; k < 6; ++k) out6[k] += o[k];
   }
   return W1_OK;
 }

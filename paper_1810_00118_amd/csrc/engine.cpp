@@ -511,14 +511,16 @@ class Prof {
   int every = 1;
   void reset() {
     for (int f = 0; f < W1_NFAM; ++f) tot_[f][0] = tot_[f][1] = tot_[f][2] = tot_[f][3] = tot_[f][4] = 0;
+    for (int f = 0; f < W1_NFAM; ++f) issued_[f] = 0;
     drawn_ = 0;
   }
   // returns the pending index (or -1 when off); `s`: the launch's stream
   // when it is not the batch's own
   // sample: subject to the 1-in-`every` draw (whole-level resident
   // launches, one per step, are always timed)
-  int begin(hipStream_t s = nullptr, bool sample = true) {
+  int begin(int fam, hipStream_t s = nullptr, bool sample = true) {
     if (!on) return -1;
+    issued_[fam] += 1;
     if (sample && every > 1 && mix64(++drawn_) % (uint64_t)every != 0) return -1;
     Pend p;
     p.a = ev();
@@ -534,9 +536,10 @@ class Prof {
   // (a fixed pseudo-random sequence, so no period of the launch pattern
   // aliases with it): timed dispatches end with a cache flush that the
   // untimed ones skip.
-  int begin_ext(hipEvent_t* a, hipEvent_t* b) {
+  int begin_ext(int fam, hipEvent_t* a, hipEvent_t* b) {
     *a = *b = nullptr;
     if (!on) return -1;
+    issued_[fam] += 1;
     if (every > 1 && mix64(++drawn_) % (uint64_t)every != 0) return -1;
     Pend p;
     p.a = ev();
@@ -585,6 +588,7 @@ class Prof {
   }
   void stats(int f, double* o) const {
     for (int k = 0; k < 5; ++k) o[k] = tot_[f][k];
+    o[5] = issued_[f];
   }
 
  private:
@@ -616,6 +620,7 @@ class Prof {
   std::vector<hipEvent_t> pool_;
   uint64_t drawn_ = 0;
   double tot_[W1_NFAM][5] = {};
+  double issued_[W1_NFAM] = {};   // launches while timing was on, timed or not
 };
 
 // ---------------------------------------------------------------------------
@@ -840,9 +845,9 @@ class Batch : public BatchBase {
     if (st) return fail(st);
     // Several iteration blocks per host synchronisation (slots that stop
     // inside the pipeline are skipped by the gated kernels), sized so each
-    // group gets a few milliseconds of device work per step.  Beside running
-    // tiled or prox levels, LDS-resident levels run in chunks of about that
-    // length.
+    // group gets the step budget of device work per step (2 ms in served
+    // mode, up to 16 ms for a closed batch).  Beside running tiled or prox levels,
+    // LDS-resident levels run in chunks of about that length.
     struct Grp {
       std::vector<Request*>* v;
       bool prox;
@@ -850,12 +855,28 @@ class Batch : public BatchBase {
       double us;
     };
     std::vector<Grp> groups;
+    // A long budget only pays for a group of many slots: the blocks queued
+    // past a slot's stop run empty for it, which a lone slot pays in full
+    // at every level (and a large set hardly at all, as its slots stop
+    // spread over the blocks).  A group of k slots gets the served budget
+    // scaled by k / 8, up to the batch's own.
+    auto budget = [&](size_t k, double* us, int* cap) {
+      const double f = std::max(1.0, (double)k / 8.0);
+      *us = std::min(step_budget_us_, kServedStepUs * f);
+      *cap = std::min(nb_cap_, (int)(kServedStepBlocks * f));
+    };
     double plain_nodes = 0;
-    for (auto& kv : P)
+    size_t plain_slots = 0;
+    for (auto& kv : P) {
+      plain_slots += kv.second.size();
       for (auto* r : kv.second) plain_nodes += node_count(r->sides[r->level]) * r->prm.check_every;
+    }
     // plain: ~3e11 node updates / s; one block count for all plain groups
     const double plain_us = std::max(30.0, plain_nodes / 3.0e5);
-    const int plain_nb = std::max(8, std::min(64, (int)(2000.0 / plain_us)));
+    double pb_us;
+    int pb_cap;
+    budget(plain_slots, &pb_us, &pb_cap);
+    const int plain_nb = std::max(8, std::min(pb_cap, (int)(pb_us / plain_us)));
     for (auto& kv : P) groups.push_back(Grp{&kv.second, false, plain_nb, plain_us});
     for (auto& kv : X) {
       // per iteration: ~42 us of launch latency for the group, the DCT
@@ -866,7 +887,10 @@ class Batch : public BatchBase {
         it_us += N * N * N / 5.0e6 + N * N / 5.0e4;
       }
       const double us = it_us * std::get<0>(kv.first);
-      groups.push_back(Grp{&kv.second, true, std::max(1, std::min(64, (int)(2000.0 / us))), us});
+      double xb_us;
+      int xb_cap;
+      budget(kv.second.size(), &xb_us, &xb_cap);
+      groups.push_back(Grp{&kv.second, true, std::max(1, std::min(xb_cap, (int)(xb_us / us))), us});
     }
     int maxnb = 0;
     double step_us = 0;
@@ -1052,6 +1076,10 @@ class Batch : public BatchBase {
     return W1_OK;
   }
 
+  void set_step_budget(double us, int max_blocks) override {
+    step_budget_us_ = us;
+    nb_cap_ = max_blocks;
+  }
   void profile(int every) override {
     prof_.on = every > 0;
     prof_.every = every > 1 ? every : 1;
@@ -1445,7 +1473,7 @@ class Batch : public BatchBase {
       int chunk = 0;
       if (budget_us > 0) chunk = std::max(1, (int)(budget_us / it_us));
       const int c = chunk > 0 ? ((chunk + ce - 1) / ce) * ce : 0;
-      const int pi = prof_.begin(ls, false);
+      const int pi = prof_.begin(kind == K_PLAIN ? W1_FAM_PLAIN_RESIDENT : W1_FAM_PROX_RESIDENT, ls, false);
       if (kind == K_PLAIN)
         K<T>::plain_resident(ls, di, nids, ddesc_, dsc_, maxside, ce, c, metric);
       else
@@ -1547,7 +1575,7 @@ class Batch : public BatchBase {
     for (int li = 0; li < nl; ++li) {
       const bool chk = fpr && li == nl - 1;
       hipEvent_t e0, e1;
-      const int pi = prof_.begin_ext(&e0, &e1);
+      const int pi = prof_.begin_ext(W1_FAM_PLAIN_TILED, &e0, &e1);
       // the second of a pair reads the set the first wrote (the stop test
       // that would flip the slot's current set has not run in between)
       K<T>::plain_tiled(st_, w, nw, ddesc_, dsc_, second ? 1 : li, tc.steps, tc.rh, tc.rw, chk, P[0]->prm.metric,
@@ -1639,13 +1667,13 @@ class Batch : public BatchBase {
       }
     }
     for (int it = 0; it < ce; ++it) {
-      int pi = prof_.begin();
+      int pi = prof_.begin(W1_FAM_PROX_ELEM);
       K<T>::div_pre(st_, dsw, nsw, ddesc_, dsc_, 0, K_PROX, 1);
       prof_.end(pi, W1_FAM_PROX_ELEM, nodes, nodes * 6.0 * sizeof(T), 0);
-      pi = prof_.begin();
+      pi = prof_.begin(W1_FAM_DCT);
       poisson(dgw, ngw, 6, 1, lv);
       prof_.end(pi, W1_FAM_DCT, nodes, dbytes, flops);
-      pi = prof_.begin();
+      pi = prof_.begin(W1_FAM_PROX_ELEM);
       K<T>::prox_post(st_, dsw, nsw, ddesc_, dsc_, fpr && it == ce - 1);
       prof_.end(pi, W1_FAM_PROX_ELEM, 0, nodes * 13.0 * sizeof(T), 0);
     }
@@ -1875,6 +1903,8 @@ class Batch : public BatchBase {
   bool speculate_ = true;
   bool side_stream_ = true;
   bool pairs_ = true;                  // W1_PAIRED_CHECK=0: a stop test after every block
+  double step_budget_us_ = kServedStepUs;   // device work queued per host synchronisation
+  int nb_cap_ = kServedStepBlocks;          // and the most iteration blocks in it
   std::vector<char> pair_open_;        // per plain group: a pair's first block is queued
   std::vector<TileChoice> pair_tc_;    // its launch shape
   bool res_side_ = false;

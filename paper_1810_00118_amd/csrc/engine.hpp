@@ -76,7 +76,12 @@ class BatchBase {
   virtual int prep_export(Request* r, void* const* rho_out) = 0;
   // per-family kernel timing (HIP events on the batch's stream)
   virtual void profile(int every) = 0;   // 0: off; k >= 1: time about one launch in k
-  virtual void kernel_stats(int family, double* out5) const = 0;
+  // device work a step queues per host synchronisation (microseconds, at
+  // its own cost model) and the most iteration blocks in it: short steps
+  // keep served requests' admission and completion prompt, long ones cut
+  // the host synchronisations of a closed batch
+  virtual void set_step_budget(double us, int max_blocks) = 0;
+  virtual void kernel_stats(int family, double* out6) const = 0;
   // device memory that work already queued on the batch's stream may still
   // read: returned to the cache at the batch's next host synchronisation
   virtual void retire(size_t bytes, char* mem) = 0;
@@ -86,6 +91,13 @@ class BatchBase {
 };
 
 std::unique_ptr<BatchBase> make_batch(bool fp64, int capacity, hipStream_t stream);
+
+// step budgets: served mode (requests arrive while others run) and a
+// closed batch (w1_solve: every request admitted up front)
+constexpr double kServedStepUs = 2000.0;
+constexpr int kServedStepBlocks = 64;
+constexpr double kBatchStepUs = 16000.0;
+constexpr int kBatchStepBlocks = 128;
 
 // device staging memory for served requests (the solve-state block cache)
 int stage_alloc(size_t bytes, char** out);
