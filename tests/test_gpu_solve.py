@@ -670,3 +670,37 @@ def test_trim_cache_releases_idle_blocks():
         b = s.solve(pairs)
     for x, y in zip(a, b):
         assert x["iters"] == y["iters"] and x["w1"] == y["w1"]
+
+
+def test_closed_batch_budget_same_bits():
+    """A closed batch (w1_solve) queues more iteration blocks per host
+    synchronisation than served mode once a group holds many slots; the
+    blocks past a slot's stop skip it, so every result is the served one bit
+    for bit, in fewer host steps."""
+    w1 = require_gpu()
+    n, L, k = 64, 2, 24
+    pairs = [w1data.pair_gauss3(200 + i, n=n) for i in range(k)]
+    prm = w1.params(n=n, levels=L, metric=2, algo=w1.ALGO_PLAIN, precision=FP32, stop_rule=w1.STOP_FPR,
+                    tol=0.0, max_iters=3000, check_every=10, flags=w1.FLAG_NO_RESIDENT)
+    with w1.Solver(prm, capacity=k) as s:
+        batch = s.solve(pairs)
+        fb = [s.fields(i) for i in range(k)]
+        steps_batch = s.counters()["host_steps"]
+    with w1.Solver(prm, capacity=k) as srv:
+        tickets = [srv.submit(p0, p1, prm) for p0, p1 in pairs]
+        srv.drain()
+        served = []
+        for t in tickets:
+            r = None
+            while r is None:
+                r = srv.poll(t, n=n, fields=True)
+            served.append(r)
+        steps_served = srv.counters()["host_steps"]
+    print(f"host steps: closed batch {steps_batch}, served {steps_served}", flush=True)
+    for i in range(k):
+        res, fs = served[i]
+        assert res["iters"] == batch[i]["iters"]
+        assert res["w1"] == batch[i]["w1"]
+        for a, b in zip(fs, fb[i]):
+            np.testing.assert_array_equal(a, b)
+    assert steps_batch < steps_served
